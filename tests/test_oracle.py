@@ -1,0 +1,391 @@
+"""Pins for the CPU oracle: brute force, closed forms, library routines, the paper's
+theorems and printed values. None of these re-types the oracle's own formulas."""
+import itertools
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+# ----------------------------------------------------------------- helpers
+
+def brute(n, src, dst):
+    """O(n^3) enumeration over vertex triples of a boolean adjacency matrix."""
+    A = np.zeros((n, n), dtype=bool)
+    for a, b in zip(src.tolist(), dst.tolist()):
+        if a != b:
+            A[a, b] = A[b, a] = True
+    tris = []
+    for i in range(n):
+        for j in range(i + 1, n):
+            if not A[i, j]:
+                continue
+            for k in range(j + 1, n):
+                if A[i, k] and A[j, k]:
+                    tris.append((i, j, k))
+    t = np.zeros(n, np.uint64)
+    for tr in tris:
+        for x in tr:
+            t[x] += 1
+    deg = A.sum(axis=1).astype(np.int64)
+    return len(tris), t, np.array(tris, dtype=np.int32).reshape(-1, 3), deg
+
+
+def messy_random_graph(n, m, seed):
+    """Random raw edge list with loops, repeats and both directions."""
+    rng = np.random.default_rng(seed)
+    src = rng.integers(0, n, m).astype(np.int32)
+    dst = rng.integers(0, n, m).astype(np.int32)
+    # repeat some edges reversed, add some self loops
+    k = m // 4
+    src = np.concatenate([src, dst[:k], np.arange(min(n, 5), dtype=np.int32)])
+    dst = np.concatenate([dst, src[:k], np.arange(min(n, 5), dtype=np.int32)])
+    return src, dst
+
+
+# ---------------------------------------------------------- brute force pins
+
+@pytest.mark.parametrize("seed", range(12))
+def test_brute_force_small(seed):
+    rng = np.random.default_rng(100 + seed)
+    n = int(rng.integers(1, 36))
+    m = int(rng.integers(0, 4 * n + 1))
+    src, dst = messy_random_graph(n, m, seed)
+    T, t, tris, deg = brute(n, src, dst)
+    r = oracle.solve(src, dst, n, per_node=True, listing=True)
+    assert r.T == T
+    np.testing.assert_array_equal(r.t, t)
+    np.testing.assert_array_equal(r.deg, deg)
+    np.testing.assert_array_equal(r.tri, tris)
+    # definition route
+    lo, hi = r.extra["lo"], r.extra["hi"]
+    off, nbr = oracle.full_adjacency(lo, hi, n)
+    Td, td = oracle.local_counts_def(off, nbr, n)
+    assert Td == T
+    np.testing.assert_array_equal(td, t)
+    # clustering as exact rationals
+    for v in range(n):
+        d = int(deg[v])
+        if d >= 2:
+            assert int(r.num[v]) * (d * (d - 1)) == 2 * int(t[v]) * int(r.den[v])
+            assert int(r.den[v]) == d * (d - 1) // 2
+            assert r.cc[v] == float(2 * int(t[v])) / float(d * (d - 1))
+        else:
+            assert r.den[v] == 0 and r.cc[v] == 0.0
+
+
+def test_empty_and_trivial():
+    for n in (1, 2, 7):
+        r = oracle.solve(np.zeros(0, np.int32), np.zeros(0, np.int32), n, listing=True)
+        assert r.T == 0 and r.m == 0 and r.tri.shape == (0, 3)
+        assert (r.t == 0).all() and (r.cc == 0).all()
+    # only self loops
+    r = oracle.solve(np.array([0, 1, 1], np.int32), np.array([0, 1, 1], np.int32), 3)
+    assert r.m == 0 and r.T == 0
+
+
+def test_range_error():
+    with pytest.raises(oracle.OracleRangeError):
+        oracle.simple(np.array([0, 5], np.int32), np.array([1, 2], np.int32), 5)
+    with pytest.raises(oracle.OracleRangeError):
+        oracle.simple(np.array([0, -1], np.int32), np.array([1, 2], np.int32), 5)
+
+
+# ------------------------------------------------------------- closed forms
+
+CLOSED = [
+    (synth.complete(2), 0), (synth.complete(3), 1), (synth.complete(4), 4), (synth.complete(7), 35),
+    (synth.complete(20), math.comb(20, 3)),
+    (synth.wheel(3), 4), (synth.wheel(4), 4), (synth.wheel(9), 9), (synth.wheel(50), 50),
+    (synth.star(30), 0), (synth.path(40), 0), (synth.cycle(3), 1), (synth.cycle(4), 0), (synth.cycle(31), 0),
+    (synth.complete_bipartite(5, 7), 0), (synth.hypercube(6), 0), (synth.grid(7, 9), 0),
+    (synth.random_tree(200, 3), 0),
+    (synth.complete_tripartite(3, 4, 5), 60), (synth.complete_tripartite(1, 1, 9), 9),
+    (synth.friendship(1), 1), (synth.friendship(13), 13),
+    (synth.empty(10), 0),
+]
+
+
+@pytest.mark.parametrize("g,T", CLOSED, ids=[g.name for g, _ in CLOSED])
+def test_closed_forms(g, T):
+    r = oracle.solve(g.src, g.dst, g.n, per_node=True, listing=True)
+    assert r.T == T
+    assert int(r.t.sum()) == 3 * T
+    assert r.tri.shape[0] == T
+
+
+def test_per_node_closed_forms():
+    n = 9
+    r = oracle.solve(*_sd(synth.complete(n)), n)
+    assert (r.t == math.comb(n - 1, 2)).all()
+    assert (r.cc == 1.0).all()
+    for rim in (4, 5, 17):
+        g = synth.wheel(rim)
+        r = oracle.solve(g.src, g.dst, g.n)
+        assert int(r.t[0]) == rim
+        assert (r.t[1:] == 2).all()
+    g = synth.star(12)
+    r = oracle.solve(g.src, g.dst, g.n)
+    assert r.cc[0] == 0.0 and r.den[0] == math.comb(12, 2)
+    g = synth.friendship(6)
+    r = oracle.solve(g.src, g.dst, g.n)
+    assert int(r.t[0]) == 6 and (r.t[1:] == 1).all()
+    assert (r.cc[1:] == 1.0).all()
+
+
+def _sd(g):
+    return g.src, g.dst
+
+
+# --------------------------------------------------- library-routine pins
+
+def _sparse_A(lo, hi, n):
+    import scipy.sparse as sp
+
+    data = np.ones(2 * lo.shape[0], dtype=np.float64)
+    rows = np.concatenate([lo, hi])
+    cols = np.concatenate([hi, lo])
+    return sp.csr_matrix((data, (rows, cols)), shape=(n, n))
+
+
+@pytest.mark.parametrize("kind", ["er", "ba", "rmat"])
+def test_scipy_trace_cubed(kind):
+    """T = trace(A^3)/6 and t_v = diag(A^3)/2 (scipy sparse products)."""
+    if kind == "er":
+        g = synth.er(3000, 0.004, 11)
+    elif kind == "ba":
+        g = synth.ba(5000, 5, 12)
+    else:
+        g = synth.rmat(12, 8, 13)
+    r = oracle.solve(g.src, g.dst, g.n)
+    A = _sparse_A(r.extra["lo"], r.extra["hi"], g.n)
+    A2 = A @ A
+    diag3 = np.asarray(A2.multiply(A).sum(axis=1)).ravel()  # (A^3)_vv = sum_u (A^2)_vu A_uv
+    assert int(round(diag3.sum())) == 6 * r.T
+    np.testing.assert_array_equal(np.rint(diag3 / 2).astype(np.uint64), r.t)
+
+
+@pytest.mark.parametrize("seed", [1, 2])
+def test_networkx(seed):
+    import networkx as nx
+
+    g = synth.rmat(11, 8, 40 + seed)
+    r = oracle.solve(g.src, g.dst, g.n)
+    G = nx.Graph()
+    G.add_nodes_from(range(g.n))
+    G.add_edges_from(zip(r.extra["lo"].tolist(), r.extra["hi"].tolist()))
+    tri = nx.triangles(G)
+    cl = nx.clustering(G)
+    assert sum(tri.values()) == 3 * r.T
+    for v in range(g.n):
+        assert tri[v] == int(r.t[v])
+        assert cl[v] == r.cc[v]  # both are one correctly rounded division of exact integers
+
+
+def test_nodeiterpp_and_definition_agree():
+    for g in (synth.ba(20000, 6, 3), synth.rmat(13, 12, 4), synth.er(5000, 0.003, 5)):
+        r = oracle.solve(g.src, g.dst, g.n)
+        off, nbr = oracle.full_adjacency(r.extra["lo"], r.extra["hi"], g.n)
+        assert oracle.count_nodeiterpp(off, nbr, r.deg, g.n) == r.T
+        Td, td = oracle.local_counts_def(off, nbr, g.n)
+        assert Td == r.T
+        np.testing.assert_array_equal(td, r.t)
+        assert oracle.count_nin_total_omp(r.off, r.adj, g.n) == r.T
+
+
+# ------------------------------------------------------- paper's theorems
+
+def test_theorem1_any_order_counts_once():
+    """Theorem 1: every total order gives the same count; Section 3: sum dhat = m."""
+    g = synth.rmat(12, 10, 21)
+    r = oracle.solve(g.src, g.dst, g.n)
+    lo, hi = r.extra["lo"], r.extra["hi"]
+    rng = np.random.default_rng(5)
+    keys = [np.zeros(g.n, np.int64), rng.permutation(g.n).astype(np.int64), -r.deg]
+    for key in keys:
+        off, adj = oracle.orient_by_key(lo, hi, key, g.n)
+        assert off[-1] == r.m
+        T, _, _ = oracle.count_nin(off, adj, g.n)
+        assert T == r.T
+
+
+def test_theorem3_degree_order_minimises_cost():
+    """Theorem 3: sum_v d_v * dhat_v is smallest under the degree order."""
+    for g in (synth.ba(3000, 4, 7), synth.rmat(11, 8, 8), synth.er(2000, 0.01, 9)):
+        r = oracle.solve(g.src, g.dst, g.n)
+        lo, hi = r.extra["lo"], r.extra["hi"]
+        dh = np.diff(r.off)
+        best = int((r.deg * dh).sum())
+        rng = np.random.default_rng(3)
+        for key in [np.zeros(g.n, np.int64), -r.deg, rng.permutation(g.n).astype(np.int64),
+                    rng.integers(0, 5, g.n).astype(np.int64)]:
+            off, _ = oracle.orient_by_key(lo, hi, key, g.n)
+            assert int((r.deg * np.diff(off)).sum()) >= best
+
+
+def test_wheel_orientation_from_paper():
+    """Wheel figure (Section 5): hub dhat = 0, every rim node dhat <= 3."""
+    with open(os.path.join(GOLDEN, "paper_values.json")) as f:
+        pv = json.load(f)["wheel_orientation"]
+    for rim in (5, 12, 100):
+        g = synth.wheel(rim)
+        r = oracle.solve(g.src, g.dst, g.n)
+        dh = np.diff(r.off)
+        assert dh[0] == pv["hub_dhat"]
+        assert dh[1:].max() <= pv["rim_dhat_max"]
+
+
+def test_oriented_rows_sorted_and_consistent():
+    g = synth.rmat(12, 8, 31)
+    r = oracle.solve(g.src, g.dst, g.n)
+    for v in range(g.n):
+        row = r.adj[r.off[v]:r.off[v + 1]]
+        assert (np.diff(row) > 0).all()
+        for u in row:
+            assert (r.deg[v], v) < (r.deg[u], u)
+
+
+def test_invariances():
+    g = synth.rmat(11, 10, 51)
+    base = oracle.solve(g.src, g.dst, g.n, listing=True)
+    rng = np.random.default_rng(0)
+    # input order, direction and duplication
+    perm = rng.permutation(g.num_edges)
+    flip = rng.random(g.num_edges) < 0.5
+    s = np.where(flip, g.dst, g.src)[perm]
+    d = np.where(flip, g.src, g.dst)[perm]
+    s2 = np.concatenate([s, d[:1000]])
+    d2 = np.concatenate([d, s[:1000]])
+    r = oracle.solve(s2, d2, g.n, listing=True)
+    assert r.T == base.T
+    np.testing.assert_array_equal(r.t, base.t)
+    np.testing.assert_array_equal(r.tri, base.tri)
+    # relabelling
+    pi = rng.permutation(g.n).astype(np.int32)
+    r = oracle.solve(pi[g.src], pi[g.dst], g.n)
+    assert r.T == base.T
+    np.testing.assert_array_equal(r.t[pi], base.t)
+
+
+def test_triangle_list_valid():
+    g = synth.ba(4000, 5, 61)
+    r = oracle.solve(g.src, g.dst, g.n, listing=True)
+    edges = set(zip(r.extra["lo"].tolist(), r.extra["hi"].tolist()))
+    assert r.tri.shape[0] == r.T
+    assert len({tuple(x) for x in r.tri.tolist()}) == r.T
+    for a, b, c in r.tri.tolist():
+        assert a < b < c
+        assert (a, b) in edges and (a, c) in edges and (b, c) in edges
+    assert (np.lexsort(r.tri.T[::-1]) == np.arange(r.T)).all()
+
+
+def test_per_node_bounds():
+    g = synth.rmat(12, 16, 71)
+    r = oracle.solve(g.src, g.dst, g.n)
+    d = r.deg.astype(np.uint64)
+    assert (r.t <= d * (d - 1) // 2 + (d < 2)).all()
+    assert int(r.t.sum()) == 3 * r.T
+
+
+# ---------------------------------------------------------- generator checks
+
+def test_er_expectation_config1():
+    """Generator sanity: E[T] = C(n,3) q^3 = 682.5 for G(10^4, 0.0016)."""
+    g = synth.config_er10k()
+    r = oracle.solve(g.src, g.dst, g.n)
+    mean = math.comb(10_000, 3) * 0.0016 ** 3
+    assert abs(r.T - mean) < 5 * math.sqrt(mean) + 20
+    assert abs(r.m - 0.0016 * 10_000 * 9_999 / 2) < 5 * math.sqrt(80_000)
+
+
+def test_gnp_row_of_paper_table():
+    """Generator sanity against the paper's Gnp(500K,20) row (1308 triangles)."""
+    with open(os.path.join(GOLDEN, "paper_values.json")) as f:
+        pv = json.load(f)["gnp_500k_20"]
+    n, d = pv["n"], pv["avg_degree"]
+    g = synth.er(n, d / (n - 1), 2024)
+    lo, hi = oracle.simple(g.src, g.dst, n)
+    deg = oracle.degrees(lo, hi, n)
+    off, adj = oracle.orient(lo, hi, deg, n)
+    T, _, _ = oracle.count_nin(off, adj, n)
+    expect = math.comb(n, 3) * (d / (n - 1)) ** 3
+    sd = math.sqrt(expect)
+    assert abs(T - expect) < 5 * sd
+    assert abs(pv["triangles"] - expect) < 5 * sd  # the printed value is consistent with the model
+
+
+# ------------------------------------------------------------ sparsification
+
+def test_sparsify_q1_is_exact():
+    g = synth.rmat(11, 8, 81)
+    r = oracle.solve(g.src, g.dst, g.n)
+    Ts, mk, est = oracle.sparsified_count(r.extra["lo"], r.extra["hi"], r.deg, g.n, 1.0, 9)
+    assert Ts == r.T and mk == r.m and est == float(r.T)
+
+
+def test_keep_threshold():
+    assert oracle.keep_threshold(0.5) == 1 << 63
+    assert oracle.keep_threshold(0.25) == 1 << 62
+    assert oracle.keep_threshold(1.0) == (1 << 64) - 1
+    assert oracle.keep_threshold(0.1) == int(math.ldexp(0.1, 64))
+
+
+def test_sparsify_keep_rate():
+    g = synth.rmat(14, 16, 82)
+    lo, hi = oracle.simple(g.src, g.dst, g.n)
+    for q, seed in ((0.1, 1), (0.5, 2), (0.2, 3)):
+        klo, _ = oracle.sparsify(lo, hi, q, seed)
+        m = lo.shape[0]
+        sd = math.sqrt(m * q * (1 - q))
+        assert abs(klo.shape[0] - q * m) < 5 * sd
+
+
+def test_sparsify_orientation_irrelevant():
+    """Reading of Section 7: orienting the sample by original or sampled degrees gives the same T_s."""
+    g = synth.ba(6000, 6, 83)
+    r = oracle.solve(g.src, g.dst, g.n)
+    klo, khi = oracle.sparsify(r.extra["lo"], r.extra["hi"], 0.3, 77)
+    T1, _, _ = oracle.count_nin(*oracle.orient(klo, khi, r.deg, g.n), g.n)
+    T2, _, _ = oracle.count_nin(*oracle.orient(klo, khi, oracle.degrees(klo, khi, g.n), g.n), g.n)
+    assert T1 == T2
+
+
+def test_doulion_unbiased_and_variance():
+    """Section 7: E[T_s/q^3] = T and Var = (1/q^3 - 1) T + 2k (1/q - 1),
+    k = pairs of triangles sharing an edge = sum_e C(t_e, 2)."""
+    g = synth.complete_tripartite(6, 7, 8)  # T = 336, every edge in several triangles
+    r = oracle.solve(g.src, g.dst, g.n, listing=True)
+    lo, hi = r.extra["lo"], r.extra["hi"]
+    te = {}
+    for a, b, c in r.tri.tolist():
+        for e in ((a, b), (a, c), (b, c)):
+            te[e] = te.get(e, 0) + 1
+    k = sum(x * (x - 1) // 2 for x in te.values())
+    q = 0.5
+    ests = []
+    for seed in range(600):
+        Ts, _, est = oracle.sparsified_count(lo, hi, r.deg, g.n, q, seed)
+        ests.append(est)
+    ests = np.array(ests)
+    var = (1 / q ** 3 - 1) * r.T + 2 * k * (1 / q - 1)
+    se = math.sqrt(var / len(ests))
+    assert abs(ests.mean() - r.T) < 4 * se
+    # sample variance of 600 draws is within ~+-25% of the model at this size
+    assert 0.7 * var < ests.var(ddof=1) < 1.4 * var
+
+
+def test_sampled_local_matches_full():
+    g = synth.rmat(13, 16, 91)
+    r = oracle.solve(g.src, g.dst, g.n)
+    rng = np.random.default_rng(1)
+    sample = np.concatenate([rng.integers(0, g.n, 60), [0, 1, 2, 3]]).astype(np.int32)
+    t, d = oracle.sampled_local(g.src, g.dst, g.n, sample)
+    np.testing.assert_array_equal(t, r.t[sample])
+    np.testing.assert_array_equal(d, r.deg[sample])
