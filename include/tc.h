@@ -1,0 +1,201 @@
+/*
+ * tc.h — C ABI of the MI355X (gfx950) exact triangle-counting library.
+ *
+ * The operations follow the problem statement of Arifuzzaman, Khan and Marathe,
+ * "Distributed-Memory Parallel Algorithms for Counting and Listing Triangles in
+ * Big Graphs" (arXiv 1706.05151):
+ *   - the input is an undirected graph G(V,E) on vertex ids 0..n-1 (Section 2);
+ *   - T is the number of triangles, T_v the number containing v (Section 2);
+ *   - C_v = T_v / C(d_v,2) is the local clustering coefficient (Section 2, Section 9);
+ *   - the triangle list is produced from the same intersections (Section 8);
+ *   - the sparsified estimate keeps each edge with probability q and returns
+ *     T_s / q^3 (Section 7).
+ * The counting method is NodeIteratorN with the degree order of Eq. (1):
+ * u precedes v iff d_u < d_v, or d_u == d_v and u < v.
+ *
+ * Conventions for every call:
+ *   - Pointers named *_dev are device (HBM) pointers of the current HIP device;
+ *     the caller allocates and owns them. The library never frees caller memory.
+ *   - `stream` is a hipStream_t passed as void* (NULL = the default stream). All
+ *     device work is ordered on it. Calls that return host scalars synchronise it.
+ *   - Functions return a tc_status and never abort. On error the outputs are
+ *     left untouched (except where stated) and tc_last_error() holds a message
+ *     for the calling thread.
+ *   - A tc_graph is read-only after it is built. Queries on one graph may run
+ *     concurrently on different streams; each call takes its own scratch memory.
+ *   - Limits: n <= 2^31 - 1, and the number of input edge records < 2^32.
+ */
+#ifndef TC_H_
+#define TC_H_
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct tc_graph tc_graph;
+
+typedef enum tc_status {
+  TC_OK = 0,
+  TC_E_INVAL = -1,  /* bad argument (NULL where required, negative size, ...) */
+  TC_E_NOMEM = -2,  /* device allocation failed */
+  TC_E_DEVICE = -3, /* HIP runtime error */
+  TC_E_RANGE = -4,  /* vertex id outside [0,n), n < 0, or q outside (0,1] */
+  TC_E_TRUNC = -5   /* output capacity smaller than the result */
+} tc_status;
+
+/* tc_build_csr flag: src/dst are device pointers (otherwise host pointers). */
+#define TC_IN_DEVICE 1u
+
+/*
+ * Build the device graph of Section 2 from a raw edge list and prepare
+ * NodeIteratorN (Section 3, the algorithm figure after Eq. (1)): drop
+ * self-loops, merge duplicate and reversed pairs, compute degrees d_v, orient
+ * every edge from the earlier to the later endpoint under Eq. (1), and store
+ * the oriented lists N_v sorted ascending as a CSR.
+ *   src, dst   : int32[num_edges] endpoint ids (host, or device with TC_IN_DEVICE).
+ *                May be freed as soon as the call returns.
+ *   num_edges  : >= 0 raw records (loops and duplicates allowed).
+ *   n          : >= 0 vertices; ids must lie in [0,n) else TC_E_RANGE.
+ *   out        : receives the new graph; owned by the caller until tc_graph_free.
+ * Internally vertices are numbered by their position in the degree order, so
+ * that every oriented list holds only later vertices in ascending order.
+ * Synchronises `stream`.
+ */
+tc_status tc_build_csr(const int32_t* src, const int32_t* dst, int64_t num_edges, int32_t n,
+                       uint32_t flags, void* stream, tc_graph** out);
+
+/* n, m (unique undirected edges), d_max and the largest oriented list size
+ * dhat_max (Definition of effective degree, Section 3). Any output may be NULL. */
+tc_status tc_graph_info(const tc_graph* g, int32_t* n, int64_t* m, int32_t* d_max, int32_t* dhat_max);
+
+/* Release the graph and its device memory. NULL is ignored. */
+void tc_graph_free(tc_graph* g);
+
+/*
+ * T = sum over oriented edges (v,u) of |N_v ∩ N_u| (NodeIteratorN, Section 3;
+ * each triangle counted once by Theorem 1). 64-bit total. Synchronises `stream`.
+ */
+tc_status tc_count(tc_graph* g, void* stream, uint64_t* T);
+
+/*
+ * T and the per-node counts T_v: each triangle (v,u,w) adds one to T_v, T_u
+ * and T_w (local-count figure, Section 9). t_dev: uint64[n] device array,
+ * indexed by the caller's vertex ids, fully overwritten. T may be NULL.
+ * Synchronises `stream`.
+ */
+tc_status tc_count_per_node(tc_graph* g, void* stream, uint64_t* T, uint64_t* t_dev);
+
+/*
+ * Local clustering coefficients C_v = T_v / C(d_v,2) (Section 2), returned as
+ * the exact rational num/den and its IEEE binary64 quotient (round to nearest,
+ * one true division). Vertices with d_v < 2 get num = den = 0 and c = 0.0.
+ * num_dev, den_dev: uint64[n]; c_dev: double[n]; any may be NULL.
+ * Synchronises `stream`.
+ */
+tc_status tc_clustering(tc_graph* g, void* stream, uint64_t* num_dev, uint64_t* den_dev, double* c_dev);
+
+/*
+ * The triangle list (Section 8): every triangle once, as three ids in
+ * ascending order, the list sorted lexicographically. tri_dev: int32[cap][3].
+ * Sizing idiom: tri_dev == NULL or cap == 0 returns TC_OK with *count = T;
+ * 0 < cap < T returns TC_E_TRUNC with *count = T and writes nothing.
+ * Synchronises `stream`.
+ */
+tc_status tc_list(tc_graph* g, void* stream, int32_t* tri_dev, int64_t cap, int64_t* count);
+
+/*
+ * Sparsified estimate (Section 7): each undirected edge {a,b} (a<b, caller ids)
+ * is kept independently with probability q, decided by
+ *   H = mix(mix(seed ^ 0x5350415253494659) ^ (a<<32 | b)),
+ * mix = the SplitMix64 output function (Steele, Lea and Flood, 2014), keep iff
+ * H < floor(q * 2^64) (q = 1 keeps all). T_sampled is the exact count on the
+ * kept edges, m_kept their number and estimate = T_sampled / (q*q*q).
+ * q outside (0,1] gives TC_E_RANGE. Any output may be NULL. Synchronises `stream`.
+ */
+tc_status tc_sparsify_count(tc_graph* g, double q, uint64_t seed, void* stream, uint64_t* T_sampled,
+                            int64_t* m_kept, double* estimate);
+
+/* ------------------------------------------------------------------ extras */
+
+/*
+ * The same total as tc_count from the plain kernel: one thread per oriented
+ * edge, two-pointer merge of N_v and N_u straight from HBM (the intersection of
+ * the NodeIteratorN figure, no staging). The baseline the tuned kernels are
+ * measured against. Synchronises `stream`.
+ */
+tc_status tc_count_plain(tc_graph* g, void* stream, uint64_t* T);
+
+/* Merge work of Theorem 2, W = sum over oriented edges (v,u) of (dhat_v + dhat_u),
+ * and the wedge count P = sum_v C(dhat_v, 2). Either may be NULL. */
+tc_status tc_graph_work(tc_graph* g, void* stream, uint64_t* W, uint64_t* P);
+
+/*
+ * Export the degree data in the caller's ids: deg_dev int32[n] = d_v and
+ * dhat_dev int32[n] = |N_v| (effective degree, Section 3). Either may be NULL.
+ */
+tc_status tc_graph_degrees(tc_graph* g, void* stream, int32_t* deg_dev, int32_t* dhat_dev);
+
+/*
+ * Export the oriented lists in the caller's ids: off_dev int64[n+1] and
+ * adj_dev int32[m] hold N_v for v = 0..n-1, each list ascending by id (the
+ * layout of the NodeIteratorN preprocessing step). Either may be NULL.
+ */
+tc_status tc_graph_oriented(tc_graph* g, void* stream, int64_t* off_dev, int32_t* adj_dev);
+
+/*
+ * Tuning options (process-wide; read at the start of each call).
+ *   TC_OPT_KERNEL        : 0 auto, 1 plain merge, 2 pivot-staged (see DESIGN)
+ *   TC_OPT_HUB_DHAT      : lists longer than this use the block-per-pivot path
+ *   TC_OPT_ITEM_WORK     : target probes per work item of the partitioner
+ *   TC_OPT_BLOCKS_PER_CU : occupancy hint for the persistent launch
+ * Returns TC_E_INVAL for an unknown key or a negative value.
+ */
+typedef enum tc_option {
+  TC_OPT_KERNEL = 0,
+  TC_OPT_HUB_DHAT = 1,
+  TC_OPT_ITEM_WORK = 2,
+  TC_OPT_BLOCKS_PER_CU = 3
+} tc_option;
+tc_status tc_set_option(tc_option key, int64_t value);
+int64_t tc_get_option(tc_option key);
+
+/* ---------------------------------------------------------------- batching */
+
+/*
+ * Build many independent graphs as one device graph (their disjoint union):
+ * graph g has n_per_graph[g] vertices and edge records
+ * [edge_off[g], edge_off[g+1]) of src/dst, with ids local to the graph.
+ * All arrays are host memory unless TC_IN_DEVICE (src/dst only; edge_off and
+ * n_per_graph are always host). Counting on the result gives per-graph totals
+ * with tc_batch_count; per-node arrays are indexed by base[g] + local id with
+ * base[g] = n_per_graph[0] + ... + n_per_graph[g-1].
+ */
+tc_status tc_batch_build(const int32_t* src, const int32_t* dst, const int64_t* edge_off,
+                         const int32_t* n_per_graph, int32_t num_graphs, uint32_t flags, void* stream,
+                         tc_graph** out);
+
+/* Number of graphs in a batch graph (1 for tc_build_csr graphs). */
+tc_status tc_batch_size(const tc_graph* g, int32_t* num_graphs);
+
+/*
+ * Per-graph totals T_dev[num_graphs] (device uint64) and, if t_dev != NULL,
+ * per-node counts t_dev[sum n] in one launch sequence. Does not synchronise
+ * `stream` (results are ready when the stream reaches this point), so the call
+ * can be captured in a HIP graph. Scratch memory comes from the graph's own
+ * workspace: calls on one batch graph must not overlap.
+ */
+tc_status tc_batch_count(tc_graph* g, void* stream, uint64_t* T_dev, uint64_t* t_dev);
+
+/* ------------------------------------------------------------------ errors */
+
+const char* tc_status_str(tc_status s);
+/* Message for the last failing call of this thread ("" if none). */
+const char* tc_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* TC_H_ */

@@ -1,0 +1,442 @@
+// The C ABI (include/tc.h): argument checks, device/stream plumbing, error
+// mapping, and the small per-node epilogues (permutation to caller ids and
+// clustering coefficients).
+#include <atomic>
+#include <cmath>
+#include <new>
+#include <string>
+
+#include "graph.hpp"
+#include "primitives.hpp"
+
+namespace tc {
+
+namespace {
+
+thread_local std::string g_last_error;
+std::atomic<int64_t> g_opt_kernel{0}, g_opt_hub{128}, g_opt_iw{4096}, g_opt_bpc{8};
+
+template <typename F>
+tc_status guarded(F&& f) {
+  g_last_error.clear();
+  try {
+    f();
+    return TC_OK;
+  } catch (const Failure& e) {
+    g_last_error = e.what();
+    return e.status;
+  } catch (const std::bad_alloc&) {
+    g_last_error = "host allocation failed";
+    return TC_E_NOMEM;
+  } catch (const std::exception& e) {
+    g_last_error = e.what();
+    return TC_E_DEVICE;
+  }
+}
+
+// Makes the graph's device current for the duration of a call.
+struct DeviceScope {
+  int prev = -1, want = 0;
+  explicit DeviceScope(int dev) : want(dev) {
+    TC_HIP(hipGetDevice(&prev));
+    if (prev != dev) TC_HIP(hipSetDevice(dev));
+  }
+  ~DeviceScope() {
+    if (prev >= 0 && prev != want) (void)hipSetDevice(prev);
+  }
+};
+
+constexpr int kBlock = 256;
+
+__global__ void k_scatter_by_order(const unsigned long long* __restrict__ by_rank, const int32_t* __restrict__ order,
+                                   int32_t n, unsigned long long* __restrict__ by_id) {
+  for (int32_t r = blockIdx.x * blockDim.x + threadIdx.x; r < n; r += gridDim.x * blockDim.x) by_id[order[r]] = by_rank[r];
+}
+
+// C_v = T_v / C(d_v,2): exact numerator and denominator, one IEEE division.
+__global__ void k_clustering(const unsigned long long* __restrict__ t, const int32_t* __restrict__ deg, int32_t n,
+                             uint64_t* __restrict__ num, uint64_t* __restrict__ den, double* __restrict__ c) {
+  for (int32_t v = blockIdx.x * blockDim.x + threadIdx.x; v < n; v += gridDim.x * blockDim.x) {
+    const uint64_t d = static_cast<uint64_t>(deg[v]);
+    const uint64_t nu = t[v];
+    const uint64_t de = d >= 2 ? d * (d - 1) / 2 : 0;
+    if (num) num[v] = nu;
+    if (den) den[v] = de;
+    if (c) c[v] = de ? static_cast<double>(nu) / static_cast<double>(de) : 0.0;
+  }
+}
+
+__global__ void k_dhat_by_id(const int64_t* __restrict__ off, const int32_t* __restrict__ order, int32_t n,
+                             int32_t* __restrict__ dhat) {
+  for (int32_t r = blockIdx.x * blockDim.x + threadIdx.x; r < n; r += gridDim.x * blockDim.x)
+    dhat[order[r]] = static_cast<int32_t>(off[r + 1] - off[r]);
+}
+
+__global__ void k_oriented_keys(const int32_t* __restrict__ adj, const int32_t* __restrict__ src,
+                                const int32_t* __restrict__ order, uint64_t m, int b, uint64_t* __restrict__ keys) {
+  for (uint64_t e = static_cast<uint64_t>(blockIdx.x) * blockDim.x + threadIdx.x; e < m;
+       e += static_cast<uint64_t>(gridDim.x) * blockDim.x)
+    keys[e] = (static_cast<uint64_t>(order[src[e]]) << b) | static_cast<uint64_t>(order[adj[e]]);
+}
+
+__global__ void k_split_keys(const uint64_t* __restrict__ keys, uint64_t m, int b, int32_t* __restrict__ row,
+                             int32_t* __restrict__ col) {
+  const uint64_t mask = (1ull << b) - 1;
+  for (uint64_t e = static_cast<uint64_t>(blockIdx.x) * blockDim.x + threadIdx.x; e < m;
+       e += static_cast<uint64_t>(gridDim.x) * blockDim.x) {
+    row[e] = static_cast<int32_t>(keys[e] >> b);
+    if (col) col[e] = static_cast<int32_t>(keys[e] & mask);
+  }
+}
+
+hipStream_t as_stream(void* s) { return reinterpret_cast<hipStream_t>(s); }
+
+void require(bool ok, tc_status st, const char* msg) {
+  if (!ok) fail(st, msg);
+}
+
+// T (and optionally per-node counts by rank) of one CSR with the selected kernel.
+uint64_t count_total(tc_graph* g, Csr& c, hipStream_t s, unsigned long long* t_rank) {
+  const Options o = get_options();
+  DevBuf<unsigned long long> tot(1, s);
+  fill_u64(tot.get(), 1, 0ull, s);
+  if (t_rank) {
+    fill_u64(t_rank, static_cast<size_t>(c.n), 0ull, s);
+    CountArgs a;
+    a.mode = kCountPerNode;
+    a.total = tot.get();
+    a.t_rank = t_rank;
+    std::lock_guard<std::mutex> lk(g->mu);
+    count_pivot(c, a, s, o);
+  } else if (o.kernel == 1) {
+    count_plain(c, tot.get(), s);
+  } else {
+    CountArgs a;
+    a.mode = kCountTotal;
+    a.total = tot.get();
+    std::lock_guard<std::mutex> lk(g->mu);
+    count_pivot(c, a, s, o);
+  }
+  unsigned long long h = 0;
+  TC_HIP(hipMemcpyAsync(&h, tot.get(), sizeof(h), hipMemcpyDeviceToHost, s));
+  TC_HIP(hipStreamSynchronize(s));
+  return h;
+}
+
+}  // namespace
+
+Options get_options() {
+  Options o;
+  o.kernel = g_opt_kernel.load();
+  o.hub_dhat = g_opt_hub.load();
+  o.item_work = g_opt_iw.load();
+  o.blocks_per_cu = g_opt_bpc.load();
+  return o;
+}
+
+}  // namespace tc
+
+using namespace tc;
+
+extern "C" {
+
+tc_status tc_build_csr(const int32_t* src, const int32_t* dst, int64_t num_edges, int32_t n, uint32_t flags,
+                       void* stream, tc_graph** out) {
+  return guarded([&] {
+    require(out != nullptr, TC_E_INVAL, "out is NULL");
+    *out = nullptr;
+    auto* g = new tc_graph();
+    try {
+      build_graph(src, dst, num_edges, n, nullptr, nullptr, 1, (flags & TC_IN_DEVICE) != 0, as_stream(stream), g);
+    } catch (...) {
+      (void)hipStreamSynchronize(as_stream(stream));
+      delete g;
+      throw;
+    }
+    *out = g;
+  });
+}
+
+tc_status tc_batch_build(const int32_t* src, const int32_t* dst, const int64_t* edge_off, const int32_t* n_per_graph,
+                         int32_t num_graphs, uint32_t flags, void* stream, tc_graph** out) {
+  return guarded([&] {
+    require(out != nullptr, TC_E_INVAL, "out is NULL");
+    require(num_graphs >= 1, TC_E_INVAL, "num_graphs < 1");
+    require(edge_off != nullptr && n_per_graph != nullptr, TC_E_INVAL, "NULL batch description");
+    *out = nullptr;
+    int64_t ntot = 0;
+    for (int32_t i = 0; i < num_graphs; i++) ntot += n_per_graph[i] > 0 ? n_per_graph[i] : 0;
+    require(ntot <= INT32_MAX, TC_E_RANGE, "batch has more than 2^31 - 1 vertices");
+    const hipStream_t s = as_stream(stream);
+    auto* g = new tc_graph();
+    try {
+      build_graph(src, dst, edge_off[num_graphs], static_cast<int32_t>(ntot), edge_off, n_per_graph, num_graphs,
+                  (flags & TC_IN_DEVICE) != 0, s, g);
+      ensure_plan(g->csr, s, get_options());
+      g->workspace.alloc((3 + static_cast<size_t>(g->n)) * sizeof(unsigned long long));
+      TC_HIP(hipStreamSynchronize(s));
+    } catch (...) {
+      (void)hipStreamSynchronize(s);
+      delete g;
+      throw;
+    }
+    *out = g;
+  });
+}
+
+tc_status tc_batch_size(const tc_graph* g, int32_t* num_graphs) {
+  return guarded([&] {
+    require(g != nullptr && num_graphs != nullptr, TC_E_INVAL, "NULL argument");
+    *num_graphs = g->num_graphs;
+  });
+}
+
+tc_status tc_graph_info(const tc_graph* g, int32_t* n, int64_t* m, int32_t* d_max, int32_t* dhat_max) {
+  return guarded([&] {
+    require(g != nullptr, TC_E_INVAL, "graph is NULL");
+    if (n) *n = g->n;
+    if (m) *m = g->m;
+    if (d_max) *d_max = g->d_max;
+    if (dhat_max) *dhat_max = g->csr.dhat_max;
+  });
+}
+
+void tc_graph_free(tc_graph* g) {
+  if (!g) return;
+  const int dev = g->device;
+  int prev = -1;
+  if (hipGetDevice(&prev) == hipSuccess && prev != dev) (void)hipSetDevice(dev);
+  (void)hipDeviceSynchronize();
+  delete g;
+  if (prev >= 0 && prev != dev) (void)hipSetDevice(prev);
+}
+
+tc_status tc_count(tc_graph* g, void* stream, uint64_t* T) {
+  return guarded([&] {
+    require(g != nullptr && T != nullptr, TC_E_INVAL, "NULL argument");
+    DeviceScope ds(g->device);
+    *T = count_total(g, g->csr, as_stream(stream), nullptr);
+  });
+}
+
+tc_status tc_count_plain(tc_graph* g, void* stream, uint64_t* T) {
+  return guarded([&] {
+    require(g != nullptr && T != nullptr, TC_E_INVAL, "NULL argument");
+    DeviceScope ds(g->device);
+    const hipStream_t s = as_stream(stream);
+    DevBuf<unsigned long long> tot(1, s);
+    fill_u64(tot.get(), 1, 0ull, s);
+    count_plain(g->csr, tot.get(), s);
+    unsigned long long h = 0;
+    TC_HIP(hipMemcpyAsync(&h, tot.get(), sizeof(h), hipMemcpyDeviceToHost, s));
+    TC_HIP(hipStreamSynchronize(s));
+    *T = h;
+  });
+}
+
+tc_status tc_count_per_node(tc_graph* g, void* stream, uint64_t* T, uint64_t* t_dev) {
+  return guarded([&] {
+    require(g != nullptr && t_dev != nullptr, TC_E_INVAL, "NULL argument");
+    DeviceScope ds(g->device);
+    const hipStream_t s = as_stream(stream);
+    DevBuf<unsigned long long> tr(g->n, s);
+    const uint64_t tot = count_total(g, g->csr, s, tr.get());
+    if (g->n > 0) {
+      k_scatter_by_order<<<grid_for(g->n, kBlock, 65536), kBlock, 0, s>>>(
+          tr.get(), g->order.p, g->n, reinterpret_cast<unsigned long long*>(t_dev));
+      TC_LAUNCH_CHECK();
+    }
+    TC_HIP(hipStreamSynchronize(s));
+    if (T) *T = tot;
+  });
+}
+
+tc_status tc_clustering(tc_graph* g, void* stream, uint64_t* num_dev, uint64_t* den_dev, double* c_dev) {
+  return guarded([&] {
+    require(g != nullptr, TC_E_INVAL, "graph is NULL");
+    DeviceScope ds(g->device);
+    const hipStream_t s = as_stream(stream);
+    DevBuf<unsigned long long> tr(g->n, s), tid(g->n, s);
+    (void)count_total(g, g->csr, s, tr.get());
+    if (g->n > 0) {
+      k_scatter_by_order<<<grid_for(g->n, kBlock, 65536), kBlock, 0, s>>>(tr.get(), g->order.p, g->n, tid.get());
+      TC_LAUNCH_CHECK();
+      k_clustering<<<grid_for(g->n, kBlock, 65536), kBlock, 0, s>>>(tid.get(), g->deg.p, g->n, num_dev, den_dev, c_dev);
+      TC_LAUNCH_CHECK();
+    }
+    TC_HIP(hipStreamSynchronize(s));
+  });
+}
+
+tc_status tc_list(tc_graph* g, void* stream, int32_t* tri_dev, int64_t cap, int64_t* count) {
+  return guarded([&] {
+    require(g != nullptr && count != nullptr, TC_E_INVAL, "NULL argument");
+    require(cap >= 0, TC_E_INVAL, "negative capacity");
+    DeviceScope ds(g->device);
+    const hipStream_t s = as_stream(stream);
+    const uint64_t T = count_total(g, g->csr, s, nullptr);
+    *count = static_cast<int64_t>(T);
+    if (!tri_dev || cap == 0 || T == 0) return;
+    if (static_cast<uint64_t>(cap) < T) fail(TC_E_TRUNC, "triangle list capacity smaller than T");
+    DevBuf<unsigned long long> cur(1, s);
+    fill_u64(cur.get(), 1, 0ull, s);
+    CountArgs a;
+    a.mode = kCountList;
+    a.order = g->order.p;
+    a.tri = tri_dev;
+    a.cursor = cur.get();
+    a.cap = static_cast<int64_t>(T);
+    {
+      std::lock_guard<std::mutex> lk(g->mu);
+      count_pivot(g->csr, a, s, get_options());
+    }
+    unsigned long long written = 0;
+    TC_HIP(hipMemcpyAsync(&written, cur.get(), sizeof(written), hipMemcpyDeviceToHost, s));
+    TC_HIP(hipStreamSynchronize(s));
+    if (written != T) fail(TC_E_DEVICE, "listing pass disagrees with the count pass");
+    sort_triangles(tri_dev, static_cast<int64_t>(T), g->bits, s);
+    TC_HIP(hipStreamSynchronize(s));
+  });
+}
+
+tc_status tc_sparsify_count(tc_graph* g, double q, uint64_t seed, void* stream, uint64_t* T_sampled, int64_t* m_kept,
+                            double* estimate) {
+  return guarded([&] {
+    require(g != nullptr, TC_E_INVAL, "graph is NULL");
+    require(q > 0.0 && q <= 1.0, TC_E_RANGE, "q outside (0, 1]");
+    DeviceScope ds(g->device);
+    const hipStream_t s = as_stream(stream);
+    Csr sampled;
+    build_sampled_csr(g, q, seed, sampled, s);
+    const uint64_t Ts = count_total(g, sampled, s, nullptr);
+    TC_HIP(hipStreamSynchronize(s));
+    if (T_sampled) *T_sampled = Ts;
+    if (m_kept) *m_kept = sampled.m;
+    if (estimate) *estimate = static_cast<double>(Ts) / ((q * q) * q);
+  });
+}
+
+tc_status tc_graph_work(tc_graph* g, void* stream, uint64_t* W, uint64_t* P) {
+  return guarded([&] {
+    require(g != nullptr, TC_E_INVAL, "graph is NULL");
+    DeviceScope ds(g->device);
+    const hipStream_t s = as_stream(stream);
+    DevBuf<unsigned long long> d(2, s);
+    fill_u64(d.get(), 2, 0ull, s);
+    graph_work(g->csr, d.get(), d.get() + 1, s);
+    unsigned long long h[2] = {0, 0};
+    TC_HIP(hipMemcpyAsync(h, d.get(), sizeof(h), hipMemcpyDeviceToHost, s));
+    TC_HIP(hipStreamSynchronize(s));
+    if (W) *W = h[0];
+    if (P) *P = h[1];
+  });
+}
+
+tc_status tc_graph_degrees(tc_graph* g, void* stream, int32_t* deg_dev, int32_t* dhat_dev) {
+  return guarded([&] {
+    require(g != nullptr, TC_E_INVAL, "graph is NULL");
+    DeviceScope ds(g->device);
+    const hipStream_t s = as_stream(stream);
+    if (deg_dev && g->n > 0)
+      TC_HIP(hipMemcpyAsync(deg_dev, g->deg.p, g->n * sizeof(int32_t), hipMemcpyDeviceToDevice, s));
+    if (dhat_dev && g->n > 0) {
+      k_dhat_by_id<<<grid_for(g->n, kBlock, 65536), kBlock, 0, s>>>(g->csr.off.p, g->order.p, g->n, dhat_dev);
+      TC_LAUNCH_CHECK();
+    }
+    TC_HIP(hipStreamSynchronize(s));
+  });
+}
+
+tc_status tc_graph_oriented(tc_graph* g, void* stream, int64_t* off_dev, int32_t* adj_dev) {
+  return guarded([&] {
+    require(g != nullptr, TC_E_INVAL, "graph is NULL");
+    DeviceScope ds(g->device);
+    const hipStream_t s = as_stream(stream);
+    const uint64_t m = static_cast<uint64_t>(g->m);
+    DevBuf<uint64_t> k1(m, s), k2(m, s);
+    DevBuf<int32_t> row(m, s);
+    uint64_t* sorted = k1.get();
+    if (m > 0) {
+      k_oriented_keys<<<grid_for(m, kBlock, 65536), kBlock, 0, s>>>(g->csr.adj.p, g->csr.src.p, g->order.p, m, g->bits,
+                                                                    k1.get());
+      TC_LAUNCH_CHECK();
+      sorted = radix_sort<uint64_t>(k1.get(), k2.get(), m, 0, 2 * g->bits, s);
+      k_split_keys<<<grid_for(m, kBlock, 65536), kBlock, 0, s>>>(sorted, m, g->bits, row.get(), adj_dev);
+      TC_LAUNCH_CHECK();
+    }
+    if (off_dev) offsets_from_rows(row.get(), m, g->n, off_dev, s);
+    TC_HIP(hipStreamSynchronize(s));
+  });
+}
+
+tc_status tc_batch_count(tc_graph* g, void* stream, uint64_t* T_dev, uint64_t* t_dev) {
+  return guarded([&] {
+    require(g != nullptr && T_dev != nullptr, TC_E_INVAL, "NULL argument");
+    require(g->workspace.p != nullptr, TC_E_INVAL, "graph was not built by tc_batch_build");
+    DeviceScope ds(g->device);
+    const hipStream_t s = as_stream(stream);
+    auto* ws = reinterpret_cast<unsigned long long*>(g->workspace.p);
+    auto* Tg = reinterpret_cast<unsigned long long*>(T_dev);
+    fill_u64(Tg, static_cast<size_t>(g->num_graphs), 0ull, s);
+    CountArgs a;
+    a.mode = t_dev ? kCountPerNode : kCountTotal;
+    a.per_graph = Tg;
+    a.graph_of_rank = g->num_graphs > 1 ? g->graph_of_rank.p : nullptr;
+    a.queues = ws;
+    if (t_dev) {
+      a.t_rank = ws + 3;
+      fill_u64(a.t_rank, static_cast<size_t>(g->n), 0ull, s);
+    }
+    count_pivot(g->csr, a, s, get_options(), /*allow_rebuild=*/false);
+    if (t_dev && g->n > 0) {
+      k_scatter_by_order<<<grid_for(g->n, kBlock, 65536), kBlock, 0, s>>>(a.t_rank, g->order.p, g->n,
+                                                                          reinterpret_cast<unsigned long long*>(t_dev));
+      TC_LAUNCH_CHECK();
+    }
+  });
+}
+
+tc_status tc_set_option(tc_option key, int64_t value) {
+  return guarded([&] {
+    require(value >= 0, TC_E_INVAL, "negative option value");
+    switch (key) {
+      case TC_OPT_KERNEL:
+        require(value <= 2, TC_E_INVAL, "kernel must be 0, 1 or 2");
+        g_opt_kernel = value;
+        break;
+      case TC_OPT_HUB_DHAT: g_opt_hub = value; break;
+      case TC_OPT_ITEM_WORK: g_opt_iw = value; break;
+      case TC_OPT_BLOCKS_PER_CU:
+        require(value >= 1, TC_E_INVAL, "blocks per CU must be >= 1");
+        g_opt_bpc = value;
+        break;
+      default: fail(TC_E_INVAL, "unknown option");
+    }
+  });
+}
+
+int64_t tc_get_option(tc_option key) {
+  switch (key) {
+    case TC_OPT_KERNEL: return g_opt_kernel.load();
+    case TC_OPT_HUB_DHAT: return g_opt_hub.load();
+    case TC_OPT_ITEM_WORK: return g_opt_iw.load();
+    case TC_OPT_BLOCKS_PER_CU: return g_opt_bpc.load();
+    default: return -1;
+  }
+}
+
+const char* tc_status_str(tc_status s) {
+  switch (s) {
+    case TC_OK: return "TC_OK";
+    case TC_E_INVAL: return "TC_E_INVAL";
+    case TC_E_NOMEM: return "TC_E_NOMEM";
+    case TC_E_DEVICE: return "TC_E_DEVICE";
+    case TC_E_RANGE: return "TC_E_RANGE";
+    case TC_E_TRUNC: return "TC_E_TRUNC";
+    default: return "TC_E_UNKNOWN";
+  }
+}
+
+const char* tc_last_error(void) { return g_last_error.c_str(); }
+
+}  // extern "C"

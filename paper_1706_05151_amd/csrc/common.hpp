@@ -1,0 +1,149 @@
+// Shared host/device utilities of the triangle-counting library (gfx950, wave64).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstdio>
+#include <stdexcept>
+#include <string>
+
+#include "../../include/tc.h"
+
+namespace tc {
+
+constexpr int kWave = 64;
+
+// ------------------------------------------------------------ host errors --
+
+struct Failure : std::runtime_error {
+  tc_status status;
+  Failure(tc_status s, const std::string& m) : std::runtime_error(m), status(s) {}
+};
+
+[[noreturn]] inline void fail(tc_status s, const std::string& m) { throw Failure(s, m); }
+
+inline void hip_check(hipError_t e, const char* what, const char* file, int line) {
+  if (e == hipSuccess) return;
+  std::string msg = std::string(what) + " failed: " + hipGetErrorString(e) + " (" + file + ":" + std::to_string(line) + ")";
+  (void)hipGetLastError();  // clear the sticky-free error state for the next call
+  if (e == hipErrorOutOfMemory || e == hipErrorMemoryAllocation) throw Failure(TC_E_NOMEM, msg);
+  throw Failure(TC_E_DEVICE, msg);
+}
+
+#define TC_HIP(x) ::tc::hip_check((x), #x, __FILE__, __LINE__)
+#define TC_LAUNCH_CHECK() ::tc::hip_check(hipGetLastError(), "kernel launch", __FILE__, __LINE__)
+
+// ------------------------------------------------- stream-ordered buffers --
+
+// Device buffer taken from the stream-ordered allocator and returned to it on
+// destruction (the free is ordered after all work queued on the stream).
+template <typename T>
+class DevBuf {
+ public:
+  DevBuf() = default;
+  DevBuf(size_t count, hipStream_t s) { alloc(count, s); }
+  ~DevBuf() { release(); }
+  DevBuf(const DevBuf&) = delete;
+  DevBuf& operator=(const DevBuf&) = delete;
+  DevBuf(DevBuf&& o) noexcept : p_(o.p_), n_(o.n_), s_(o.s_) { o.p_ = nullptr; o.n_ = 0; }
+  DevBuf& operator=(DevBuf&& o) noexcept {
+    if (this != &o) {
+      release();
+      p_ = o.p_; n_ = o.n_; s_ = o.s_;
+      o.p_ = nullptr; o.n_ = 0;
+    }
+    return *this;
+  }
+  void alloc(size_t count, hipStream_t s) {
+    release();
+    s_ = s;
+    n_ = count;
+    if (count == 0) return;
+    TC_HIP(hipMallocAsync(reinterpret_cast<void**>(&p_), count * sizeof(T), s));
+  }
+  void release() {
+    if (p_) (void)hipFreeAsync(p_, s_);
+    p_ = nullptr;
+    n_ = 0;
+  }
+  T* get() const { return p_; }
+  size_t size() const { return n_; }
+  T* detach() { T* p = p_; p_ = nullptr; n_ = 0; return p; }
+
+ private:
+  T* p_ = nullptr;
+  size_t n_ = 0;
+  hipStream_t s_ = nullptr;
+};
+
+inline int bits_for(uint64_t max_value) {  // bits needed to hold values 0..max_value
+  int b = 0;
+  while (b < 64 && (max_value >> b) != 0) b++;
+  return b < 1 ? 1 : b;
+}
+
+inline unsigned grid_for(uint64_t work, unsigned per_block, unsigned cap = 1u << 30) {
+  uint64_t g = (work + per_block - 1) / per_block;
+  if (g < 1) g = 1;
+  if (g > cap) g = cap;
+  return static_cast<unsigned>(g);
+}
+
+// ------------------------------------------------------- device helpers --
+
+__device__ __forceinline__ int lane_id() { return __lane_id(); }
+
+__device__ __forceinline__ uint64_t lanemask_lt() {
+  return (1ull << lane_id()) - 1ull;
+}
+
+template <typename T>
+__device__ __forceinline__ T wave_incl_scan(T x) {
+#pragma unroll
+  for (int d = 1; d < kWave; d <<= 1) {
+    T y = __shfl_up(x, d, kWave);
+    if (lane_id() >= d) x += y;
+  }
+  return x;
+}
+
+template <typename T>
+__device__ __forceinline__ T wave_sum(T x) {
+#pragma unroll
+  for (int d = kWave / 2; d > 0; d >>= 1) x += __shfl_xor(x, d, kWave);
+  return x;
+}
+
+template <typename T>
+__device__ __forceinline__ T wave_max(T x) {
+#pragma unroll
+  for (int d = kWave / 2; d > 0; d >>= 1) {
+    T y = __shfl_xor(x, d, kWave);
+    x = y > x ? y : x;
+  }
+  return x;
+}
+
+// Exclusive scan across a block of BLOCK threads; `smem` holds BLOCK/64 T.
+// Returns the exclusive prefix of x and writes the block total to `total`.
+template <typename T, int BLOCK>
+__device__ __forceinline__ T block_excl_scan(T x, T* smem, T& total) {
+  constexpr int NW = BLOCK / kWave;
+  const int w = threadIdx.x / kWave;
+  T incl = wave_incl_scan(x);
+  if (lane_id() == kWave - 1) smem[w] = incl;
+  __syncthreads();
+  T before = 0, all = 0;
+#pragma unroll
+  for (int i = 0; i < NW; i++) {
+    T s = smem[i];
+    if (i < w) before += s;
+    all += s;
+  }
+  __syncthreads();
+  total = all;
+  return before + incl - x;
+}
+
+}  // namespace tc

@@ -1,0 +1,705 @@
+// Intersection kernels of NodeIteratorN on MI355X.
+//
+// The graph is an oriented CSR in rank space (ranks follow the degree order of
+// Eq. (1)), so for an oriented edge (v,u) every w of N_v ∩ N_u satisfies
+// u < w, and the intersection equals A ∩ N_u with A the part of N_v after u.
+//
+//  * count_plain: the intersection exactly as the NodeIteratorN figure states
+//    it (one thread per oriented edge, two-pointer merge of the full N_v and
+//    N_u straight from HBM). Kept as the in-binary baseline.
+//
+//  * count_pivot: the same |N_v ∩ N_u| terms grouped by the middle vertex u
+//    (the "pivot"): N_u is staged once in an LDS hash table and the suffix A
+//    of each in-edge (v,u) is streamed through it. Work items come from a
+//    cost prefix sum and the boundary rule of Section 5 (load balancing),
+//    with per-item cost |A| plus fixed overheads, instead of per-processor
+//    partitions. Large lists are staged by whole blocks, small ones by single
+//    waves. Per-node counts accumulate in LDS beside the table and leave with
+//    one atomic per (pivot, w).
+#include <cmath>
+
+#include "graph.hpp"
+#include "primitives.hpp"
+
+namespace tc {
+
+
+namespace {
+
+constexpr int kBlock = 256;
+constexpr int kWavesPerBlock = kBlock / kWave;
+constexpr int32_t kEmpty = -1;
+constexpr int kWaveSlots = 512;          // hash slots per wave (lists up to 256 entries)
+constexpr int kCostPerRecord = 4;        // fixed probe-equivalents per in-edge record
+constexpr int kCostPerStaged = 2;        // probe-equivalents per staged list entry
+constexpr int kGroupChunk = 8;           // grouped pivots taken per queue fetch
+
+// ------------------------------------------------------------- plain ---
+
+__global__ __launch_bounds__(kBlock) void k_count_plain(const int64_t* __restrict__ off, const int32_t* __restrict__ adj,
+                                                         const int32_t* __restrict__ src, uint64_t m,
+                                                         unsigned long long* __restrict__ total) {
+  unsigned long long cnt = 0;
+  for (uint64_t e = static_cast<uint64_t>(blockIdx.x) * blockDim.x + threadIdx.x; e < m;
+       e += static_cast<uint64_t>(gridDim.x) * blockDim.x) {
+    const int32_t v = src[e], u = adj[e];
+    int64_t i = off[v], ie = off[v + 1], j = off[u], je = off[u + 1];
+    while (i < ie && j < je) {
+      const int32_t a = adj[i], b = adj[j];
+      cnt += (a == b);
+      i += (a <= b);
+      j += (b <= a);
+    }
+  }
+  cnt = wave_sum(cnt);
+  if (lane_id() == 0 && cnt) atomicAdd(total, cnt);
+}
+
+// W = sum_e (dhat_v + dhat_u) and P = sum_v C(dhat_v, 2)
+__global__ __launch_bounds__(kBlock) void k_work(const int64_t* __restrict__ off, const int32_t* __restrict__ adj,
+                                                  const int32_t* __restrict__ src, uint64_t m,
+                                                  unsigned long long* __restrict__ W, unsigned long long* __restrict__ P) {
+  unsigned long long w = 0, p = 0;
+  for (uint64_t e = static_cast<uint64_t>(blockIdx.x) * blockDim.x + threadIdx.x; e < m;
+       e += static_cast<uint64_t>(gridDim.x) * blockDim.x) {
+    const int32_t v = src[e], u = adj[e];
+    const int64_t rv = off[v + 1];
+    w += static_cast<unsigned long long>((rv - off[v]) + (off[u + 1] - off[u]));
+    p += static_cast<unsigned long long>(rv - static_cast<int64_t>(e) - 1);
+  }
+  w = wave_sum(w);
+  p = wave_sum(p);
+  if (lane_id() == 0) {
+    if (W) atomicAdd(W, w);
+    if (P) atomicAdd(P, p);
+  }
+}
+
+// -------------------------------------------------------- plan building ---
+
+struct InEdgePred {
+  const int64_t* off;
+  const int32_t* adj;
+  const int32_t* src;
+  __device__ bool operator()(size_t e) const {
+    const int32_t v = src[e], u = adj[e];
+    return off[v + 1] - static_cast<int64_t>(e) - 1 > 0 && off[u + 1] - off[u] > 0;
+  }
+};
+
+struct InEdgeKey {
+  const int32_t* adj;
+  __device__ uint64_t operator()(size_t e) const {
+    return (static_cast<uint64_t>(static_cast<uint32_t>(adj[e])) << 32) | static_cast<uint64_t>(e);
+  }
+};
+
+__global__ void k_inrec_fill(const uint64_t* __restrict__ ikeys, uint64_t mi, const int64_t* __restrict__ off,
+                             const int32_t* __restrict__ src, InRec* __restrict__ rec, int32_t* __restrict__ piv,
+                             int64_t* __restrict__ cost) {
+  for (uint64_t i = static_cast<uint64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < mi;
+       i += static_cast<uint64_t>(gridDim.x) * blockDim.x) {
+    const uint64_t k = ikeys[i];
+    const uint32_t e = static_cast<uint32_t>(k & 0xffffffffu);
+    const uint32_t len = static_cast<uint32_t>(off[src[e] + 1] - static_cast<int64_t>(e) - 1);
+    rec[i] = InRec{e + 1, len};
+    piv[i] = static_cast<int32_t>(k >> 32);
+    cost[i] = static_cast<int64_t>(len) + kCostPerRecord;
+  }
+}
+
+__device__ __forceinline__ int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+// Per pivot: number of block items, number of split wave items, and whether it
+// is served from the grouped queue.
+__global__ void k_pivot_classify(int32_t n, const int64_t* __restrict__ off, const int64_t* __restrict__ in_off,
+                                 const int64_t* __restrict__ fin, int64_t hub_dhat, int64_t hub_cap, int64_t iw_hub,
+                                 int64_t iw_wave, int64_t* __restrict__ n_hub, int64_t* __restrict__ n_split,
+                                 int32_t* __restrict__ grouped) {
+  for (int32_t u = blockIdx.x * blockDim.x + threadIdx.x; u < n; u += gridDim.x * blockDim.x) {
+    const int64_t dh = off[u + 1] - off[u];
+    const int64_t i0 = in_off[u], i1 = in_off[u + 1];
+    const int64_t cost = fin[i1] - fin[i0];
+    int64_t h = 0, sp = 0;
+    int32_t gr = 0;
+    if (dh > 0 && i1 > i0) {
+      if (dh > hub_dhat) {
+        h = ceil_div(dh, hub_cap) * ceil_div(cost, iw_hub);
+      } else if (cost + kCostPerStaged * dh > iw_wave) {
+        sp = ceil_div(cost, iw_wave);
+      } else {
+        gr = 1;
+      }
+    }
+    n_hub[u] = h;
+    n_split[u] = sp;
+    grouped[u] = gr;
+  }
+}
+
+// First in-edge index in [i0,i1] whose cost prefix reaches target (boundary
+// rule: x_j is the first position with F >= j * alpha).
+__device__ __forceinline__ int64_t boundary(const int64_t* fin, int64_t i0, int64_t i1, int64_t target) {
+  int64_t lo = i0, hi = i1;
+  while (lo < hi) {
+    const int64_t mid = (lo + hi) >> 1;
+    if (fin[mid] < target) lo = mid + 1;
+    else hi = mid;
+  }
+  return lo;
+}
+
+__global__ void k_items_fill(uint64_t n_items, const int64_t* __restrict__ item_off, int32_t n,
+                             const int64_t* __restrict__ off, const int64_t* __restrict__ in_off,
+                             const int64_t* __restrict__ fin, int64_t cap, int64_t iw, PivotItem* __restrict__ items) {
+  for (uint64_t t = static_cast<uint64_t>(blockIdx.x) * blockDim.x + threadIdx.x; t < n_items;
+       t += static_cast<uint64_t>(gridDim.x) * blockDim.x) {
+    // pivot: largest u with item_off[u] <= t (item_off holds n+1 exclusive offsets)
+    int32_t lo = 0, hi = n - 1;
+    while (lo < hi) {
+      const int32_t mid = static_cast<int32_t>((static_cast<int64_t>(lo) + hi + 1) >> 1);
+      if (item_off[mid] <= static_cast<int64_t>(t)) lo = mid;
+      else hi = mid - 1;
+    }
+    const int32_t u = lo;
+    const int64_t dh = off[u + 1] - off[u];
+    const int64_t i0 = in_off[u], i1 = in_off[u + 1];
+    const int64_t f0 = fin[i0], tot = fin[i1] - f0;
+    const int64_t pieces = ceil_div(tot, iw);
+    const int64_t local = static_cast<int64_t>(t) - item_off[u];
+    const int64_t c = local / pieces, j = local % pieces;
+    const int64_t b0 = j == 0 ? i0 : boundary(fin, i0, i1, f0 + (tot * j) / pieces);
+    const int64_t b1 = j + 1 == pieces ? i1 : boundary(fin, i0, i1, f0 + (tot * (j + 1)) / pieces);
+    const int64_t nb = c * cap;
+    const int64_t nl = dh - nb < cap ? dh - nb : cap;
+    items[t] = PivotItem{u, static_cast<uint32_t>(b0), static_cast<uint32_t>(b1), static_cast<uint32_t>(nb),
+                         static_cast<uint32_t>(nl), 0u};
+  }
+}
+
+struct GroupedPred {
+  const int32_t* flag;
+  __device__ bool operator()(size_t u) const { return flag[u] != 0; }
+};
+struct IdentityI32 {
+  __device__ int32_t operator()(size_t u) const { return static_cast<int32_t>(u); }
+};
+
+// ------------------------------------------------------------ hashing ---
+
+// Orders the LDS accesses of one wave around a point (lanes of a wave share
+// the hash table and the record arrays).
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+__device__ __forceinline__ uint32_t slot_of(int32_t x, int log2s) {
+  return (static_cast<uint32_t>(x) * 0x9E3779B1u) >> (32 - log2s);
+}
+
+__device__ __forceinline__ void hash_insert(int32_t* H, int log2s, int32_t x) {
+  const uint32_t mask = (1u << log2s) - 1u;
+  uint32_t h = slot_of(x, log2s);
+  while (atomicCAS(&H[h], kEmpty, x) != kEmpty) h = (h + 1u) & mask;
+}
+
+__device__ __forceinline__ int hash_find(const int32_t* H, int log2s, int32_t x) {
+  const uint32_t mask = (1u << log2s) - 1u;
+  uint32_t h = slot_of(x, log2s);
+  for (;;) {
+    const int32_t y = H[h];
+    if (y == x) return static_cast<int>(h);
+    if (y == kEmpty) return -1;
+    h = (h + 1u) & mask;
+  }
+}
+
+__device__ __forceinline__ int log2_slots(int64_t len, int min_log2) {
+  int l = min_log2;
+  while ((1ll << l) < 2 * len) l++;
+  return l;
+}
+
+struct KernelArgs {
+  const int64_t* off;
+  const int32_t* adj;
+  const int32_t* src;
+  const InRec* rec;
+  const int64_t* in_off;
+  int mode;
+  unsigned long long* total;
+  unsigned long long* per_graph;
+  const int32_t* graph_of_rank;
+  unsigned long long* t_rank;
+  const int32_t* order;
+  int32_t* tri;
+  unsigned long long* cursor;
+  int64_t cap;
+};
+
+__device__ __forceinline__ void emit_triangle(const KernelArgs& a, int32_t v, int32_t u, int32_t w) {
+  int32_t x = a.order[v], y = a.order[u], z = a.order[w], t;
+  if (x > y) { t = x; x = y; y = t; }
+  if (y > z) { t = y; y = z; z = t; }
+  if (x > y) { t = x; x = y; y = t; }
+  const unsigned long long pos = atomicAdd(a.cursor, 1ull);
+  if (static_cast<int64_t>(pos) < a.cap) {
+    a.tri[3 * pos + 0] = x;
+    a.tri[3 * pos + 1] = y;
+    a.tri[3 * pos + 2] = z;
+  }
+}
+
+// Probe the in-edge records [r0, r1) (at most 64) of pivot u against the
+// staged table. Lanes walk the concatenated suffixes A of the records; each
+// finds its record by binary search over the exclusive prefix in `pre`.
+// Returns this lane's hits.
+__device__ __forceinline__ uint32_t probe_batch(const KernelArgs& a, int32_t u, uint32_t r0, uint32_t r1,
+                                                const int32_t* H, int log2s, uint32_t* C, uint32_t* pre,
+                                                uint32_t* beg, uint32_t* hits) {
+  const int lane = lane_id();
+  const uint32_t r = r0 + lane;
+  const bool valid = r < r1;
+  InRec rc{0u, 0u};
+  if (valid) rc = a.rec[r];
+  const uint32_t incl = wave_incl_scan(rc.a_len);
+  const uint32_t tot = __shfl(incl, kWave - 1, kWave);
+  pre[lane] = incl - rc.a_len;
+  beg[lane] = rc.a_begin;
+  if (a.mode != kCountTotal) hits[lane] = 0;
+  wave_sync();
+  uint32_t cnt = 0;
+  for (uint32_t k = lane; k < tot; k += kWave) {
+    int j = 0;
+#pragma unroll
+    for (int step = 32; step > 0; step >>= 1)
+      if (pre[j + step] <= k) j += step;  // pre[64] is never read: j + step <= 63
+    const int32_t x = a.adj[beg[j] + (k - pre[j])];
+    const int s = hash_find(H, log2s, x);
+    if (s >= 0) {
+      cnt++;
+      if (a.mode == kCountPerNode) {
+        atomicAdd(&C[s], 1u);
+        atomicAdd(&hits[j], 1u);
+      } else if (a.mode == kCountList) {
+        emit_triangle(a, a.src[beg[j] - 1], u, x);
+      }
+    }
+  }
+  if (a.mode == kCountPerNode) {
+    wave_sync();
+    if (valid && hits[lane]) atomicAdd(&a.t_rank[a.src[rc.a_begin - 1]], static_cast<unsigned long long>(hits[lane]));
+  }
+  wave_sync();
+  return cnt;
+}
+
+// -------------------------------------------------------- block kernel ---
+
+// One item per block at a time: stage a slice of N_u (all threads), then each
+// wave probes a quarter of the item's in-edge records.
+__global__ __launch_bounds__(kBlock) void k_pivot_hub(KernelArgs a, const PivotItem* __restrict__ items,
+                                                      uint64_t n_items, unsigned long long* __restrict__ queue,
+                                                      int max_log2s) {
+  extern __shared__ int32_t smem[];
+  int32_t* H = smem;
+  uint32_t* C = reinterpret_cast<uint32_t*>(smem + (1 << max_log2s));  // per-node mode only
+  __shared__ uint32_t pre[kWavesPerBlock][kWave + 1];
+  __shared__ uint32_t beg[kWavesPerBlock][kWave];
+  __shared__ uint32_t hits[kWavesPerBlock][kWave];
+  __shared__ unsigned long long cur;
+  __shared__ unsigned long long red[kWavesPerBlock];
+  const int tid = threadIdx.x, w = tid / kWave, lane = lane_id();
+  unsigned long long acc = 0;
+  for (;;) {
+    if (tid == 0) cur = atomicAdd(queue, 1ull);
+    __syncthreads();
+    const unsigned long long it = cur;
+    if (it >= n_items) break;
+    const PivotItem item = items[it];
+    const int log2s = log2_slots(item.nlen, 6);
+    const int S = 1 << log2s;
+    for (int s = tid; s < S; s += kBlock) {
+      H[s] = kEmpty;
+      if (a.mode == kCountPerNode) C[s] = 0;
+    }
+    __syncthreads();
+    const int64_t nb = a.off[item.u] + item.nbeg_rel;
+    for (uint32_t k = tid; k < item.nlen; k += kBlock) hash_insert(H, log2s, a.adj[nb + k]);
+    __syncthreads();
+    uint32_t cnt = 0;
+    for (uint32_t r0 = item.ibeg + static_cast<uint32_t>(w) * kWave; r0 < item.iend; r0 += kBlock)
+      cnt += probe_batch(a, item.u, r0, item.iend < r0 + kWave ? item.iend : r0 + kWave, H, log2s, C, pre[w], beg[w],
+                         hits[w]);
+    unsigned long long ws = wave_sum(static_cast<unsigned long long>(cnt));
+    if (lane == 0) red[w] = ws;
+    __syncthreads();
+    if (a.mode == kCountPerNode) {
+      for (int s = tid; s < S; s += kBlock)
+        if (C[s]) atomicAdd(&a.t_rank[H[s]], static_cast<unsigned long long>(C[s]));
+    }
+    if (tid == 0) {
+      unsigned long long tot = 0;
+      for (int x = 0; x < kWavesPerBlock; x++) tot += red[x];
+      if (tot) {
+        acc += tot;
+        if (a.per_graph) atomicAdd(&a.per_graph[a.graph_of_rank ? a.graph_of_rank[item.u] : 0], tot);
+        if (a.mode == kCountPerNode) atomicAdd(&a.t_rank[item.u], tot);
+      }
+    }
+    __syncthreads();
+  }
+  if (tid == 0 && acc && a.total) atomicAdd(a.total, acc);
+}
+
+// --------------------------------------------------------- wave kernel ---
+
+__device__ __forceinline__ unsigned long long wave_pivot(const KernelArgs& a, int32_t u, uint32_t ibeg, uint32_t iend,
+                                                         int32_t* H, uint32_t* C, uint32_t* pre, uint32_t* beg,
+                                                         uint32_t* hits) {
+  const int lane = lane_id();
+  const int64_t nb = a.off[u];
+  const uint32_t nlen = static_cast<uint32_t>(a.off[u + 1] - nb);
+  const int log2s = log2_slots(nlen, 6);
+  const int S = 1 << log2s;
+  for (int s = lane; s < S; s += kWave) {
+    H[s] = kEmpty;
+    if (a.mode == kCountPerNode) C[s] = 0;
+  }
+  wave_sync();
+  for (uint32_t k = lane; k < nlen; k += kWave) hash_insert(H, log2s, a.adj[nb + k]);
+  wave_sync();
+  uint32_t cnt = 0;
+  for (uint32_t r0 = ibeg; r0 < iend; r0 += kWave)
+    cnt += probe_batch(a, u, r0, iend < r0 + kWave ? iend : r0 + kWave, H, log2s, C, pre, beg, hits);
+  const unsigned long long tot = wave_sum(static_cast<unsigned long long>(cnt));
+  if (a.mode == kCountPerNode) {
+    for (int s = lane; s < S; s += kWave)
+      if (C[s]) atomicAdd(&a.t_rank[H[s]], static_cast<unsigned long long>(C[s]));
+  }
+  if (lane == 0 && tot) {
+    if (a.per_graph) atomicAdd(&a.per_graph[a.graph_of_rank ? a.graph_of_rank[u] : 0], tot);
+    if (a.mode == kCountPerNode) atomicAdd(&a.t_rank[u], tot);
+  }
+  wave_sync();
+  return tot;
+}
+
+// Each wave serves split items first, then the grouped queue of small pivots.
+__global__ __launch_bounds__(kBlock) void k_pivot_wave(KernelArgs a, const PivotItem* __restrict__ items,
+                                                       uint64_t n_items, const int32_t* __restrict__ grouped,
+                                                       uint64_t n_grouped, unsigned long long* __restrict__ queues) {
+  __shared__ int32_t H[kWavesPerBlock][kWaveSlots];
+  __shared__ uint32_t C[kWavesPerBlock][kWaveSlots];
+  __shared__ uint32_t pre[kWavesPerBlock][kWave + 1];
+  __shared__ uint32_t beg[kWavesPerBlock][kWave];
+  __shared__ uint32_t hits[kWavesPerBlock][kWave];
+  const int w = threadIdx.x / kWave, lane = lane_id();
+  unsigned long long acc = 0;
+  for (;;) {
+    unsigned long long it = 0;
+    if (lane == 0) it = atomicAdd(&queues[0], 1ull);
+    it = __shfl(it, 0, kWave);
+    if (it >= n_items) break;
+    const PivotItem item = items[it];
+    acc += wave_pivot(a, item.u, item.ibeg, item.iend, H[w], C[w], pre[w], beg[w], hits[w]);
+  }
+  for (;;) {
+    unsigned long long g0 = 0;
+    if (lane == 0) g0 = atomicAdd(&queues[1], static_cast<unsigned long long>(kGroupChunk));
+    g0 = __shfl(g0, 0, kWave);
+    if (g0 >= n_grouped) break;
+    const uint64_t g1 = g0 + kGroupChunk < n_grouped ? g0 + kGroupChunk : n_grouped;
+    for (uint64_t g = g0; g < g1; g++) {
+      const int32_t u = grouped[g];
+      acc += wave_pivot(a, u, static_cast<uint32_t>(a.in_off[u]), static_cast<uint32_t>(a.in_off[u + 1]), H[w], C[w],
+                        pre[w], beg[w], hits[w]);
+    }
+  }
+  if (lane == 0 && acc && a.total) atomicAdd(a.total, acc);
+}
+
+__global__ void k_int32_from_u64_hi(const uint64_t* __restrict__ k, uint64_t n, int32_t* __restrict__ out) {
+  for (uint64_t i = static_cast<uint64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < n;
+       i += static_cast<uint64_t>(gridDim.x) * blockDim.x)
+    out[i] = static_cast<int32_t>(k[i] >> 32);
+}
+
+}  // namespace
+
+// Hub items stage at most this many list entries at once (the slice size):
+// table and per-node counters then need at most 2 * 4096 * 4 B = 32 KB of LDS.
+static int64_t hub_slice_cap(int) { return 2048; }
+
+static int device_cus() {
+  int dev = 0, cus = 0;
+  TC_HIP(hipGetDevice(&dev));
+  TC_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+  return cus > 0 ? cus : 1;
+}
+
+void count_plain(const Csr& c, unsigned long long* total, hipStream_t s) {
+  if (c.m == 0) return;
+  const unsigned grid = grid_for(static_cast<uint64_t>(c.m), kBlock, static_cast<unsigned>(device_cus()) * 64u);
+  k_count_plain<<<grid, kBlock, 0, s>>>(c.off.p, c.adj.p, c.src.p, static_cast<uint64_t>(c.m), total);
+  TC_LAUNCH_CHECK();
+}
+
+void graph_work(const Csr& c, unsigned long long* W, unsigned long long* P, hipStream_t s) {
+  if (c.m == 0) return;
+  k_work<<<grid_for(static_cast<uint64_t>(c.m), kBlock, 16384), kBlock, 0, s>>>(c.off.p, c.adj.p, c.src.p,
+                                                                                 static_cast<uint64_t>(c.m), W, P);
+  TC_LAUNCH_CHECK();
+}
+
+// Builds the in-edge records and the work items of the pivot kernels. The
+// plan depends on hub_dhat and item_work and is rebuilt when they change.
+// The item lists are built for the per-node slice cap (4096), which also
+// serves the total-only mode.
+static int64_t clamp_hub(int64_t h) { return h < 0 ? 0 : (h > kWaveSlots / 2 ? kWaveSlots / 2 : h); }
+
+void ensure_plan(Csr& c, hipStream_t s, const Options& o) {
+  PivotPlan& P = c.plan;
+  if (P.ready && P.hub_dhat == clamp_hub(o.hub_dhat) && P.item_work == o.item_work) return;
+  P.reset();
+  const int32_t n = c.n;
+  const uint64_t m = static_cast<uint64_t>(c.m);
+  P.in_off.alloc(static_cast<size_t>(n) + 1);
+  if (m == 0 || n == 0) {
+    if (n >= 0) TC_HIP(hipMemsetAsync(P.in_off.p, 0, (static_cast<size_t>(n) + 1) * sizeof(int64_t), s));
+    P.hub_dhat = clamp_hub(o.hub_dhat);
+    P.item_work = o.item_work;
+    P.ready = true;
+    return;
+  }
+  const int b = bits_for(n > 1 ? static_cast<uint64_t>(n - 1) : 1);
+  // in-edge keys (u, e) for edges with a non-empty suffix and non-empty N_u
+  DevBuf<uint64_t> ik(m, s), ik2(m, s);
+  DevBuf<uint64_t> d_cnt(1, s);
+  compact_if<uint64_t>(m, InEdgePred{c.off.p, c.adj.p, c.src.p}, InEdgeKey{c.adj.p}, ik.get(), d_cnt.get(), s);
+  uint64_t mi = 0;
+  TC_HIP(hipMemcpyAsync(&mi, d_cnt.get(), sizeof(uint64_t), hipMemcpyDeviceToHost, s));
+  TC_HIP(hipStreamSynchronize(s));
+  uint64_t* sk = radix_sort<uint64_t>(ik.get(), ik2.get(), mi, 32, 32 + b, s);
+  P.inrec.alloc(mi);
+  DevBuf<int32_t> piv(mi, s);
+  DevBuf<int64_t> fin(mi + 1, s);
+  if (mi > 0) {
+    k_inrec_fill<<<grid_for(mi, kBlock, 65536), kBlock, 0, s>>>(sk, mi, c.off.p, c.src.p, P.inrec.p, piv.get(), fin.get());
+    TC_LAUNCH_CHECK();
+  }
+  offsets_from_rows(piv.get(), mi, n, P.in_off.p, s);
+  exclusive_scan<int64_t>(fin.get(), fin.get(), mi, s, fin.get() + mi);
+  ik.release();
+  ik2.release();
+  piv.release();
+
+  // classify pivots and count items
+  const int64_t iw_wave = o.item_work > 64 ? o.item_work : 64;
+  const int64_t iw_hub = 8 * iw_wave;
+  const int64_t cap = hub_slice_cap(kCountPerNode);
+  DevBuf<int64_t> nh(static_cast<size_t>(n) + 1, s), ns(static_cast<size_t>(n) + 1, s);
+  DevBuf<int32_t> grp(n, s);
+  k_pivot_classify<<<grid_for(n, kBlock, 65536), kBlock, 0, s>>>(n, c.off.p, P.in_off.p, fin.get(), clamp_hub(o.hub_dhat), cap,
+                                                                 iw_hub, iw_wave, nh.get(), ns.get(), grp.get());
+  TC_LAUNCH_CHECK();
+  exclusive_scan<int64_t>(nh.get(), nh.get(), n, s, nh.get() + n);
+  exclusive_scan<int64_t>(ns.get(), ns.get(), n, s, ns.get() + n);
+  int64_t counts[2] = {0, 0};
+  TC_HIP(hipMemcpyAsync(&counts[0], nh.get() + n, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+  TC_HIP(hipMemcpyAsync(&counts[1], ns.get() + n, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+  TC_HIP(hipStreamSynchronize(s));
+  P.n_hub_items = static_cast<uint64_t>(counts[0]);
+  P.n_wave_items = static_cast<uint64_t>(counts[1]);
+  // items: [hub items | split wave items | grouped pivots as int32 at the end]
+  P.items.alloc(P.n_hub_items + P.n_wave_items);
+  if (P.n_hub_items) {
+    k_items_fill<<<grid_for(P.n_hub_items, kBlock, 65536), kBlock, 0, s>>>(P.n_hub_items, nh.get(), n, c.off.p,
+                                                                          P.in_off.p, fin.get(), cap, iw_hub, P.items.p);
+    TC_LAUNCH_CHECK();
+  }
+  if (P.n_wave_items) {
+    k_items_fill<<<grid_for(P.n_wave_items, kBlock, 65536), kBlock, 0, s>>>(
+        P.n_wave_items, ns.get(), n, c.off.p, P.in_off.p, fin.get(), 1ll << 40, iw_wave, P.items.p + P.n_hub_items);
+    TC_LAUNCH_CHECK();
+  }
+  // grouped pivot list
+  DevBuf<uint64_t> d_g(1, s);
+  DevBuf<int32_t> glist(n, s);
+  compact_if<int32_t>(n, GroupedPred{grp.get()}, IdentityI32{}, glist.get(), d_g.get(), s);
+  uint64_t ng = 0;
+  TC_HIP(hipMemcpyAsync(&ng, d_g.get(), sizeof(uint64_t), hipMemcpyDeviceToHost, s));
+  TC_HIP(hipStreamSynchronize(s));
+  P.grouped.alloc(ng);
+  if (ng) TC_HIP(hipMemcpyAsync(P.grouped.p, glist.get(), ng * sizeof(int32_t), hipMemcpyDeviceToDevice, s));
+  P.n_grouped = ng;
+  TC_HIP(hipStreamSynchronize(s));
+  P.hub_dhat = clamp_hub(o.hub_dhat);
+  P.item_work = o.item_work;
+  P.ready = true;
+}
+
+namespace {
+__global__ void k_fill_u64(unsigned long long* __restrict__ p, size_t n, unsigned long long v) {
+  for (size_t i = static_cast<size_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += static_cast<size_t>(gridDim.x) * blockDim.x)
+    p[i] = v;
+}
+}  // namespace
+
+// A fill kernel rather than hipMemsetAsync so that captured graphs hold no memset node.
+void fill_u64(unsigned long long* p, size_t n, unsigned long long v, hipStream_t s) {
+  if (n == 0) return;
+  k_fill_u64<<<grid_for(n, kBlock, 65536), kBlock, 0, s>>>(p, n, v);
+  TC_LAUNCH_CHECK();
+}
+
+void count_pivot(Csr& c, const CountArgs& ca, hipStream_t s, const Options& o, bool allow_rebuild) {
+  if (c.m == 0) return;
+  if (allow_rebuild) ensure_plan(c, s, o);
+  else if (!c.plan.ready) fail(TC_E_INVAL, "no work plan on this graph");
+  const PivotPlan& P = c.plan;
+  KernelArgs a{c.off.p,     c.adj.p,          c.src.p,   P.inrec.p, P.in_off.p, ca.mode,  ca.total,
+               ca.per_graph, ca.graph_of_rank, ca.t_rank, ca.order,  ca.tri,     ca.cursor, ca.cap};
+  DevBuf<unsigned long long> qbuf;
+  unsigned long long* q = ca.queues;
+  if (!q) {
+    qbuf.alloc(3, s);
+    q = qbuf.get();
+  }
+  fill_u64(q, 3, 0ull, s);
+  const unsigned cus = static_cast<unsigned>(device_cus());
+  const unsigned bpc = static_cast<unsigned>(o.blocks_per_cu > 0 ? o.blocks_per_cu : 8);
+  if (P.n_hub_items) {
+    int64_t maxlen = c.dhat_max < hub_slice_cap(kCountPerNode) ? c.dhat_max : hub_slice_cap(kCountPerNode);
+    int l = 6;
+    while ((1ll << l) < 2 * maxlen) l++;
+    const size_t lds = (static_cast<size_t>(1) << l) * sizeof(int32_t) * (ca.mode == kCountPerNode ? 2 : 1);
+    const unsigned grid = static_cast<unsigned>(P.n_hub_items < static_cast<uint64_t>(cus) * bpc ? P.n_hub_items : cus * bpc);
+    k_pivot_hub<<<grid, kBlock, lds, s>>>(a, P.items.p, P.n_hub_items, q, l);
+    TC_LAUNCH_CHECK();
+  }
+  if (P.n_wave_items || P.n_grouped) {
+    const uint64_t waves_needed = P.n_wave_items + (P.n_grouped + kGroupChunk - 1) / kGroupChunk;
+    const uint64_t blocks_needed = (waves_needed + kWavesPerBlock - 1) / kWavesPerBlock;
+    const unsigned grid = static_cast<unsigned>(blocks_needed < static_cast<uint64_t>(cus) * bpc ? blocks_needed : cus * bpc);
+    k_pivot_wave<<<grid, kBlock, 0, s>>>(a, P.items.p + P.n_hub_items, P.n_wave_items, P.grouped.p, P.n_grouped,
+                                          q + 1);
+    TC_LAUNCH_CHECK();
+  }
+}
+
+// --------------------------------------------------------- sparsified ---
+
+namespace {
+
+__device__ __forceinline__ uint64_t splitmix64_output(uint64_t z) {
+  z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ull;
+  z = (z ^ (z >> 27)) * 0x94d049bb133111ebull;
+  return z ^ (z >> 31);
+}
+
+struct KeepPred {
+  const int32_t* adj;
+  const int32_t* src;
+  const int32_t* order;
+  uint64_t key;  // mix(seed ^ domain)
+  uint64_t tau;
+  bool all;
+  __device__ bool operator()(size_t e) const {
+    if (all) return true;
+    const uint32_t a = static_cast<uint32_t>(order[src[e]]), b = static_cast<uint32_t>(order[adj[e]]);
+    const uint64_t lo = a < b ? a : b, hi = a < b ? b : a;
+    return splitmix64_output(key ^ ((lo << 32) | hi)) < tau;
+  }
+};
+
+struct PackEntry {
+  const int32_t* adj;
+  const int32_t* src;
+  __device__ uint64_t operator()(size_t e) const {
+    return (static_cast<uint64_t>(static_cast<uint32_t>(src[e])) << 32) | static_cast<uint32_t>(adj[e]);
+  }
+};
+
+__global__ void k_unpack_entries(const uint64_t* __restrict__ k, uint64_t n, int32_t* __restrict__ adj,
+                                 int32_t* __restrict__ src) {
+  for (uint64_t i = static_cast<uint64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < n;
+       i += static_cast<uint64_t>(gridDim.x) * blockDim.x) {
+    adj[i] = static_cast<int32_t>(k[i] & 0xffffffffu);
+    src[i] = static_cast<int32_t>(k[i] >> 32);
+  }
+}
+
+}  // namespace
+
+void build_sampled_csr(const tc_graph* g, double q, uint64_t seed, Csr& out, hipStream_t s) {
+  const Csr& c = g->csr;
+  const uint64_t m = static_cast<uint64_t>(c.m);
+  const bool all = q >= 1.0;
+  const uint64_t tau = all ? ~0ull : static_cast<uint64_t>(std::ldexp(q, 64));
+  KeepPred pred{c.adj.p, c.src.p, g->order.p, 0, tau, all};
+  {
+    uint64_t z = seed ^ 0x5350415253494659ull;  // domain separation constant ("SPARSIFY")
+    z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ull;
+    z = (z ^ (z >> 27)) * 0x94d049bb133111ebull;
+    pred.key = z ^ (z >> 31);
+  }
+  DevBuf<uint64_t> packed(m, s);
+  DevBuf<uint64_t> d_cnt(1, s);
+  compact_if<uint64_t>(m, pred, PackEntry{c.adj.p, c.src.p}, packed.get(), d_cnt.get(), s);
+  uint64_t mk = 0;
+  TC_HIP(hipMemcpyAsync(&mk, d_cnt.get(), sizeof(uint64_t), hipMemcpyDeviceToHost, s));
+  TC_HIP(hipStreamSynchronize(s));
+  out.n = c.n;
+  out.m = static_cast<int64_t>(mk);
+  out.off.alloc(static_cast<size_t>(c.n) + 1);
+  out.adj.alloc(mk);
+  out.src.alloc(mk);
+  if (mk) {
+    k_unpack_entries<<<grid_for(mk, kBlock, 65536), kBlock, 0, s>>>(packed.get(), mk, out.adj.p, out.src.p);
+    TC_LAUNCH_CHECK();
+  }
+  offsets_from_rows(out.src.p, mk, c.n, out.off.p, s);
+  out.dhat_max = max_row_length(out.off.p, c.n, s);
+}
+
+// ------------------------------------------------------------ listing ---
+
+namespace {
+
+__global__ void k_pack_tri(const int32_t* __restrict__ tri, int64_t count, int bits, u128* __restrict__ k) {
+  for (int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < count;
+       i += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+    const uint64_t a = static_cast<uint32_t>(tri[3 * i]), b = static_cast<uint32_t>(tri[3 * i + 1]),
+                   c = static_cast<uint32_t>(tri[3 * i + 2]);
+    k[i] = u128{(b << bits) | c, a};
+  }
+}
+
+__global__ void k_unpack_tri(const u128* __restrict__ k, int64_t count, int bits, int32_t* __restrict__ tri) {
+  const uint64_t mask = (1ull << bits) - 1;
+  for (int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < count;
+       i += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+    const u128 x = k[i];
+    tri[3 * i] = static_cast<int32_t>(x.hi);
+    tri[3 * i + 1] = static_cast<int32_t>(x.lo >> bits);
+    tri[3 * i + 2] = static_cast<int32_t>(x.lo & mask);
+  }
+}
+
+}  // namespace
+
+void sort_triangles(int32_t* tri, int64_t count, int bits, hipStream_t s) {
+  if (count <= 1) return;
+  DevBuf<u128> k1(count, s), k2(count, s);
+  k_pack_tri<<<grid_for(count, kBlock, 65536), kBlock, 0, s>>>(tri, count, bits, k1.get());
+  TC_LAUNCH_CHECK();
+  u128* r = radix_sort<u128>(k1.get(), k2.get(), count, 0, 2 * bits, s);
+  r = radix_sort<u128>(r, r == k1.get() ? k2.get() : k1.get(), count, 64, 64 + bits, s);
+  k_unpack_tri<<<grid_for(count, kBlock, 65536), kBlock, 0, s>>>(r, count, bits, tri);
+  TC_LAUNCH_CHECK();
+}
+
+}  // namespace tc

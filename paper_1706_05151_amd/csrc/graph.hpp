@@ -1,0 +1,155 @@
+// The device graph behind the opaque tc_graph handle, and the internal entry
+// points shared by the library's translation units.
+#pragma once
+
+#include <memory>
+#include <mutex>
+#include <vector>
+
+#include "common.hpp"
+
+namespace tc {
+
+// Device arrays owned by a graph (freed with hipFree on graph destruction).
+template <typename T>
+struct Owned {
+  T* p = nullptr;
+  size_t n = 0;
+  Owned() = default;
+  Owned(const Owned&) = delete;
+  Owned& operator=(const Owned&) = delete;
+  ~Owned() { reset(); }
+  void reset() {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    n = 0;
+  }
+  void alloc(size_t count) {
+    reset();
+    n = count;
+    if (count) TC_HIP(hipMalloc(reinterpret_cast<void**>(&p), count * sizeof(T)));
+  }
+  // take over a stream-ordered buffer
+  void adopt(DevBuf<T>& b) {
+    reset();
+    n = b.size();
+    p = b.detach();
+  }
+};
+
+// Work item of the pivot-staged intersection: pivot u (a rank), the slice
+// [nbeg, nend) of the CSR entries of N_u to stage, and the slice [ibeg, iend)
+// of u's in-edge records to probe against it.
+struct PivotItem {
+  int32_t u;
+  uint32_t ibeg, iend;
+  uint32_t nbeg_rel;  // offset of the staged slice inside N_u
+  uint32_t nlen;      // length of the staged slice
+  uint32_t pad;
+};
+
+// In-edge record for pivot u: the oriented edge (v,u) sits at CSR index e of
+// N_v; the candidates for third vertices are N_v[e+1 .. end of row v).
+struct InRec {
+  uint32_t a_begin;  // e + 1
+  uint32_t a_len;    // entries of N_v after u
+};
+
+// The pivot work plan of one oriented CSR (built lazily, cached on the graph).
+struct PivotPlan {
+  bool ready = false;
+  Owned<InRec> inrec;        // in-edge records grouped by pivot
+  Owned<int64_t> in_off;     // [n+1]
+  Owned<PivotItem> items;    // hub items first, then wave items
+  uint64_t n_hub_items = 0;  // items processed by whole blocks
+  uint64_t n_wave_items = 0; // items processed by single waves
+  Owned<int32_t> grouped;    // small pivots served from a shared queue
+  uint64_t n_grouped = 0;
+  int64_t hub_dhat = 0, item_work = 0;  // options the plan was built with
+  void reset() {
+    ready = false;
+    inrec.reset();
+    in_off.reset();
+    items.reset();
+    grouped.reset();
+    n_hub_items = n_wave_items = n_grouped = 0;
+    hub_dhat = item_work = 0;
+  }
+};
+
+// An oriented CSR in rank space: vertices are numbered by their position in
+// the degree order (Eq. (1)), so N_v holds only ranks > v, ascending.
+struct Csr {
+  int32_t n = 0;
+  int64_t m = 0;
+  int32_t dhat_max = 0;
+  Owned<int64_t> off;  // [n+1]
+  Owned<int32_t> adj;  // [m]
+  Owned<int32_t> src;  // [m] row of each entry
+  PivotPlan plan;
+};
+
+}  // namespace tc
+
+struct tc_graph {
+  int device = 0;
+  int32_t n = 0;   // vertices (all graphs of a batch together)
+  int64_t m = 0;   // unique undirected edges
+  int32_t d_max = 0;
+  int bits = 1;    // bits of a vertex id
+  tc::Csr csr;
+  tc::Owned<int32_t> order;  // [n] rank -> caller id
+  tc::Owned<int32_t> rank;   // [n] caller id -> rank
+  tc::Owned<int32_t> deg;    // [n] d_v by caller id
+  // batches
+  int32_t num_graphs = 1;
+  tc::Owned<int32_t> graph_of_rank;  // [n] graph index of each rank (batches only)
+  std::vector<int32_t> vbase;        // [num_graphs+1] first caller id of each graph
+  // workspace for the capturable batched count
+  tc::Owned<unsigned char> workspace;
+  size_t workspace_bytes = 0;
+  std::mutex mu;  // guards lazy plan construction
+};
+
+namespace tc {
+
+struct Options {
+  int64_t kernel = 0;        // 0 auto, 1 plain, 2 pivot
+  int64_t hub_dhat = 128;    // pivots with |N_u| > hub_dhat use the block path
+  int64_t item_work = 4096;  // target probes per work item
+  int64_t blocks_per_cu = 8; // persistent launch occupancy
+};
+Options get_options();
+
+// build.hip
+void build_graph(const int32_t* src, const int32_t* dst, int64_t E, int32_t n, const int64_t* edge_off_host,
+                 const int32_t* n_per_graph_host, int32_t num_graphs, bool on_device, hipStream_t s, tc_graph* g);
+
+// count.hip
+enum CountMode { kCountTotal = 0, kCountPerNode = 1, kCountList = 2 };
+struct CountArgs {
+  int mode = kCountTotal;
+  unsigned long long* total = nullptr;     // device, one counter (whole graph)
+  unsigned long long* per_graph = nullptr; // device [num_graphs] (optional)
+  const int32_t* graph_of_rank = nullptr;  // device [n] (with per_graph)
+  unsigned long long* t_rank = nullptr;    // device [n] per-node counts by rank
+  const int32_t* order = nullptr;          // rank -> caller id (listing)
+  int32_t* tri = nullptr;                  // device [cap][3] (listing)
+  unsigned long long* cursor = nullptr;    // device listing cursor
+  int64_t cap = 0;
+  unsigned long long* queues = nullptr;    // device [3] work-queue counters (optional)
+};
+void ensure_plan(Csr& c, hipStream_t s, const Options& o);
+// allow_rebuild = false: use the cached plan as is (capturable; fails if absent)
+void count_pivot(Csr& c, const CountArgs& a, hipStream_t s, const Options& o, bool allow_rebuild = true);
+void fill_u64(unsigned long long* p, size_t n, unsigned long long v, hipStream_t s);
+void count_plain(const Csr& c, unsigned long long* total, hipStream_t s);
+void graph_work(const Csr& c, unsigned long long* W, unsigned long long* P, hipStream_t s);
+void build_sampled_csr(const tc_graph* g, double q, uint64_t seed, Csr& out, hipStream_t s);
+void sort_triangles(int32_t* tri, int64_t count, int bits, hipStream_t s);
+// off[r] = first index whose row is >= r, for rows sorted ascending (length m); off has n+1 entries
+void offsets_from_rows(const int32_t* row, uint64_t m, int32_t n, int64_t* off, hipStream_t s);
+// largest off[r+1]-off[r] (0 if n == 0); synchronises s
+int32_t max_row_length(const int64_t* off, int32_t n, hipStream_t s);
+
+}  // namespace tc

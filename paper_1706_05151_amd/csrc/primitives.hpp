@@ -1,0 +1,335 @@
+// Device-wide building blocks: exclusive scan, stream compaction and an LSD
+// radix sort. Header-only templates; every translation unit that uses one
+// instantiates its own kernels.
+#pragma once
+
+#include "common.hpp"
+
+namespace tc {
+
+// ================================================================== scan ===
+
+constexpr int kScanBlock = 256;
+constexpr int kScanItems = 8;
+constexpr int kScanChunk = kScanBlock * kScanItems;
+
+template <typename T>
+__global__ __launch_bounds__(kScanBlock) void k_scan_reduce(const T* __restrict__ in, size_t N, T* __restrict__ partial) {
+  __shared__ T sm[kScanBlock / kWave];
+  const size_t base = static_cast<size_t>(blockIdx.x) * kScanChunk;
+  T s = 0;
+#pragma unroll
+  for (int i = 0; i < kScanItems; i++) {
+    size_t idx = base + static_cast<size_t>(i) * kScanBlock + threadIdx.x;
+    if (idx < N) s += in[idx];
+  }
+  T tot;
+  (void)block_excl_scan<T, kScanBlock>(s, sm, tot);
+  if (threadIdx.x == 0) partial[blockIdx.x] = tot;
+}
+
+// out[i] = carry(block) + sum of in[j] for j < i within the block's chunk.
+// `in` and `out` may alias. The last block stores the grand total.
+template <typename T>
+__global__ __launch_bounds__(kScanBlock) void k_scan_apply(const T* in, T* out, size_t N, const T* __restrict__ carry,
+                                                            T* __restrict__ total_out) {
+  __shared__ T sm[kScanBlock / kWave];
+  __shared__ T tile[kScanChunk + kScanChunk / 32];
+  auto pad = [](int j) { return j + (j >> 5); };
+  const size_t base = static_cast<size_t>(blockIdx.x) * kScanChunk;
+#pragma unroll
+  for (int i = 0; i < kScanItems; i++) {
+    int j = i * kScanBlock + threadIdx.x;
+    size_t idx = base + j;
+    tile[pad(j)] = idx < N ? in[idx] : T(0);
+  }
+  __syncthreads();
+  T v[kScanItems];
+  T s = 0;
+#pragma unroll
+  for (int j = 0; j < kScanItems; j++) {
+    v[j] = tile[pad(threadIdx.x * kScanItems + j)];
+    s += v[j];
+  }
+  T tot;
+  T pre = block_excl_scan<T, kScanBlock>(s, sm, tot);
+  T run = (carry ? carry[blockIdx.x] : T(0)) + pre;
+#pragma unroll
+  for (int j = 0; j < kScanItems; j++) {
+    tile[pad(threadIdx.x * kScanItems + j)] = run;
+    run += v[j];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < kScanItems; i++) {
+    int j = i * kScanBlock + threadIdx.x;
+    size_t idx = base + j;
+    if (idx < N) out[idx] = tile[pad(j)];
+  }
+  if (total_out && blockIdx.x == gridDim.x - 1 && threadIdx.x == kScanBlock - 1) *total_out = run;
+}
+
+template <typename T>
+__global__ void k_store_zero(T* p) { *p = T(0); }
+
+// Exclusive prefix sum of in[0..N) into out (may alias); total_dev (optional)
+// receives the sum of all N inputs.
+template <typename T>
+void exclusive_scan(const T* in, T* out, size_t N, hipStream_t s, T* total_dev = nullptr) {
+  if (N == 0) {
+    if (total_dev) {
+      k_store_zero<T><<<1, 1, 0, s>>>(total_dev);
+      TC_LAUNCH_CHECK();
+    }
+    return;
+  }
+  const size_t nb = (N + kScanChunk - 1) / kScanChunk;
+  if (nb == 1) {
+    k_scan_apply<T><<<1, kScanBlock, 0, s>>>(in, out, N, nullptr, total_dev);
+    TC_LAUNCH_CHECK();
+    return;
+  }
+  DevBuf<T> part(nb, s);
+  k_scan_reduce<T><<<static_cast<unsigned>(nb), kScanBlock, 0, s>>>(in, N, part.get());
+  TC_LAUNCH_CHECK();
+  exclusive_scan<T>(part.get(), part.get(), nb, s, nullptr);
+  k_scan_apply<T><<<static_cast<unsigned>(nb), kScanBlock, 0, s>>>(in, out, N, part.get(), total_dev);
+  TC_LAUNCH_CHECK();
+}
+
+// ============================================================ compaction ===
+
+// Pred: __device__ bool operator()(size_t i) const; Gen: __device__ T operator()(size_t i) const.
+template <typename Pred>
+__global__ __launch_bounds__(kScanBlock) void k_count_if(size_t N, Pred pred, uint64_t* __restrict__ counts) {
+  __shared__ uint64_t sm[kScanBlock / kWave];
+  const size_t base = static_cast<size_t>(blockIdx.x) * kScanChunk + static_cast<size_t>(threadIdx.x) * kScanItems;
+  uint64_t c = 0;
+#pragma unroll
+  for (int j = 0; j < kScanItems; j++) {
+    size_t i = base + j;
+    if (i < N && pred(i)) c++;
+  }
+  uint64_t tot;
+  (void)block_excl_scan<uint64_t, kScanBlock>(c, sm, tot);
+  if (threadIdx.x == 0) counts[blockIdx.x] = tot;
+}
+
+template <typename T, typename Pred, typename Gen>
+__global__ __launch_bounds__(kScanBlock) void k_compact(size_t N, Pred pred, Gen gen, T* __restrict__ out,
+                                                         const uint64_t* __restrict__ offs) {
+  __shared__ uint64_t sm[kScanBlock / kWave];
+  const size_t base = static_cast<size_t>(blockIdx.x) * kScanChunk + static_cast<size_t>(threadIdx.x) * kScanItems;
+  bool f[kScanItems];
+  uint64_t c = 0;
+#pragma unroll
+  for (int j = 0; j < kScanItems; j++) {
+    size_t i = base + j;
+    f[j] = i < N && pred(i);
+    c += f[j];
+  }
+  uint64_t tot;
+  uint64_t pos = offs[blockIdx.x] + block_excl_scan<uint64_t, kScanBlock>(c, sm, tot);
+#pragma unroll
+  for (int j = 0; j < kScanItems; j++)
+    if (f[j]) out[pos++] = gen(base + j);
+}
+
+// Writes gen(i) for every i in [0,N) with pred(i), in index order, to out.
+// Returns nothing on the host; the kept count goes to count_dev (device uint64).
+template <typename T, typename Pred, typename Gen>
+void compact_if(size_t N, Pred pred, Gen gen, T* out, uint64_t* count_dev, hipStream_t s) {
+  if (N == 0) {
+    k_store_zero<uint64_t><<<1, 1, 0, s>>>(count_dev);
+    TC_LAUNCH_CHECK();
+    return;
+  }
+  const size_t nb = (N + kScanChunk - 1) / kScanChunk;
+  DevBuf<uint64_t> cnt(nb, s);
+  k_count_if<Pred><<<static_cast<unsigned>(nb), kScanBlock, 0, s>>>(N, pred, cnt.get());
+  TC_LAUNCH_CHECK();
+  exclusive_scan<uint64_t>(cnt.get(), cnt.get(), nb, s, count_dev);
+  k_compact<T, Pred, Gen><<<static_cast<unsigned>(nb), kScanBlock, 0, s>>>(N, pred, gen, out, cnt.get());
+  TC_LAUNCH_CHECK();
+}
+
+// ============================================================ radix sort ===
+
+struct u128 {
+  uint64_t lo, hi;
+};
+
+template <typename K>
+struct RadixKey;
+
+template <>
+struct RadixKey<uint64_t> {
+  __device__ __forceinline__ static uint32_t digit(uint64_t k, int shift) {
+    return static_cast<uint32_t>(k >> shift) & 255u;
+  }
+};
+
+template <>
+struct RadixKey<u128> {
+  __device__ __forceinline__ static uint32_t digit(const u128& k, int shift) {
+    return shift < 64 ? static_cast<uint32_t>(k.lo >> shift) & 255u : static_cast<uint32_t>(k.hi >> (shift - 64)) & 255u;
+  }
+};
+
+template <typename K>
+struct RadixItems;
+template <>
+struct RadixItems<uint64_t> {
+  static constexpr int value = 16;
+};
+template <>
+struct RadixItems<u128> {
+  static constexpr int value = 8;
+};
+
+constexpr int kSortBlock = 256;
+constexpr int kSortWaves = kSortBlock / kWave;
+
+// Mask of the lanes whose 9-bit value equals this lane's (all 64 lanes active).
+__device__ __forceinline__ uint64_t match_any9(uint32_t d) {
+  uint64_t peers = ~0ull;
+#pragma unroll
+  for (int b = 0; b < 9; b++) {
+    const bool bit = (d >> b) & 1u;
+    const uint64_t bb = __ballot(bit);
+    peers &= bit ? bb : ~bb;
+  }
+  return peers;
+}
+
+// Per-tile digit histogram, stored digit-major: hist[d * tiles + tile].
+template <typename K>
+__global__ __launch_bounds__(kSortBlock) void k_radix_hist(const K* __restrict__ keys, uint32_t N, int shift,
+                                                            uint32_t* __restrict__ hist, uint32_t tiles) {
+  constexpr int ITEMS = RadixItems<K>::value;
+  constexpr int TILE = kSortBlock * ITEMS;
+  __shared__ uint32_t h[kSortWaves][256];
+  const int tid = threadIdx.x, w = tid / kWave;
+#pragma unroll
+  for (int x = 0; x < kSortWaves; x++) h[x][tid] = 0;
+  __syncthreads();
+  const size_t base = static_cast<size_t>(blockIdx.x) * TILE;
+#pragma unroll 4
+  for (int i = 0; i < ITEMS; i++) {
+    const size_t idx = base + static_cast<size_t>(i) * kSortBlock + tid;
+    const bool valid = idx < N;
+    const uint32_t d = valid ? RadixKey<K>::digit(keys[idx], shift) : 256u;
+    const uint64_t peers = match_any9(d);
+    if (valid && __popcll(peers & lanemask_lt()) == 0) h[w][d] += static_cast<uint32_t>(__popcll(peers));
+  }
+  __syncthreads();
+  uint32_t t = 0;
+#pragma unroll
+  for (int x = 0; x < kSortWaves; x++) t += h[x][tid];
+  hist[static_cast<size_t>(tid) * tiles + blockIdx.x] = t;
+}
+
+// Stable scatter of one tile: rank each key among equal digits in index
+// order (round-major, then wave, then lane), stage the tile in LDS sorted by
+// digit, and write each digit run contiguously to its global offset.
+template <typename K>
+__global__ __launch_bounds__(kSortBlock) void k_radix_scatter(const K* __restrict__ in, K* __restrict__ out, uint32_t N,
+                                                               int shift, const uint32_t* __restrict__ offs,
+                                                               uint32_t tiles) {
+  constexpr int ITEMS = RadixItems<K>::value;
+  constexpr int TILE = kSortBlock * ITEMS;
+  __shared__ K tile[TILE];
+  __shared__ uint32_t wcnt[2][kSortWaves][256];
+  __shared__ uint32_t run[256];
+  __shared__ uint32_t dstart[256];
+  __shared__ uint32_t gbase[256];
+  __shared__ uint32_t scan_tmp[kSortWaves];
+  const int tid = threadIdx.x, w = tid / kWave;
+  const size_t base = static_cast<size_t>(blockIdx.x) * TILE;
+
+  run[tid] = 0;
+#pragma unroll
+  for (int x = 0; x < kSortWaves; x++) {
+    wcnt[0][x][tid] = 0;
+    wcnt[1][x][tid] = 0;
+  }
+  gbase[tid] = offs[static_cast<size_t>(tid) * tiles + blockIdx.x];
+  __syncthreads();
+
+  K key[ITEMS];
+  uint32_t rk[ITEMS];
+  uint32_t dg[ITEMS];
+#pragma unroll
+  for (int i = 0; i < ITEMS; i++) {
+    const int buf = i & 1;
+    const size_t idx = base + static_cast<size_t>(i) * kSortBlock + tid;
+    const bool valid = idx < N;
+    K k{};
+    if (valid) k = in[idx];
+    const uint32_t d = valid ? RadixKey<K>::digit(k, shift) : 256u;
+    const uint64_t peers = match_any9(d);
+    const uint32_t lr = static_cast<uint32_t>(__popcll(peers & lanemask_lt()));
+    if (valid && lr == 0) wcnt[buf][w][d] = static_cast<uint32_t>(__popcll(peers));
+    __syncthreads();
+    {
+      uint32_t acc = run[tid];
+#pragma unroll
+      for (int x = 0; x < kSortWaves; x++) {
+        const uint32_t c = wcnt[buf][x][tid];
+        wcnt[buf][x][tid] = acc;
+        acc += c;
+      }
+      run[tid] = acc;
+#pragma unroll
+      for (int x = 0; x < kSortWaves; x++) wcnt[buf ^ 1][x][tid] = 0;
+    }
+    __syncthreads();
+    key[i] = k;
+    dg[i] = d;
+    rk[i] = valid ? wcnt[buf][w][d] + lr : 0u;
+  }
+  uint32_t total;
+  const uint32_t ds = block_excl_scan<uint32_t, kSortBlock>(run[tid], scan_tmp, total);
+  dstart[tid] = ds;
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < ITEMS; i++)
+    if (dg[i] < 256u) tile[dstart[dg[i]] + rk[i]] = key[i];
+  __syncthreads();
+  const uint32_t cnt = static_cast<uint32_t>(N - base < static_cast<size_t>(TILE) ? N - base : TILE);
+#pragma unroll
+  for (int i = 0; i < ITEMS; i++) {
+    const uint32_t j = static_cast<uint32_t>(i * kSortBlock + tid);
+    if (j < cnt) {
+      const K k = tile[j];
+      const uint32_t d = RadixKey<K>::digit(k, shift);
+      out[gbase[d] + (j - dstart[d])] = k;
+    }
+  }
+}
+
+// Sorts N keys ascending by bits [bit_lo, bit_hi) (8-bit digits, stable).
+// Uses `keys` and `tmp` as ping-pong buffers; returns the one holding the result.
+template <typename K>
+K* radix_sort(K* keys, K* tmp, size_t N, int bit_lo, int bit_hi, hipStream_t s) {
+  if (N <= 1 || bit_hi <= bit_lo) return keys;
+  if (N >= (1ull << 32)) fail(TC_E_INVAL, "radix_sort: more than 2^32 - 1 keys");
+  constexpr int TILE = kSortBlock * RadixItems<K>::value;
+  const uint32_t tiles = static_cast<uint32_t>((N + TILE - 1) / TILE);
+  DevBuf<uint32_t> hist(static_cast<size_t>(256) * tiles, s);
+  K* a = keys;
+  K* b = tmp;
+  for (int shift = bit_lo; shift < bit_hi; shift += 8) {
+    k_radix_hist<K><<<tiles, kSortBlock, 0, s>>>(a, static_cast<uint32_t>(N), shift, hist.get(), tiles);
+    TC_LAUNCH_CHECK();
+    exclusive_scan<uint32_t>(hist.get(), hist.get(), static_cast<size_t>(256) * tiles, s);
+    k_radix_scatter<K><<<tiles, kSortBlock, 0, s>>>(a, b, static_cast<uint32_t>(N), shift, hist.get(), tiles);
+    TC_LAUNCH_CHECK();
+    K* t = a;
+    a = b;
+    b = t;
+  }
+  return a;
+}
+
+}  // namespace tc

@@ -1,0 +1,248 @@
+"""ctypes binding of the C ABI in include/tc.h (argument marshalling only).
+
+Every operation runs in the HIP kernels of ``libtc.so``; PyTorch only supplies
+device memory and the current HIP stream. There is no CPU fallback: if the
+library is missing or no GPU is present, the calls raise.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional, Tuple
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libtc.so")
+
+TC_OK, TC_E_INVAL, TC_E_NOMEM, TC_E_DEVICE, TC_E_RANGE, TC_E_TRUNC = 0, -1, -2, -3, -4, -5
+TC_IN_DEVICE = 1
+OPT_KERNEL, OPT_HUB_DHAT, OPT_ITEM_WORK, OPT_BLOCKS_PER_CU = 0, 1, 2, 3
+
+# (name, argtypes, restype) for every symbol include/tc.h declares
+_vp, _i32, _i64, _u32, _u64, _dbl = (ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_uint32,
+                                      ctypes.c_uint64, ctypes.c_double)
+_P = ctypes.POINTER
+SIGNATURES = {
+    "tc_build_csr": ([_vp, _vp, _i64, _i32, _u32, _vp, _P(_vp)], ctypes.c_int),
+    "tc_graph_info": ([_vp, _P(_i32), _P(_i64), _P(_i32), _P(_i32)], ctypes.c_int),
+    "tc_graph_free": ([_vp], None),
+    "tc_count": ([_vp, _vp, _P(_u64)], ctypes.c_int),
+    "tc_count_per_node": ([_vp, _vp, _P(_u64), _vp], ctypes.c_int),
+    "tc_clustering": ([_vp, _vp, _vp, _vp, _vp], ctypes.c_int),
+    "tc_list": ([_vp, _vp, _vp, _i64, _P(_i64)], ctypes.c_int),
+    "tc_sparsify_count": ([_vp, _dbl, _u64, _vp, _P(_u64), _P(_i64), _P(_dbl)], ctypes.c_int),
+    "tc_count_plain": ([_vp, _vp, _P(_u64)], ctypes.c_int),
+    "tc_graph_work": ([_vp, _vp, _P(_u64), _P(_u64)], ctypes.c_int),
+    "tc_graph_degrees": ([_vp, _vp, _vp, _vp], ctypes.c_int),
+    "tc_graph_oriented": ([_vp, _vp, _vp, _vp], ctypes.c_int),
+    "tc_set_option": ([ctypes.c_int, _i64], ctypes.c_int),
+    "tc_get_option": ([ctypes.c_int], _i64),
+    "tc_batch_build": ([_vp, _vp, _vp, _vp, _i32, _u32, _vp, _P(_vp)], ctypes.c_int),
+    "tc_batch_size": ([_vp, _P(_i32)], ctypes.c_int),
+    "tc_batch_count": ([_vp, _vp, _vp, _vp], ctypes.c_int),
+    "tc_status_str": ([ctypes.c_int], ctypes.c_char_p),
+    "tc_last_error": ([], ctypes.c_char_p),
+}
+
+_lib = None
+
+
+class TCError(RuntimeError):
+    def __init__(self, status: int, where: str, msg: str):
+        super().__init__(f"{where}: {msg} (status {status})")
+        self.status = status
+
+
+def lib():
+    """Load libtc.so once; raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with __graft_entry__.build() "
+                          "or python paper_1706_05151_amd/build_lib.py")
+    L = ctypes.CDLL(LIB_PATH)
+    for name, (args, res) in SIGNATURES.items():
+        f = getattr(L, name)
+        f.argtypes = args
+        f.restype = res
+    _lib = L
+    return L
+
+
+def _check(st: int, where: str):
+    if st != TC_OK:
+        L = lib()
+        raise TCError(st, where, (L.tc_last_error() or b"").decode() or L.tc_status_str(st).decode())
+
+
+def _torch():
+    import torch
+
+    if not torch.cuda.is_available():
+        raise RuntimeError("no HIP device visible: the triangle-counting library runs on the GPU only")
+    return torch
+
+
+def _stream(stream) -> ctypes.c_void_p:
+    torch = _torch()
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def _dptr(t) -> ctypes.c_void_p:
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def set_option(key: int, value: int):
+    _check(lib().tc_set_option(key, int(value)), "tc_set_option")
+
+
+def get_option(key: int) -> int:
+    return int(lib().tc_get_option(key))
+
+
+class Graph:
+    """A device graph built by tc_build_csr / tc_batch_build (freed on close/del)."""
+
+    def __init__(self, handle: ctypes.c_void_p, device: int):
+        self._h = handle
+        self.device = device
+        n, m, dmax, dhmax = _i32(), _i64(), _i32(), _i32()
+        _check(lib().tc_graph_info(self._h, ctypes.byref(n), ctypes.byref(m), ctypes.byref(dmax), ctypes.byref(dhmax)),
+               "tc_graph_info")
+        self.n, self.m, self.d_max, self.dhat_max = n.value, m.value, dmax.value, dhmax.value
+        ng = _i32()
+        _check(lib().tc_batch_size(self._h, ctypes.byref(ng)), "tc_batch_size")
+        self.num_graphs = ng.value
+
+    # ------------------------------------------------------------ builders
+    @classmethod
+    def build(cls, src, dst, n: int, stream=None) -> "Graph":
+        """src/dst: int32 device tensors, or host numpy arrays (copied by the library)."""
+        torch = _torch()
+        h = _vp()
+        if isinstance(src, np.ndarray):
+            s = np.ascontiguousarray(src, dtype=np.int32)
+            d = np.ascontiguousarray(dst, dtype=np.int32)
+            st = lib().tc_build_csr(s.ctypes.data_as(_vp), d.ctypes.data_as(_vp), s.shape[0], int(n), 0,
+                                    _stream(stream), ctypes.byref(h))
+        else:
+            assert src.dtype == torch.int32 and dst.dtype == torch.int32 and src.is_cuda
+            s, d = src.contiguous(), dst.contiguous()
+            st = lib().tc_build_csr(_dptr(s), _dptr(d), s.numel(), int(n), TC_IN_DEVICE, _stream(stream),
+                                    ctypes.byref(h))
+        _check(st, "tc_build_csr")
+        return cls(h, torch.cuda.current_device())
+
+    @classmethod
+    def build_batch(cls, src, dst, edge_off: np.ndarray, n_per_graph: np.ndarray, stream=None) -> "Graph":
+        """Disjoint union of many graphs; ids in src/dst are local to each graph."""
+        torch = _torch()
+        h = _vp()
+        eo = np.ascontiguousarray(edge_off, dtype=np.int64)
+        npg = np.ascontiguousarray(n_per_graph, dtype=np.int32)
+        if isinstance(src, np.ndarray):
+            s = np.ascontiguousarray(src, dtype=np.int32)
+            d = np.ascontiguousarray(dst, dtype=np.int32)
+            st = lib().tc_batch_build(s.ctypes.data_as(_vp), d.ctypes.data_as(_vp), eo.ctypes.data_as(_vp),
+                                      npg.ctypes.data_as(_vp), npg.shape[0], 0, _stream(stream), ctypes.byref(h))
+        else:
+            s, d = src.contiguous(), dst.contiguous()
+            st = lib().tc_batch_build(_dptr(s), _dptr(d), eo.ctypes.data_as(_vp), npg.ctypes.data_as(_vp),
+                                      npg.shape[0], TC_IN_DEVICE, _stream(stream), ctypes.byref(h))
+        _check(st, "tc_batch_build")
+        return cls(h, torch.cuda.current_device())
+
+    # ------------------------------------------------------------- queries
+    def count(self, stream=None) -> int:
+        T = _u64()
+        _check(lib().tc_count(self._h, _stream(stream), ctypes.byref(T)), "tc_count")
+        return T.value
+
+    def count_plain(self, stream=None) -> int:
+        T = _u64()
+        _check(lib().tc_count_plain(self._h, _stream(stream), ctypes.byref(T)), "tc_count_plain")
+        return T.value
+
+    def count_per_node(self, out=None, stream=None) -> Tuple[int, "object"]:
+        torch = _torch()
+        t = out if out is not None else torch.empty(max(self.n, 1), dtype=torch.int64, device="cuda")
+        T = _u64()
+        _check(lib().tc_count_per_node(self._h, _stream(stream), ctypes.byref(T), _dptr(t)), "tc_count_per_node")
+        return T.value, t[: self.n]
+
+    def clustering(self, stream=None):
+        torch = _torch()
+        k = max(self.n, 1)
+        num = torch.empty(k, dtype=torch.int64, device="cuda")
+        den = torch.empty(k, dtype=torch.int64, device="cuda")
+        c = torch.empty(k, dtype=torch.float64, device="cuda")
+        _check(lib().tc_clustering(self._h, _stream(stream), _dptr(num), _dptr(den), _dptr(c)), "tc_clustering")
+        return num[: self.n], den[: self.n], c[: self.n]
+
+    def list_size(self, stream=None) -> int:
+        cnt = _i64()
+        _check(lib().tc_list(self._h, _stream(stream), None, 0, ctypes.byref(cnt)), "tc_list")
+        return cnt.value
+
+    def list(self, cap: Optional[int] = None, stream=None):
+        torch = _torch()
+        if cap is None:
+            cap = self.list_size(stream)
+        tri = torch.empty((max(cap, 1), 3), dtype=torch.int32, device="cuda")
+        cnt = _i64()
+        st = lib().tc_list(self._h, _stream(stream), _dptr(tri), int(cap), ctypes.byref(cnt))
+        _check(st, "tc_list")
+        return tri[: cnt.value]
+
+    def sparsify_count(self, q: float, seed: int, stream=None):
+        Ts, mk, est = _u64(), _i64(), _dbl()
+        _check(lib().tc_sparsify_count(self._h, float(q), int(seed) & (2 ** 64 - 1), _stream(stream), ctypes.byref(Ts),
+                                       ctypes.byref(mk), ctypes.byref(est)), "tc_sparsify_count")
+        return Ts.value, mk.value, est.value
+
+    def work(self, stream=None) -> Tuple[int, int]:
+        W, P = _u64(), _u64()
+        _check(lib().tc_graph_work(self._h, _stream(stream), ctypes.byref(W), ctypes.byref(P)), "tc_graph_work")
+        return W.value, P.value
+
+    def degrees(self, stream=None):
+        torch = _torch()
+        k = max(self.n, 1)
+        deg = torch.empty(k, dtype=torch.int32, device="cuda")
+        dhat = torch.empty(k, dtype=torch.int32, device="cuda")
+        _check(lib().tc_graph_degrees(self._h, _stream(stream), _dptr(deg), _dptr(dhat)), "tc_graph_degrees")
+        return deg[: self.n], dhat[: self.n]
+
+    def oriented(self, stream=None):
+        torch = _torch()
+        off = torch.empty(self.n + 1, dtype=torch.int64, device="cuda")
+        adj = torch.empty(max(self.m, 1), dtype=torch.int32, device="cuda")
+        _check(lib().tc_graph_oriented(self._h, _stream(stream), _dptr(off), _dptr(adj)), "tc_graph_oriented")
+        return off, adj[: self.m]
+
+    def batch_count(self, T_out, t_out=None, stream=None):
+        """Per-graph totals (int64[num_graphs]) and optional per-node counts; no host sync."""
+        _check(lib().tc_batch_count(self._h, _stream(stream), _dptr(T_out), _dptr(t_out) if t_out is not None else None),
+               "tc_batch_count")
+
+    # ----------------------------------------------------------- lifetime
+    def close(self):
+        if self._h is not None and self._h.value:
+            lib().tc_graph_free(self._h)
+        self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()

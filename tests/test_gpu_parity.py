@@ -1,0 +1,269 @@
+"""GPU parity: every output of the HIP library against the CPU oracle, element by element.
+
+Integer results (T, t_v, m', T_s, lists, orientation) must be bit-exact; the
+clustering doubles are compared bit for bit as well, beside the exact rationals.
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def tc():
+    import torch
+
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    import paper_1706_05151_amd.tc as tcm
+
+    tcm.lib()
+    for k, v in ((tcm.OPT_KERNEL, 0), (tcm.OPT_HUB_DHAT, 128), (tcm.OPT_ITEM_WORK, 4096), (tcm.OPT_BLOCKS_PER_CU, 8)):
+        tcm.set_option(k, v)
+    yield tcm
+    for k, v in ((tcm.OPT_KERNEL, 0), (tcm.OPT_HUB_DHAT, 128), (tcm.OPT_ITEM_WORK, 4096), (tcm.OPT_BLOCKS_PER_CU, 8)):
+        tcm.set_option(k, v)
+
+
+def to_dev(el):
+    import torch
+
+    return (torch.from_numpy(np.ascontiguousarray(el.src)).cuda(), torch.from_numpy(np.ascontiguousarray(el.dst)).cuda())
+
+
+def u64(t):
+    return t.cpu().numpy().astype(np.uint64)
+
+
+def check_all(tc, el, listing=True, label=""):
+    """Build on the GPU and compare every output with the oracle."""
+    say(f"[parity] {label or el.name}: n={el.n} E={el.num_edges}")
+    ref = oracle.solve(el.src, el.dst, el.n, per_node=True, listing=listing)
+    s, d = to_dev(el)
+    with tc.Graph.build(s, d, el.n) as g:
+        assert g.n == el.n and g.m == ref.m
+        assert g.d_max == (int(ref.deg.max()) if el.n else 0)
+        assert g.dhat_max == (int(np.diff(ref.off).max()) if el.n else 0)
+        assert g.count() == ref.T
+        assert g.count_plain() == ref.T
+        T, t = g.count_per_node()
+        assert T == ref.T
+        np.testing.assert_array_equal(u64(t), ref.t)
+        num, den, c = g.clustering()
+        np.testing.assert_array_equal(u64(num), ref.num)
+        np.testing.assert_array_equal(u64(den), ref.den)
+        np.testing.assert_array_equal(c.cpu().numpy().view(np.uint64), ref.cc.view(np.uint64))
+        if listing:
+            tri = g.list()
+            np.testing.assert_array_equal(tri.cpu().numpy(), ref.tri)
+        deg, dhat = g.degrees()
+        np.testing.assert_array_equal(deg.cpu().numpy(), ref.deg.astype(np.int32))
+        np.testing.assert_array_equal(dhat.cpu().numpy(), np.diff(ref.off).astype(np.int32))
+        off, adj = g.oriented()
+        np.testing.assert_array_equal(off.cpu().numpy(), ref.off)
+        np.testing.assert_array_equal(adj.cpu().numpy(), ref.adj)
+        W, P = g.work()
+        assert W == oracle.work(ref.off, ref.adj, el.n)
+        dh = np.diff(ref.off).astype(np.int64)
+        assert P == int((dh * (dh - 1) // 2).sum())
+    return ref
+
+
+CLOSED = [synth.complete(3), synth.complete(4), synth.complete(30), synth.wheel(4), synth.wheel(3), synth.wheel(200),
+          synth.star(300), synth.path(50), synth.cycle(3), synth.cycle(64), synth.complete_bipartite(20, 30),
+          synth.hypercube(8), synth.grid(20, 30), synth.random_tree(1000, 5), synth.complete_tripartite(10, 12, 14),
+          synth.friendship(100), synth.empty(5), synth.empty(0), synth.complete(2)]
+
+
+@pytest.mark.parametrize("el", CLOSED, ids=[g.name for g in CLOSED])
+def test_closed_forms(tc, el):
+    check_all(tc, el)
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_random_messy(tc, seed):
+    rng = np.random.default_rng(seed)
+    n = int(rng.integers(2, 3000))
+    m = int(rng.integers(0, 20 * n))
+    src = rng.integers(0, n, m).astype(np.int32)
+    dst = rng.integers(0, n, m).astype(np.int32)
+    k = m // 3
+    src = np.concatenate([src, dst[:k], np.arange(min(n, 7), dtype=np.int32)])
+    dst = np.concatenate([dst, src[:k], np.arange(min(n, 7), dtype=np.int32)])
+    check_all(tc, synth.EdgeList(n, src, dst, f"messy{seed}"))
+
+
+@pytest.mark.parametrize("spec", ["er", "ba", "rmat13", "rmat15"])
+def test_families(tc, spec):
+    el = {"er": lambda: synth.er(20000, 0.002, 3), "ba": lambda: synth.ba(50000, 6, 4),
+          "rmat13": lambda: synth.rmat(13, 16, 5), "rmat15": lambda: synth.rmat(15, 16, 6)}[spec]()
+    check_all(tc, el, listing=True)
+
+
+@pytest.mark.parametrize("hub,iw", [(0, 64), (0, 4096), (16, 64), (256, 100000), (64, 512)])
+def test_partitioner_settings_identical(tc, hub, iw):
+    """Every bucket threshold and work-item size gives the same exact results."""
+    el = synth.rmat(14, 16, 9)
+    ref = oracle.solve(el.src, el.dst, el.n, per_node=True, listing=True)
+    tc.set_option(tc.OPT_HUB_DHAT, hub)
+    tc.set_option(tc.OPT_ITEM_WORK, iw)
+    try:
+        s, d = to_dev(el)
+        with tc.Graph.build(s, d, el.n) as g:
+            say(f"[parity] partitioner hub={hub} iw={iw}")
+            assert g.count() == ref.T
+            T, t = g.count_per_node()
+            np.testing.assert_array_equal(u64(t), ref.t)
+            np.testing.assert_array_equal(g.list().cpu().numpy(), ref.tri)
+    finally:
+        tc.set_option(tc.OPT_HUB_DHAT, 128)
+        tc.set_option(tc.OPT_ITEM_WORK, 4096)
+
+
+def test_host_and_device_inputs_agree(tc):
+    el = synth.ba(30000, 5, 7)
+    s, d = to_dev(el)
+    with tc.Graph.build(s, d, el.n) as g1, tc.Graph.build(el.src, el.dst, el.n) as g2:
+        assert g1.count() == g2.count()
+        np.testing.assert_array_equal(u64(g1.count_per_node()[1]), u64(g2.count_per_node()[1]))
+
+
+def test_repeatable(tc):
+    el = synth.rmat(15, 16, 11)
+    s, d = to_dev(el)
+    with tc.Graph.build(s, d, el.n) as g:
+        T0, t0 = g.count_per_node()
+        t0 = u64(t0)
+        for _ in range(3):
+            assert g.count() == T0
+            T, t = g.count_per_node()
+            np.testing.assert_array_equal(u64(t), t0)
+
+
+# -------------------------------------------------------------- sparsify ---
+
+@pytest.mark.parametrize("q,seed", [(0.1, 3), (0.5, 3), (0.2, 5), (1.0, 1), (0.37, 123456789)])
+def test_sparsify_matches_oracle(tc, q, seed):
+    el = synth.rmat(15, 16, 12)
+    lo, hi = oracle.simple(el.src, el.dst, el.n)
+    deg = oracle.degrees(lo, hi, el.n)
+    Ts, mk, est = oracle.sparsified_count(lo, hi, deg, el.n, q, seed)
+    s, d = to_dev(el)
+    with tc.Graph.build(s, d, el.n) as g:
+        say(f"[parity] sparsify q={q} seed={seed}")
+        gTs, gmk, gest = g.sparsify_count(q, seed)
+        assert (gTs, gmk) == (Ts, mk)
+        assert gest == est
+
+
+def test_sparsify_relabelled_ids_follow_caller_ids(tc):
+    """The sample is a function of the caller's ids, not of the internal ranks."""
+    el = synth.ba(20000, 6, 13)
+    lo, hi = oracle.simple(el.src, el.dst, el.n)
+    deg = oracle.degrees(lo, hi, el.n)
+    klo, khi = oracle.sparsify(lo, hi, 0.3, 99)
+    s, d = to_dev(el)
+    with tc.Graph.build(s, d, el.n) as g:
+        _, mk, _ = g.sparsify_count(0.3, 99)
+        assert mk == klo.shape[0]
+        Ts_ref, _, _ = oracle.count_nin(*oracle.orient(klo, khi, deg, el.n), el.n)
+        assert g.sparsify_count(0.3, 99)[0] == Ts_ref
+
+
+# ----------------------------------------------------------------- errors ---
+
+def test_errors(tc):
+    import torch
+
+    s = torch.tensor([0, 1, 5], dtype=torch.int32, device="cuda")
+    d = torch.tensor([1, 2, 0], dtype=torch.int32, device="cuda")
+    with pytest.raises(tc.TCError) as e:
+        tc.Graph.build(s, d, 5)
+    assert e.value.status == tc.TC_E_RANGE
+    s = torch.tensor([0, -1], dtype=torch.int32, device="cuda")
+    d = torch.tensor([1, 2], dtype=torch.int32, device="cuda")
+    with pytest.raises(tc.TCError) as e:
+        tc.Graph.build(s, d, 5)
+    assert e.value.status == tc.TC_E_RANGE
+    el = synth.complete(6)
+    with tc.Graph.build(*to_dev(el), el.n) as g:
+        with pytest.raises(tc.TCError) as e:
+            g.sparsify_count(0.0, 1)
+        assert e.value.status == tc.TC_E_RANGE
+        with pytest.raises(tc.TCError) as e:
+            g.sparsify_count(1.5, 1)
+        assert e.value.status == tc.TC_E_RANGE
+        assert g.list_size() == 20
+        with pytest.raises(tc.TCError) as e:
+            g.list(cap=5)
+        assert e.value.status == tc.TC_E_TRUNC
+        assert g.list(cap=20).shape == (20, 3)
+    with pytest.raises(tc.TCError):
+        tc.set_option(tc.OPT_KERNEL, 7)
+
+
+# ---------------------------------------------------------------- batches ---
+
+def _mixed_batch(count, seed):
+    specs = synth.batch_specs(count, seed)
+    els = [sp.make() for sp in specs]
+    return els
+
+
+def test_batch_matches_standalone(tc):
+    import torch
+
+    els = _mixed_batch(40, 77)
+    els += [synth.empty(5), synth.complete(12), synth.wheel(9)]
+    src = np.concatenate([e.src for e in els])
+    dst = np.concatenate([e.dst for e in els])
+    eoff = np.zeros(len(els) + 1, np.int64)
+    eoff[1:] = np.cumsum([e.num_edges for e in els])
+    npg = np.array([e.n for e in els], np.int32)
+    s, d = torch.from_numpy(src).cuda(), torch.from_numpy(dst).cuda()
+    with tc.Graph.build_batch(s, d, eoff, npg) as g:
+        assert g.num_graphs == len(els)
+        T = torch.zeros(len(els), dtype=torch.int64, device="cuda")
+        t = torch.zeros(int(npg.sum()), dtype=torch.int64, device="cuda")
+        g.batch_count(T, t)
+        torch.cuda.synchronize()
+        T = T.cpu().numpy()
+        t = u64(t)
+        base = 0
+        for i, e in enumerate(els):
+            ref = oracle.solve(e.src, e.dst, e.n)
+            assert T[i] == ref.T, (i, e.name)
+            np.testing.assert_array_equal(t[base:base + e.n], ref.t)
+            base += e.n
+        assert g.count() == int(T.sum())
+
+
+def test_batch_range_error(tc):
+    import torch
+
+    src = np.array([0, 1, 0, 2], np.int32)
+    dst = np.array([1, 2, 1, 3], np.int32)  # graph 1 has 3 vertices: id 3 is out of range
+    with pytest.raises(tc.TCError) as e:
+        tc.Graph.build_batch(src, dst, np.array([0, 2, 4]), np.array([3, 3]))
+    assert e.value.status == tc.TC_E_RANGE
+
+
+# ---------------------------------------------------------- config sizes ---
+
+def test_config_er10k(tc):
+    check_all(tc, synth.config_er10k(), listing=True, label="ER G(10^4, 0.0016) seed 1")
+
+
+def test_config_ba22(tc):
+    """PA n=2^22, 8 edges per new node, seed 2: T, t_v, clustering and the sorted list."""
+    check_all(tc, synth.config_ba22(), listing=True, label="BA n=2^22 k=8 seed 2")
