@@ -146,17 +146,21 @@ tc_status tc_graph_oriented(tc_graph* g, void* stream, int64_t* off_dev, int32_t
 
 /*
  * Tuning options (process-wide; read at the start of each call).
- *   TC_OPT_KERNEL        : 0 auto, 1 plain merge, 2 pivot-staged (see DESIGN)
+ *   TC_OPT_KERNEL        : 0 auto, 1 plain merge, 2 pivot-staged
  *   TC_OPT_HUB_DHAT      : lists longer than this use the block-per-pivot path
  *   TC_OPT_ITEM_WORK     : target probes per work item of the partitioner
- *   TC_OPT_BLOCKS_PER_CU : occupancy hint for the persistent launch
- * Returns TC_E_INVAL for an unknown key or a negative value.
+ *   TC_OPT_BLOCKS_PER_CU : blocks per compute unit of the persistent launch
+ *   TC_OPT_HUB_BUCKET_LOAD : target list entries per 4-slot LDS hash bucket
+ *                          of the block path (1 or 2)
+ * Options change speed only, never results. Returns TC_E_INVAL for an
+ * unknown key or an out-of-range value.
  */
 typedef enum tc_option {
   TC_OPT_KERNEL = 0,
   TC_OPT_HUB_DHAT = 1,
   TC_OPT_ITEM_WORK = 2,
-  TC_OPT_BLOCKS_PER_CU = 3
+  TC_OPT_BLOCKS_PER_CU = 3,
+  TC_OPT_HUB_BUCKET_LOAD = 4
 } tc_option;
 tc_status tc_set_option(tc_option key, int64_t value);
 int64_t tc_get_option(tc_option key);

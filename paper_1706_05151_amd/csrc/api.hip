@@ -14,7 +14,7 @@ namespace tc {
 namespace {
 
 thread_local std::string g_last_error;
-std::atomic<int64_t> g_opt_kernel{0}, g_opt_hub{128}, g_opt_iw{4096}, g_opt_bpc{8};
+std::atomic<int64_t> g_opt_kernel{0}, g_opt_hub{128}, g_opt_iw{16384}, g_opt_bpc{4}, g_opt_load{2};
 
 template <typename F>
 tc_status guarded(F&& f) {
@@ -131,6 +131,7 @@ Options get_options() {
   o.hub_dhat = g_opt_hub.load();
   o.item_work = g_opt_iw.load();
   o.blocks_per_cu = g_opt_bpc.load();
+  o.hub_bucket_load = g_opt_load.load();
   return o;
 }
 
@@ -410,6 +411,10 @@ tc_status tc_set_option(tc_option key, int64_t value) {
         require(value >= 1, TC_E_INVAL, "blocks per CU must be >= 1");
         g_opt_bpc = value;
         break;
+      case TC_OPT_HUB_BUCKET_LOAD:
+        require(value == 1 || value == 2, TC_E_INVAL, "bucket load must be 1 or 2");
+        g_opt_load = value;
+        break;
       default: fail(TC_E_INVAL, "unknown option");
     }
   });
@@ -421,6 +426,7 @@ int64_t tc_get_option(tc_option key) {
     case TC_OPT_HUB_DHAT: return g_opt_hub.load();
     case TC_OPT_ITEM_WORK: return g_opt_iw.load();
     case TC_OPT_BLOCKS_PER_CU: return g_opt_bpc.load();
+    case TC_OPT_HUB_BUCKET_LOAD: return g_opt_load.load();
     default: return -1;
   }
 }

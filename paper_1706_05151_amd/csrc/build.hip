@@ -137,13 +137,18 @@ __global__ void k_csr_fill(const uint64_t* __restrict__ ok, uint64_t m, int b, i
   }
 }
 
-// off[r] = first entry whose row is >= r, for sorted rows `row` of length m.
+// off[r] = first entry whose row is >= r, for sorted rows `row` of length m
+// (one binary search per row, so long runs of empty rows cost nothing extra).
 __global__ void k_offsets_from_rows(const int32_t* __restrict__ row, uint64_t m, int32_t n, int64_t* __restrict__ off) {
-  for (uint64_t i = static_cast<uint64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i <= m;
-       i += static_cast<uint64_t>(gridDim.x) * blockDim.x) {
-    const int64_t cur = i < m ? row[i] : n;
-    const int64_t prev = i > 0 ? row[i - 1] : -1;
-    for (int64_t r = prev + 1; r <= cur; r++) off[r] = static_cast<int64_t>(i);
+  for (int64_t r = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; r <= n;
+       r += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+    uint64_t lo = 0, hi = m;
+    while (lo < hi) {
+      const uint64_t mid = (lo + hi) >> 1;
+      if (row[mid] < r) lo = mid + 1;
+      else hi = mid;
+    }
+    off[r] = static_cast<int64_t>(lo);
   }
 }
 
@@ -167,7 +172,7 @@ __global__ void k_array_max(const int32_t* __restrict__ a, int32_t n, int* __res
 }  // namespace
 
 void offsets_from_rows(const int32_t* row, uint64_t m, int32_t n, int64_t* off, hipStream_t s) {
-  k_offsets_from_rows<<<grid_for(m + 1, kBlock, 65536), kBlock, 0, s>>>(row, m, n, off);
+  k_offsets_from_rows<<<grid_for(static_cast<uint64_t>(n) + 1, kBlock, 65536), kBlock, 0, s>>>(row, m, n, off);
   TC_LAUNCH_CHECK();
 }
 

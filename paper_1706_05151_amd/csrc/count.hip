@@ -27,7 +27,8 @@ namespace tc {
 namespace {
 
 constexpr int kBlock = 256;
-constexpr int kWavesPerBlock = kBlock / kWave;
+constexpr int kPivotBlock = 512;  // threads of a pivot-kernel block (hub items are staged once per 8 waves)
+constexpr int kPivotWaves = kPivotBlock / kWave;
 constexpr int32_t kEmpty = -1;
 constexpr int kWaveSlots = 512;          // hash slots per wave (lists up to 256 entries)
 constexpr int kCostPerRecord = 4;        // fixed probe-equivalents per in-edge record
@@ -195,34 +196,45 @@ __device__ __forceinline__ void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-__device__ __forceinline__ uint32_t slot_of(int32_t x, int log2s) {
-  return (static_cast<uint32_t>(x) * 0x9E3779B1u) >> (32 - log2s);
+// Bucketed hash set in LDS: 2^log2b buckets of 4 int32 slots. A bucket's
+// slots fill in order and a full bucket spills into the next one, so a lookup
+// reads one 16-byte bucket and stops there unless that bucket is full.
+__device__ __forceinline__ uint32_t bucket_of(int32_t x, int log2b) {
+  return (static_cast<uint32_t>(x) * 0x9E3779B1u) >> (32 - log2b);
 }
 
-__device__ __forceinline__ void hash_insert(int32_t* H, int log2s, int32_t x) {
-  const uint32_t mask = (1u << log2s) - 1u;
-  uint32_t h = slot_of(x, log2s);
-  while (atomicCAS(&H[h], kEmpty, x) != kEmpty) h = (h + 1u) & mask;
-}
-
-__device__ __forceinline__ int hash_find(const int32_t* H, int log2s, int32_t x) {
-  const uint32_t mask = (1u << log2s) - 1u;
-  uint32_t h = slot_of(x, log2s);
+__device__ __forceinline__ void bt_insert(int32_t* T, int log2b, int32_t x) {
+  const uint32_t mask = (1u << log2b) - 1u;
+  uint32_t b = bucket_of(x, log2b);
   for (;;) {
-    const int32_t y = H[h];
-    if (y == x) return static_cast<int>(h);
-    if (y == kEmpty) return -1;
-    h = (h + 1u) & mask;
+#pragma unroll
+    for (int i = 0; i < 4; i++)
+      if (atomicCAS(&T[4 * b + i], kEmpty, x) == kEmpty) return;
+    b = (b + 1u) & mask;
   }
 }
 
-__device__ __forceinline__ int log2_slots(int64_t len, int min_log2) {
-  int l = min_log2;
-  while ((1ll << l) < 2 * len) l++;
+// Slot index of x, or -1.
+__device__ __forceinline__ int bt_find(const int32_t* T, int log2b, int32_t x) {
+  const uint32_t mask = (1u << log2b) - 1u;
+  uint32_t b = bucket_of(x, log2b);
+  for (;;) {
+    const int4 q = *reinterpret_cast<const int4*>(T + 4 * b);
+    const int s = q.x == x ? 0 : q.y == x ? 1 : q.z == x ? 2 : q.w == x ? 3 : -1;
+    if (s >= 0) return static_cast<int>(4 * b) + s;
+    if (q.w == kEmpty) return -1;
+    b = (b + 1u) & mask;
+  }
+}
+
+__device__ __forceinline__ int log2_buckets(int64_t len, int load = 1) {
+  int l = 4;
+  while ((1ll << l) * load < len) l++;
   return l;
 }
 
 struct KernelArgs {
+  int bucket_load;  // target entries per 4-slot bucket of a hub table (1 or 2)
   const int64_t* off;
   const int32_t* adj;
   const int32_t* src;
@@ -252,132 +264,201 @@ __device__ __forceinline__ void emit_triangle(const KernelArgs& a, int32_t v, in
   }
 }
 
-// Probe the in-edge records [r0, r1) (at most 64) of pivot u against the
-// staged table. Lanes walk the concatenated suffixes A of the records; each
-// finds its record by binary search over the exclusive prefix in `pre`.
-// Returns this lane's hits.
-__device__ __forceinline__ uint32_t probe_batch(const KernelArgs& a, int32_t u, uint32_t r0, uint32_t r1,
-                                                const int32_t* H, int log2s, uint32_t* C, uint32_t* pre,
-                                                uint32_t* beg, uint32_t* hits) {
+// ------------------------------------------------------------- probing ---
+//
+// A batch of in-edge records (one per thread) is split in two:
+//   long records (suffix >= kLongMin): cut into segments of kSeg elements; a
+//     whole wave takes one segment, lane L reading elements L, L+64, ... so the
+//     loads are coalesced, up to four are in flight per lane, and the owning
+//     record is found once per segment;
+//   short records: their elements are concatenated and each lane takes
+//     kPerLane consecutive ones, finding the owner by binary search.
+
+constexpr int kPerLane = 4;
+constexpr uint32_t kLongMin = 64;
+constexpr uint32_t kSeg = kWave * kPerLane;
+
+// Record arrays of one batch of NR records (NR = 256 for a block, 64 for a wave).
+template <int NR>
+struct BatchLds {
+  uint32_t segpre[NR + 1];  // exclusive prefix of segment counts (long records)
+  uint32_t spre[NR + 1];    // exclusive prefix of lengths (short records)
+  uint32_t beg[NR];
+  uint32_t len[NR];
+  uint32_t hits[NR];        // per-node mode: hits of each record
+};
+
+// Probe one element against the table; counts, per-node tallies and listing.
+__device__ __forceinline__ uint32_t probe_one(const KernelArgs& a, int32_t u, int32_t x, const int32_t* T, int log2b,
+                                              uint32_t* C, uint32_t* hit_rec, uint32_t rec_begin) {
+  const int s = bt_find(T, log2b, x);
+  if (s < 0) return 0u;
+  if (a.mode == kCountPerNode) {
+    atomicAdd(&C[s], 1u);
+    atomicAdd(hit_rec, 1u);
+  } else if (a.mode == kCountList) {
+    emit_triangle(a, a.src[rec_begin - 1], u, x);
+  }
+  return 1u;
+}
+
+// Segments [seg0, nsegs) step `stride` of the long records, one wave per segment.
+template <int NR>
+__device__ __forceinline__ uint32_t probe_long(const KernelArgs& a, int32_t u, const BatchLds<NR>& B, uint32_t nsegs,
+                                               uint32_t seg0, uint32_t stride, const int32_t* T, int log2b,
+                                               uint32_t* C, uint32_t* hits) {
+  const int lane = lane_id();
+  uint32_t cnt = 0;
+  for (uint32_t sg = seg0; sg < nsegs; sg += stride) {
+    int j = 0;
+#pragma unroll
+    for (int step = NR / 2; step > 0; step >>= 1)
+      if (B.segpre[j + step] <= sg) j += step;
+    j = __builtin_amdgcn_readfirstlane(j);
+    const uint32_t rel = (sg - B.segpre[j]) * kSeg;
+    const uint32_t base = __builtin_amdgcn_readfirstlane(B.beg[j] + rel);
+    const uint32_t rem = __builtin_amdgcn_readfirstlane(B.len[j] - rel);
+    int32_t x[kPerLane];
+#pragma unroll
+    for (int i = 0; i < kPerLane; i++) {
+      const uint32_t k = static_cast<uint32_t>(lane + kWave * i);
+      x[i] = (static_cast<uint32_t>(kWave * i) < rem && k < rem) ? a.adj[base + k] : kEmpty;
+    }
+    uint32_t h = 0;
+#pragma unroll
+    for (int i = 0; i < kPerLane; i++)
+      if (x[i] != kEmpty) h += probe_one(a, u, x[i], T, log2b, C, &hits[j], B.beg[j]);
+    cnt += h;
+  }
+  return cnt;
+}
+
+// Concatenated short-record elements [k_first, tot) in windows of width*kPerLane,
+// this thread taking kPerLane consecutive ones at its slot `slot` of `width`.
+template <int NR>
+__device__ __forceinline__ uint32_t probe_short(const KernelArgs& a, int32_t u, const BatchLds<NR>& B, uint32_t tot,
+                                                int slot, int width, const int32_t* T, int log2b, uint32_t* C,
+                                                uint32_t* hits) {
+  uint32_t cnt = 0;
+  for (uint32_t k0 = 0; k0 < tot; k0 += static_cast<uint32_t>(width) * kPerLane) {
+    const uint32_t kb = k0 + static_cast<uint32_t>(slot) * kPerLane;
+    int j = 0;
+    if (kb < tot) {
+#pragma unroll
+      for (int step = NR / 2; step > 0; step >>= 1)
+        if (B.spre[j + step] <= kb) j += step;  // j + step <= NR - 1
+    }
+    int32_t x[kPerLane];
+    int jj[kPerLane];
+#pragma unroll
+    for (int i = 0; i < kPerLane; i++) {
+      const uint32_t k = kb + i;
+      jj[i] = -1;
+      x[i] = kEmpty;
+      if (k < tot) {
+        while (B.spre[j + 1] <= k) j++;  // stops at j = NR - 1 because spre[NR] = tot > k
+        jj[i] = j;
+        x[i] = a.adj[B.beg[j] + (k - B.spre[j])];
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < kPerLane; i++)
+      if (jj[i] >= 0) cnt += probe_one(a, u, x[i], T, log2b, C, &hits[jj[i]], B.beg[jj[i]]);
+  }
+  return cnt;
+}
+
+// Fill the batch arrays for the record this thread holds (idx in [0,NR)).
+template <int NR>
+__device__ __forceinline__ void batch_fill(const KernelArgs& a, BatchLds<NR>& B, int idx, const InRec& rc,
+                                           uint64_t excl, uint64_t tot) {
+  B.segpre[idx] = static_cast<uint32_t>(excl >> 32);
+  B.spre[idx] = static_cast<uint32_t>(excl);
+  B.beg[idx] = rc.a_begin;
+  B.len[idx] = rc.a_len;
+  if (a.mode != kCountTotal) B.hits[idx] = 0;
+  if (idx == NR - 1) {
+    B.segpre[NR] = static_cast<uint32_t>(tot >> 32);
+    B.spre[NR] = static_cast<uint32_t>(tot);
+  }
+}
+
+__device__ __forceinline__ uint64_t seg_short_pack(uint32_t len) {
+  const uint64_t nseg = len >= kLongMin ? (len + kSeg - 1) / kSeg : 0;
+  const uint64_t slen = len >= kLongMin ? 0 : len;
+  return (nseg << 32) | slen;
+}
+
+// Block-wide batch of up to kPivotBlock records for a hub item.
+__device__ __forceinline__ uint32_t probe_batch_block(const KernelArgs& a, int32_t u, uint32_t r0, uint32_t r1,
+                                                      const int32_t* T, int log2b, uint32_t* C, BatchLds<kPivotBlock>& B,
+                                                      uint64_t* scan_tmp) {
+  const int tid = threadIdx.x, w = tid / kWave;
+  const uint32_t r = r0 + tid;
+  const bool valid = r < r1;
+  InRec rc{0u, 0u};
+  if (valid) rc = a.rec[r];
+  uint64_t tot;
+  const uint64_t excl = block_excl_scan<uint64_t, kPivotBlock>(seg_short_pack(rc.a_len), scan_tmp, tot);
+  batch_fill<kPivotBlock>(a, B, tid, rc, excl, tot);
+  __syncthreads();
+  uint32_t cnt = probe_long<kPivotBlock>(a, u, B, static_cast<uint32_t>(tot >> 32), static_cast<uint32_t>(w),
+                                    kPivotWaves, T, log2b, C, B.hits);
+  cnt += probe_short<kPivotBlock>(a, u, B, static_cast<uint32_t>(tot), tid, kPivotBlock, T, log2b, C, B.hits);
+  __syncthreads();
+  if (a.mode == kCountPerNode && valid && B.hits[tid])
+    atomicAdd(&a.t_rank[a.src[rc.a_begin - 1]], static_cast<unsigned long long>(B.hits[tid]));
+  __syncthreads();
+  return cnt;
+}
+
+// Wave-wide batch of up to 64 records for a small pivot.
+__device__ __forceinline__ uint32_t probe_batch_wave(const KernelArgs& a, int32_t u, uint32_t r0, uint32_t r1,
+                                                     const int32_t* T, int log2b, uint32_t* C, BatchLds<kWave>& B) {
   const int lane = lane_id();
   const uint32_t r = r0 + lane;
   const bool valid = r < r1;
   InRec rc{0u, 0u};
   if (valid) rc = a.rec[r];
-  const uint32_t incl = wave_incl_scan(rc.a_len);
-  const uint32_t tot = __shfl(incl, kWave - 1, kWave);
-  pre[lane] = incl - rc.a_len;
-  beg[lane] = rc.a_begin;
-  if (a.mode != kCountTotal) hits[lane] = 0;
+  const uint64_t p = seg_short_pack(rc.a_len);
+  const uint64_t incl = wave_incl_scan(p);
+  const uint64_t tot = __shfl(incl, kWave - 1, kWave);
+  batch_fill<kWave>(a, B, lane, rc, incl - p, tot);
   wave_sync();
-  uint32_t cnt = 0;
-  for (uint32_t k = lane; k < tot; k += kWave) {
-    int j = 0;
-#pragma unroll
-    for (int step = 32; step > 0; step >>= 1)
-      if (pre[j + step] <= k) j += step;  // pre[64] is never read: j + step <= 63
-    const int32_t x = a.adj[beg[j] + (k - pre[j])];
-    const int s = hash_find(H, log2s, x);
-    if (s >= 0) {
-      cnt++;
-      if (a.mode == kCountPerNode) {
-        atomicAdd(&C[s], 1u);
-        atomicAdd(&hits[j], 1u);
-      } else if (a.mode == kCountList) {
-        emit_triangle(a, a.src[beg[j] - 1], u, x);
-      }
-    }
-  }
+  uint32_t cnt = probe_long<kWave>(a, u, B, static_cast<uint32_t>(tot >> 32), 0u, 1u, T, log2b, C, B.hits);
+  cnt += probe_short<kWave>(a, u, B, static_cast<uint32_t>(tot), lane, kWave, T, log2b, C, B.hits);
   if (a.mode == kCountPerNode) {
     wave_sync();
-    if (valid && hits[lane]) atomicAdd(&a.t_rank[a.src[rc.a_begin - 1]], static_cast<unsigned long long>(hits[lane]));
+    if (valid && B.hits[lane]) atomicAdd(&a.t_rank[a.src[rc.a_begin - 1]], static_cast<unsigned long long>(B.hits[lane]));
   }
   wave_sync();
   return cnt;
 }
 
-// -------------------------------------------------------- block kernel ---
-
-// One item per block at a time: stage a slice of N_u (all threads), then each
-// wave probes a quarter of the item's in-edge records.
-__global__ __launch_bounds__(kBlock) void k_pivot_hub(KernelArgs a, const PivotItem* __restrict__ items,
-                                                      uint64_t n_items, unsigned long long* __restrict__ queue,
-                                                      int max_log2s) {
-  extern __shared__ int32_t smem[];
-  int32_t* H = smem;
-  uint32_t* C = reinterpret_cast<uint32_t*>(smem + (1 << max_log2s));  // per-node mode only
-  __shared__ uint32_t pre[kWavesPerBlock][kWave + 1];
-  __shared__ uint32_t beg[kWavesPerBlock][kWave];
-  __shared__ uint32_t hits[kWavesPerBlock][kWave];
-  __shared__ unsigned long long cur;
-  __shared__ unsigned long long red[kWavesPerBlock];
-  const int tid = threadIdx.x, w = tid / kWave, lane = lane_id();
-  unsigned long long acc = 0;
-  for (;;) {
-    if (tid == 0) cur = atomicAdd(queue, 1ull);
-    __syncthreads();
-    const unsigned long long it = cur;
-    if (it >= n_items) break;
-    const PivotItem item = items[it];
-    const int log2s = log2_slots(item.nlen, 6);
-    const int S = 1 << log2s;
-    for (int s = tid; s < S; s += kBlock) {
-      H[s] = kEmpty;
-      if (a.mode == kCountPerNode) C[s] = 0;
-    }
-    __syncthreads();
-    const int64_t nb = a.off[item.u] + item.nbeg_rel;
-    for (uint32_t k = tid; k < item.nlen; k += kBlock) hash_insert(H, log2s, a.adj[nb + k]);
-    __syncthreads();
-    uint32_t cnt = 0;
-    for (uint32_t r0 = item.ibeg + static_cast<uint32_t>(w) * kWave; r0 < item.iend; r0 += kBlock)
-      cnt += probe_batch(a, item.u, r0, item.iend < r0 + kWave ? item.iend : r0 + kWave, H, log2s, C, pre[w], beg[w],
-                         hits[w]);
-    unsigned long long ws = wave_sum(static_cast<unsigned long long>(cnt));
-    if (lane == 0) red[w] = ws;
-    __syncthreads();
-    if (a.mode == kCountPerNode) {
-      for (int s = tid; s < S; s += kBlock)
-        if (C[s]) atomicAdd(&a.t_rank[H[s]], static_cast<unsigned long long>(C[s]));
-    }
-    if (tid == 0) {
-      unsigned long long tot = 0;
-      for (int x = 0; x < kWavesPerBlock; x++) tot += red[x];
-      if (tot) {
-        acc += tot;
-        if (a.per_graph) atomicAdd(&a.per_graph[a.graph_of_rank ? a.graph_of_rank[item.u] : 0], tot);
-        if (a.mode == kCountPerNode) atomicAdd(&a.t_rank[item.u], tot);
-      }
-    }
-    __syncthreads();
-  }
-  if (tid == 0 && acc && a.total) atomicAdd(a.total, acc);
-}
-
-// --------------------------------------------------------- wave kernel ---
-
+// Per-wave staging of one small pivot (|N_u| <= 256) into a table of at most
+// kWaveSlots / 4 buckets.
 __device__ __forceinline__ unsigned long long wave_pivot(const KernelArgs& a, int32_t u, uint32_t ibeg, uint32_t iend,
-                                                         int32_t* H, uint32_t* C, uint32_t* pre, uint32_t* beg,
-                                                         uint32_t* hits) {
+                                                         int32_t* T, uint32_t* C, BatchLds<kWave>& B) {
   const int lane = lane_id();
   const int64_t nb = a.off[u];
   const uint32_t nlen = static_cast<uint32_t>(a.off[u + 1] - nb);
-  const int log2s = log2_slots(nlen, 6);
-  const int S = 1 << log2s;
+  int log2b = log2_buckets(nlen);
+  while ((4 << log2b) > kWaveSlots) log2b--;  // at most kWaveSlots/4 buckets (>= 2 slots per entry)
+  const int S = 4 << log2b;
   for (int s = lane; s < S; s += kWave) {
-    H[s] = kEmpty;
+    T[s] = kEmpty;
     if (a.mode == kCountPerNode) C[s] = 0;
   }
   wave_sync();
-  for (uint32_t k = lane; k < nlen; k += kWave) hash_insert(H, log2s, a.adj[nb + k]);
+  for (uint32_t k = lane; k < nlen; k += kWave) bt_insert(T, log2b, a.adj[nb + k]);
   wave_sync();
   uint32_t cnt = 0;
   for (uint32_t r0 = ibeg; r0 < iend; r0 += kWave)
-    cnt += probe_batch(a, u, r0, iend < r0 + kWave ? iend : r0 + kWave, H, log2s, C, pre, beg, hits);
+    cnt += probe_batch_wave(a, u, r0, iend < r0 + kWave ? iend : r0 + kWave, T, log2b, C, B);
   const unsigned long long tot = wave_sum(static_cast<unsigned long long>(cnt));
   if (a.mode == kCountPerNode) {
     for (int s = lane; s < S; s += kWave)
-      if (C[s]) atomicAdd(&a.t_rank[H[s]], static_cast<unsigned long long>(C[s]));
+      if (C[s]) atomicAdd(&a.t_rank[T[s]], static_cast<unsigned long long>(C[s]));
   }
   if (lane == 0 && tot) {
     if (a.per_graph) atomicAdd(&a.per_graph[a.graph_of_rank ? a.graph_of_rank[u] : 0], tot);
@@ -387,37 +468,102 @@ __device__ __forceinline__ unsigned long long wave_pivot(const KernelArgs& a, in
   return tot;
 }
 
-// Each wave serves split items first, then the grouped queue of small pivots.
-__global__ __launch_bounds__(kBlock) void k_pivot_wave(KernelArgs a, const PivotItem* __restrict__ items,
-                                                       uint64_t n_items, const int32_t* __restrict__ grouped,
-                                                       uint64_t n_grouped, unsigned long long* __restrict__ queues) {
-  __shared__ int32_t H[kWavesPerBlock][kWaveSlots];
-  __shared__ uint32_t C[kWavesPerBlock][kWaveSlots];
-  __shared__ uint32_t pre[kWavesPerBlock][kWave + 1];
-  __shared__ uint32_t beg[kWavesPerBlock][kWave];
-  __shared__ uint32_t hits[kWavesPerBlock][kWave];
-  const int w = threadIdx.x / kWave, lane = lane_id();
+// The persistent intersection kernel. Phase 1: blocks take hub items from
+// queue 0 (a slice of a long N_u staged by all 256 threads, in-edge records
+// probed by the four waves). Phase 2: each wave takes split items from queue 1
+// and then chunks of small pivots from queue 2, each staged by the wave alone.
+// The dynamic LDS region serves as the block table in phase 1 and as four
+// per-wave tables in phase 2 (a block enters phase 2 only after its phase 1).
+__global__ __launch_bounds__(kPivotBlock) void k_pivot(KernelArgs a, const PivotItem* __restrict__ hub_items,
+                                                  uint64_t n_hub, const PivotItem* __restrict__ split_items,
+                                                  uint64_t n_split, const int32_t* __restrict__ grouped,
+                                                  uint64_t n_grouped, unsigned long long* __restrict__ queues,
+                                                  int hub_log2b) {
+  extern __shared__ int4 smem4[];
+  int32_t* smem = reinterpret_cast<int32_t*>(smem4);
+  // record arrays: the block's in phase 1, one per wave in phase 2
+  __shared__ union {
+    BatchLds<kPivotBlock> block;
+    BatchLds<kWave> wave[kPivotWaves];
+  } rl;
+  __shared__ uint64_t scan_tmp[kPivotWaves];
+  __shared__ unsigned long long cur;
+  __shared__ unsigned long long red[kPivotWaves];
+  const int tid = threadIdx.x, w = tid / kWave, lane = lane_id();
+  const bool per_node = a.mode == kCountPerNode;
   unsigned long long acc = 0;
-  for (;;) {
-    unsigned long long it = 0;
-    if (lane == 0) it = atomicAdd(&queues[0], 1ull);
-    it = __shfl(it, 0, kWave);
-    if (it >= n_items) break;
-    const PivotItem item = items[it];
-    acc += wave_pivot(a, item.u, item.ibeg, item.iend, H[w], C[w], pre[w], beg[w], hits[w]);
-  }
-  for (;;) {
-    unsigned long long g0 = 0;
-    if (lane == 0) g0 = atomicAdd(&queues[1], static_cast<unsigned long long>(kGroupChunk));
-    g0 = __shfl(g0, 0, kWave);
-    if (g0 >= n_grouped) break;
-    const uint64_t g1 = g0 + kGroupChunk < n_grouped ? g0 + kGroupChunk : n_grouped;
-    for (uint64_t g = g0; g < g1; g++) {
-      const int32_t u = grouped[g];
-      acc += wave_pivot(a, u, static_cast<uint32_t>(a.in_off[u]), static_cast<uint32_t>(a.in_off[u + 1]), H[w], C[w],
-                        pre[w], beg[w], hits[w]);
+
+  // ---- phase 1: hub items, one block each
+  {
+    int32_t* T = smem;
+    uint32_t* C = reinterpret_cast<uint32_t*>(smem + (4 << hub_log2b));
+    for (;;) {
+      if (tid == 0) cur = n_hub ? atomicAdd(&queues[0], 1ull) : 0ull;
+      __syncthreads();
+      const unsigned long long it = cur;
+      if (it >= n_hub) break;
+      const PivotItem item = hub_items[it];
+      const int log2b = log2_buckets(item.nlen, a.bucket_load);
+      const int S = 4 << log2b;
+      for (int s = tid; s < S; s += kPivotBlock) {
+        T[s] = kEmpty;
+        if (per_node) C[s] = 0;
+      }
+      __syncthreads();
+      const int64_t nb = a.off[item.u] + item.nbeg_rel;
+      for (uint32_t k = tid; k < item.nlen; k += kPivotBlock) bt_insert(T, log2b, a.adj[nb + k]);
+      __syncthreads();
+      uint32_t cnt = 0;
+      for (uint32_t r0 = item.ibeg; r0 < item.iend; r0 += kPivotBlock)
+        cnt += probe_batch_block(a, item.u, r0, item.iend < r0 + kPivotBlock ? item.iend : r0 + kPivotBlock, T, log2b,
+                                 C, rl.block, scan_tmp);
+      const unsigned long long ws = wave_sum(static_cast<unsigned long long>(cnt));
+      if (lane == 0) red[w] = ws;
+      __syncthreads();
+      if (per_node) {
+        for (int s = tid; s < S; s += kPivotBlock)
+          if (C[s]) atomicAdd(&a.t_rank[T[s]], static_cast<unsigned long long>(C[s]));
+      }
+      if (tid == 0) {
+        unsigned long long tot = 0;
+        for (int x = 0; x < kPivotWaves; x++) tot += red[x];
+        if (tot) {
+          acc += tot;
+          if (a.per_graph) atomicAdd(&a.per_graph[a.graph_of_rank ? a.graph_of_rank[item.u] : 0], tot);
+          if (per_node) atomicAdd(&a.t_rank[item.u], tot);
+        }
+      }
+      __syncthreads();
     }
   }
+
+  // ---- phase 2: split items and grouped small pivots, one wave each
+  {
+    const int per_wave = kWaveSlots * (per_node ? 2 : 1);
+    int32_t* T = smem + w * per_wave;
+    uint32_t* C = reinterpret_cast<uint32_t*>(T + kWaveSlots);
+    for (;;) {
+      unsigned long long it = 0;
+      if (lane == 0) it = n_split ? atomicAdd(&queues[1], 1ull) : 0ull;
+      it = __shfl(it, 0, kWave);
+      if (it >= n_split) break;
+      const PivotItem item = split_items[it];
+      acc += wave_pivot(a, item.u, item.ibeg, item.iend, T, C, rl.wave[w]);
+    }
+    for (;;) {
+      unsigned long long g0 = 0;
+      if (lane == 0) g0 = n_grouped ? atomicAdd(&queues[2], static_cast<unsigned long long>(kGroupChunk)) : 0ull;
+      g0 = __shfl(g0, 0, kWave);
+      if (g0 >= n_grouped) break;
+      const uint64_t g1 = g0 + kGroupChunk < n_grouped ? g0 + kGroupChunk : n_grouped;
+      for (uint64_t g = g0; g < g1; g++) {
+        const int32_t u = grouped[g];
+        acc += wave_pivot(a, u, static_cast<uint32_t>(a.in_off[u]), static_cast<uint32_t>(a.in_off[u + 1]), T, C,
+                          rl.wave[w]);
+      }
+    }
+  }
+  // phase 1 accumulates in thread 0 of each block, phase 2 in lane 0 of each wave
   if (lane == 0 && acc && a.total) atomicAdd(a.total, acc);
 }
 
@@ -560,7 +706,7 @@ void count_pivot(Csr& c, const CountArgs& ca, hipStream_t s, const Options& o, b
   if (allow_rebuild) ensure_plan(c, s, o);
   else if (!c.plan.ready) fail(TC_E_INVAL, "no work plan on this graph");
   const PivotPlan& P = c.plan;
-  KernelArgs a{c.off.p,     c.adj.p,          c.src.p,   P.inrec.p, P.in_off.p, ca.mode,  ca.total,
+  KernelArgs a{static_cast<int>(o.hub_bucket_load), c.off.p,     c.adj.p,          c.src.p,   P.inrec.p, P.in_off.p, ca.mode,  ca.total,
                ca.per_graph, ca.graph_of_rank, ca.t_rank, ca.order,  ca.tri,     ca.cursor, ca.cap};
   DevBuf<unsigned long long> qbuf;
   unsigned long long* q = ca.queues;
@@ -571,23 +717,24 @@ void count_pivot(Csr& c, const CountArgs& ca, hipStream_t s, const Options& o, b
   fill_u64(q, 3, 0ull, s);
   const unsigned cus = static_cast<unsigned>(device_cus());
   const unsigned bpc = static_cast<unsigned>(o.blocks_per_cu > 0 ? o.blocks_per_cu : 8);
+  const bool per_node = ca.mode == kCountPerNode;
+  int hub_log2b = 4;
   if (P.n_hub_items) {
-    int64_t maxlen = c.dhat_max < hub_slice_cap(kCountPerNode) ? c.dhat_max : hub_slice_cap(kCountPerNode);
-    int l = 6;
-    while ((1ll << l) < 2 * maxlen) l++;
-    const size_t lds = (static_cast<size_t>(1) << l) * sizeof(int32_t) * (ca.mode == kCountPerNode ? 2 : 1);
-    const unsigned grid = static_cast<unsigned>(P.n_hub_items < static_cast<uint64_t>(cus) * bpc ? P.n_hub_items : cus * bpc);
-    k_pivot_hub<<<grid, kBlock, lds, s>>>(a, P.items.p, P.n_hub_items, q, l);
-    TC_LAUNCH_CHECK();
+    const int64_t cap = hub_slice_cap(kCountPerNode);
+    const int64_t maxlen = c.dhat_max < cap ? c.dhat_max : cap;
+    while ((1ll << hub_log2b) * o.hub_bucket_load < maxlen) hub_log2b++;
   }
-  if (P.n_wave_items || P.n_grouped) {
-    const uint64_t waves_needed = P.n_wave_items + (P.n_grouped + kGroupChunk - 1) / kGroupChunk;
-    const uint64_t blocks_needed = (waves_needed + kWavesPerBlock - 1) / kWavesPerBlock;
-    const unsigned grid = static_cast<unsigned>(blocks_needed < static_cast<uint64_t>(cus) * bpc ? blocks_needed : cus * bpc);
-    k_pivot_wave<<<grid, kBlock, 0, s>>>(a, P.items.p + P.n_hub_items, P.n_wave_items, P.grouped.p, P.n_grouped,
-                                          q + 1);
-    TC_LAUNCH_CHECK();
-  }
+  const size_t hub_lds = (static_cast<size_t>(4) << hub_log2b) * sizeof(int32_t) * (per_node ? 2 : 1);
+  const size_t wave_lds = static_cast<size_t>(kPivotWaves) * kWaveSlots * sizeof(int32_t) * (per_node ? 2 : 1);
+  const size_t lds = hub_lds > wave_lds ? hub_lds : wave_lds;
+  const uint64_t wave_units = P.n_split_items() + (P.n_grouped + kGroupChunk - 1) / kGroupChunk;
+  const uint64_t blocks_needed = P.n_hub_items + (wave_units + kPivotWaves - 1) / kPivotWaves;
+  if (blocks_needed == 0) return;
+  const uint64_t cap_blocks = static_cast<uint64_t>(cus) * bpc;
+  const unsigned grid = static_cast<unsigned>(blocks_needed < cap_blocks ? blocks_needed : cap_blocks);
+  k_pivot<<<grid, kPivotBlock, lds, s>>>(a, P.items.p, P.n_hub_items, P.items.p + P.n_hub_items, P.n_wave_items,
+                                    P.grouped.p, P.n_grouped, q, hub_log2b);
+  TC_LAUNCH_CHECK();
 }
 
 // --------------------------------------------------------- sparsified ---

@@ -66,6 +66,7 @@ struct PivotPlan {
   Owned<int32_t> grouped;    // small pivots served from a shared queue
   uint64_t n_grouped = 0;
   int64_t hub_dhat = 0, item_work = 0;  // options the plan was built with
+  uint64_t n_split_items() const { return n_wave_items; }
   void reset() {
     ready = false;
     inrec.reset();
@@ -118,6 +119,7 @@ struct Options {
   int64_t hub_dhat = 128;    // pivots with |N_u| > hub_dhat use the block path
   int64_t item_work = 4096;  // target probes per work item
   int64_t blocks_per_cu = 8; // persistent launch occupancy
+  int64_t hub_bucket_load = 2;  // entries per 4-slot bucket of a hub table (1 or 2)
 };
 Options get_options();
 

@@ -17,7 +17,7 @@ LIB_PATH = os.path.join(_HERE, "libtc.so")
 
 TC_OK, TC_E_INVAL, TC_E_NOMEM, TC_E_DEVICE, TC_E_RANGE, TC_E_TRUNC = 0, -1, -2, -3, -4, -5
 TC_IN_DEVICE = 1
-OPT_KERNEL, OPT_HUB_DHAT, OPT_ITEM_WORK, OPT_BLOCKS_PER_CU = 0, 1, 2, 3
+OPT_KERNEL, OPT_HUB_DHAT, OPT_ITEM_WORK, OPT_BLOCKS_PER_CU, OPT_HUB_BUCKET_LOAD = 0, 1, 2, 3, 4
 
 # (name, argtypes, restype) for every symbol include/tc.h declares
 _vp, _i32, _i64, _u32, _u64, _dbl = (ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_uint32,

@@ -28,10 +28,10 @@ def tc():
     import paper_1706_05151_amd.tc as tcm
 
     tcm.lib()
-    for k, v in ((tcm.OPT_KERNEL, 0), (tcm.OPT_HUB_DHAT, 128), (tcm.OPT_ITEM_WORK, 4096), (tcm.OPT_BLOCKS_PER_CU, 8)):
-        tcm.set_option(k, v)
+    keys = (tcm.OPT_KERNEL, tcm.OPT_HUB_DHAT, tcm.OPT_ITEM_WORK, tcm.OPT_BLOCKS_PER_CU, tcm.OPT_HUB_BUCKET_LOAD)
+    saved = {k: tcm.get_option(k) for k in keys}
     yield tcm
-    for k, v in ((tcm.OPT_KERNEL, 0), (tcm.OPT_HUB_DHAT, 128), (tcm.OPT_ITEM_WORK, 4096), (tcm.OPT_BLOCKS_PER_CU, 8)):
+    for k, v in saved.items():
         tcm.set_option(k, v)
 
 
@@ -110,13 +110,16 @@ def test_families(tc, spec):
     check_all(tc, el, listing=True)
 
 
-@pytest.mark.parametrize("hub,iw", [(0, 64), (0, 4096), (16, 64), (256, 100000), (64, 512)])
-def test_partitioner_settings_identical(tc, hub, iw):
-    """Every bucket threshold and work-item size gives the same exact results."""
+@pytest.mark.parametrize("hub,iw,load", [(0, 64, 1), (0, 4096, 2), (16, 64, 2), (256, 100000, 1), (64, 512, 2),
+                                         (128, 16384, 1)])
+def test_partitioner_settings_identical(tc, hub, iw, load):
+    """Every bucket threshold, work-item size and table load gives the same exact results."""
     el = synth.rmat(14, 16, 9)
     ref = oracle.solve(el.src, el.dst, el.n, per_node=True, listing=True)
+    old = (tc.get_option(tc.OPT_HUB_DHAT), tc.get_option(tc.OPT_ITEM_WORK), tc.get_option(tc.OPT_HUB_BUCKET_LOAD))
     tc.set_option(tc.OPT_HUB_DHAT, hub)
     tc.set_option(tc.OPT_ITEM_WORK, iw)
+    tc.set_option(tc.OPT_HUB_BUCKET_LOAD, load)
     try:
         s, d = to_dev(el)
         with tc.Graph.build(s, d, el.n) as g:
@@ -126,8 +129,9 @@ def test_partitioner_settings_identical(tc, hub, iw):
             np.testing.assert_array_equal(u64(t), ref.t)
             np.testing.assert_array_equal(g.list().cpu().numpy(), ref.tri)
     finally:
-        tc.set_option(tc.OPT_HUB_DHAT, 128)
-        tc.set_option(tc.OPT_ITEM_WORK, 4096)
+        tc.set_option(tc.OPT_HUB_DHAT, old[0])
+        tc.set_option(tc.OPT_ITEM_WORK, old[1])
+        tc.set_option(tc.OPT_HUB_BUCKET_LOAD, old[2])
 
 
 def test_host_and_device_inputs_agree(tc):
