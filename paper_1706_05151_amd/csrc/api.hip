@@ -149,6 +149,8 @@ tc_status tc_build_csr(const int32_t* src, const int32_t* dst, int64_t num_edges
     auto* g = new tc_graph();
     try {
       build_graph(src, dst, num_edges, n, nullptr, nullptr, 1, (flags & TC_IN_DEVICE) != 0, as_stream(stream), g);
+      ensure_plan(g->csr, as_stream(stream), get_options());  // work plan of the intersection kernel
+      TC_HIP(hipStreamSynchronize(as_stream(stream)));
     } catch (...) {
       (void)hipStreamSynchronize(as_stream(stream));
       delete g;

@@ -27,6 +27,9 @@ namespace tc {
 namespace {
 
 constexpr int kBlock = 256;
+#ifndef TC_PIVOT_MIN_WAVES
+#define TC_PIVOT_MIN_WAVES 8  // waves per SIMD the pivot kernel is compiled for (register budget)
+#endif
 constexpr int kPivotBlock = 512;  // threads of a pivot-kernel block (hub items are staged once per 8 waves)
 constexpr int kPivotWaves = kPivotBlock / kWave;
 constexpr int32_t kEmpty = -1;
@@ -289,21 +292,22 @@ struct BatchLds {
 };
 
 // Probe one element against the table; counts, per-node tallies and listing.
+template <int MODE>
 __device__ __forceinline__ uint32_t probe_one(const KernelArgs& a, int32_t u, int32_t x, const int32_t* T, int log2b,
                                               uint32_t* C, uint32_t* hit_rec, uint32_t rec_begin) {
   const int s = bt_find(T, log2b, x);
   if (s < 0) return 0u;
-  if (a.mode == kCountPerNode) {
+  if (MODE == kCountPerNode) {
     atomicAdd(&C[s], 1u);
     atomicAdd(hit_rec, 1u);
-  } else if (a.mode == kCountList) {
+  } else if (MODE == kCountList) {
     emit_triangle(a, a.src[rec_begin - 1], u, x);
   }
   return 1u;
 }
 
 // Segments [seg0, nsegs) step `stride` of the long records, one wave per segment.
-template <int NR>
+template <int MODE, int NR>
 __device__ __forceinline__ uint32_t probe_long(const KernelArgs& a, int32_t u, const BatchLds<NR>& B, uint32_t nsegs,
                                                uint32_t seg0, uint32_t stride, const int32_t* T, int log2b,
                                                uint32_t* C, uint32_t* hits) {
@@ -327,7 +331,7 @@ __device__ __forceinline__ uint32_t probe_long(const KernelArgs& a, int32_t u, c
     uint32_t h = 0;
 #pragma unroll
     for (int i = 0; i < kPerLane; i++)
-      if (x[i] != kEmpty) h += probe_one(a, u, x[i], T, log2b, C, &hits[j], B.beg[j]);
+      if (x[i] != kEmpty) h += probe_one<MODE>(a, u, x[i], T, log2b, C, &hits[j], B.beg[j]);
     cnt += h;
   }
   return cnt;
@@ -335,7 +339,7 @@ __device__ __forceinline__ uint32_t probe_long(const KernelArgs& a, int32_t u, c
 
 // Concatenated short-record elements [k_first, tot) in windows of width*kPerLane,
 // this thread taking kPerLane consecutive ones at its slot `slot` of `width`.
-template <int NR>
+template <int MODE, int NR>
 __device__ __forceinline__ uint32_t probe_short(const KernelArgs& a, int32_t u, const BatchLds<NR>& B, uint32_t tot,
                                                 int slot, int width, const int32_t* T, int log2b, uint32_t* C,
                                                 uint32_t* hits) {
@@ -363,20 +367,20 @@ __device__ __forceinline__ uint32_t probe_short(const KernelArgs& a, int32_t u, 
     }
 #pragma unroll
     for (int i = 0; i < kPerLane; i++)
-      if (jj[i] >= 0) cnt += probe_one(a, u, x[i], T, log2b, C, &hits[jj[i]], B.beg[jj[i]]);
+      if (jj[i] >= 0) cnt += probe_one<MODE>(a, u, x[i], T, log2b, C, &hits[jj[i]], B.beg[jj[i]]);
   }
   return cnt;
 }
 
 // Fill the batch arrays for the record this thread holds (idx in [0,NR)).
-template <int NR>
+template <int MODE, int NR>
 __device__ __forceinline__ void batch_fill(const KernelArgs& a, BatchLds<NR>& B, int idx, const InRec& rc,
                                            uint64_t excl, uint64_t tot) {
   B.segpre[idx] = static_cast<uint32_t>(excl >> 32);
   B.spre[idx] = static_cast<uint32_t>(excl);
   B.beg[idx] = rc.a_begin;
   B.len[idx] = rc.a_len;
-  if (a.mode != kCountTotal) B.hits[idx] = 0;
+  if (MODE != kCountTotal) B.hits[idx] = 0;
   if (idx == NR - 1) {
     B.segpre[NR] = static_cast<uint32_t>(tot >> 32);
     B.spre[NR] = static_cast<uint32_t>(tot);
@@ -390,6 +394,7 @@ __device__ __forceinline__ uint64_t seg_short_pack(uint32_t len) {
 }
 
 // Block-wide batch of up to kPivotBlock records for a hub item.
+template <int MODE>
 __device__ __forceinline__ uint32_t probe_batch_block(const KernelArgs& a, int32_t u, uint32_t r0, uint32_t r1,
                                                       const int32_t* T, int log2b, uint32_t* C, BatchLds<kPivotBlock>& B,
                                                       uint64_t* scan_tmp) {
@@ -400,19 +405,20 @@ __device__ __forceinline__ uint32_t probe_batch_block(const KernelArgs& a, int32
   if (valid) rc = a.rec[r];
   uint64_t tot;
   const uint64_t excl = block_excl_scan<uint64_t, kPivotBlock>(seg_short_pack(rc.a_len), scan_tmp, tot);
-  batch_fill<kPivotBlock>(a, B, tid, rc, excl, tot);
+  batch_fill<MODE, kPivotBlock>(a, B, tid, rc, excl, tot);
   __syncthreads();
-  uint32_t cnt = probe_long<kPivotBlock>(a, u, B, static_cast<uint32_t>(tot >> 32), static_cast<uint32_t>(w),
+  uint32_t cnt = probe_long<MODE, kPivotBlock>(a, u, B, static_cast<uint32_t>(tot >> 32), static_cast<uint32_t>(w),
                                     kPivotWaves, T, log2b, C, B.hits);
-  cnt += probe_short<kPivotBlock>(a, u, B, static_cast<uint32_t>(tot), tid, kPivotBlock, T, log2b, C, B.hits);
+  cnt += probe_short<MODE, kPivotBlock>(a, u, B, static_cast<uint32_t>(tot), tid, kPivotBlock, T, log2b, C, B.hits);
   __syncthreads();
-  if (a.mode == kCountPerNode && valid && B.hits[tid])
+  if (MODE == kCountPerNode && valid && B.hits[tid])
     atomicAdd(&a.t_rank[a.src[rc.a_begin - 1]], static_cast<unsigned long long>(B.hits[tid]));
   __syncthreads();
   return cnt;
 }
 
 // Wave-wide batch of up to 64 records for a small pivot.
+template <int MODE>
 __device__ __forceinline__ uint32_t probe_batch_wave(const KernelArgs& a, int32_t u, uint32_t r0, uint32_t r1,
                                                      const int32_t* T, int log2b, uint32_t* C, BatchLds<kWave>& B) {
   const int lane = lane_id();
@@ -423,11 +429,11 @@ __device__ __forceinline__ uint32_t probe_batch_wave(const KernelArgs& a, int32_
   const uint64_t p = seg_short_pack(rc.a_len);
   const uint64_t incl = wave_incl_scan(p);
   const uint64_t tot = __shfl(incl, kWave - 1, kWave);
-  batch_fill<kWave>(a, B, lane, rc, incl - p, tot);
+  batch_fill<MODE, kWave>(a, B, lane, rc, incl - p, tot);
   wave_sync();
-  uint32_t cnt = probe_long<kWave>(a, u, B, static_cast<uint32_t>(tot >> 32), 0u, 1u, T, log2b, C, B.hits);
-  cnt += probe_short<kWave>(a, u, B, static_cast<uint32_t>(tot), lane, kWave, T, log2b, C, B.hits);
-  if (a.mode == kCountPerNode) {
+  uint32_t cnt = probe_long<MODE, kWave>(a, u, B, static_cast<uint32_t>(tot >> 32), 0u, 1u, T, log2b, C, B.hits);
+  cnt += probe_short<MODE, kWave>(a, u, B, static_cast<uint32_t>(tot), lane, kWave, T, log2b, C, B.hits);
+  if (MODE == kCountPerNode) {
     wave_sync();
     if (valid && B.hits[lane]) atomicAdd(&a.t_rank[a.src[rc.a_begin - 1]], static_cast<unsigned long long>(B.hits[lane]));
   }
@@ -437,6 +443,7 @@ __device__ __forceinline__ uint32_t probe_batch_wave(const KernelArgs& a, int32_
 
 // Per-wave staging of one small pivot (|N_u| <= 256) into a table of at most
 // kWaveSlots / 4 buckets.
+template <int MODE>
 __device__ __forceinline__ unsigned long long wave_pivot(const KernelArgs& a, int32_t u, uint32_t ibeg, uint32_t iend,
                                                          int32_t* T, uint32_t* C, BatchLds<kWave>& B) {
   const int lane = lane_id();
@@ -447,22 +454,22 @@ __device__ __forceinline__ unsigned long long wave_pivot(const KernelArgs& a, in
   const int S = 4 << log2b;
   for (int s = lane; s < S; s += kWave) {
     T[s] = kEmpty;
-    if (a.mode == kCountPerNode) C[s] = 0;
+    if (MODE == kCountPerNode) C[s] = 0;
   }
   wave_sync();
   for (uint32_t k = lane; k < nlen; k += kWave) bt_insert(T, log2b, a.adj[nb + k]);
   wave_sync();
   uint32_t cnt = 0;
   for (uint32_t r0 = ibeg; r0 < iend; r0 += kWave)
-    cnt += probe_batch_wave(a, u, r0, iend < r0 + kWave ? iend : r0 + kWave, T, log2b, C, B);
+    cnt += probe_batch_wave<MODE>(a, u, r0, iend < r0 + kWave ? iend : r0 + kWave, T, log2b, C, B);
   const unsigned long long tot = wave_sum(static_cast<unsigned long long>(cnt));
-  if (a.mode == kCountPerNode) {
+  if (MODE == kCountPerNode) {
     for (int s = lane; s < S; s += kWave)
       if (C[s]) atomicAdd(&a.t_rank[T[s]], static_cast<unsigned long long>(C[s]));
   }
   if (lane == 0 && tot) {
     if (a.per_graph) atomicAdd(&a.per_graph[a.graph_of_rank ? a.graph_of_rank[u] : 0], tot);
-    if (a.mode == kCountPerNode) atomicAdd(&a.t_rank[u], tot);
+    if (MODE == kCountPerNode) atomicAdd(&a.t_rank[u], tot);
   }
   wave_sync();
   return tot;
@@ -474,7 +481,8 @@ __device__ __forceinline__ unsigned long long wave_pivot(const KernelArgs& a, in
 // and then chunks of small pivots from queue 2, each staged by the wave alone.
 // The dynamic LDS region serves as the block table in phase 1 and as four
 // per-wave tables in phase 2 (a block enters phase 2 only after its phase 1).
-__global__ __launch_bounds__(kPivotBlock) void k_pivot(KernelArgs a, const PivotItem* __restrict__ hub_items,
+template <int MODE>
+__global__ __launch_bounds__(kPivotBlock, TC_PIVOT_MIN_WAVES) void k_pivot(KernelArgs a, const PivotItem* __restrict__ hub_items,
                                                   uint64_t n_hub, const PivotItem* __restrict__ split_items,
                                                   uint64_t n_split, const int32_t* __restrict__ grouped,
                                                   uint64_t n_grouped, unsigned long long* __restrict__ queues,
@@ -490,7 +498,7 @@ __global__ __launch_bounds__(kPivotBlock) void k_pivot(KernelArgs a, const Pivot
   __shared__ unsigned long long cur;
   __shared__ unsigned long long red[kPivotWaves];
   const int tid = threadIdx.x, w = tid / kWave, lane = lane_id();
-  const bool per_node = a.mode == kCountPerNode;
+  const bool per_node = MODE == kCountPerNode;
   unsigned long long acc = 0;
 
   // ---- phase 1: hub items, one block each
@@ -515,7 +523,7 @@ __global__ __launch_bounds__(kPivotBlock) void k_pivot(KernelArgs a, const Pivot
       __syncthreads();
       uint32_t cnt = 0;
       for (uint32_t r0 = item.ibeg; r0 < item.iend; r0 += kPivotBlock)
-        cnt += probe_batch_block(a, item.u, r0, item.iend < r0 + kPivotBlock ? item.iend : r0 + kPivotBlock, T, log2b,
+        cnt += probe_batch_block<MODE>(a, item.u, r0, item.iend < r0 + kPivotBlock ? item.iend : r0 + kPivotBlock, T, log2b,
                                  C, rl.block, scan_tmp);
       const unsigned long long ws = wave_sum(static_cast<unsigned long long>(cnt));
       if (lane == 0) red[w] = ws;
@@ -548,7 +556,7 @@ __global__ __launch_bounds__(kPivotBlock) void k_pivot(KernelArgs a, const Pivot
       it = __shfl(it, 0, kWave);
       if (it >= n_split) break;
       const PivotItem item = split_items[it];
-      acc += wave_pivot(a, item.u, item.ibeg, item.iend, T, C, rl.wave[w]);
+      acc += wave_pivot<MODE>(a, item.u, item.ibeg, item.iend, T, C, rl.wave[w]);
     }
     for (;;) {
       unsigned long long g0 = 0;
@@ -558,7 +566,7 @@ __global__ __launch_bounds__(kPivotBlock) void k_pivot(KernelArgs a, const Pivot
       const uint64_t g1 = g0 + kGroupChunk < n_grouped ? g0 + kGroupChunk : n_grouped;
       for (uint64_t g = g0; g < g1; g++) {
         const int32_t u = grouped[g];
-        acc += wave_pivot(a, u, static_cast<uint32_t>(a.in_off[u]), static_cast<uint32_t>(a.in_off[u + 1]), T, C,
+        acc += wave_pivot<MODE>(a, u, static_cast<uint32_t>(a.in_off[u]), static_cast<uint32_t>(a.in_off[u + 1]), T, C,
                           rl.wave[w]);
       }
     }
@@ -732,8 +740,17 @@ void count_pivot(Csr& c, const CountArgs& ca, hipStream_t s, const Options& o, b
   if (blocks_needed == 0) return;
   const uint64_t cap_blocks = static_cast<uint64_t>(cus) * bpc;
   const unsigned grid = static_cast<unsigned>(blocks_needed < cap_blocks ? blocks_needed : cap_blocks);
-  k_pivot<<<grid, kPivotBlock, lds, s>>>(a, P.items.p, P.n_hub_items, P.items.p + P.n_hub_items, P.n_wave_items,
-                                    P.grouped.p, P.n_grouped, q, hub_log2b);
+  const PivotItem* hub = P.items.p;
+  const PivotItem* split = P.items.p + P.n_hub_items;
+  if (ca.mode == kCountPerNode)
+    k_pivot<kCountPerNode><<<grid, kPivotBlock, lds, s>>>(a, hub, P.n_hub_items, split, P.n_wave_items, P.grouped.p,
+                                                          P.n_grouped, q, hub_log2b);
+  else if (ca.mode == kCountList)
+    k_pivot<kCountList><<<grid, kPivotBlock, lds, s>>>(a, hub, P.n_hub_items, split, P.n_wave_items, P.grouped.p,
+                                                       P.n_grouped, q, hub_log2b);
+  else
+    k_pivot<kCountTotal><<<grid, kPivotBlock, lds, s>>>(a, hub, P.n_hub_items, split, P.n_wave_items, P.grouped.p,
+                                                        P.n_grouped, q, hub_log2b);
   TC_LAUNCH_CHECK();
 }
 
