@@ -192,6 +192,40 @@ tc_status tc_batch_size(const tc_graph* g, int32_t* num_graphs);
  */
 tc_status tc_batch_count(tc_graph* g, void* stream, uint64_t* T_dev, uint64_t* t_dev);
 
+/* ------------------------------------------------------------ serving */
+
+/*
+ * Counts of several resident graphs in one launch of the persistent kernel:
+ * the work items of all graphs are drained from one device queue. T_dev:
+ * device uint64[k], T of graph i at index i. With per_node != 0, t_dev[i] is a
+ * device uint64[n_i] array (caller ids) receiving T_v of graph i. Graphs must
+ * live on one device; sampled graphs (tc_sparsify_build) are allowed for
+ * totals. Does not synchronise `stream`; scratch is taken from the stream-
+ * ordered allocator and released on `stream`.
+ */
+tc_status tc_multi_count(tc_graph* const* graphs, int32_t k, int32_t per_node, void* stream, uint64_t* T_dev,
+                         uint64_t* const* t_dev);
+
+/*
+ * Clustering coefficients (Section 2) from per-node counts t_dev (caller ids,
+ * e.g. from tc_multi_count) without recounting: same outputs and rules as
+ * tc_clustering. Does not synchronise `stream`.
+ */
+tc_status tc_clustering_from_counts(tc_graph* g, void* stream, const uint64_t* t_dev, uint64_t* num_dev,
+                                    uint64_t* den_dev, double* c_dev);
+
+/*
+ * The edge sample of tc_sparsify_count (Section 7: same keep rule, q, seed)
+ * as a graph of its own, ready for tc_count / tc_multi_count. Orientation
+ * follows the degrees of the full graph. Per-node, clustering and listing
+ * calls on the result return TC_E_INVAL. Free with tc_graph_free.
+ * Synchronises `stream`.
+ */
+tc_status tc_sparsify_build(tc_graph* g, double q, uint64_t seed, void* stream, tc_graph** out);
+
+/* T_sampled / (q*q*q), the estimate of Section 7 (the expression tc_sparsify_count uses). */
+double tc_sparsify_estimate(uint64_t T_sampled, double q);
+
 /* ------------------------------------------------------------------ errors */
 
 const char* tc_status_str(tc_status s);

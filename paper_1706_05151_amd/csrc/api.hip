@@ -5,6 +5,7 @@
 #include <cmath>
 #include <new>
 #include <string>
+#include <vector>
 
 #include "graph.hpp"
 #include "primitives.hpp"
@@ -240,6 +241,7 @@ tc_status tc_count_plain(tc_graph* g, void* stream, uint64_t* T) {
 tc_status tc_count_per_node(tc_graph* g, void* stream, uint64_t* T, uint64_t* t_dev) {
   return guarded([&] {
     require(g != nullptr && t_dev != nullptr, TC_E_INVAL, "NULL argument");
+    require(!g->sampled, TC_E_INVAL, "per-node counts are not available on a sampled graph");
     DeviceScope ds(g->device);
     const hipStream_t s = as_stream(stream);
     DevBuf<unsigned long long> tr(g->n, s);
@@ -257,6 +259,7 @@ tc_status tc_count_per_node(tc_graph* g, void* stream, uint64_t* T, uint64_t* t_
 tc_status tc_clustering(tc_graph* g, void* stream, uint64_t* num_dev, uint64_t* den_dev, double* c_dev) {
   return guarded([&] {
     require(g != nullptr, TC_E_INVAL, "graph is NULL");
+    require(!g->sampled, TC_E_INVAL, "clustering is not available on a sampled graph");
     DeviceScope ds(g->device);
     const hipStream_t s = as_stream(stream);
     DevBuf<unsigned long long> tr(g->n, s), tid(g->n, s);
@@ -275,6 +278,7 @@ tc_status tc_list(tc_graph* g, void* stream, int32_t* tri_dev, int64_t cap, int6
   return guarded([&] {
     require(g != nullptr && count != nullptr, TC_E_INVAL, "NULL argument");
     require(cap >= 0, TC_E_INVAL, "negative capacity");
+    require(!g->sampled, TC_E_INVAL, "listing is not available on a sampled graph");
     DeviceScope ds(g->device);
     const hipStream_t s = as_stream(stream);
     const uint64_t T = count_total(g, g->csr, s, nullptr);
@@ -306,6 +310,7 @@ tc_status tc_sparsify_count(tc_graph* g, double q, uint64_t seed, void* stream, 
                             double* estimate) {
   return guarded([&] {
     require(g != nullptr, TC_E_INVAL, "graph is NULL");
+    require(!g->sampled, TC_E_INVAL, "cannot sample a sampled graph");
     require(q > 0.0 && q <= 1.0, TC_E_RANGE, "q outside (0, 1]");
     DeviceScope ds(g->device);
     const hipStream_t s = as_stream(stream);
@@ -338,6 +343,7 @@ tc_status tc_graph_work(tc_graph* g, void* stream, uint64_t* W, uint64_t* P) {
 tc_status tc_graph_degrees(tc_graph* g, void* stream, int32_t* deg_dev, int32_t* dhat_dev) {
   return guarded([&] {
     require(g != nullptr, TC_E_INVAL, "graph is NULL");
+    require(!g->sampled, TC_E_INVAL, "not available on a sampled graph");
     DeviceScope ds(g->device);
     const hipStream_t s = as_stream(stream);
     if (deg_dev && g->n > 0)
@@ -353,6 +359,7 @@ tc_status tc_graph_degrees(tc_graph* g, void* stream, int32_t* deg_dev, int32_t*
 tc_status tc_graph_oriented(tc_graph* g, void* stream, int64_t* off_dev, int32_t* adj_dev) {
   return guarded([&] {
     require(g != nullptr, TC_E_INVAL, "graph is NULL");
+    require(!g->sampled, TC_E_INVAL, "not available on a sampled graph");
     DeviceScope ds(g->device);
     const hipStream_t s = as_stream(stream);
     const uint64_t m = static_cast<uint64_t>(g->m);
@@ -398,6 +405,88 @@ tc_status tc_batch_count(tc_graph* g, void* stream, uint64_t* T_dev, uint64_t* t
     }
   });
 }
+
+tc_status tc_multi_count(tc_graph* const* graphs, int32_t k, int32_t per_node, void* stream, uint64_t* T_dev,
+                         uint64_t* const* t_dev) {
+  return guarded([&] {
+    require(k >= 0, TC_E_INVAL, "negative graph count");
+    if (k == 0) return;
+    require(graphs != nullptr && T_dev != nullptr, TC_E_INVAL, "NULL argument");
+    require(!per_node || t_dev != nullptr, TC_E_INVAL, "per-node counts need t_dev");
+    const int dev = graphs[0] ? graphs[0]->device : 0;
+    std::vector<Csr*> cs(k);
+    for (int32_t i = 0; i < k; i++) {
+      require(graphs[i] != nullptr, TC_E_INVAL, "NULL graph in list");
+      require(graphs[i]->device == dev, TC_E_INVAL, "graphs of one multi count must share a device");
+      require(!per_node || (graphs[i]->order.p != nullptr || graphs[i]->n == 0), TC_E_INVAL,
+              "per-node counts are not available on a sampled graph");
+      require(!per_node || t_dev[i] != nullptr, TC_E_INVAL, "NULL per-node output");
+      cs[i] = &graphs[i]->csr;
+    }
+    DeviceScope ds(dev);
+    const hipStream_t s = as_stream(stream);
+    std::vector<DevBuf<unsigned long long>> tr(per_node ? k : 0);
+    std::vector<unsigned long long*> trp(k, nullptr);
+    if (per_node)
+      for (int32_t i = 0; i < k; i++) {
+        tr[i].alloc(static_cast<size_t>(graphs[i]->n), s);
+        trp[i] = tr[i].get();
+      }
+    count_multi(cs, trp, per_node ? kCountPerNode : kCountTotal, reinterpret_cast<unsigned long long*>(T_dev), s,
+                get_options());
+    if (per_node)
+      for (int32_t i = 0; i < k; i++)
+        if (graphs[i]->n > 0) {
+          k_scatter_by_order<<<grid_for(graphs[i]->n, kBlock, 65536), kBlock, 0, s>>>(
+              trp[i], graphs[i]->order.p, graphs[i]->n, reinterpret_cast<unsigned long long*>(t_dev[i]));
+          TC_LAUNCH_CHECK();
+        }
+  });
+}
+
+tc_status tc_clustering_from_counts(tc_graph* g, void* stream, const uint64_t* t_dev, uint64_t* num_dev,
+                                    uint64_t* den_dev, double* c_dev) {
+  return guarded([&] {
+    require(g != nullptr && t_dev != nullptr, TC_E_INVAL, "NULL argument");
+    require(g->deg.p != nullptr || g->n == 0, TC_E_INVAL, "no degrees on a sampled graph");
+    DeviceScope ds(g->device);
+    if (g->n > 0) {
+      k_clustering<<<grid_for(g->n, kBlock, 65536), kBlock, 0, as_stream(stream)>>>(
+          reinterpret_cast<const unsigned long long*>(t_dev), g->deg.p, g->n, num_dev, den_dev, c_dev);
+      TC_LAUNCH_CHECK();
+    }
+  });
+}
+
+tc_status tc_sparsify_build(tc_graph* g, double q, uint64_t seed, void* stream, tc_graph** out) {
+  return guarded([&] {
+    require(g != nullptr && out != nullptr, TC_E_INVAL, "NULL argument");
+    require(q > 0.0 && q <= 1.0, TC_E_RANGE, "q outside (0, 1]");
+    require(g->order.p != nullptr || g->n == 0, TC_E_INVAL, "cannot sample a sampled graph");
+    *out = nullptr;
+    DeviceScope ds(g->device);
+    const hipStream_t s = as_stream(stream);
+    auto* h = new tc_graph();
+    try {
+      h->device = g->device;
+      h->n = g->n;
+      h->bits = g->bits;
+      h->sampled = true;
+      h->q = q;
+      build_sampled_csr(g, q, seed, h->csr, s);
+      h->m = h->csr.m;
+      ensure_plan(h->csr, s, get_options());
+      TC_HIP(hipStreamSynchronize(s));
+    } catch (...) {
+      (void)hipStreamSynchronize(s);
+      delete h;
+      throw;
+    }
+    *out = h;
+  });
+}
+
+double tc_sparsify_estimate(uint64_t T_sampled, double q) { return static_cast<double>(T_sampled) / ((q * q) * q); }
 
 tc_status tc_set_option(tc_option key, int64_t value) {
   return guarded([&] {

@@ -475,18 +475,105 @@ __device__ __forceinline__ unsigned long long wave_pivot(const KernelArgs& a, in
   return tot;
 }
 
-// The persistent intersection kernel. Phase 1: blocks take hub items from
-// queue 0 (a slice of a long N_u staged by all 256 threads, in-edge records
-// probed by the four waves). Phase 2: each wave takes split items from queue 1
-// and then chunks of small pivots from queue 2, each staged by the wave alone.
-// The dynamic LDS region serves as the block table in phase 1 and as four
-// per-wave tables in phase 2 (a block enters phase 2 only after its phase 1).
+// One hub item processed by the whole block: stage the slice of N_u, probe
+// the item's in-edge records block-wide, flush per-node tallies. Returns the
+// item's triangle count (valid in thread 0).
 template <int MODE>
-__global__ __launch_bounds__(kPivotBlock, TC_PIVOT_MIN_WAVES) void k_pivot(KernelArgs a, const PivotItem* __restrict__ hub_items,
-                                                  uint64_t n_hub, const PivotItem* __restrict__ split_items,
-                                                  uint64_t n_split, const int32_t* __restrict__ grouped,
-                                                  uint64_t n_grouped, unsigned long long* __restrict__ queues,
-                                                  int hub_log2b) {
+__device__ __forceinline__ unsigned long long hub_item(const KernelArgs& a, const PivotItem& item, int32_t* T,
+                                                       uint32_t* C, BatchLds<kPivotBlock>& bl, uint64_t* scan_tmp,
+                                                       unsigned long long* red) {
+  const int tid = threadIdx.x, w = tid / kWave, lane = lane_id();
+  constexpr bool per_node = MODE == kCountPerNode;
+  const int log2b = log2_buckets(item.nlen, a.bucket_load);
+  const int S = 4 << log2b;
+  for (int s = tid; s < S; s += kPivotBlock) {
+    T[s] = kEmpty;
+    if (per_node) C[s] = 0;
+  }
+  __syncthreads();
+  const int64_t nb = a.off[item.u] + item.nbeg_rel;
+  for (uint32_t k = tid; k < item.nlen; k += kPivotBlock) bt_insert(T, log2b, a.adj[nb + k]);
+  __syncthreads();
+  uint32_t cnt = 0;
+  for (uint32_t r0 = item.ibeg; r0 < item.iend; r0 += kPivotBlock)
+    cnt += probe_batch_block<MODE>(a, item.u, r0, item.iend < r0 + kPivotBlock ? item.iend : r0 + kPivotBlock, T,
+                                   log2b, C, bl, scan_tmp);
+  const unsigned long long ws = wave_sum(static_cast<unsigned long long>(cnt));
+  if (lane == 0) red[w] = ws;
+  __syncthreads();
+  if (per_node) {
+    for (int s = tid; s < S; s += kPivotBlock)
+      if (C[s]) atomicAdd(&a.t_rank[T[s]], static_cast<unsigned long long>(C[s]));
+  }
+  unsigned long long tot = 0;
+  if (tid == 0) {
+    for (int x = 0; x < kPivotWaves; x++) tot += red[x];
+    if (tot) {
+      if (a.per_graph) atomicAdd(&a.per_graph[a.graph_of_rank ? a.graph_of_rank[item.u] : 0], tot);
+      if (per_node) atomicAdd(&a.t_rank[item.u], tot);
+    }
+  }
+  __syncthreads();
+  return tot;
+}
+
+// Work of many graphs in one launch: graph g's hub items, split items and
+// chunks of grouped pivots follow those of graphs 0..g-1 in three global
+// queues; pre[q * (k+1) + g] is the first queue index of graph g.
+struct GraphDesc {
+  const int64_t* off;
+  const int32_t* adj;
+  const int32_t* src;
+  const InRec* rec;
+  const int64_t* in_off;
+  const PivotItem* hub;
+  const PivotItem* split;
+  const int32_t* grouped;
+  uint64_t n_grouped;
+  unsigned long long* t_rank;  // per-node counts by rank (per-node mode)
+};
+
+struct JobList {
+  const GraphDesc* descs;  // [k]
+  const uint64_t* pre;     // [3][k+1]
+  int32_t k;
+};
+
+__device__ __forceinline__ int32_t job_of(const uint64_t* pre, int32_t k, uint64_t idx) {
+  int32_t lo = 0, hi = k - 1;  // last g with pre[g] <= idx
+  while (lo < hi) {
+    const int32_t mid = (lo + hi + 1) >> 1;
+    if (pre[mid] <= idx) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
+
+__device__ __forceinline__ KernelArgs job_args(const KernelArgs& base, const GraphDesc& d, int32_t g) {
+  KernelArgs a = base;
+  a.off = d.off;
+  a.adj = d.adj;
+  a.src = d.src;
+  a.rec = d.rec;
+  a.in_off = d.in_off;
+  a.t_rank = d.t_rank;
+  a.per_graph = base.per_graph ? base.per_graph + g : nullptr;
+  a.graph_of_rank = nullptr;
+  return a;
+}
+
+// The persistent intersection kernel. Phase 1: blocks take hub items from
+// queue 0 (a slice of a long N_u staged by all 512 threads, in-edge records
+// probed by the eight waves). Phase 2: each wave takes split items from queue 1
+// and then chunks of small pivots from queue 2, each staged by the wave alone.
+// The dynamic LDS region serves as the block table in phase 1 and as eight
+// per-wave tables in phase 2 (a block enters phase 2 only after its phase 1).
+// With MULTI the queues run over the work of the graphs of a JobList.
+template <int MODE, bool MULTI>
+__global__ __launch_bounds__(kPivotBlock, TC_PIVOT_MIN_WAVES) void k_pivot(
+    KernelArgs a, const PivotItem* __restrict__ hub_items, uint64_t n_hub, const PivotItem* __restrict__ split_items,
+    uint64_t n_split, const int32_t* __restrict__ grouped, uint64_t n_grouped, unsigned long long* __restrict__ queues,
+    int hub_log2b, JobList jobs) {
   extern __shared__ int4 smem4[];
   int32_t* smem = reinterpret_cast<int32_t*>(smem4);
   // record arrays: the block's in phase 1, one per wave in phase 2
@@ -498,7 +585,7 @@ __global__ __launch_bounds__(kPivotBlock, TC_PIVOT_MIN_WAVES) void k_pivot(Kerne
   __shared__ unsigned long long cur;
   __shared__ unsigned long long red[kPivotWaves];
   const int tid = threadIdx.x, w = tid / kWave, lane = lane_id();
-  const bool per_node = MODE == kCountPerNode;
+  constexpr bool per_node = MODE == kCountPerNode;
   unsigned long long acc = 0;
 
   // ---- phase 1: hub items, one block each
@@ -510,38 +597,13 @@ __global__ __launch_bounds__(kPivotBlock, TC_PIVOT_MIN_WAVES) void k_pivot(Kerne
       __syncthreads();
       const unsigned long long it = cur;
       if (it >= n_hub) break;
-      const PivotItem item = hub_items[it];
-      const int log2b = log2_buckets(item.nlen, a.bucket_load);
-      const int S = 4 << log2b;
-      for (int s = tid; s < S; s += kPivotBlock) {
-        T[s] = kEmpty;
-        if (per_node) C[s] = 0;
+      if (MULTI) {
+        const int32_t g = job_of(jobs.pre, jobs.k, it);
+        const GraphDesc d = jobs.descs[g];
+        acc += hub_item<MODE>(job_args(a, d, g), d.hub[it - jobs.pre[g]], T, C, rl.block, scan_tmp, red);
+      } else {
+        acc += hub_item<MODE>(a, hub_items[it], T, C, rl.block, scan_tmp, red);
       }
-      __syncthreads();
-      const int64_t nb = a.off[item.u] + item.nbeg_rel;
-      for (uint32_t k = tid; k < item.nlen; k += kPivotBlock) bt_insert(T, log2b, a.adj[nb + k]);
-      __syncthreads();
-      uint32_t cnt = 0;
-      for (uint32_t r0 = item.ibeg; r0 < item.iend; r0 += kPivotBlock)
-        cnt += probe_batch_block<MODE>(a, item.u, r0, item.iend < r0 + kPivotBlock ? item.iend : r0 + kPivotBlock, T, log2b,
-                                 C, rl.block, scan_tmp);
-      const unsigned long long ws = wave_sum(static_cast<unsigned long long>(cnt));
-      if (lane == 0) red[w] = ws;
-      __syncthreads();
-      if (per_node) {
-        for (int s = tid; s < S; s += kPivotBlock)
-          if (C[s]) atomicAdd(&a.t_rank[T[s]], static_cast<unsigned long long>(C[s]));
-      }
-      if (tid == 0) {
-        unsigned long long tot = 0;
-        for (int x = 0; x < kPivotWaves; x++) tot += red[x];
-        if (tot) {
-          acc += tot;
-          if (a.per_graph) atomicAdd(&a.per_graph[a.graph_of_rank ? a.graph_of_rank[item.u] : 0], tot);
-          if (per_node) atomicAdd(&a.t_rank[item.u], tot);
-        }
-      }
-      __syncthreads();
     }
   }
 
@@ -555,19 +617,40 @@ __global__ __launch_bounds__(kPivotBlock, TC_PIVOT_MIN_WAVES) void k_pivot(Kerne
       if (lane == 0) it = n_split ? atomicAdd(&queues[1], 1ull) : 0ull;
       it = __shfl(it, 0, kWave);
       if (it >= n_split) break;
-      const PivotItem item = split_items[it];
-      acc += wave_pivot<MODE>(a, item.u, item.ibeg, item.iend, T, C, rl.wave[w]);
+      if (MULTI) {
+        const uint64_t* pre = jobs.pre + (jobs.k + 1);
+        const int32_t g = job_of(pre, jobs.k, it);
+        const GraphDesc d = jobs.descs[g];
+        const PivotItem item = d.split[it - pre[g]];
+        acc += wave_pivot<MODE>(job_args(a, d, g), item.u, item.ibeg, item.iend, T, C, rl.wave[w]);
+      } else {
+        const PivotItem item = split_items[it];
+        acc += wave_pivot<MODE>(a, item.u, item.ibeg, item.iend, T, C, rl.wave[w]);
+      }
     }
     for (;;) {
-      unsigned long long g0 = 0;
-      if (lane == 0) g0 = n_grouped ? atomicAdd(&queues[2], static_cast<unsigned long long>(kGroupChunk)) : 0ull;
-      g0 = __shfl(g0, 0, kWave);
-      if (g0 >= n_grouped) break;
-      const uint64_t g1 = g0 + kGroupChunk < n_grouped ? g0 + kGroupChunk : n_grouped;
-      for (uint64_t g = g0; g < g1; g++) {
-        const int32_t u = grouped[g];
-        acc += wave_pivot<MODE>(a, u, static_cast<uint32_t>(a.in_off[u]), static_cast<uint32_t>(a.in_off[u + 1]), T, C,
-                          rl.wave[w]);
+      unsigned long long c = 0;
+      if (lane == 0) c = n_grouped ? atomicAdd(&queues[2], 1ull) : 0ull;  // one chunk of kGroupChunk pivots
+      c = __shfl(c, 0, kWave);
+      const uint64_t n_chunks = MULTI ? n_grouped : (n_grouped + kGroupChunk - 1) / kGroupChunk;
+      if (c >= n_chunks) break;
+      KernelArgs ga = a;
+      const int32_t* glist = grouped;
+      uint64_t g0 = c * kGroupChunk, gend = n_grouped;
+      if (MULTI) {
+        const uint64_t* pre = jobs.pre + 2 * (jobs.k + 1);
+        const int32_t g = job_of(pre, jobs.k, c);
+        const GraphDesc d = jobs.descs[g];
+        ga = job_args(a, d, g);
+        glist = d.grouped;
+        g0 = (c - pre[g]) * kGroupChunk;
+        gend = d.n_grouped;
+      }
+      const uint64_t g1 = g0 + kGroupChunk < gend ? g0 + kGroupChunk : gend;
+      for (uint64_t x = g0; x < g1; x++) {
+        const int32_t u = glist[x];
+        acc += wave_pivot<MODE>(ga, u, static_cast<uint32_t>(ga.in_off[u]), static_cast<uint32_t>(ga.in_off[u + 1]), T,
+                                C, rl.wave[w]);
       }
     }
   }
@@ -742,15 +825,72 @@ void count_pivot(Csr& c, const CountArgs& ca, hipStream_t s, const Options& o, b
   const unsigned grid = static_cast<unsigned>(blocks_needed < cap_blocks ? blocks_needed : cap_blocks);
   const PivotItem* hub = P.items.p;
   const PivotItem* split = P.items.p + P.n_hub_items;
+  const JobList none{nullptr, nullptr, 0};
   if (ca.mode == kCountPerNode)
-    k_pivot<kCountPerNode><<<grid, kPivotBlock, lds, s>>>(a, hub, P.n_hub_items, split, P.n_wave_items, P.grouped.p,
-                                                          P.n_grouped, q, hub_log2b);
+    k_pivot<kCountPerNode, false><<<grid, kPivotBlock, lds, s>>>(a, hub, P.n_hub_items, split, P.n_wave_items,
+                                                                 P.grouped.p, P.n_grouped, q, hub_log2b, none);
   else if (ca.mode == kCountList)
-    k_pivot<kCountList><<<grid, kPivotBlock, lds, s>>>(a, hub, P.n_hub_items, split, P.n_wave_items, P.grouped.p,
-                                                       P.n_grouped, q, hub_log2b);
+    k_pivot<kCountList, false><<<grid, kPivotBlock, lds, s>>>(a, hub, P.n_hub_items, split, P.n_wave_items,
+                                                              P.grouped.p, P.n_grouped, q, hub_log2b, none);
   else
-    k_pivot<kCountTotal><<<grid, kPivotBlock, lds, s>>>(a, hub, P.n_hub_items, split, P.n_wave_items, P.grouped.p,
-                                                        P.n_grouped, q, hub_log2b);
+    k_pivot<kCountTotal, false><<<grid, kPivotBlock, lds, s>>>(a, hub, P.n_hub_items, split, P.n_wave_items,
+                                                               P.grouped.p, P.n_grouped, q, hub_log2b, none);
+  TC_LAUNCH_CHECK();
+}
+
+// One launch over the work of several graphs (plans must be ready). mode is
+// kCountTotal or kCountPerNode; per-graph totals go to T_dev[g] (zeroed here),
+// per-node counts by rank to t_rank[g] (zeroed here, per-node mode only).
+void count_multi(const std::vector<Csr*>& gs, const std::vector<unsigned long long*>& t_rank, int mode,
+                 unsigned long long* T_dev, hipStream_t s, const Options& o) {
+  const int32_t k = static_cast<int32_t>(gs.size());
+  if (k == 0) return;
+  std::vector<GraphDesc> descs(k);
+  std::vector<uint64_t> pre(3 * (static_cast<size_t>(k) + 1), 0);
+  int32_t dmax = 0;
+  for (int32_t g = 0; g < k; g++) {
+    Csr& c = *gs[g];
+    if (!c.plan.ready) fail(TC_E_INVAL, "graph without a work plan in a multi-graph count");
+    const PivotPlan& P = c.plan;
+    descs[g] = GraphDesc{c.off.p, c.adj.p, c.src.p, P.inrec.p, P.in_off.p, P.items.p, P.items.p + P.n_hub_items,
+                         P.grouped.p, P.n_grouped, mode == kCountPerNode ? t_rank[g] : nullptr};
+    pre[g + 1] = pre[g] + (c.m ? P.n_hub_items : 0);
+    pre[(k + 1) + g + 1] = pre[(k + 1) + g] + (c.m ? P.n_wave_items : 0);
+    pre[2 * (k + 1) + g + 1] = pre[2 * (k + 1) + g] + (c.m ? (P.n_grouped + kGroupChunk - 1) / kGroupChunk : 0);
+    if (P.n_hub_items && c.dhat_max > dmax) dmax = c.dhat_max;
+    if (mode == kCountPerNode && c.n > 0) fill_u64(t_rank[g], static_cast<size_t>(c.n), 0ull, s);
+  }
+  fill_u64(T_dev, static_cast<size_t>(k), 0ull, s);
+  const uint64_t n_hub = pre[k], n_split = pre[2 * k + 1], n_chunks = pre[3 * k + 2];
+  if (n_hub + n_split + n_chunks == 0) return;
+  DevBuf<GraphDesc> d_desc(k, s);
+  DevBuf<uint64_t> d_pre(pre.size(), s);
+  DevBuf<unsigned long long> q(3, s);
+  TC_HIP(hipMemcpyAsync(d_desc.get(), descs.data(), k * sizeof(GraphDesc), hipMemcpyHostToDevice, s));
+  TC_HIP(hipMemcpyAsync(d_pre.get(), pre.data(), pre.size() * sizeof(uint64_t), hipMemcpyHostToDevice, s));
+  fill_u64(q.get(), 3, 0ull, s);
+  const bool per_node = mode == kCountPerNode;
+  int hub_log2b = 4;
+  const int64_t cap = hub_slice_cap(kCountPerNode);
+  const int64_t maxlen = dmax < cap ? dmax : cap;
+  while ((1ll << hub_log2b) * o.hub_bucket_load < maxlen) hub_log2b++;
+  const size_t hub_lds = (static_cast<size_t>(4) << hub_log2b) * sizeof(int32_t) * (per_node ? 2 : 1);
+  const size_t wave_lds = static_cast<size_t>(kPivotWaves) * kWaveSlots * sizeof(int32_t) * (per_node ? 2 : 1);
+  const size_t lds = hub_lds > wave_lds ? hub_lds : wave_lds;
+  const unsigned cus = static_cast<unsigned>(device_cus());
+  const unsigned bpc = static_cast<unsigned>(o.blocks_per_cu > 0 ? o.blocks_per_cu : 4);
+  const uint64_t blocks_needed = n_hub + (n_split + n_chunks + kPivotWaves - 1) / kPivotWaves;
+  const uint64_t cap_blocks = static_cast<uint64_t>(cus) * bpc;
+  const unsigned grid = static_cast<unsigned>(blocks_needed < cap_blocks ? blocks_needed : cap_blocks);
+  KernelArgs a{static_cast<int>(o.hub_bucket_load), nullptr, nullptr, nullptr, nullptr, nullptr, mode, nullptr, T_dev,
+               nullptr, nullptr, nullptr, nullptr, nullptr, 0};
+  const JobList jobs{d_desc.get(), d_pre.get(), k};
+  if (per_node)
+    k_pivot<kCountPerNode, true><<<grid, kPivotBlock, lds, s>>>(a, nullptr, n_hub, nullptr, n_split, nullptr,
+                                                                n_chunks, q.get(), hub_log2b, jobs);
+  else
+    k_pivot<kCountTotal, true><<<grid, kPivotBlock, lds, s>>>(a, nullptr, n_hub, nullptr, n_split, nullptr, n_chunks,
+                                                              q.get(), hub_log2b, jobs);
   TC_LAUNCH_CHECK();
 }
 

@@ -109,6 +109,9 @@ struct tc_graph {
   // workspace for the capturable batched count
   tc::Owned<unsigned char> workspace;
   size_t workspace_bytes = 0;
+  // sampled graphs (tc_sparsify_build): edges kept and the keep probability
+  bool sampled = false;
+  double q = 1.0;
   std::mutex mu;  // guards lazy plan construction
 };
 
@@ -145,6 +148,8 @@ void ensure_plan(Csr& c, hipStream_t s, const Options& o);
 // allow_rebuild = false: use the cached plan as is (capturable; fails if absent)
 void count_pivot(Csr& c, const CountArgs& a, hipStream_t s, const Options& o, bool allow_rebuild = true);
 void fill_u64(unsigned long long* p, size_t n, unsigned long long v, hipStream_t s);
+void count_multi(const std::vector<Csr*>& gs, const std::vector<unsigned long long*>& t_rank, int mode,
+                 unsigned long long* T_dev, hipStream_t s, const Options& o);
 void count_plain(const Csr& c, unsigned long long* total, hipStream_t s);
 void graph_work(const Csr& c, unsigned long long* W, unsigned long long* P, hipStream_t s);
 void build_sampled_csr(const tc_graph* g, double q, uint64_t seed, Csr& out, hipStream_t s);

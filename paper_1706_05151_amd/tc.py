@@ -41,6 +41,10 @@ SIGNATURES = {
     "tc_batch_build": ([_vp, _vp, _vp, _vp, _i32, _u32, _vp, _P(_vp)], ctypes.c_int),
     "tc_batch_size": ([_vp, _P(_i32)], ctypes.c_int),
     "tc_batch_count": ([_vp, _vp, _vp, _vp], ctypes.c_int),
+    "tc_multi_count": ([_vp, _i32, _i32, _vp, _vp, _vp], ctypes.c_int),
+    "tc_clustering_from_counts": ([_vp, _vp, _vp, _vp, _vp, _vp], ctypes.c_int),
+    "tc_sparsify_build": ([_vp, _dbl, _u64, _vp, _P(_vp)], ctypes.c_int),
+    "tc_sparsify_estimate": ([_u64, _dbl], _dbl),
     "tc_status_str": ([ctypes.c_int], ctypes.c_char_p),
     "tc_last_error": ([], ctypes.c_char_p),
 }
@@ -229,6 +233,18 @@ class Graph:
         _check(lib().tc_batch_count(self._h, _stream(stream), _dptr(T_out), _dptr(t_out) if t_out is not None else None),
                "tc_batch_count")
 
+    def sparsify_build(self, q: float, seed: int, stream=None) -> "Graph":
+        """The Section 7 edge sample as a graph of its own (totals only)."""
+        torch = _torch()
+        h = _vp()
+        _check(lib().tc_sparsify_build(self._h, float(q), int(seed) & (2 ** 64 - 1), _stream(stream), ctypes.byref(h)),
+               "tc_sparsify_build")
+        return Graph(h, torch.cuda.current_device())
+
+    def clustering_from_counts(self, t, num, den, c, stream=None):
+        _check(lib().tc_clustering_from_counts(self._h, _stream(stream), _dptr(t), _dptr(num), _dptr(den), _dptr(c)),
+               "tc_clustering_from_counts")
+
     # ----------------------------------------------------------- lifetime
     def close(self):
         if self._h is not None and self._h.value:
@@ -246,3 +262,19 @@ class Graph:
 
     def __exit__(self, *exc):
         self.close()
+
+
+def multi_count(graphs, T_out, t_outs=None, stream=None):
+    """One launch counting every graph of ``graphs``; T_out int64[k] (device),
+    optional per-node outputs t_outs[i] int64[n_i] (device). No host sync."""
+    k = len(graphs)
+    arr = (_vp * max(k, 1))(*[g._h for g in graphs])
+    tp = None
+    if t_outs is not None:
+        tp = (_vp * max(k, 1))(*[ctypes.c_void_p(t.data_ptr()) for t in t_outs])
+    _check(lib().tc_multi_count(arr, k, 1 if t_outs is not None else 0, _stream(stream), _dptr(T_out), tp),
+           "tc_multi_count")
+
+
+def sparsify_estimate(Ts: int, q: float) -> float:
+    return float(lib().tc_sparsify_estimate(int(Ts), float(q)))

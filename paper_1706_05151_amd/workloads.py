@@ -1,0 +1,163 @@
+"""Benchmark drivers for the batched and served workloads (used by bench.py)."""
+from __future__ import annotations
+
+import time
+
+import numpy as np
+
+from . import batch, serve, tc
+
+METRIC = "exact-count oriented edges/s vs plain kernel; served graphs/s + p50/p99 latency"
+
+
+def _log(*a):
+    import sys
+
+    print(*a, file=sys.stderr, flush=True)
+
+
+def run_batch(args):
+    """4096 graphs, n ~ U[64,8192], 1/3 ER (avg degree U[8,32]), 1/3 BA (k ~ U{4..16}),
+    1/3 R-MAT (edge factor 8, scale floor(log2 n)), seed 4. One step = batched
+    build + per-graph T and t_v. Baseline: per-graph tc_build_csr + tc_count_per_node."""
+    import torch
+
+    import synth
+
+    torch.cuda.set_device(0)
+    t0 = time.perf_counter()
+    specs = synth.batch_specs(4096, 4)
+    els = [s.make() for s in specs]
+    packed = batch.pack(els)
+    _log(f"[batch] {len(els)} graphs, {packed['src'].shape[0]} edge records, generated in {time.perf_counter() - t0:.1f} s")
+    bc = batch.BatchCounter(packed, per_node=True)
+    bc.build()
+    best, table = batch.autotune(bc, key="batch4096-seed4", persist=False)
+    _log(f"[batch] autotuned options {best['options']} ({best['ms']:.2f} ms count)")
+    bc.count()
+    torch.cuda.synchronize()
+    T_ref = bc.T.cpu().numpy().copy()
+    t_ref = bc.per_graph_t()
+    for _ in range(args.warmup):
+        bc.build()
+        bc.count()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        bc.build()
+        bc.count()
+    torch.cuda.synchronize()
+    step_s = (time.perf_counter() - t0) / args.steps
+    assert np.array_equal(bc.T.cpu().numpy(), T_ref)
+    # count only, eager and replayed from a HIP graph
+    reps = 20
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        bc.count()
+    torch.cuda.synchronize()
+    eager_ms = 1e3 * (time.perf_counter() - t0) / reps
+    bc.capture()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        bc.replay()
+    torch.cuda.synchronize()
+    replay_ms = 1e3 * (time.perf_counter() - t0) / reps
+    assert np.array_equal(bc.T.cpu().numpy(), T_ref)
+    # baseline: one graph at a time
+    src_d, dst_d = bc.src, bc.dst
+    eoff = packed["edge_off"]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    same = True
+    for i, el in enumerate(els):
+        g = tc.Graph.build(src_d[eoff[i]:eoff[i + 1]], dst_d[eoff[i]:eoff[i + 1]], el.n)
+        T, t = g.count_per_node()
+        if T != int(T_ref[i]) or not np.array_equal(t.cpu().numpy().astype(np.uint64), t_ref[i]):
+            same = False
+        g.close()
+    torch.cuda.synchronize()
+    plain_s = time.perf_counter() - t0
+    assert same, "batched and per-graph results differ"
+    m_total = int(bc.graph.m)
+    out = {
+        "metric": METRIC, "value": len(els) / step_s, "unit": "graphs/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": 1e3 * step_s, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "int32", "data": "synthetic",
+        "config": {"workload": "batch4096-mixed-seed4", "graphs": len(els), "edge_records": int(packed["src"].shape[0]),
+                   "m": m_total, "T_total": int(T_ref.sum()),
+                   "step": "tc_batch_build + tc_batch_count (per-graph T and t_v) for all graphs",
+                   "parallelism": "single GPU"},
+        "count_eager_ms": eager_ms, "count_hipgraph_replay_ms": replay_ms,
+        "plain_per_graph_s": plain_s, "plain_graphs_per_s": len(els) / plain_s,
+        "speedup_vs_plain_per_graph": plain_s / step_s, "identical_to_per_graph": same,
+        "autotune": {"best": best, "table": table},
+    }
+    bc.close()
+    return out
+
+
+def run_serve(args):
+    """Pool of 1024 graphs (n log-uniform in [1e3,1e6], avg degree 16: ER, BA k=8,
+    R-MAT edge factor 8), seed 5; Poisson arrivals at 2000 req/s; mix 60% count,
+    25% clustering, 15% sparsified estimate q=0.2. HBM budget 64 GiB."""
+    import torch
+
+    import synth
+
+    torch.cuda.set_device(0)
+    duration = float(getattr(args, "serve_seconds", 60.0))
+    rate = 2000.0
+    t0 = time.perf_counter()
+    specs = synth.pool_specs(1024, 5)
+    els = [s.make() for s in specs]
+    m_sum = sum(e.num_edges for e in els)
+    _log(f"[serve] pool of {len(els)} graphs, {m_sum} edge records, generated in {time.perf_counter() - t0:.1f} s")
+    reg = serve.Registry(els, budget_bytes=64 << 30)
+    t0 = time.perf_counter()
+    for i in range(len(els)):
+        reg.get(i)
+        reg.get(i, (0.2, 5))
+    torch.cuda.synchronize()
+    _log(f"[serve] pool resident ({reg.used / 2**30:.1f} GiB) after {time.perf_counter() - t0:.1f} s")
+    trace = serve.make_trace(len(els), rate, duration, 5)
+    srv = serve.Server(reg, max_batch=64, streams=3)
+    t0 = time.perf_counter()
+    ans = srv.run(trace, t0)
+    wall = time.perf_counter() - t0
+    stats = serve.latency_stats(trace, ans, wall)
+    _log(f"[serve] batched: {stats}")
+    # FIFO baseline on the first 10 s of the same trace
+    sub = [r for r in trace if r.arrival < min(10.0, duration)]
+    t0 = time.perf_counter()
+    fans = serve.serve_fifo(reg, sub, t0)
+    fwall = time.perf_counter() - t0
+    fstats = serve.latency_stats(sub, fans, fwall)
+    srv2 = serve.Server(reg, max_batch=64, streams=3)
+    t0 = time.perf_counter()
+    bans = srv2.run(sub, t0)
+    bstats = serve.latency_stats(sub, bans, time.perf_counter() - t0)
+    same = all(serve.same_answer(fans[r.rid], bans[r.rid]) and serve.same_answer(fans[r.rid], ans[r.rid]) for r in sub)
+    _log(f"[serve] fifo (first 10 s): {fstats}; batched on the same: {bstats}; identical={same}")
+    assert same, "served results differ from one-at-a-time results"
+    out = {
+        "metric": METRIC, "value": stats["req_per_s"], "unit": "graphs/s", "n_gpus": 1, "steps": 1, "warmup": 0,
+        "ms_per_step": 1e3 * wall, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "int32", "data": "synthetic",
+        "config": {"workload": "serve-pool1024-poisson2000-seed5", "pool_graphs": len(els), "pool_edge_records": m_sum,
+                   "rate_per_s": rate, "duration_s": duration, "mix": "60% count, 25% clustering, 15% q=0.2 estimate",
+                   "hbm_budget_gib": 64, "parallelism": "single GPU"},
+        "served": stats, "batches": srv.batches, "mean_batch": float(np.mean(srv.batch_sizes)),
+        "fifo_first10s": fstats, "batched_first10s": bstats,
+        "speedup_vs_fifo": fstats["wall_s"] / bstats["wall_s"], "identical_to_fifo": same,
+        "registry": {"builds": reg.builds, "evictions": reg.evictions, "resident_gib": reg.used / 2**30},
+    }
+    reg.close()
+    return out
+
+
+def run(args):
+    if args.workload == "batch":
+        return run_batch(args)
+    return run_serve(args)

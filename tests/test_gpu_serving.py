@@ -1,0 +1,174 @@
+"""GPU tests of the batched and served paths: every result equals the
+single-graph result (exact counts, bit-identical clustering doubles and estimates)."""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+@pytest.fixture(scope="module")
+def tcm():
+    import torch
+
+    assert torch.cuda.is_available()
+    from paper_1706_05151_amd import tc
+
+    keys = (tc.OPT_KERNEL, tc.OPT_HUB_DHAT, tc.OPT_ITEM_WORK, tc.OPT_BLOCKS_PER_CU, tc.OPT_HUB_BUCKET_LOAD)
+    saved = {k: tc.get_option(k) for k in keys}
+    yield tc
+    for k, v in saved.items():
+        tc.set_option(k, v)
+
+
+def _graphs(count, seed):
+    return [s.make() for s in synth.batch_specs(count, seed)]
+
+
+def test_multi_count_matches_single(tcm):
+    import torch
+
+    els = _graphs(24, 31) + [synth.complete(10), synth.empty(3), synth.rmat(13, 16, 2)]
+    gs = [tcm.Graph.build(torch.from_numpy(e.src).cuda(), torch.from_numpy(e.dst).cuda(), e.n) for e in els]
+    say(f"[serving] multi count over {len(gs)} graphs")
+    T = torch.zeros(len(gs), dtype=torch.int64, device="cuda")
+    ts = [torch.zeros(max(g.n, 1), dtype=torch.int64, device="cuda") for g in gs]
+    tcm.multi_count(gs, T, None)
+    torch.cuda.synchronize()
+    T1 = T.cpu().numpy().copy()
+    tcm.multi_count(gs, T, ts)
+    torch.cuda.synchronize()
+    for i, (e, g) in enumerate(zip(els, gs)):
+        ref = oracle.solve(e.src, e.dst, e.n)
+        assert T1[i] == ref.T and T[i].item() == ref.T
+        np.testing.assert_array_equal(ts[i][: e.n].cpu().numpy().astype(np.uint64), ref.t)
+        num = torch.empty(max(e.n, 1), dtype=torch.int64, device="cuda")
+        den = torch.empty_like(num)
+        c = torch.empty(max(e.n, 1), dtype=torch.float64, device="cuda")
+        g.clustering_from_counts(ts[i], num, den, c)
+        torch.cuda.synchronize()
+        np.testing.assert_array_equal(c[: e.n].cpu().numpy().view(np.uint64), ref.cc.view(np.uint64))
+    for g in gs:
+        g.close()
+
+
+def test_sparsify_build_matches_sparsify_count(tcm):
+    import torch
+
+    el = synth.rmat(14, 16, 7)
+    with tcm.Graph.build(torch.from_numpy(el.src).cuda(), torch.from_numpy(el.dst).cuda(), el.n) as g:
+        Ts, mk, est = g.sparsify_count(0.2, 5)
+        with g.sparsify_build(0.2, 5) as h:
+            assert h.m == mk and h.count() == Ts
+            assert tcm.sparsify_estimate(Ts, 0.2) == est
+            with pytest.raises(tcm.TCError):
+                h.count_per_node()
+    lo, hi = oracle.simple(el.src, el.dst, el.n)
+    rTs, rmk, rest = oracle.sparsified_count(lo, hi, oracle.degrees(lo, hi, el.n), el.n, 0.2, 5)
+    assert (Ts, mk, est) == (rTs, rmk, rest)
+
+
+def test_batch_hipgraph_replays(tcm):
+    """The captured batched count equals the eager one on every replay, with
+    eager work and synchronisations between the replays."""
+    import torch
+
+    from paper_1706_05151_amd import batch
+
+    els = _graphs(200, 44)
+    packed = batch.pack(els)
+    bc = batch.BatchCounter(packed, per_node=True)
+    bc.build()
+    say(f"[serving] batch of {len(els)} graphs, capture and replay")
+    bc.count()
+    torch.cuda.synchronize()
+    T_ref = bc.T.cpu().numpy().copy()
+    t_ref = [x.copy() for x in bc.per_graph_t()]
+    for i in (0, 7, 199):
+        ref = oracle.solve(els[i].src, els[i].dst, els[i].n)
+        assert T_ref[i] == ref.T
+        np.testing.assert_array_equal(t_ref[i], ref.t)
+    bc.capture()
+    for rep in range(4):
+        bc.T.fill_(-1)
+        bc.t.fill_(-1)
+        bc.replay()
+        torch.cuda.synchronize()
+        np.testing.assert_array_equal(bc.T.cpu().numpy(), T_ref)
+        for a, b in zip(bc.per_graph_t(), t_ref):
+            np.testing.assert_array_equal(a, b)
+        bc.count()  # eager work between replays
+        torch.cuda.synchronize()
+        np.testing.assert_array_equal(bc.T.cpu().numpy(), T_ref)
+    bc.close()
+
+
+def test_autotune_keeps_results(tcm):
+    import torch
+
+    from paper_1706_05151_amd import batch
+
+    els = _graphs(64, 45)
+    bc = batch.BatchCounter(batch.pack(els), per_node=False)
+    bc.build()
+    bc.count()
+    torch.cuda.synchronize()
+    T0 = bc.T.cpu().numpy().copy()
+    old = batch.current_options()
+    try:
+        best, table = batch.autotune(bc, candidates=[(128, 16384, 4, 2), (16, 256, 2, 1), (0, 100000, 3, 2)],
+                                     reps=1, persist=False)
+        assert len(table) == 3
+        bc.count()
+        torch.cuda.synchronize()
+        np.testing.assert_array_equal(bc.T.cpu().numpy(), T0)
+    finally:
+        batch.apply_options(old)
+        bc.close()
+
+
+def test_served_results_equal_standalone(tcm):
+    """Each request's answer in the continuous-batching server equals its
+    one-at-a-time answer, under a budget that forces evictions."""
+    from paper_1706_05151_amd import serve
+
+    els = [s.make() for s in synth.pool_specs(24, 9, n_lo=1e3, n_hi=3e4)]
+    trace = serve.make_trace(len(els), rate=3000.0, duration=0.4, seed=9)
+    say(f"[serving] trace of {len(trace)} requests on {len(els)} graphs")
+    reg = serve.Registry(els, budget_bytes=12 << 20)  # a few graphs at a time
+    srv = serve.Server(reg, max_batch=16, streams=3)
+    ans = srv.run(trace)
+    reg2 = serve.Registry(els, budget_bytes=1 << 34)
+    fifo = serve.serve_fifo(reg2, trace)
+    assert all(not ans[r.rid].error for r in trace)
+    for r in trace:
+        assert serve.same_answer(ans[r.rid], fifo[r.rid]), r
+    assert reg.evictions > 0
+    # spot-check against the oracle
+    for r in trace[:10]:
+        e = els[r.graph]
+        ref = oracle.solve(e.src, e.dst, e.n)
+        if r.kind == serve.COUNT:
+            assert ans[r.rid].value == ref.T
+        elif r.kind == serve.CLUSTER:
+            np.testing.assert_array_equal(ans[r.rid].value[2].view(np.uint64), ref.cc.view(np.uint64))
+    reg.close()
+    reg2.close()
+
+
+def test_served_oversized_graph_is_refused(tcm):
+    from paper_1706_05151_amd import serve
+
+    els = [synth.rmat(12, 16, 1)]
+    reg = serve.Registry(els, budget_bytes=1 << 10)
+    srv = serve.Server(reg, max_batch=4, streams=2)
+    ans = srv.run([serve.Request(0, serve.COUNT, 0, 0.0)])
+    assert ans[0].error == "TC_E_NOMEM"
