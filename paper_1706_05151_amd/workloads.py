@@ -138,7 +138,17 @@ def run_serve(args):
     t0 = time.perf_counter()
     bans = srv2.run(sub, t0)
     bstats = serve.latency_stats(sub, bans, time.perf_counter() - t0)
-    same = all(serve.same_answer(fans[r.rid], bans[r.rid]) and serve.same_answer(fans[r.rid], ans[r.rid]) for r in sub)
+    # capacity at saturation: the same requests all waiting at time 0
+    sat = [serve.Request(r.rid, r.kind, r.graph, 0.0, r.q, r.seed) for r in sub]
+    srv3 = serve.Server(reg, max_batch=256, streams=3)
+    t0 = time.perf_counter()
+    sans = srv3.run(sat, t0)
+    swall = time.perf_counter() - t0
+    sat_stats = {"requests": len(sat), "wall_s": swall, "req_per_s": len(sat) / swall,
+                 "mean_batch": float(np.mean(srv3.batch_sizes))}
+    _log(f"[serve] saturation: {sat_stats}")
+    same = all(serve.same_answer(fans[r.rid], bans[r.rid]) and serve.same_answer(fans[r.rid], ans[r.rid])
+               and serve.same_answer(fans[r.rid], sans[r.rid]) for r in sub)
     _log(f"[serve] fifo (first 10 s): {fstats}; batched on the same: {bstats}; identical={same}")
     assert same, "served results differ from one-at-a-time results"
     out = {
@@ -151,6 +161,7 @@ def run_serve(args):
         "served": stats, "batches": srv.batches, "mean_batch": float(np.mean(srv.batch_sizes)),
         "fifo_first10s": fstats, "batched_first10s": bstats,
         "speedup_vs_fifo": fstats["wall_s"] / bstats["wall_s"], "identical_to_fifo": same,
+        "saturation": sat_stats, "capacity_vs_fifo": sat_stats["req_per_s"] / fstats["req_per_s"],
         "registry": {"builds": reg.builds, "evictions": reg.evictions, "resident_gib": reg.used / 2**30},
     }
     reg.close()
