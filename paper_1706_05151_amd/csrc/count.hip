@@ -284,7 +284,6 @@ constexpr uint32_t kSeg = kWave * kPerLane;
 // Record arrays of one batch of NR records (NR = 256 for a block, 64 for a wave).
 template <int NR>
 struct BatchLds {
-  uint32_t segpre[NR + 1];  // exclusive prefix of segment counts (long records)
   uint32_t spre[NR + 1];    // exclusive prefix of lengths (short records)
   uint32_t beg[NR];
   uint32_t len[NR];
@@ -306,33 +305,33 @@ __device__ __forceinline__ uint32_t probe_one(const KernelArgs& a, int32_t u, in
   return 1u;
 }
 
-// Segments [seg0, nsegs) step `stride` of the long records, one wave per segment.
+// Long records of the batch, wave `w0` of `stride` taking records w0,
+// w0+stride, ...: the wave walks a record's suffix in windows of kSeg
+// elements, lane L reading elements L, L+64, L+128, L+192 of the window.
 template <int MODE, int NR>
-__device__ __forceinline__ uint32_t probe_long(const KernelArgs& a, int32_t u, const BatchLds<NR>& B, uint32_t nsegs,
-                                               uint32_t seg0, uint32_t stride, const int32_t* T, int log2b,
+__device__ __forceinline__ uint32_t probe_long(const KernelArgs& a, int32_t u, const BatchLds<NR>& B, uint32_t nrec,
+                                               uint32_t w0, uint32_t stride, const int32_t* T, int log2b,
                                                uint32_t* C, uint32_t* hits) {
   const int lane = lane_id();
   uint32_t cnt = 0;
-  for (uint32_t sg = seg0; sg < nsegs; sg += stride) {
-    int j = 0;
+  for (uint32_t j = w0; j < nrec; j += stride) {
+    const uint32_t len = __builtin_amdgcn_readfirstlane(B.len[j]);
+    if (len < kLongMin) continue;
+    const uint32_t beg = __builtin_amdgcn_readfirstlane(B.beg[j]);
+    for (uint32_t k0 = 0; k0 < len; k0 += kSeg) {
+      const uint32_t rem = len - k0;
+      int32_t x[kPerLane];
 #pragma unroll
-    for (int step = NR / 2; step > 0; step >>= 1)
-      if (B.segpre[j + step] <= sg) j += step;
-    j = __builtin_amdgcn_readfirstlane(j);
-    const uint32_t rel = (sg - B.segpre[j]) * kSeg;
-    const uint32_t base = __builtin_amdgcn_readfirstlane(B.beg[j] + rel);
-    const uint32_t rem = __builtin_amdgcn_readfirstlane(B.len[j] - rel);
-    int32_t x[kPerLane];
+      for (int i = 0; i < kPerLane; i++) {
+        const uint32_t k = static_cast<uint32_t>(lane + kWave * i);
+        x[i] = (static_cast<uint32_t>(kWave * i) < rem && k < rem) ? a.adj[beg + k0 + k] : kEmpty;
+      }
+      uint32_t h = 0;
 #pragma unroll
-    for (int i = 0; i < kPerLane; i++) {
-      const uint32_t k = static_cast<uint32_t>(lane + kWave * i);
-      x[i] = (static_cast<uint32_t>(kWave * i) < rem && k < rem) ? a.adj[base + k] : kEmpty;
+      for (int i = 0; i < kPerLane; i++)
+        if (x[i] != kEmpty) h += probe_one<MODE>(a, u, x[i], T, log2b, C, &hits[j], beg);
+      cnt += h;
     }
-    uint32_t h = 0;
-#pragma unroll
-    for (int i = 0; i < kPerLane; i++)
-      if (x[i] != kEmpty) h += probe_one<MODE>(a, u, x[i], T, log2b, C, &hits[j], B.beg[j]);
-    cnt += h;
   }
   return cnt;
 }
@@ -372,44 +371,36 @@ __device__ __forceinline__ uint32_t probe_short(const KernelArgs& a, int32_t u, 
   return cnt;
 }
 
-// Fill the batch arrays for the record this thread holds (idx in [0,NR)).
+// Fill the batch arrays for the record this thread holds (idx in [0,NR)):
+// `excl`/`tot` are the exclusive prefix and total of the short-record lengths.
 template <int MODE, int NR>
-__device__ __forceinline__ void batch_fill(const KernelArgs& a, BatchLds<NR>& B, int idx, const InRec& rc,
-                                           uint64_t excl, uint64_t tot) {
-  B.segpre[idx] = static_cast<uint32_t>(excl >> 32);
-  B.spre[idx] = static_cast<uint32_t>(excl);
+__device__ __forceinline__ void batch_fill(BatchLds<NR>& B, int idx, const InRec& rc, uint32_t excl, uint32_t tot) {
+  B.spre[idx] = excl;
   B.beg[idx] = rc.a_begin;
   B.len[idx] = rc.a_len;
   if (MODE != kCountTotal) B.hits[idx] = 0;
-  if (idx == NR - 1) {
-    B.segpre[NR] = static_cast<uint32_t>(tot >> 32);
-    B.spre[NR] = static_cast<uint32_t>(tot);
-  }
+  if (idx == NR - 1) B.spre[NR] = tot;
 }
 
-__device__ __forceinline__ uint64_t seg_short_pack(uint32_t len) {
-  const uint64_t nseg = len >= kLongMin ? (len + kSeg - 1) / kSeg : 0;
-  const uint64_t slen = len >= kLongMin ? 0 : len;
-  return (nseg << 32) | slen;
-}
+__device__ __forceinline__ uint32_t short_len(uint32_t len) { return len >= kLongMin ? 0u : len; }
 
 // Block-wide batch of up to kPivotBlock records for a hub item.
 template <int MODE>
 __device__ __forceinline__ uint32_t probe_batch_block(const KernelArgs& a, int32_t u, uint32_t r0, uint32_t r1,
                                                       const int32_t* T, int log2b, uint32_t* C, BatchLds<kPivotBlock>& B,
-                                                      uint64_t* scan_tmp) {
+                                                      uint32_t* scan_tmp) {
   const int tid = threadIdx.x, w = tid / kWave;
   const uint32_t r = r0 + tid;
   const bool valid = r < r1;
   InRec rc{0u, 0u};
   if (valid) rc = a.rec[r];
-  uint64_t tot;
-  const uint64_t excl = block_excl_scan<uint64_t, kPivotBlock>(seg_short_pack(rc.a_len), scan_tmp, tot);
-  batch_fill<MODE, kPivotBlock>(a, B, tid, rc, excl, tot);
+  uint32_t tot;
+  const uint32_t excl = block_excl_scan<uint32_t, kPivotBlock>(short_len(rc.a_len), scan_tmp, tot);
+  batch_fill<MODE, kPivotBlock>(B, tid, rc, excl, tot);
   __syncthreads();
-  uint32_t cnt = probe_long<MODE, kPivotBlock>(a, u, B, static_cast<uint32_t>(tot >> 32), static_cast<uint32_t>(w),
-                                    kPivotWaves, T, log2b, C, B.hits);
-  cnt += probe_short<MODE, kPivotBlock>(a, u, B, static_cast<uint32_t>(tot), tid, kPivotBlock, T, log2b, C, B.hits);
+  uint32_t cnt = probe_long<MODE, kPivotBlock>(a, u, B, r1 - r0, static_cast<uint32_t>(w), kPivotWaves, T, log2b, C,
+                                               B.hits);
+  cnt += probe_short<MODE, kPivotBlock>(a, u, B, tot, tid, kPivotBlock, T, log2b, C, B.hits);
   __syncthreads();
   if (MODE == kCountPerNode && valid && B.hits[tid])
     atomicAdd(&a.t_rank[a.src[rc.a_begin - 1]], static_cast<unsigned long long>(B.hits[tid]));
@@ -426,13 +417,13 @@ __device__ __forceinline__ uint32_t probe_batch_wave(const KernelArgs& a, int32_
   const bool valid = r < r1;
   InRec rc{0u, 0u};
   if (valid) rc = a.rec[r];
-  const uint64_t p = seg_short_pack(rc.a_len);
-  const uint64_t incl = wave_incl_scan(p);
-  const uint64_t tot = __shfl(incl, kWave - 1, kWave);
-  batch_fill<MODE, kWave>(a, B, lane, rc, incl - p, tot);
+  const uint32_t p = short_len(rc.a_len);
+  const uint32_t incl = wave_incl_scan(p);
+  const uint32_t tot = __shfl(incl, kWave - 1, kWave);
+  batch_fill<MODE, kWave>(B, lane, rc, incl - p, tot);
   wave_sync();
-  uint32_t cnt = probe_long<MODE, kWave>(a, u, B, static_cast<uint32_t>(tot >> 32), 0u, 1u, T, log2b, C, B.hits);
-  cnt += probe_short<MODE, kWave>(a, u, B, static_cast<uint32_t>(tot), lane, kWave, T, log2b, C, B.hits);
+  uint32_t cnt = probe_long<MODE, kWave>(a, u, B, r1 - r0, 0u, 1u, T, log2b, C, B.hits);
+  cnt += probe_short<MODE, kWave>(a, u, B, tot, lane, kWave, T, log2b, C, B.hits);
   if (MODE == kCountPerNode) {
     wave_sync();
     if (valid && B.hits[lane]) atomicAdd(&a.t_rank[a.src[rc.a_begin - 1]], static_cast<unsigned long long>(B.hits[lane]));
@@ -480,7 +471,7 @@ __device__ __forceinline__ unsigned long long wave_pivot(const KernelArgs& a, in
 // item's triangle count (valid in thread 0).
 template <int MODE>
 __device__ __forceinline__ unsigned long long hub_item(const KernelArgs& a, const PivotItem& item, int32_t* T,
-                                                       uint32_t* C, BatchLds<kPivotBlock>& bl, uint64_t* scan_tmp,
+                                                       uint32_t* C, BatchLds<kPivotBlock>& bl, uint32_t* scan_tmp,
                                                        unsigned long long* red) {
   const int tid = threadIdx.x, w = tid / kWave, lane = lane_id();
   constexpr bool per_node = MODE == kCountPerNode;
@@ -581,7 +572,7 @@ __global__ __launch_bounds__(kPivotBlock, TC_PIVOT_MIN_WAVES) void k_pivot(
     BatchLds<kPivotBlock> block;
     BatchLds<kWave> wave[kPivotWaves];
   } rl;
-  __shared__ uint64_t scan_tmp[kPivotWaves];
+  __shared__ uint32_t scan_tmp[kPivotWaves];
   __shared__ unsigned long long cur;
   __shared__ unsigned long long red[kPivotWaves];
   const int tid = threadIdx.x, w = tid / kWave, lane = lane_id();
