@@ -1,0 +1,70 @@
+"""Parity at the full R-MAT scale-26 size (edge factor 16, seed 3), in the
+launch configuration bench.py times: totals, work, degrees and the sparsified
+counts against the oracle's stored results (tests/golden/rmat26.json, written
+by tests/golden/make_rmat26.py), per-node counts at 64 sampled vertices
+computed by the oracle from the definition, and sum_v t_v = 3T."""
+import json
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+pytestmark = pytest.mark.gpu
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "rmat26.json")
+
+
+@pytest.fixture(scope="module")
+def rmat26():
+    import torch
+
+    from paper_1706_05151_amd import tc
+
+    with open(GOLDEN) as f:
+        gold = json.load(f)
+    el = synth.config_rmat(26)
+    print(f"[rmat26] generated E={el.num_edges}", flush=True)
+    src = torch.from_numpy(el.src).cuda()
+    dst = torch.from_numpy(el.dst).cuda()
+    n = el.n
+    del el
+    g = tc.Graph.build(src, dst, n)
+    del src, dst
+    torch.cuda.empty_cache()
+    print(f"[rmat26] built m={g.m}", flush=True)
+    yield g, gold
+    g.close()
+
+
+def test_totals(rmat26):
+    g, gold = rmat26
+    assert g.n == gold["n"] and g.m == gold["m"]
+    assert g.d_max == gold["d_max"] and g.dhat_max == gold["dhat_max"]
+    assert g.count() == gold["T"]
+    W, P = g.work()
+    assert W == gold["W"]
+
+
+def test_per_node_samples(rmat26):
+    g, gold = rmat26
+    T, t = g.count_per_node()
+    assert T == gold["T"]
+    assert int(t.sum().item()) == 3 * gold["T"]
+    ids = np.array(gold["sample_ids"], dtype=np.int64)
+    tt = t.cpu().numpy().astype(np.uint64)
+    np.testing.assert_array_equal(tt[ids], np.array(gold["sample_t"], dtype=np.uint64))
+    deg, dhat = g.degrees()
+    np.testing.assert_array_equal(deg.cpu().numpy()[ids], np.array(gold["sample_deg"], dtype=np.int32))
+    assert int(dhat.sum().item()) == gold["m"]
+
+
+@pytest.mark.parametrize("q", ["0.1", "0.5"])
+def test_sparsified(rmat26, q):
+    g, gold = rmat26
+    ref = gold["sparsified"][q]
+    Ts, mk, est = g.sparsify_count(float(q), ref["seed"])
+    assert (Ts, mk) == (ref["T_s"], ref["m_kept"])
+    assert est == oracle.estimate(Ts, float(q))
