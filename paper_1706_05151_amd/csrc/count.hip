@@ -236,6 +236,57 @@ __device__ __forceinline__ int log2_buckets(int64_t len, int load = 1) {
   return l;
 }
 
+// A staged list: the bucket table T (4 << log2b slots), a bit filter F with
+// 8 bits per slot (16 per entry at two entries per bucket) tested before the
+// table, and per-slot tallies C (per-node mode). A probe reads one 4-byte
+// filter word; only filter hits (true hits and ~6% false positives) read the
+// 16-byte bucket.
+struct Table {
+  int32_t* T;
+  uint32_t* F;
+  uint32_t* C;
+  int log2b;
+};
+
+__device__ __forceinline__ uint32_t filter_bit(int32_t x, int log2b) {
+  return (static_cast<uint32_t>(x) * 0x85EBCA77u) >> (32 - (log2b + 5));
+}
+
+// Words of a table region of 2^log2b buckets: T, then F, then C (per-node).
+__host__ __device__ __forceinline__ int table_words(int log2b, bool per_node) {
+  return (4 << log2b) + (1 << log2b) + (per_node ? (4 << log2b) : 0);
+}
+
+__device__ __forceinline__ Table table_at(int32_t* base, int log2b, bool per_node) {
+  Table t;
+  t.log2b = log2b;
+  t.T = base;
+  t.F = reinterpret_cast<uint32_t*>(base + (4 << log2b));
+  t.C = per_node ? reinterpret_cast<uint32_t*>(base + (4 << log2b) + (1 << log2b)) : nullptr;
+  return t;
+}
+
+__device__ __forceinline__ void tb_clear(const Table& t, int i0, int step) {
+  const int S = 4 << t.log2b;
+  for (int s = i0; s < S; s += step) {
+    t.T[s] = kEmpty;
+    if (t.C) t.C[s] = 0;
+  }
+  for (int w = i0; w < (1 << t.log2b); w += step) t.F[w] = 0u;
+}
+
+__device__ __forceinline__ void tb_insert(const Table& t, int32_t x) {
+  bt_insert(t.T, t.log2b, x);
+  const uint32_t f = filter_bit(x, t.log2b);
+  atomicOr(&t.F[f >> 5], 1u << (f & 31u));
+}
+
+__device__ __forceinline__ int tb_find(const Table& t, int32_t x) {
+  const uint32_t f = filter_bit(x, t.log2b);
+  if (!((t.F[f >> 5] >> (f & 31u)) & 1u)) return -1;
+  return bt_find(t.T, t.log2b, x);
+}
+
 struct KernelArgs {
   int bucket_load;  // target entries per 4-slot bucket of a hub table (1 or 2)
   const int64_t* off;
@@ -292,12 +343,12 @@ struct BatchLds {
 
 // Probe one element against the table; counts, per-node tallies and listing.
 template <int MODE>
-__device__ __forceinline__ uint32_t probe_one(const KernelArgs& a, int32_t u, int32_t x, const int32_t* T, int log2b,
-                                              uint32_t* C, uint32_t* hit_rec, uint32_t rec_begin) {
-  const int s = bt_find(T, log2b, x);
+__device__ __forceinline__ uint32_t probe_one(const KernelArgs& a, int32_t u, int32_t x, const Table& tab,
+                                              uint32_t* hit_rec, uint32_t rec_begin) {
+  const int s = tb_find(tab, x);
   if (s < 0) return 0u;
   if (MODE == kCountPerNode) {
-    atomicAdd(&C[s], 1u);
+    atomicAdd(&tab.C[s], 1u);
     atomicAdd(hit_rec, 1u);
   } else if (MODE == kCountList) {
     emit_triangle(a, a.src[rec_begin - 1], u, x);
@@ -310,8 +361,8 @@ __device__ __forceinline__ uint32_t probe_one(const KernelArgs& a, int32_t u, in
 // elements, lane L reading elements L, L+64, L+128, L+192 of the window.
 template <int MODE, int NR>
 __device__ __forceinline__ uint32_t probe_long(const KernelArgs& a, int32_t u, const BatchLds<NR>& B, uint32_t nrec,
-                                               uint32_t w0, uint32_t stride, const int32_t* T, int log2b,
-                                               uint32_t* C, uint32_t* hits) {
+                                               uint32_t w0, uint32_t stride, const Table& tab,
+                                               uint32_t* hits) {
   const int lane = lane_id();
   uint32_t cnt = 0;
   for (uint32_t j = w0; j < nrec; j += stride) {
@@ -329,7 +380,7 @@ __device__ __forceinline__ uint32_t probe_long(const KernelArgs& a, int32_t u, c
       uint32_t h = 0;
 #pragma unroll
       for (int i = 0; i < kPerLane; i++)
-        if (x[i] != kEmpty) h += probe_one<MODE>(a, u, x[i], T, log2b, C, &hits[j], beg);
+        if (x[i] != kEmpty) h += probe_one<MODE>(a, u, x[i], tab, &hits[j], beg);
       cnt += h;
     }
   }
@@ -340,8 +391,7 @@ __device__ __forceinline__ uint32_t probe_long(const KernelArgs& a, int32_t u, c
 // this thread taking kPerLane consecutive ones at its slot `slot` of `width`.
 template <int MODE, int NR>
 __device__ __forceinline__ uint32_t probe_short(const KernelArgs& a, int32_t u, const BatchLds<NR>& B, uint32_t tot,
-                                                int slot, int width, const int32_t* T, int log2b, uint32_t* C,
-                                                uint32_t* hits) {
+                                                int slot, int width, const Table& tab, uint32_t* hits) {
   uint32_t cnt = 0;
   for (uint32_t k0 = 0; k0 < tot; k0 += static_cast<uint32_t>(width) * kPerLane) {
     const uint32_t kb = k0 + static_cast<uint32_t>(slot) * kPerLane;
@@ -366,7 +416,7 @@ __device__ __forceinline__ uint32_t probe_short(const KernelArgs& a, int32_t u, 
     }
 #pragma unroll
     for (int i = 0; i < kPerLane; i++)
-      if (jj[i] >= 0) cnt += probe_one<MODE>(a, u, x[i], T, log2b, C, &hits[jj[i]], B.beg[jj[i]]);
+      if (jj[i] >= 0) cnt += probe_one<MODE>(a, u, x[i], tab, &hits[jj[i]], B.beg[jj[i]]);
   }
   return cnt;
 }
@@ -387,8 +437,7 @@ __device__ __forceinline__ uint32_t short_len(uint32_t len) { return len >= kLon
 // Block-wide batch of up to kPivotBlock records for a hub item.
 template <int MODE>
 __device__ __forceinline__ uint32_t probe_batch_block(const KernelArgs& a, int32_t u, uint32_t r0, uint32_t r1,
-                                                      const int32_t* T, int log2b, uint32_t* C, BatchLds<kPivotBlock>& B,
-                                                      uint32_t* scan_tmp) {
+                                                      const Table& tab, BatchLds<kPivotBlock>& B, uint32_t* scan_tmp) {
   const int tid = threadIdx.x, w = tid / kWave;
   const uint32_t r = r0 + tid;
   const bool valid = r < r1;
@@ -398,9 +447,8 @@ __device__ __forceinline__ uint32_t probe_batch_block(const KernelArgs& a, int32
   const uint32_t excl = block_excl_scan<uint32_t, kPivotBlock>(short_len(rc.a_len), scan_tmp, tot);
   batch_fill<MODE, kPivotBlock>(B, tid, rc, excl, tot);
   __syncthreads();
-  uint32_t cnt = probe_long<MODE, kPivotBlock>(a, u, B, r1 - r0, static_cast<uint32_t>(w), kPivotWaves, T, log2b, C,
-                                               B.hits);
-  cnt += probe_short<MODE, kPivotBlock>(a, u, B, tot, tid, kPivotBlock, T, log2b, C, B.hits);
+  uint32_t cnt = probe_long<MODE, kPivotBlock>(a, u, B, r1 - r0, static_cast<uint32_t>(w), kPivotWaves, tab, B.hits);
+  cnt += probe_short<MODE, kPivotBlock>(a, u, B, tot, tid, kPivotBlock, tab, B.hits);
   __syncthreads();
   if (MODE == kCountPerNode && valid && B.hits[tid])
     atomicAdd(&a.t_rank[a.src[rc.a_begin - 1]], static_cast<unsigned long long>(B.hits[tid]));
@@ -411,7 +459,7 @@ __device__ __forceinline__ uint32_t probe_batch_block(const KernelArgs& a, int32
 // Wave-wide batch of up to 64 records for a small pivot.
 template <int MODE>
 __device__ __forceinline__ uint32_t probe_batch_wave(const KernelArgs& a, int32_t u, uint32_t r0, uint32_t r1,
-                                                     const int32_t* T, int log2b, uint32_t* C, BatchLds<kWave>& B) {
+                                                     const Table& tab, BatchLds<kWave>& B) {
   const int lane = lane_id();
   const uint32_t r = r0 + lane;
   const bool valid = r < r1;
@@ -422,8 +470,8 @@ __device__ __forceinline__ uint32_t probe_batch_wave(const KernelArgs& a, int32_
   const uint32_t tot = __shfl(incl, kWave - 1, kWave);
   batch_fill<MODE, kWave>(B, lane, rc, incl - p, tot);
   wave_sync();
-  uint32_t cnt = probe_long<MODE, kWave>(a, u, B, r1 - r0, 0u, 1u, T, log2b, C, B.hits);
-  cnt += probe_short<MODE, kWave>(a, u, B, tot, lane, kWave, T, log2b, C, B.hits);
+  uint32_t cnt = probe_long<MODE, kWave>(a, u, B, r1 - r0, 0u, 1u, tab, B.hits);
+  cnt += probe_short<MODE, kWave>(a, u, B, tot, lane, kWave, tab, B.hits);
   if (MODE == kCountPerNode) {
     wave_sync();
     if (valid && B.hits[lane]) atomicAdd(&a.t_rank[a.src[rc.a_begin - 1]], static_cast<unsigned long long>(B.hits[lane]));
@@ -432,31 +480,29 @@ __device__ __forceinline__ uint32_t probe_batch_wave(const KernelArgs& a, int32_
   return cnt;
 }
 
-// Per-wave staging of one small pivot (|N_u| <= 256) into a table of at most
-// kWaveSlots / 4 buckets.
+constexpr int kWaveLog2b = 7;  // per-wave tables: 128 buckets (kWaveSlots slots), lists up to 256 entries
+
+// Per-wave staging of one small pivot (|N_u| <= 256) into the wave's region.
 template <int MODE>
 __device__ __forceinline__ unsigned long long wave_pivot(const KernelArgs& a, int32_t u, uint32_t ibeg, uint32_t iend,
-                                                         int32_t* T, uint32_t* C, BatchLds<kWave>& B) {
+                                                         int32_t* region, BatchLds<kWave>& B) {
   const int lane = lane_id();
   const int64_t nb = a.off[u];
   const uint32_t nlen = static_cast<uint32_t>(a.off[u + 1] - nb);
   int log2b = log2_buckets(nlen);
-  while ((4 << log2b) > kWaveSlots) log2b--;  // at most kWaveSlots/4 buckets (>= 2 slots per entry)
-  const int S = 4 << log2b;
-  for (int s = lane; s < S; s += kWave) {
-    T[s] = kEmpty;
-    if (MODE == kCountPerNode) C[s] = 0;
-  }
+  if (log2b > kWaveLog2b) log2b = kWaveLog2b;  // >= 2 slots per entry
+  const Table tab = table_at(region, log2b, MODE == kCountPerNode);
+  tb_clear(tab, lane, kWave);
   wave_sync();
-  for (uint32_t k = lane; k < nlen; k += kWave) bt_insert(T, log2b, a.adj[nb + k]);
+  for (uint32_t k = lane; k < nlen; k += kWave) tb_insert(tab, a.adj[nb + k]);
   wave_sync();
   uint32_t cnt = 0;
   for (uint32_t r0 = ibeg; r0 < iend; r0 += kWave)
-    cnt += probe_batch_wave<MODE>(a, u, r0, iend < r0 + kWave ? iend : r0 + kWave, T, log2b, C, B);
+    cnt += probe_batch_wave<MODE>(a, u, r0, iend < r0 + kWave ? iend : r0 + kWave, tab, B);
   const unsigned long long tot = wave_sum(static_cast<unsigned long long>(cnt));
   if (MODE == kCountPerNode) {
-    for (int s = lane; s < S; s += kWave)
-      if (C[s]) atomicAdd(&a.t_rank[T[s]], static_cast<unsigned long long>(C[s]));
+    for (int s = lane; s < (4 << log2b); s += kWave)
+      if (tab.C[s]) atomicAdd(&a.t_rank[tab.T[s]], static_cast<unsigned long long>(tab.C[s]));
   }
   if (lane == 0 && tot) {
     if (a.per_graph) atomicAdd(&a.per_graph[a.graph_of_rank ? a.graph_of_rank[u] : 0], tot);
@@ -470,31 +516,28 @@ __device__ __forceinline__ unsigned long long wave_pivot(const KernelArgs& a, in
 // the item's in-edge records block-wide, flush per-node tallies. Returns the
 // item's triangle count (valid in thread 0).
 template <int MODE>
-__device__ __forceinline__ unsigned long long hub_item(const KernelArgs& a, const PivotItem& item, int32_t* T,
-                                                       uint32_t* C, BatchLds<kPivotBlock>& bl, uint32_t* scan_tmp,
+__device__ __forceinline__ unsigned long long hub_item(const KernelArgs& a, const PivotItem& item, int32_t* region,
+                                                       BatchLds<kPivotBlock>& bl, uint32_t* scan_tmp,
                                                        unsigned long long* red) {
   const int tid = threadIdx.x, w = tid / kWave, lane = lane_id();
   constexpr bool per_node = MODE == kCountPerNode;
   const int log2b = log2_buckets(item.nlen, a.bucket_load);
-  const int S = 4 << log2b;
-  for (int s = tid; s < S; s += kPivotBlock) {
-    T[s] = kEmpty;
-    if (per_node) C[s] = 0;
-  }
+  const Table tab = table_at(region, log2b, per_node);
+  tb_clear(tab, tid, kPivotBlock);
   __syncthreads();
   const int64_t nb = a.off[item.u] + item.nbeg_rel;
-  for (uint32_t k = tid; k < item.nlen; k += kPivotBlock) bt_insert(T, log2b, a.adj[nb + k]);
+  for (uint32_t k = tid; k < item.nlen; k += kPivotBlock) tb_insert(tab, a.adj[nb + k]);
   __syncthreads();
   uint32_t cnt = 0;
   for (uint32_t r0 = item.ibeg; r0 < item.iend; r0 += kPivotBlock)
-    cnt += probe_batch_block<MODE>(a, item.u, r0, item.iend < r0 + kPivotBlock ? item.iend : r0 + kPivotBlock, T,
-                                   log2b, C, bl, scan_tmp);
+    cnt += probe_batch_block<MODE>(a, item.u, r0, item.iend < r0 + kPivotBlock ? item.iend : r0 + kPivotBlock, tab, bl,
+                                   scan_tmp);
   const unsigned long long ws = wave_sum(static_cast<unsigned long long>(cnt));
   if (lane == 0) red[w] = ws;
   __syncthreads();
   if (per_node) {
-    for (int s = tid; s < S; s += kPivotBlock)
-      if (C[s]) atomicAdd(&a.t_rank[T[s]], static_cast<unsigned long long>(C[s]));
+    for (int s = tid; s < (4 << log2b); s += kPivotBlock)
+      if (tab.C[s]) atomicAdd(&a.t_rank[tab.T[s]], static_cast<unsigned long long>(tab.C[s]));
   }
   unsigned long long tot = 0;
   if (tid == 0) {
@@ -581,8 +624,6 @@ __global__ __launch_bounds__(kPivotBlock, TC_PIVOT_MIN_WAVES) void k_pivot(
 
   // ---- phase 1: hub items, one block each
   {
-    int32_t* T = smem;
-    uint32_t* C = reinterpret_cast<uint32_t*>(smem + (4 << hub_log2b));
     for (;;) {
       if (tid == 0) cur = n_hub ? atomicAdd(&queues[0], 1ull) : 0ull;
       __syncthreads();
@@ -591,18 +632,16 @@ __global__ __launch_bounds__(kPivotBlock, TC_PIVOT_MIN_WAVES) void k_pivot(
       if (MULTI) {
         const int32_t g = job_of(jobs.pre, jobs.k, it);
         const GraphDesc d = jobs.descs[g];
-        acc += hub_item<MODE>(job_args(a, d, g), d.hub[it - jobs.pre[g]], T, C, rl.block, scan_tmp, red);
+        acc += hub_item<MODE>(job_args(a, d, g), d.hub[it - jobs.pre[g]], smem, rl.block, scan_tmp, red);
       } else {
-        acc += hub_item<MODE>(a, hub_items[it], T, C, rl.block, scan_tmp, red);
+        acc += hub_item<MODE>(a, hub_items[it], smem, rl.block, scan_tmp, red);
       }
     }
   }
 
   // ---- phase 2: split items and grouped small pivots, one wave each
   {
-    const int per_wave = kWaveSlots * (per_node ? 2 : 1);
-    int32_t* T = smem + w * per_wave;
-    uint32_t* C = reinterpret_cast<uint32_t*>(T + kWaveSlots);
+    int32_t* region = smem + w * table_words(kWaveLog2b, per_node);
     for (;;) {
       unsigned long long it = 0;
       if (lane == 0) it = n_split ? atomicAdd(&queues[1], 1ull) : 0ull;
@@ -613,10 +652,10 @@ __global__ __launch_bounds__(kPivotBlock, TC_PIVOT_MIN_WAVES) void k_pivot(
         const int32_t g = job_of(pre, jobs.k, it);
         const GraphDesc d = jobs.descs[g];
         const PivotItem item = d.split[it - pre[g]];
-        acc += wave_pivot<MODE>(job_args(a, d, g), item.u, item.ibeg, item.iend, T, C, rl.wave[w]);
+        acc += wave_pivot<MODE>(job_args(a, d, g), item.u, item.ibeg, item.iend, region, rl.wave[w]);
       } else {
         const PivotItem item = split_items[it];
-        acc += wave_pivot<MODE>(a, item.u, item.ibeg, item.iend, T, C, rl.wave[w]);
+        acc += wave_pivot<MODE>(a, item.u, item.ibeg, item.iend, region, rl.wave[w]);
       }
     }
     for (;;) {
@@ -640,8 +679,8 @@ __global__ __launch_bounds__(kPivotBlock, TC_PIVOT_MIN_WAVES) void k_pivot(
       const uint64_t g1 = g0 + kGroupChunk < gend ? g0 + kGroupChunk : gend;
       for (uint64_t x = g0; x < g1; x++) {
         const int32_t u = glist[x];
-        acc += wave_pivot<MODE>(ga, u, static_cast<uint32_t>(ga.in_off[u]), static_cast<uint32_t>(ga.in_off[u + 1]), T,
-                                C, rl.wave[w]);
+        acc += wave_pivot<MODE>(ga, u, static_cast<uint32_t>(ga.in_off[u]), static_cast<uint32_t>(ga.in_off[u + 1]),
+                                region, rl.wave[w]);
       }
     }
   }
@@ -806,8 +845,8 @@ void count_pivot(Csr& c, const CountArgs& ca, hipStream_t s, const Options& o, b
     const int64_t maxlen = c.dhat_max < cap ? c.dhat_max : cap;
     while ((1ll << hub_log2b) * o.hub_bucket_load < maxlen) hub_log2b++;
   }
-  const size_t hub_lds = (static_cast<size_t>(4) << hub_log2b) * sizeof(int32_t) * (per_node ? 2 : 1);
-  const size_t wave_lds = static_cast<size_t>(kPivotWaves) * kWaveSlots * sizeof(int32_t) * (per_node ? 2 : 1);
+  const size_t hub_lds = static_cast<size_t>(table_words(hub_log2b, per_node)) * sizeof(int32_t);
+  const size_t wave_lds = static_cast<size_t>(kPivotWaves) * table_words(kWaveLog2b, per_node) * sizeof(int32_t);
   const size_t lds = hub_lds > wave_lds ? hub_lds : wave_lds;
   const uint64_t wave_units = P.n_split_items() + (P.n_grouped + kGroupChunk - 1) / kGroupChunk;
   const uint64_t blocks_needed = P.n_hub_items + (wave_units + kPivotWaves - 1) / kPivotWaves;
@@ -865,8 +904,8 @@ void count_multi(const std::vector<Csr*>& gs, const std::vector<unsigned long lo
   const int64_t cap = hub_slice_cap(kCountPerNode);
   const int64_t maxlen = dmax < cap ? dmax : cap;
   while ((1ll << hub_log2b) * o.hub_bucket_load < maxlen) hub_log2b++;
-  const size_t hub_lds = (static_cast<size_t>(4) << hub_log2b) * sizeof(int32_t) * (per_node ? 2 : 1);
-  const size_t wave_lds = static_cast<size_t>(kPivotWaves) * kWaveSlots * sizeof(int32_t) * (per_node ? 2 : 1);
+  const size_t hub_lds = static_cast<size_t>(table_words(hub_log2b, per_node)) * sizeof(int32_t);
+  const size_t wave_lds = static_cast<size_t>(kPivotWaves) * table_words(kWaveLog2b, per_node) * sizeof(int32_t);
   const size_t lds = hub_lds > wave_lds ? hub_lds : wave_lds;
   const unsigned cus = static_cast<unsigned>(device_cus());
   const unsigned bpc = static_cast<unsigned>(o.blocks_per_cu > 0 ? o.blocks_per_cu : 4);
