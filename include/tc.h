@@ -132,6 +132,13 @@ tc_status tc_count_plain(tc_graph* g, void* stream, uint64_t* T);
 tc_status tc_graph_work(tc_graph* g, void* stream, uint64_t* W, uint64_t* P);
 
 /*
+ * sum_v d_v * dhat_v, the quantity Theorem 3 shows the degree order minimises,
+ * for the order this graph was built with (its TC_OPT_ORDER value goes to
+ * *order_kind). Either output may be NULL. Synchronises `stream`.
+ */
+tc_status tc_graph_order_cost(tc_graph* g, void* stream, uint64_t* cost, int32_t* order_kind);
+
+/*
  * Export the degree data in the caller's ids: deg_dev int32[n] = d_v and
  * dhat_dev int32[n] = |N_v| (effective degree, Section 3). Either may be NULL.
  */
@@ -146,21 +153,29 @@ tc_status tc_graph_oriented(tc_graph* g, void* stream, int64_t* off_dev, int32_t
 
 /*
  * Tuning options (process-wide; read at the start of each call).
- *   TC_OPT_KERNEL        : 0 auto, 1 plain merge, 2 pivot-staged
+ *   TC_OPT_KERNEL        : 0 auto (plain merge when the wedge checks are
+ *                          fewer than 16 per edge, else pivot-staged),
+ *                          1 plain merge, 2 pivot-staged
  *   TC_OPT_HUB_DHAT      : lists longer than this use the block-per-pivot path
  *   TC_OPT_ITEM_WORK     : target probes per work item of the partitioner
  *   TC_OPT_BLOCKS_PER_CU : blocks per compute unit of the persistent launch
  *   TC_OPT_HUB_BUCKET_LOAD : target list entries per 4-slot LDS hash bucket
  *                          of the block path (1 or 2)
- * Options change speed only, never results. Returns TC_E_INVAL for an
- * unknown key or an out-of-range value.
+ *   TC_OPT_ORDER         : total order used by graphs built afterwards:
+ *                          0 degree (Eq. (1), the default), 1 id, 2 a fixed
+ *                          pseudo-random permutation, 3 degree descending
+ *                          (the orderings compared in Section 4)
+ * Options change speed only, never results (Theorem 1: any total order counts
+ * each triangle once). Returns TC_E_INVAL for an unknown key or an
+ * out-of-range value.
  */
 typedef enum tc_option {
   TC_OPT_KERNEL = 0,
   TC_OPT_HUB_DHAT = 1,
   TC_OPT_ITEM_WORK = 2,
   TC_OPT_BLOCKS_PER_CU = 3,
-  TC_OPT_HUB_BUCKET_LOAD = 4
+  TC_OPT_HUB_BUCKET_LOAD = 4,
+  TC_OPT_ORDER = 5
 } tc_option;
 tc_status tc_set_option(tc_option key, int64_t value);
 int64_t tc_get_option(tc_option key);

@@ -15,7 +15,7 @@ namespace tc {
 namespace {
 
 thread_local std::string g_last_error;
-std::atomic<int64_t> g_opt_kernel{0}, g_opt_hub{128}, g_opt_iw{16384}, g_opt_bpc{4}, g_opt_load{2};
+std::atomic<int64_t> g_opt_kernel{0}, g_opt_hub{128}, g_opt_iw{16384}, g_opt_bpc{4}, g_opt_load{2}, g_opt_order{0};
 
 template <typename F>
 tc_status guarded(F&& f) {
@@ -109,7 +109,9 @@ uint64_t count_total(tc_graph* g, Csr& c, hipStream_t s, unsigned long long* t_r
     a.t_rank = t_rank;
     std::lock_guard<std::mutex> lk(g->mu);
     count_pivot(c, a, s, o);
-  } else if (o.kernel == 1) {
+  } else if (o.kernel == 1 || (o.kernel == 0 && c.plan.ready && c.plan.probes < 16ull * static_cast<uint64_t>(c.m))) {
+    // plain merge for graphs with few wedge checks per edge (near-uniform low degrees), where the
+    // persistent pivot kernel's staging overhead exceeds the merge work
     count_plain(c, tot.get(), s);
   } else {
     CountArgs a;
@@ -133,6 +135,7 @@ Options get_options() {
   o.item_work = g_opt_iw.load();
   o.blocks_per_cu = g_opt_bpc.load();
   o.hub_bucket_load = g_opt_load.load();
+  o.order = g_opt_order.load();
   return o;
 }
 
@@ -340,6 +343,23 @@ tc_status tc_graph_work(tc_graph* g, void* stream, uint64_t* W, uint64_t* P) {
   });
 }
 
+tc_status tc_graph_order_cost(tc_graph* g, void* stream, uint64_t* cost, int32_t* order_kind) {
+  return guarded([&] {
+    require(g != nullptr, TC_E_INVAL, "graph is NULL");
+    require(!g->sampled, TC_E_INVAL, "not available on a sampled graph");
+    DeviceScope ds(g->device);
+    const hipStream_t s = as_stream(stream);
+    DevBuf<unsigned long long> d(1, s);
+    fill_u64(d.get(), 1, 0ull, s);
+    order_cost(g->csr, g->deg.p, g->order.p, d.get(), s);
+    unsigned long long h = 0;
+    TC_HIP(hipMemcpyAsync(&h, d.get(), sizeof(h), hipMemcpyDeviceToHost, s));
+    TC_HIP(hipStreamSynchronize(s));
+    if (cost) *cost = h;
+    if (order_kind) *order_kind = g->order_kind;
+  });
+}
+
 tc_status tc_graph_degrees(tc_graph* g, void* stream, int32_t* deg_dev, int32_t* dhat_dev) {
   return guarded([&] {
     require(g != nullptr, TC_E_INVAL, "graph is NULL");
@@ -506,6 +526,10 @@ tc_status tc_set_option(tc_option key, int64_t value) {
         require(value == 1 || value == 2, TC_E_INVAL, "bucket load must be 1 or 2");
         g_opt_load = value;
         break;
+      case TC_OPT_ORDER:
+        require(value <= 3, TC_E_INVAL, "order must be 0 (degree), 1 (id), 2 (random) or 3 (degree descending)");
+        g_opt_order = value;
+        break;
       default: fail(TC_E_INVAL, "unknown option");
     }
   });
@@ -518,6 +542,7 @@ int64_t tc_get_option(tc_option key) {
     case TC_OPT_ITEM_WORK: return g_opt_iw.load();
     case TC_OPT_BLOCKS_PER_CU: return g_opt_bpc.load();
     case TC_OPT_HUB_BUCKET_LOAD: return g_opt_load.load();
+    case TC_OPT_ORDER: return g_opt_order.load();
     default: return -1;
   }
 }

@@ -83,9 +83,21 @@ __global__ void k_degrees(const uint64_t* __restrict__ uk, uint64_t m, int b, in
   }
 }
 
-// Rank key of a vertex: graph index (hi word), then degree, then id.
+// Rank key of a vertex: graph index (hi word), then the order key, then id.
+// order 0: degree (Eq. (1)); 1: id; 2: a fixed pseudo-random permutation;
+// 3: degree descending. Any total order counts each triangle once (Theorem 1).
+__device__ __forceinline__ uint64_t order_key(int order, int32_t v, int32_t d, int b) {
+  const uint64_t mask = (1ull << b) - 1;
+  switch (order) {
+    case 1: return 0;
+    case 2: return ((static_cast<uint64_t>(static_cast<uint32_t>(v)) + 1ull) * 0x9E3779B97F4A7C15ull >> 40) & mask;
+    case 3: return mask - static_cast<uint64_t>(d);
+    default: return static_cast<uint64_t>(d);
+  }
+}
+
 __global__ void k_rank_keys(int32_t n, int b, const int32_t* __restrict__ deg, const int32_t* __restrict__ vbase,
-                            int32_t G, u128* __restrict__ out) {
+                            int32_t G, int order, u128* __restrict__ out) {
   for (int32_t v = blockIdx.x * blockDim.x + threadIdx.x; v < n; v += gridDim.x * blockDim.x) {
     uint64_t g = 0;
     if (G > 1) {
@@ -97,7 +109,7 @@ __global__ void k_rank_keys(int32_t n, int b, const int32_t* __restrict__ deg, c
       }
       g = static_cast<uint64_t>(lo);
     }
-    out[v] = u128{(static_cast<uint64_t>(deg[v]) << b) | static_cast<uint64_t>(v), g};
+    out[v] = u128{(order_key(order, v, deg[v], b) << b) | static_cast<uint64_t>(v), g};
   }
 }
 
@@ -213,6 +225,7 @@ void build_graph(const int32_t* src, const int32_t* dst, int64_t E, int32_t n, c
   }
   const int b = bits_for(n > 1 ? static_cast<uint64_t>(n - 1) : 1);
   g->bits = b;
+  g->order_kind = static_cast<int>(get_options().order);
   const int gbits = G > 1 ? bits_for(static_cast<uint64_t>(G - 1)) : 0;
 
   // ---- inputs on the device
@@ -281,7 +294,8 @@ void build_graph(const int32_t* src, const int32_t* dst, int64_t E, int32_t n, c
   if (G > 1) g->graph_of_rank.alloc(n);
   if (n > 0) {
     DevBuf<u128> rk(n, s), rk2(n, s);
-    k_rank_keys<<<grid_for(n, kBlock, 65536), kBlock, 0, s>>>(n, b, g->deg.p, d_vbase.get(), G, rk.get());
+    k_rank_keys<<<grid_for(n, kBlock, 65536), kBlock, 0, s>>>(n, b, g->deg.p, d_vbase.get(), G,
+                                                               static_cast<int>(get_options().order), rk.get());
     TC_LAUNCH_CHECK();
     u128* r1 = radix_sort<u128>(rk.get(), rk2.get(), n, 0, 2 * b, s);
     u128* r2 = r1;

@@ -721,6 +721,23 @@ void graph_work(const Csr& c, unsigned long long* W, unsigned long long* P, hipS
   TC_LAUNCH_CHECK();
 }
 
+namespace {
+__global__ void k_order_cost(const int64_t* __restrict__ off, const int32_t* __restrict__ deg,
+                             const int32_t* __restrict__ order, int32_t n, unsigned long long* __restrict__ out) {
+  unsigned long long acc = 0;
+  for (int32_t r = blockIdx.x * blockDim.x + threadIdx.x; r < n; r += gridDim.x * blockDim.x)
+    acc += static_cast<unsigned long long>(off[r + 1] - off[r]) * static_cast<unsigned long long>(deg[order[r]]);
+  acc = wave_sum(acc);
+  if (lane_id() == 0 && acc) atomicAdd(out, acc);
+}
+}  // namespace
+
+void order_cost(const Csr& c, const int32_t* deg, const int32_t* order, unsigned long long* out, hipStream_t s) {
+  if (c.n == 0) return;
+  k_order_cost<<<grid_for(c.n, kBlock, 16384), kBlock, 0, s>>>(c.off.p, deg, order, c.n, out);
+  TC_LAUNCH_CHECK();
+}
+
 // Builds the in-edge records and the work items of the pivot kernels. The
 // plan depends on hub_dhat and item_work and is rebuilt when they change.
 // The item lists are built for the per-node slice cap (4096), which also
@@ -774,10 +791,12 @@ void ensure_plan(Csr& c, hipStream_t s, const Options& o) {
   TC_LAUNCH_CHECK();
   exclusive_scan<int64_t>(nh.get(), nh.get(), n, s, nh.get() + n);
   exclusive_scan<int64_t>(ns.get(), ns.get(), n, s, ns.get() + n);
-  int64_t counts[2] = {0, 0};
+  int64_t counts[3] = {0, 0, 0};
   TC_HIP(hipMemcpyAsync(&counts[0], nh.get() + n, sizeof(int64_t), hipMemcpyDeviceToHost, s));
   TC_HIP(hipMemcpyAsync(&counts[1], ns.get() + n, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+  TC_HIP(hipMemcpyAsync(&counts[2], fin.get() + mi, sizeof(int64_t), hipMemcpyDeviceToHost, s));
   TC_HIP(hipStreamSynchronize(s));
+  P.probes = static_cast<uint64_t>(counts[2]) - static_cast<uint64_t>(kCostPerRecord) * mi;
   P.n_hub_items = static_cast<uint64_t>(counts[0]);
   P.n_wave_items = static_cast<uint64_t>(counts[1]);
   // items: [hub items | split wave items | grouped pivots as int32 at the end]

@@ -66,6 +66,7 @@ struct PivotPlan {
   Owned<int32_t> grouped;    // small pivots served from a shared queue
   uint64_t n_grouped = 0;
   int64_t hub_dhat = 0, item_work = 0;  // options the plan was built with
+  uint64_t probes = 0;       // sum of suffix lengths |A| over in-edge records (the wedge checks P)
   uint64_t n_split_items() const { return n_wave_items; }
   void reset() {
     ready = false;
@@ -73,7 +74,7 @@ struct PivotPlan {
     in_off.reset();
     items.reset();
     grouped.reset();
-    n_hub_items = n_wave_items = n_grouped = 0;
+    n_hub_items = n_wave_items = n_grouped = probes = 0;
     hub_dhat = item_work = 0;
   }
 };
@@ -98,6 +99,7 @@ struct tc_graph {
   int64_t m = 0;   // unique undirected edges
   int32_t d_max = 0;
   int bits = 1;    // bits of a vertex id
+  int order_kind = 0;  // total order the orientation used (TC_OPT_ORDER at build time)
   tc::Csr csr;
   tc::Owned<int32_t> order;  // [n] rank -> caller id
   tc::Owned<int32_t> rank;   // [n] caller id -> rank
@@ -123,6 +125,7 @@ struct Options {
   int64_t item_work = 4096;  // target probes per work item
   int64_t blocks_per_cu = 8; // persistent launch occupancy
   int64_t hub_bucket_load = 2;  // entries per 4-slot bucket of a hub table (1 or 2)
+  int64_t order = 0;            // total order of the orientation (0 degree, 1 id, 2 random, 3 degree descending)
 };
 Options get_options();
 
@@ -152,6 +155,8 @@ void count_multi(const std::vector<Csr*>& gs, const std::vector<unsigned long lo
                  unsigned long long* T_dev, hipStream_t s, const Options& o);
 void count_plain(const Csr& c, unsigned long long* total, hipStream_t s);
 void graph_work(const Csr& c, unsigned long long* W, unsigned long long* P, hipStream_t s);
+// sum_v d_v * dhat_v (the objective of Theorem 3); deg by caller id, order rank -> id
+void order_cost(const Csr& c, const int32_t* deg, const int32_t* order, unsigned long long* out, hipStream_t s);
 void build_sampled_csr(const tc_graph* g, double q, uint64_t seed, Csr& out, hipStream_t s);
 void sort_triangles(int32_t* tri, int64_t count, int bits, hipStream_t s);
 // off[r] = first index whose row is >= r, for rows sorted ascending (length m); off has n+1 entries

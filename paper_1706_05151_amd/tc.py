@@ -17,7 +17,8 @@ LIB_PATH = os.path.join(_HERE, "libtc.so")
 
 TC_OK, TC_E_INVAL, TC_E_NOMEM, TC_E_DEVICE, TC_E_RANGE, TC_E_TRUNC = 0, -1, -2, -3, -4, -5
 TC_IN_DEVICE = 1
-OPT_KERNEL, OPT_HUB_DHAT, OPT_ITEM_WORK, OPT_BLOCKS_PER_CU, OPT_HUB_BUCKET_LOAD = 0, 1, 2, 3, 4
+OPT_KERNEL, OPT_HUB_DHAT, OPT_ITEM_WORK, OPT_BLOCKS_PER_CU, OPT_HUB_BUCKET_LOAD, OPT_ORDER = 0, 1, 2, 3, 4, 5
+ORDER_DEGREE, ORDER_ID, ORDER_RANDOM, ORDER_DEGREE_DESC = 0, 1, 2, 3
 
 # (name, argtypes, restype) for every symbol include/tc.h declares
 _vp, _i32, _i64, _u32, _u64, _dbl = (ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_uint32,
@@ -35,6 +36,7 @@ SIGNATURES = {
     "tc_count_plain": ([_vp, _vp, _P(_u64)], ctypes.c_int),
     "tc_graph_work": ([_vp, _vp, _P(_u64), _P(_u64)], ctypes.c_int),
     "tc_graph_degrees": ([_vp, _vp, _vp, _vp], ctypes.c_int),
+    "tc_graph_order_cost": ([_vp, _vp, _P(_u64), _P(_i32)], ctypes.c_int),
     "tc_graph_oriented": ([_vp, _vp, _vp, _vp], ctypes.c_int),
     "tc_set_option": ([ctypes.c_int, _i64], ctypes.c_int),
     "tc_get_option": ([ctypes.c_int], _i64),
@@ -212,6 +214,13 @@ class Graph:
         W, P = _u64(), _u64()
         _check(lib().tc_graph_work(self._h, _stream(stream), ctypes.byref(W), ctypes.byref(P)), "tc_graph_work")
         return W.value, P.value
+
+    def order_cost(self, stream=None) -> Tuple[int, int]:
+        """(sum_v d_v * dhat_v, order kind the graph was built with)."""
+        c, k = _u64(), _i32()
+        _check(lib().tc_graph_order_cost(self._h, _stream(stream), ctypes.byref(c), ctypes.byref(k)),
+               "tc_graph_order_cost")
+        return c.value, k.value
 
     def degrees(self, stream=None):
         torch = _torch()

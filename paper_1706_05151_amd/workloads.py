@@ -168,7 +168,79 @@ def run_serve(args):
     return out
 
 
+def run_orders(args):
+    """Ordering study (Section 4): the same graphs oriented by degree, id,
+    a random permutation and degree descending; exact counts must agree
+    (Theorem 1) while the work W, the wedges P, the Theorem 3 objective
+    sum d_v * dhat_v and the times change."""
+    import torch
+
+    import synth
+
+    torch.cuda.set_device(0)
+    names = {0: "degree", 1: "id", 2: "random", 3: "degree-desc"}
+    graphs = [("er", synth.er(1 << 20, 16.0 / ((1 << 20) - 1), 11)), ("ba", synth.ba(1 << 20, 8, 12)),
+              ("rmat", synth.rmat(args.scale if args.scale <= 22 else 22, 16, 3))]
+    old = tc.get_option(tc.OPT_ORDER)
+    table = []
+    try:
+        for gname, el in graphs:
+            s = torch.from_numpy(el.src).cuda()
+            d = torch.from_numpy(el.dst).cuda()
+            T0 = None
+            for order in (0, 1, 2, 3):
+                tc.set_option(tc.OPT_ORDER, order)
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                g = tc.Graph.build(s, d, el.n)
+                torch.cuda.synchronize()
+                tb = time.perf_counter() - t0
+                T = g.count()
+                best = float("inf")
+                for _ in range(3):
+                    torch.cuda.synchronize()
+                    t0 = time.perf_counter()
+                    assert g.count() == T
+                    torch.cuda.synchronize()
+                    best = min(best, time.perf_counter() - t0)
+                tp = float("inf")
+                if not args.no_plain:
+                    torch.cuda.synchronize()
+                    t0 = time.perf_counter()
+                    assert g.count_plain() == T
+                    torch.cuda.synchronize()
+                    tp = time.perf_counter() - t0
+                W, P = g.work()
+                cost, _ = g.order_cost()
+                if T0 is None:
+                    T0 = T
+                assert T == T0, "orders disagree on T"
+                row = {"graph": gname, "order": names[order], "n": g.n, "m": g.m, "T": T, "dhat_max": g.dhat_max,
+                       "sum_d_dhat": cost, "W": W, "P": P, "build_ms": 1e3 * tb, "count_ms": 1e3 * best,
+                       "plain_ms": 1e3 * tp if tp != float("inf") else None}
+                _log(f"[orders] {row}")
+                table.append(row)
+                g.close()
+            del s, d
+            torch.cuda.empty_cache()
+    finally:
+        tc.set_option(tc.OPT_ORDER, old)
+    deg_rows = {r["graph"]: r for r in table if r["order"] == "degree"}
+    theorem3 = all(r["sum_d_dhat"] >= deg_rows[r["graph"]]["sum_d_dhat"] for r in table)
+    rm = [r for r in table if r["graph"] == "rmat"]
+    dr = deg_rows["rmat"]
+    return {"metric": METRIC, "value": dr["m"] / (dr["count_ms"] / 1e3), "unit": "oriented edges/s", "n_gpus": 1,
+            "steps": 3, "warmup": 1, "ms_per_step": dr["count_ms"], "higher_is_better": True, "scaling": "weak",
+            "vs_baseline": None, "dtype": "int32", "data": "synthetic",
+            "config": {"workload": "ordering-study", "graphs": "ER 2^20 deg 16, PA 2^20 k=8, R-MAT scale 22 ef 16",
+                       "parallelism": "single GPU"},
+            "theorem3_holds": theorem3, "rmat_count_ms_by_order": {r["order"]: r["count_ms"] for r in rm},
+            "table": table}
+
+
 def run(args):
     if args.workload == "batch":
         return run_batch(args)
+    if args.workload == "orders":
+        return run_orders(args)
     return run_serve(args)

@@ -107,7 +107,15 @@ def test_random_messy(tc, seed):
 def test_families(tc, spec):
     el = {"er": lambda: synth.er(20000, 0.002, 3), "ba": lambda: synth.ba(50000, 6, 4),
           "rmat13": lambda: synth.rmat(13, 16, 5), "rmat15": lambda: synth.rmat(15, 16, 6)}[spec]()
-    check_all(tc, el, listing=True)
+    ref = check_all(tc, el, listing=True)
+    old = tc.get_option(tc.OPT_KERNEL)
+    try:
+        for k in (1, 2):  # forced plain merge / forced pivot kernel for the total
+            tc.set_option(tc.OPT_KERNEL, k)
+            with tc.Graph.build(*to_dev(el), el.n) as g:
+                assert g.count() == ref.T
+    finally:
+        tc.set_option(tc.OPT_KERNEL, old)
 
 
 @pytest.mark.parametrize("hub,iw,load", [(0, 64, 1), (0, 4096, 2), (16, 64, 2), (256, 100000, 1), (64, 512, 2),
@@ -271,3 +279,40 @@ def test_config_er10k(tc):
 def test_config_ba22(tc):
     """PA n=2^22, 8 edges per new node, seed 2: T, t_v, clustering and the sorted list."""
     check_all(tc, synth.config_ba22(), listing=True, label="BA n=2^22 k=8 seed 2")
+
+
+# ----------------------------------------------------------------- orders ---
+
+@pytest.mark.parametrize("order", [0, 1, 2, 3])
+def test_orders_count_each_triangle_once(tc, order):
+    """Theorem 1: every total order gives the same exact outputs; Theorem 3:
+    the degree order has the smallest sum_v d_v * dhat_v."""
+    el = synth.rmat(13, 16, 17)
+    ref = oracle.solve(el.src, el.dst, el.n, per_node=True, listing=True)
+    lo, hi = ref.extra["lo"], ref.extra["hi"]
+    best = int((ref.deg * np.diff(ref.off)).sum())
+    old = tc.get_option(tc.OPT_ORDER)
+    tc.set_option(tc.OPT_ORDER, order)
+    try:
+        s, d = to_dev(el)
+        with tc.Graph.build(s, d, el.n) as g:
+            say(f"[parity] order {order}")
+            assert g.count() == ref.T and g.count_plain() == ref.T
+            T, t = g.count_per_node()
+            np.testing.assert_array_equal(u64(t), ref.t)
+            np.testing.assert_array_equal(g.list().cpu().numpy(), ref.tri)
+            cost, kind = g.order_cost()
+            assert kind == order and cost >= best
+            if order == 0:
+                assert cost == best
+            if order in (1, 3):  # orders the oracle can reproduce: id, degree descending (ties by id)
+                key = np.zeros(el.n, np.int64) if order == 1 else -ref.deg
+                off, adj = oracle.orient_by_key(lo, hi, key, el.n)
+                goff, gadj = g.oriented()
+                np.testing.assert_array_equal(goff.cpu().numpy(), off)
+                np.testing.assert_array_equal(gadj.cpu().numpy(), adj)
+                assert cost == int((ref.deg * np.diff(off)).sum())
+            Ts, mk, est = g.sparsify_count(0.3, 4)
+            assert (Ts, mk) == oracle.sparsified_count(lo, hi, ref.deg, el.n, 0.3, 4)[:2]
+    finally:
+        tc.set_option(tc.OPT_ORDER, old)
