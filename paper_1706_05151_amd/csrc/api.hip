@@ -41,6 +41,7 @@ struct DeviceScope {
   explicit DeviceScope(int dev) : want(dev) {
     TC_HIP(hipGetDevice(&prev));
     if (prev != dev) TC_HIP(hipSetDevice(dev));
+    retain_pool_memory();
   }
   ~DeviceScope() {
     if (prev >= 0 && prev != want) (void)hipSetDevice(prev);
@@ -180,7 +181,7 @@ tc_status tc_batch_build(const int32_t* src, const int32_t* dst, const int64_t* 
       build_graph(src, dst, edge_off[num_graphs], static_cast<int32_t>(ntot), edge_off, n_per_graph, num_graphs,
                   (flags & TC_IN_DEVICE) != 0, s, g);
       ensure_plan(g->csr, s, get_options());
-      g->workspace.alloc((3 + static_cast<size_t>(g->n)) * sizeof(unsigned long long));
+      g->workspace.alloc((3 + static_cast<size_t>(g->n)) * sizeof(unsigned long long), s);
       TC_HIP(hipStreamSynchronize(s));
     } catch (...) {
       (void)hipStreamSynchronize(s);

@@ -207,6 +207,7 @@ void build_graph(const int32_t* src, const int32_t* dst, int64_t E, int32_t n, c
   if (E >= (1ll << 32) - 1) fail(TC_E_INVAL, "more than 2^32 - 2 edge records");
   if (E > 0 && (!src || !dst)) fail(TC_E_INVAL, "NULL edge array");
   TC_HIP(hipGetDevice(&g->device));
+  retain_pool_memory();
   g->n = n;
   g->num_graphs = G;
   g->vbase.assign(static_cast<size_t>(G) + 1, 0);
@@ -281,7 +282,7 @@ void build_graph(const int32_t* src, const int32_t* dst, int64_t E, int32_t n, c
   g->m = static_cast<int64_t>(m);
 
   // ---- 3: degrees
-  g->deg.alloc(n);
+  g->deg.alloc(n, s);
   if (n > 0) TC_HIP(hipMemsetAsync(g->deg.p, 0, n * sizeof(int32_t), s));
   if (m > 0) {
     k_degrees<<<grid_for(m, kBlock, 65536), kBlock, 0, s>>>(uniq, m, b, g->deg.p);
@@ -289,9 +290,9 @@ void build_graph(const int32_t* src, const int32_t* dst, int64_t E, int32_t n, c
   }
 
   // ---- 4: ranks in the degree order
-  g->order.alloc(n);
-  g->rank.alloc(n);
-  if (G > 1) g->graph_of_rank.alloc(n);
+  g->order.alloc(n, s);
+  g->rank.alloc(n, s);
+  if (G > 1) g->graph_of_rank.alloc(n, s);
   if (n > 0) {
     DevBuf<u128> rk(n, s), rk2(n, s);
     k_rank_keys<<<grid_for(n, kBlock, 65536), kBlock, 0, s>>>(n, b, g->deg.p, d_vbase.get(), G,
@@ -309,9 +310,9 @@ void build_graph(const int32_t* src, const int32_t* dst, int64_t E, int32_t n, c
   Csr& c = g->csr;
   c.n = n;
   c.m = static_cast<int64_t>(m);
-  c.off.alloc(static_cast<size_t>(n) + 1);
-  c.adj.alloc(m);
-  c.src.alloc(m);
+  c.off.alloc(static_cast<size_t>(n) + 1, s);
+  c.adj.alloc(m, s);
+  c.src.alloc(m, s);
   if (m > 0) {
     k_relabel<<<grid_for(m, kBlock, 65536), kBlock, 0, s>>>(uniq, m, b, g->rank.p, spare);
     TC_LAUNCH_CHECK();

@@ -3,6 +3,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <atomic>
 #include <cstdint>
 #include <cstdio>
 #include <stdexcept>
@@ -35,6 +36,24 @@ inline void hip_check(hipError_t e, const char* what, const char* file, int line
 #define TC_LAUNCH_CHECK() ::tc::hip_check(hipGetLastError(), "kernel launch", __FILE__, __LINE__)
 
 // ------------------------------------------------- stream-ordered buffers --
+
+// The library allocates from the device's default stream-ordered pool and
+// lets it keep up to 96 GiB of freed memory cached, so repeated builds and
+// queries reuse mappings instead of returning memory to the driver at every
+// synchronisation (the default release threshold is 0).
+inline void retain_pool_memory() {
+  static std::atomic<uint64_t> done_mask{0};
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return;
+  const uint64_t bit = 1ull << dev;
+  if (done_mask.load() & bit) return;
+  hipMemPool_t pool;
+  if (hipDeviceGetDefaultMemPool(&pool, dev) == hipSuccess) {
+    uint64_t threshold = 96ull << 30;
+    (void)hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &threshold);
+  }
+  done_mask.fetch_or(bit);
+}
 
 // Device buffer taken from the stream-ordered allocator and returned to it on
 // destruction (the free is ordered after all work queued on the stream).

@@ -747,10 +747,11 @@ static int64_t clamp_hub(int64_t h) { return h < 0 ? 0 : (h > kWaveSlots / 2 ? k
 void ensure_plan(Csr& c, hipStream_t s, const Options& o) {
   PivotPlan& P = c.plan;
   if (P.ready && P.hub_dhat == clamp_hub(o.hub_dhat) && P.item_work == o.item_work) return;
+  if (P.ready) TC_HIP(hipDeviceSynchronize());  // launches on other streams may still read the old plan
   P.reset();
   const int32_t n = c.n;
   const uint64_t m = static_cast<uint64_t>(c.m);
-  P.in_off.alloc(static_cast<size_t>(n) + 1);
+  P.in_off.alloc(static_cast<size_t>(n) + 1, s);
   if (m == 0 || n == 0) {
     if (n >= 0) TC_HIP(hipMemsetAsync(P.in_off.p, 0, (static_cast<size_t>(n) + 1) * sizeof(int64_t), s));
     P.hub_dhat = clamp_hub(o.hub_dhat);
@@ -767,7 +768,7 @@ void ensure_plan(Csr& c, hipStream_t s, const Options& o) {
   TC_HIP(hipMemcpyAsync(&mi, d_cnt.get(), sizeof(uint64_t), hipMemcpyDeviceToHost, s));
   TC_HIP(hipStreamSynchronize(s));
   uint64_t* sk = radix_sort<uint64_t>(ik.get(), ik2.get(), mi, 32, 32 + b, s);
-  P.inrec.alloc(mi);
+  P.inrec.alloc(mi, s);
   DevBuf<int32_t> piv(mi, s);
   DevBuf<int64_t> fin(mi + 1, s);
   if (mi > 0) {
@@ -800,7 +801,7 @@ void ensure_plan(Csr& c, hipStream_t s, const Options& o) {
   P.n_hub_items = static_cast<uint64_t>(counts[0]);
   P.n_wave_items = static_cast<uint64_t>(counts[1]);
   // items: [hub items | split wave items | grouped pivots as int32 at the end]
-  P.items.alloc(P.n_hub_items + P.n_wave_items);
+  P.items.alloc(P.n_hub_items + P.n_wave_items, s);
   if (P.n_hub_items) {
     k_items_fill<<<grid_for(P.n_hub_items, kBlock, 65536), kBlock, 0, s>>>(P.n_hub_items, nh.get(), n, c.off.p,
                                                                           P.in_off.p, fin.get(), cap, iw_hub, P.items.p);
@@ -818,7 +819,7 @@ void ensure_plan(Csr& c, hipStream_t s, const Options& o) {
   uint64_t ng = 0;
   TC_HIP(hipMemcpyAsync(&ng, d_g.get(), sizeof(uint64_t), hipMemcpyDeviceToHost, s));
   TC_HIP(hipStreamSynchronize(s));
-  P.grouped.alloc(ng);
+  P.grouped.alloc(ng, s);
   if (ng) TC_HIP(hipMemcpyAsync(P.grouped.p, glist.get(), ng * sizeof(int32_t), hipMemcpyDeviceToDevice, s));
   P.n_grouped = ng;
   TC_HIP(hipStreamSynchronize(s));
@@ -1007,9 +1008,9 @@ void build_sampled_csr(const tc_graph* g, double q, uint64_t seed, Csr& out, hip
   TC_HIP(hipStreamSynchronize(s));
   out.n = c.n;
   out.m = static_cast<int64_t>(mk);
-  out.off.alloc(static_cast<size_t>(c.n) + 1);
-  out.adj.alloc(mk);
-  out.src.alloc(mk);
+  out.off.alloc(static_cast<size_t>(c.n) + 1, s);
+  out.adj.alloc(mk, s);
+  out.src.alloc(mk, s);
   if (mk) {
     k_unpack_entries<<<grid_for(mk, kBlock, 65536), kBlock, 0, s>>>(packed.get(), mk, out.adj.p, out.src.p);
     TC_LAUNCH_CHECK();

@@ -10,7 +10,10 @@
 
 namespace tc {
 
-// Device arrays owned by a graph (freed with hipFree on graph destruction).
+// Device arrays owned by a graph, taken from the stream-ordered pool on the
+// building stream and returned on the null stream, which orders the free
+// after the work of every blocking stream (graphs are freed after a device
+// synchronisation).
 template <typename T>
 struct Owned {
   T* p = nullptr;
@@ -20,14 +23,14 @@ struct Owned {
   Owned& operator=(const Owned&) = delete;
   ~Owned() { reset(); }
   void reset() {
-    if (p) (void)hipFree(p);
+    if (p) (void)hipFreeAsync(p, nullptr);
     p = nullptr;
     n = 0;
   }
-  void alloc(size_t count) {
+  void alloc(size_t count, hipStream_t s = nullptr) {
     reset();
     n = count;
-    if (count) TC_HIP(hipMalloc(reinterpret_cast<void**>(&p), count * sizeof(T)));
+    if (count) TC_HIP(hipMallocAsync(reinterpret_cast<void**>(&p), count * sizeof(T), s));
   }
   // take over a stream-ordered buffer
   void adopt(DevBuf<T>& b) {
