@@ -197,12 +197,19 @@ def run_graph_bench(args):
     if args.workload == "rmat":
         sp = {}
         for q in (0.1, 0.5):
-            torch.cuda.synchronize()
-            t0 = time.perf_counter()
-            Ts_, mk, est = g.sparsify_count(q, 3, stream)
-            dt = time.perf_counter() - t0
-            sp[str(q)] = {"ms": 1e3 * dt, "T_s": Ts_, "m_kept": mk, "estimate": est, "rel_err": est / T - 1}
-            log(f"[bench] sparsified q={q}: {1e3 * dt:.1f} ms, estimate {est:.4e} ({est / T - 1:+.4%})")
+            # The first call at a given q also grows the memory pool for the
+            # sampled graph's arrays; report it apart from the best of three.
+            times = []
+            for _ in range(4):
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                Ts_, mk, est = g.sparsify_count(q, 3, stream)
+                times.append(1e3 * (time.perf_counter() - t0))
+            dt = min(times[1:])
+            sp[str(q)] = {"ms": dt, "first_call_ms": times[0], "T_s": Ts_, "m_kept": mk, "estimate": est,
+                          "rel_err": est / T - 1}
+            log(f"[bench] sparsified q={q}: {dt:.1f} ms (first call {times[0]:.1f} ms), estimate {est:.4e} "
+                f"({est / T - 1:+.4%})")
         out["sparsified"] = sp
     if args.workload in ("ba22", "er10k"):
         torch.cuda.synchronize()

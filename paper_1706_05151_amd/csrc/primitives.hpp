@@ -229,78 +229,82 @@ __global__ __launch_bounds__(kSortBlock) void k_radix_hist(const K* __restrict__
   hist[static_cast<size_t>(tid) * tiles + blockIdx.x] = t;
 }
 
-// Stable scatter of one tile: rank each key among equal digits in index
-// order (round-major, then wave, then lane), stage the tile in LDS sorted by
-// digit, and write each digit run contiguously to its global offset.
+// Stable scatter of one tile. Wave w owns the contiguous chunk
+// [w*ITEMS*64, (w+1)*ITEMS*64) of the tile and ranks its keys among equal
+// digits with wave-private counters (ballot match of equal digits, the
+// lowest lane of each group updating the counter); one block-wide prefix over
+// waves and digits then places every key, so tile order = index order.
+// The tile is staged in LDS sorted by digit and each digit run is written
+// contiguously to its global offset.
 template <typename K>
 __global__ __launch_bounds__(kSortBlock) void k_radix_scatter(const K* __restrict__ in, K* __restrict__ out, uint32_t N,
                                                                int shift, const uint32_t* __restrict__ offs,
                                                                uint32_t tiles) {
   constexpr int ITEMS = RadixItems<K>::value;
   constexpr int TILE = kSortBlock * ITEMS;
+  constexpr int CHUNK = kWave * ITEMS;
   __shared__ K tile[TILE];
-  __shared__ uint32_t wcnt[2][kSortWaves][256];
-  __shared__ uint32_t run[256];
+  __shared__ uint32_t wc[kSortWaves][256];
   __shared__ uint32_t dstart[256];
   __shared__ uint32_t gbase[256];
   __shared__ uint32_t scan_tmp[kSortWaves];
-  const int tid = threadIdx.x, w = tid / kWave;
+  const int tid = threadIdx.x, w = tid / kWave, lane = lane_id();
   const size_t base = static_cast<size_t>(blockIdx.x) * TILE;
 
-  run[tid] = 0;
 #pragma unroll
-  for (int x = 0; x < kSortWaves; x++) {
-    wcnt[0][x][tid] = 0;
-    wcnt[1][x][tid] = 0;
-  }
+  for (int x = 0; x < kSortWaves; x++) wc[x][tid] = 0;
   gbase[tid] = offs[static_cast<size_t>(tid) * tiles + blockIdx.x];
   __syncthreads();
 
   K key[ITEMS];
   uint32_t rk[ITEMS];
   uint32_t dg[ITEMS];
+  uint32_t* cnt = wc[w];
 #pragma unroll
   for (int i = 0; i < ITEMS; i++) {
-    const int buf = i & 1;
-    const size_t idx = base + static_cast<size_t>(i) * kSortBlock + tid;
+    const size_t idx = base + static_cast<size_t>(w) * CHUNK + static_cast<size_t>(i) * kWave + lane;
     const bool valid = idx < N;
     K k{};
     if (valid) k = in[idx];
     const uint32_t d = valid ? RadixKey<K>::digit(k, shift) : 256u;
     const uint64_t peers = match_any9(d);
     const uint32_t lr = static_cast<uint32_t>(__popcll(peers & lanemask_lt()));
-    if (valid && lr == 0) wcnt[buf][w][d] = static_cast<uint32_t>(__popcll(peers));
-    __syncthreads();
-    {
-      uint32_t acc = run[tid];
-#pragma unroll
-      for (int x = 0; x < kSortWaves; x++) {
-        const uint32_t c = wcnt[buf][x][tid];
-        wcnt[buf][x][tid] = acc;
-        acc += c;
-      }
-      run[tid] = acc;
-#pragma unroll
-      for (int x = 0; x < kSortWaves; x++) wcnt[buf ^ 1][x][tid] = 0;
+    const int leader = __ffsll(static_cast<long long>(peers)) - 1;
+    uint32_t old = 0;
+    if (valid && lr == 0) {
+      old = cnt[d];
+      cnt[d] = old + static_cast<uint32_t>(__popcll(peers));
     }
-    __syncthreads();
+    old = __shfl(old, leader, kWave);
     key[i] = k;
     dg[i] = d;
-    rk[i] = valid ? wcnt[buf][w][d] + lr : 0u;
+    rk[i] = old + lr;
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
   }
-  uint32_t total;
-  const uint32_t ds = block_excl_scan<uint32_t, kSortBlock>(run[tid], scan_tmp, total);
+  __syncthreads();
+  // per digit (thread tid owns digit tid): offsets of each wave's keys inside the digit group
+  uint32_t tot = 0;
+#pragma unroll
+  for (int x = 0; x < kSortWaves; x++) {
+    const uint32_t c = wc[x][tid];
+    wc[x][tid] = tot;
+    tot += c;
+  }
+  uint32_t all;
+  const uint32_t ds = block_excl_scan<uint32_t, kSortBlock>(tot, scan_tmp, all);
   dstart[tid] = ds;
   __syncthreads();
 #pragma unroll
   for (int i = 0; i < ITEMS; i++)
-    if (dg[i] < 256u) tile[dstart[dg[i]] + rk[i]] = key[i];
+    if (dg[i] < 256u) tile[dstart[dg[i]] + wc[w][dg[i]] + rk[i]] = key[i];
   __syncthreads();
-  const uint32_t cnt = static_cast<uint32_t>(N - base < static_cast<size_t>(TILE) ? N - base : TILE);
+  const uint32_t count = static_cast<uint32_t>(N - base < static_cast<size_t>(TILE) ? N - base : TILE);
 #pragma unroll
   for (int i = 0; i < ITEMS; i++) {
     const uint32_t j = static_cast<uint32_t>(i * kSortBlock + tid);
-    if (j < cnt) {
+    if (j < count) {
       const K k = tile[j];
       const uint32_t d = RadixKey<K>::digit(k, shift);
       out[gbase[d] + (j - dstart[d])] = k;
