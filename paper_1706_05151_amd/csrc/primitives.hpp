@@ -180,7 +180,7 @@ template <typename K>
 struct RadixItems;
 template <>
 struct RadixItems<uint64_t> {
-  static constexpr int value = 16;
+  static constexpr int value = 32;
 };
 template <>
 struct RadixItems<u128> {
@@ -202,44 +202,83 @@ __device__ __forceinline__ uint64_t match_any9(uint32_t d) {
   return peers;
 }
 
-// Per-tile digit histogram, stored digit-major: hist[d * tiles + tile].
-template <typename K>
-__global__ __launch_bounds__(kSortBlock) void k_radix_hist(const K* __restrict__ keys, uint32_t N, int shift,
-                                                            uint32_t* __restrict__ hist, uint32_t tiles) {
-  constexpr int ITEMS = RadixItems<K>::value;
-  constexpr int TILE = kSortBlock * ITEMS;
-  __shared__ uint32_t h[kSortWaves][256];
-  const int tid = threadIdx.x, w = tid / kWave;
-#pragma unroll
-  for (int x = 0; x < kSortWaves; x++) h[x][tid] = 0;
-  __syncthreads();
-  const size_t base = static_cast<size_t>(blockIdx.x) * TILE;
-#pragma unroll 4
-  for (int i = 0; i < ITEMS; i++) {
-    const size_t idx = base + static_cast<size_t>(i) * kSortBlock + tid;
-    const bool valid = idx < N;
-    const uint32_t d = valid ? RadixKey<K>::digit(keys[idx], shift) : 256u;
-    const uint64_t peers = match_any9(d);
-    if (valid && __popcll(peers & lanemask_lt()) == 0) h[w][d] += static_cast<uint32_t>(__popcll(peers));
-  }
-  __syncthreads();
-  uint32_t t = 0;
-#pragma unroll
-  for (int x = 0; x < kSortWaves; x++) t += h[x][tid];
-  hist[static_cast<size_t>(tid) * tiles + blockIdx.x] = t;
+// Single-sweep LSD radix sort. One read of the keys counts the digits of
+// every pass; each pass is then one kernel that ranks a tile in LDS, finds
+// the tile's global offset per digit from its predecessors' published counts
+// (decoupled look-back: tiles take their index from a counter, so a tile only
+// waits on tiles that are already running) and scatters the tile.
+
+constexpr int kMaxPasses = 16;
+constexpr uint64_t kKindAgg = 1ull << 62;   // status word: count of this tile only
+constexpr uint64_t kKindInc = 2ull << 62;   // status word: count of all tiles up to this one
+constexpr uint64_t kKindMask = 3ull << 62;
+constexpr int kTagShift = 56;               // bits 56..61 hold the pass number + 1
+constexpr uint64_t kValMask = (1ull << kTagShift) - 1;
+constexpr uint32_t kSpinLimit = 1u << 22;   // polls of a not-yet-published word before giving up
+
+__device__ __forceinline__ uint32_t radix_digit_bits(int shift, int bit_hi) {
+  const int w = bit_hi - shift;
+  return w >= 8 ? 255u : (1u << w) - 1u;
 }
 
-// Stable scatter of one tile. Wave w owns the contiguous chunk
-// [w*ITEMS*64, (w+1)*ITEMS*64) of the tile and ranks its keys among equal
-// digits with wave-private counters (ballot match of equal digits, the
-// lowest lane of each group updating the counter); one block-wide prefix over
-// waves and digits then places every key, so tile order = index order.
-// The tile is staged in LDS sorted by digit and each digit run is written
-// contiguously to its global offset.
+// hist[p * 256 + d] += number of keys whose pass-p digit is d.
 template <typename K>
-__global__ __launch_bounds__(kSortBlock) void k_radix_scatter(const K* __restrict__ in, K* __restrict__ out, uint32_t N,
-                                                               int shift, const uint32_t* __restrict__ offs,
-                                                               uint32_t tiles) {
+__global__ __launch_bounds__(kSortBlock) void k_sweep_hist(const K* __restrict__ keys, uint32_t N, int bit_lo,
+                                                            int bit_hi, int passes, uint32_t* __restrict__ hist) {
+  constexpr int ITEMS = RadixItems<K>::value;
+  constexpr int TILE = kSortBlock * ITEMS;
+  __shared__ uint32_t h[kMaxPasses * 256];
+  for (int i = threadIdx.x; i < passes * 256; i += kSortBlock) h[i] = 0;
+  __syncthreads();
+  for (size_t base = static_cast<size_t>(blockIdx.x) * TILE; base < N; base += static_cast<size_t>(gridDim.x) * TILE) {
+    K k[ITEMS];
+#pragma unroll
+    for (int i = 0; i < ITEMS; i++) {
+      const size_t idx = base + static_cast<size_t>(i) * kSortBlock + threadIdx.x;
+      if (idx < N) k[i] = keys[idx];
+    }
+    for (int p = 0; p < passes; p++) {
+      const int shift = bit_lo + 8 * p;
+      const uint32_t dm = radix_digit_bits(shift, bit_hi);
+#pragma unroll
+      for (int i = 0; i < ITEMS; i++) {
+        const size_t idx = base + static_cast<size_t>(i) * kSortBlock + threadIdx.x;
+        if (idx < N) atomicAdd(&h[p * 256 + (RadixKey<K>::digit(k[i], shift) & dm)], 1u);
+      }
+    }
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < passes * 256; i += kSortBlock)
+    if (h[i]) atomicAdd(&hist[i], h[i]);
+}
+
+// In place: each pass's 256 counts become exclusive digit starts (one block per pass).
+static __global__ __launch_bounds__(kSortBlock) void k_sweep_starts(uint32_t* __restrict__ hist) {
+  __shared__ uint32_t tmp[kSortWaves];
+  uint32_t* h = hist + static_cast<size_t>(blockIdx.x) * 256;
+  const uint32_t x = h[threadIdx.x];
+  uint32_t all;
+  const uint32_t ex = block_excl_scan<uint32_t, kSortBlock>(x, tmp, all);
+  h[threadIdx.x] = ex;
+}
+
+__device__ __forceinline__ uint64_t status_load(const uint64_t* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void status_store(uint64_t* p, uint64_t v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// One pass. Wave w ranks the contiguous chunk [w*ITEMS*64, (w+1)*ITEMS*64)
+// of the tile among equal digits with wave-private counters (ballot match,
+// the lowest lane of each group updating the counter), so tile order is
+// index order and the pass is stable. ctr[0] hands out tile indices; ctr[1]
+// is set if a look-back gave up.
+template <typename K>
+__global__ __launch_bounds__(kSortBlock) void k_sweep_scatter(const K* __restrict__ in, K* __restrict__ out, uint32_t N,
+                                                               int shift, uint32_t dmask, uint64_t tag,
+                                                               const uint32_t* __restrict__ starts,
+                                                               uint64_t* __restrict__ status, uint32_t* __restrict__ ctr) {
   constexpr int ITEMS = RadixItems<K>::value;
   constexpr int TILE = kSortBlock * ITEMS;
   constexpr int CHUNK = kWave * ITEMS;
@@ -248,25 +287,30 @@ __global__ __launch_bounds__(kSortBlock) void k_radix_scatter(const K* __restric
   __shared__ uint32_t dstart[256];
   __shared__ uint32_t gbase[256];
   __shared__ uint32_t scan_tmp[kSortWaves];
+  __shared__ uint32_t s_tile;
   const int tid = threadIdx.x, w = tid / kWave, lane = lane_id();
-  const size_t base = static_cast<size_t>(blockIdx.x) * TILE;
-
+  if (tid == 0) s_tile = atomicAdd(&ctr[0], 1u);
 #pragma unroll
   for (int x = 0; x < kSortWaves; x++) wc[x][tid] = 0;
-  gbase[tid] = offs[static_cast<size_t>(tid) * tiles + blockIdx.x];
   __syncthreads();
+  const uint32_t t = s_tile;
+  const size_t base = static_cast<size_t>(t) * TILE;
 
   K key[ITEMS];
   uint32_t rk[ITEMS];
   uint32_t dg[ITEMS];
+#pragma unroll
+  for (int i = 0; i < ITEMS; i++) {
+    const size_t idx = base + static_cast<size_t>(w) * CHUNK + static_cast<size_t>(i) * kWave + lane;
+    key[i] = K{};
+    if (idx < N) key[i] = in[idx];
+  }
   uint32_t* cnt = wc[w];
 #pragma unroll
   for (int i = 0; i < ITEMS; i++) {
     const size_t idx = base + static_cast<size_t>(w) * CHUNK + static_cast<size_t>(i) * kWave + lane;
     const bool valid = idx < N;
-    K k{};
-    if (valid) k = in[idx];
-    const uint32_t d = valid ? RadixKey<K>::digit(k, shift) : 256u;
+    const uint32_t d = valid ? (RadixKey<K>::digit(key[i], shift) & dmask) : 256u;
     const uint64_t peers = match_any9(d);
     const uint32_t lr = static_cast<uint32_t>(__popcll(peers & lanemask_lt()));
     const int leader = __ffsll(static_cast<long long>(peers)) - 1;
@@ -276,15 +320,12 @@ __global__ __launch_bounds__(kSortBlock) void k_radix_scatter(const K* __restric
       cnt[d] = old + static_cast<uint32_t>(__popcll(peers));
     }
     old = __shfl(old, leader, kWave);
-    key[i] = k;
     dg[i] = d;
     rk[i] = old + lr;
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
   }
   __syncthreads();
-  // per digit (thread tid owns digit tid): offsets of each wave's keys inside the digit group
+  // thread tid owns digit tid: per-wave offsets inside the digit, and the tile's count
   uint32_t tot = 0;
 #pragma unroll
   for (int x = 0; x < kSortWaves; x++) {
@@ -292,9 +333,35 @@ __global__ __launch_bounds__(kSortBlock) void k_radix_scatter(const K* __restric
     wc[x][tid] = tot;
     tot += c;
   }
+  uint64_t* mine = status + static_cast<size_t>(t) * 256 + tid;
+  uint64_t excl = 0;
+  if (t == 0) {
+    status_store(mine, kKindInc | tag | tot);
+  } else {
+    status_store(mine, kKindAgg | tag | tot);
+    uint32_t j = t - 1;
+    uint32_t polls = 0;
+    for (;;) {
+      const uint64_t v = status_load(status + static_cast<size_t>(j) * 256 + tid);
+      const uint64_t kind = v & kKindMask;
+      if (kind == 0 || (v & ~kKindMask & ~kValMask) != tag) {
+        if (++polls > kSpinLimit) {
+          atomicOr(&ctr[1], 1u);
+          break;
+        }
+        __builtin_amdgcn_s_sleep(1);
+        continue;
+      }
+      excl += v & kValMask;
+      if (kind == kKindInc || j == 0) break;
+      --j;
+    }
+    status_store(mine, kKindInc | tag | (excl + tot));
+  }
   uint32_t all;
   const uint32_t ds = block_excl_scan<uint32_t, kSortBlock>(tot, scan_tmp, all);
   dstart[tid] = ds;
+  gbase[tid] = starts[tid] + static_cast<uint32_t>(excl);
   __syncthreads();
 #pragma unroll
   for (int i = 0; i < ITEMS; i++)
@@ -306,10 +373,17 @@ __global__ __launch_bounds__(kSortBlock) void k_radix_scatter(const K* __restric
     const uint32_t j = static_cast<uint32_t>(i * kSortBlock + tid);
     if (j < count) {
       const K k = tile[j];
-      const uint32_t d = RadixKey<K>::digit(k, shift);
+      const uint32_t d = RadixKey<K>::digit(k, shift) & dmask;
       out[gbase[d] + (j - dstart[d])] = k;
     }
   }
+}
+
+template <typename T>
+__global__ void k_fill_words(T* __restrict__ p, size_t n, T v) {
+  for (size_t i = static_cast<size_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < n;
+       i += static_cast<size_t>(gridDim.x) * blockDim.x)
+    p[i] = v;
 }
 
 // Sorts N keys ascending by bits [bit_lo, bit_hi) (8-bit digits, stable).
@@ -319,20 +393,45 @@ K* radix_sort(K* keys, K* tmp, size_t N, int bit_lo, int bit_hi, hipStream_t s) 
   if (N <= 1 || bit_hi <= bit_lo) return keys;
   if (N >= (1ull << 32)) fail(TC_E_INVAL, "radix_sort: more than 2^32 - 1 keys");
   constexpr int TILE = kSortBlock * RadixItems<K>::value;
+  const int passes = (bit_hi - bit_lo + 7) / 8;
+  if (passes > kMaxPasses) fail(TC_E_INVAL, "radix_sort: bit range too wide");
   const uint32_t tiles = static_cast<uint32_t>((N + TILE - 1) / TILE);
-  DevBuf<uint32_t> hist(static_cast<size_t>(256) * tiles, s);
+  // words: passes*256 histogram/starts, then per pass {tile counter, look-back failure flag}
+  const size_t nwords = static_cast<size_t>(passes) * 256 + 2 * passes;
+  DevBuf<uint32_t> words(nwords, s);
+  DevBuf<uint64_t> status(static_cast<size_t>(tiles) * 256, s);
+  k_fill_words<uint32_t><<<grid_for(nwords, 256, 64), 256, 0, s>>>(words.get(), nwords, 0u);
+  TC_LAUNCH_CHECK();
+  k_fill_words<uint64_t><<<grid_for(static_cast<uint64_t>(tiles) * 256, 256, 8192), 256, 0, s>>>(
+      status.get(), static_cast<size_t>(tiles) * 256, 0ull);
+  TC_LAUNCH_CHECK();
+  uint32_t* hist = words.get();
+  uint32_t* ctrs = hist + static_cast<size_t>(passes) * 256;
+  k_sweep_hist<K><<<tiles < 2048u ? tiles : 2048u, kSortBlock, 0, s>>>(keys, static_cast<uint32_t>(N), bit_lo, bit_hi,
+                                                                       passes, hist);
+  TC_LAUNCH_CHECK();
+  k_sweep_starts<<<passes, kSortBlock, 0, s>>>(hist);
+  TC_LAUNCH_CHECK();
   K* a = keys;
   K* b = tmp;
-  for (int shift = bit_lo; shift < bit_hi; shift += 8) {
-    k_radix_hist<K><<<tiles, kSortBlock, 0, s>>>(a, static_cast<uint32_t>(N), shift, hist.get(), tiles);
-    TC_LAUNCH_CHECK();
-    exclusive_scan<uint32_t>(hist.get(), hist.get(), static_cast<size_t>(256) * tiles, s);
-    k_radix_scatter<K><<<tiles, kSortBlock, 0, s>>>(a, b, static_cast<uint32_t>(N), shift, hist.get(), tiles);
+  for (int p = 0; p < passes; p++) {
+    const int shift = bit_lo + 8 * p;
+    const int w = bit_hi - shift;
+    const uint32_t dmask = w >= 8 ? 255u : (1u << w) - 1u;
+    uint32_t* ctr = ctrs + 2 * p;
+    k_sweep_scatter<K><<<tiles, kSortBlock, 0, s>>>(a, b, static_cast<uint32_t>(N), shift, dmask,
+                                                    static_cast<uint64_t>(p + 1) << kTagShift,
+                                                    hist + static_cast<size_t>(p) * 256, status.get(), ctr);
     TC_LAUNCH_CHECK();
     K* t = a;
     a = b;
     b = t;
   }
+  uint32_t h_err[2 * kMaxPasses] = {};
+  TC_HIP(hipMemcpyAsync(h_err, ctrs, 2 * passes * sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+  TC_HIP(hipStreamSynchronize(s));
+  for (int p = 0; p < passes; p++)
+    if (h_err[2 * p + 1]) fail(TC_E_DEVICE, "radix_sort: a tile's look-back did not complete");
   return a;
 }
 
