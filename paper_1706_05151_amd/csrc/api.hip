@@ -41,7 +41,6 @@ struct DeviceScope {
   explicit DeviceScope(int dev) : want(dev) {
     TC_HIP(hipGetDevice(&prev));
     if (prev != dev) TC_HIP(hipSetDevice(dev));
-    retain_pool_memory();
   }
   ~DeviceScope() {
     if (prev >= 0 && prev != want) (void)hipSetDevice(prev);

@@ -61,26 +61,45 @@ struct GatherU64 {
   __device__ uint64_t operator()(size_t i) const { return k[i]; }
 };
 
-// d_v: the lo side is sorted, so runs inside a wave are added once per run.
-__global__ void k_degrees(const uint64_t* __restrict__ uk, uint64_t m, int b, int32_t* __restrict__ deg) {
-  const uint64_t mask = (1ull << b) - 1;
+// Endpoint accessors over the sorted unique keys (smaller endpoint) and over
+// the sorted larger endpoints.
+struct LoEnd {
+  const uint64_t* k;
+  int b;
+  __device__ int32_t operator()(size_t i) const { return static_cast<int32_t>(k[i] >> b); }
+};
+struct HiEnd {
+  const uint32_t* h;
+  __device__ int32_t operator()(size_t i) const { return static_cast<int32_t>(h[i]); }
+};
+
+// deg[v] += number of positions i in [0, m) with get(i) == v, for a sorted
+// sequence: each run inside a wave is added with one atomic.
+template <typename Get>
+__global__ __launch_bounds__(kBlock) void k_run_counts(Get get, uint64_t m, int32_t* __restrict__ deg) {
   const uint64_t stride = static_cast<uint64_t>(gridDim.x) * blockDim.x;
   for (uint64_t i0 = static_cast<uint64_t>(blockIdx.x) * blockDim.x; i0 < m; i0 += stride) {
     const uint64_t i = i0 + threadIdx.x;
     const bool valid = i < m;
-    const uint64_t key = valid ? uk[i] : ~0ull;
-    const int32_t lo = static_cast<int32_t>(key >> b), hi = static_cast<int32_t>(key & mask);
-    const int32_t prev = __shfl_up(lo, 1, kWave);
-    const bool head = valid && (lane_id() == 0 || prev != lo);
+    const int32_t v = valid ? get(i) : -1;
+    const int32_t prev = __shfl_up(v, 1, kWave);
+    const bool head = valid && (lane_id() == 0 || prev != v);
     const uint64_t heads = __ballot(head);
     const uint64_t vmask = __ballot(valid);
     if (head) {
       const uint64_t above = heads & ~((2ull << lane_id()) - 1ull);  // heads after this lane (lane 63: none)
       const int end = above ? __ffsll(static_cast<long long>(above)) - 1 : 64 - __clzll(static_cast<long long>(vmask));
-      atomicAdd(&deg[lo], end - lane_id());
+      atomicAdd(&deg[v], end - lane_id());
     }
-    if (valid) atomicAdd(&deg[hi], 1);
   }
+}
+
+__global__ __launch_bounds__(kBlock) void k_larger_ends(const uint64_t* __restrict__ uk, uint64_t m, int b,
+                                                         uint32_t* __restrict__ out) {
+  const uint64_t mask = (1ull << b) - 1;
+  for (uint64_t i = static_cast<uint64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < m;
+       i += static_cast<uint64_t>(gridDim.x) * blockDim.x)
+    out[i] = static_cast<uint32_t>(uk[i] & mask);
 }
 
 // Rank key of a vertex: graph index (hi word), then the order key, then id.
@@ -151,13 +170,24 @@ __global__ void k_csr_fill(const uint64_t* __restrict__ ok, uint64_t m, int b, i
 
 // off[r] = first entry whose row is >= r, for sorted rows `row` of length m
 // (one binary search per row, so long runs of empty rows cost nothing extra).
-__global__ void k_offsets_from_rows(const int32_t* __restrict__ row, uint64_t m, int32_t n, int64_t* __restrict__ off) {
+struct RowOfI32 {
+  const int32_t* r;
+  __device__ int64_t operator()(uint64_t i) const { return r[i]; }
+};
+struct RowOfKeyHi {
+  const uint64_t* k;
+  __device__ int64_t operator()(uint64_t i) const { return static_cast<int64_t>(k[i] >> 32); }
+};
+
+// off[r] = first position whose row is >= r (one binary search per row).
+template <typename Row>
+__global__ void k_offsets_from_rows(Row row, uint64_t m, int32_t n, int64_t* __restrict__ off) {
   for (int64_t r = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; r <= n;
        r += static_cast<int64_t>(gridDim.x) * blockDim.x) {
     uint64_t lo = 0, hi = m;
     while (lo < hi) {
       const uint64_t mid = (lo + hi) >> 1;
-      if (row[mid] < r) lo = mid + 1;
+      if (row(mid) < r) lo = mid + 1;
       else hi = mid;
     }
     off[r] = static_cast<int64_t>(lo);
@@ -184,7 +214,13 @@ __global__ void k_array_max(const int32_t* __restrict__ a, int32_t n, int* __res
 }  // namespace
 
 void offsets_from_rows(const int32_t* row, uint64_t m, int32_t n, int64_t* off, hipStream_t s) {
-  k_offsets_from_rows<<<grid_for(static_cast<uint64_t>(n) + 1, kBlock, 65536), kBlock, 0, s>>>(row, m, n, off);
+  k_offsets_from_rows<<<grid_for(static_cast<uint64_t>(n) + 1, kBlock, 65536), kBlock, 0, s>>>(RowOfI32{row}, m, n, off);
+  TC_LAUNCH_CHECK();
+}
+
+void offsets_from_key_rows(const uint64_t* keys, uint64_t m, int32_t n, int64_t* off, hipStream_t s) {
+  k_offsets_from_rows<<<grid_for(static_cast<uint64_t>(n) + 1, kBlock, 65536), kBlock, 0, s>>>(RowOfKeyHi{keys}, m, n,
+                                                                                                 off);
   TC_LAUNCH_CHECK();
 }
 
@@ -207,7 +243,6 @@ void build_graph(const int32_t* src, const int32_t* dst, int64_t E, int32_t n, c
   if (E >= (1ll << 32) - 1) fail(TC_E_INVAL, "more than 2^32 - 2 edge records");
   if (E > 0 && (!src || !dst)) fail(TC_E_INVAL, "NULL edge array");
   TC_HIP(hipGetDevice(&g->device));
-  retain_pool_memory();
   g->n = n;
   g->num_graphs = G;
   g->vbase.assign(static_cast<size_t>(G) + 1, 0);
@@ -285,7 +320,16 @@ void build_graph(const int32_t* src, const int32_t* dst, int64_t E, int32_t n, c
   g->deg.alloc(n, s);
   if (n > 0) TC_HIP(hipMemsetAsync(g->deg.p, 0, n * sizeof(int32_t), s));
   if (m > 0) {
-    k_degrees<<<grid_for(m, kBlock, 65536), kBlock, 0, s>>>(uniq, m, b, g->deg.p);
+    // d_v = (edges with v as the smaller endpoint: runs of the sorted keys)
+    //     + (edges with v as the larger endpoint: runs after sorting those ends);
+    // the larger ends and their sort buffer live in the spare key buffer (E >= m)
+    k_run_counts<<<grid_for(m, kBlock, 65536), kBlock, 0, s>>>(LoEnd{uniq, b}, m, g->deg.p);
+    TC_LAUNCH_CHECK();
+    uint32_t* ends = reinterpret_cast<uint32_t*>(spare);
+    k_larger_ends<<<grid_for(m, kBlock, 65536), kBlock, 0, s>>>(uniq, m, b, ends);
+    TC_LAUNCH_CHECK();
+    const uint32_t* sorted_ends = radix_sort<uint32_t>(ends, ends + m, m, 0, b, s);
+    k_run_counts<<<grid_for(m, kBlock, 65536), kBlock, 0, s>>>(HiEnd{sorted_ends}, m, g->deg.p);
     TC_LAUNCH_CHECK();
   }
 

@@ -3,7 +3,6 @@
 
 #include <hip/hip_runtime.h>
 
-#include <atomic>
 #include <cstdint>
 #include <cstdio>
 #include <stdexcept>
@@ -35,28 +34,18 @@ inline void hip_check(hipError_t e, const char* what, const char* file, int line
 #define TC_HIP(x) ::tc::hip_check((x), #x, __FILE__, __LINE__)
 #define TC_LAUNCH_CHECK() ::tc::hip_check(hipGetLastError(), "kernel launch", __FILE__, __LINE__)
 
-// ------------------------------------------------- stream-ordered buffers --
+// ------------------------------------------------------- device memory --
 
-// The library allocates from the device's default stream-ordered pool and
-// lets it keep up to 96 GiB of freed memory cached, so repeated builds and
-// queries reuse mappings instead of returning memory to the driver at every
-// synchronisation (the default release threshold is 0).
-inline void retain_pool_memory() {
-  static std::atomic<uint64_t> done_mask{0};
-  int dev = 0;
-  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return;
-  const uint64_t bit = 1ull << dev;
-  if (done_mask.load() & bit) return;
-  hipMemPool_t pool;
-  if (hipDeviceGetDefaultMemPool(&pool, dev) == hipSuccess) {
-    uint64_t threshold = 96ull << 30;
-    (void)hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &threshold);
-  }
-  done_mask.fetch_or(bit);
-}
+// Device memory from the library's per-device block cache (memory.hip).
+// dev_alloc: the block is usable by work queued on `s` after the call.
+// dev_free: the block may be reused once the work queued on `s` before the
+// call is done; work on other streams must be finished by the caller.
+void* dev_alloc(size_t bytes, hipStream_t s);
+void dev_free(void* p, hipStream_t s);
+void dev_release_cached();   // returns the current device's idle blocks to the driver
+size_t dev_cached_bytes();   // idle bytes held for the current device
 
-// Device buffer taken from the stream-ordered allocator and returned to it on
-// destruction (the free is ordered after all work queued on the stream).
+// Scratch buffer released on destruction, ordered after the work queued on its stream.
 template <typename T>
 class DevBuf {
  public:
@@ -79,10 +68,10 @@ class DevBuf {
     s_ = s;
     n_ = count;
     if (count == 0) return;
-    TC_HIP(hipMallocAsync(reinterpret_cast<void**>(&p_), count * sizeof(T), s));
+    p_ = static_cast<T*>(dev_alloc(count * sizeof(T), s));
   }
   void release() {
-    if (p_) (void)hipFreeAsync(p_, s_);
+    if (p_) dev_free(p_, s_);
     p_ = nullptr;
     n_ = 0;
   }

@@ -81,33 +81,28 @@ __global__ __launch_bounds__(kBlock) void k_work(const int64_t* __restrict__ off
 
 // -------------------------------------------------------- plan building ---
 
-struct InEdgePred {
-  const int64_t* off;
-  const int32_t* adj;
-  const int32_t* src;
-  __device__ bool operator()(size_t e) const {
-    const int32_t v = src[e], u = adj[e];
-    return off[v + 1] - static_cast<int64_t>(e) - 1 > 0 && off[u + 1] - off[u] > 0;
+// In-edge key of every oriented edge e = (v, u), in edge order: (u << 32) | e,
+// and the length of the suffix of N_v after u. Pivots with an empty N_u and
+// records with an empty suffix stay in the list; they are given no work.
+__global__ __launch_bounds__(kBlock) void k_inkeys(const int64_t* __restrict__ off, const int32_t* __restrict__ adj,
+                                                   const int32_t* __restrict__ src, uint64_t m,
+                                                   uint64_t* __restrict__ keys, uint32_t* __restrict__ lens) {
+  for (uint64_t e = static_cast<uint64_t>(blockIdx.x) * blockDim.x + threadIdx.x; e < m;
+       e += static_cast<uint64_t>(gridDim.x) * blockDim.x) {
+    keys[e] = (static_cast<uint64_t>(static_cast<uint32_t>(adj[e])) << 32) | e;
+    lens[e] = static_cast<uint32_t>(off[src[e] + 1] - static_cast<int64_t>(e) - 1);
   }
-};
+}
 
-struct InEdgeKey {
-  const int32_t* adj;
-  __device__ uint64_t operator()(size_t e) const {
-    return (static_cast<uint64_t>(static_cast<uint32_t>(adj[e])) << 32) | static_cast<uint64_t>(e);
-  }
-};
-
-__global__ void k_inrec_fill(const uint64_t* __restrict__ ikeys, uint64_t mi, const int64_t* __restrict__ off,
-                             const int32_t* __restrict__ src, InRec* __restrict__ rec, int32_t* __restrict__ piv,
-                             int64_t* __restrict__ cost) {
+// Records in pivot order from the sorted keys and their suffix lengths.
+__global__ __launch_bounds__(kBlock) void k_inrec_fill(const uint64_t* __restrict__ ikeys,
+                                                       const uint32_t* __restrict__ lens, uint64_t mi,
+                                                       InRec* __restrict__ rec, int64_t* __restrict__ cost) {
   for (uint64_t i = static_cast<uint64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < mi;
        i += static_cast<uint64_t>(gridDim.x) * blockDim.x) {
-    const uint64_t k = ikeys[i];
-    const uint32_t e = static_cast<uint32_t>(k & 0xffffffffu);
-    const uint32_t len = static_cast<uint32_t>(off[src[e] + 1] - static_cast<int64_t>(e) - 1);
+    const uint32_t e = static_cast<uint32_t>(ikeys[i] & 0xffffffffu);
+    const uint32_t len = lens[i];
     rec[i] = InRec{e + 1, len};
-    piv[i] = static_cast<int32_t>(k >> 32);
     cost[i] = static_cast<int64_t>(len) + kCostPerRecord;
   }
 }
@@ -119,14 +114,17 @@ __device__ __forceinline__ int64_t ceil_div(int64_t a, int64_t b) { return (a + 
 __global__ void k_pivot_classify(int32_t n, const int64_t* __restrict__ off, const int64_t* __restrict__ in_off,
                                  const int64_t* __restrict__ fin, int64_t hub_dhat, int64_t hub_cap, int64_t iw_hub,
                                  int64_t iw_wave, int64_t* __restrict__ n_hub, int64_t* __restrict__ n_split,
-                                 int32_t* __restrict__ grouped) {
+                                 int32_t* __restrict__ grouped, unsigned long long* __restrict__ probes) {
+  unsigned long long pr = 0;
   for (int32_t u = blockIdx.x * blockDim.x + threadIdx.x; u < n; u += gridDim.x * blockDim.x) {
     const int64_t dh = off[u + 1] - off[u];
     const int64_t i0 = in_off[u], i1 = in_off[u + 1];
     const int64_t cost = fin[i1] - fin[i0];
+    const int64_t work = cost - kCostPerRecord * (i1 - i0);  // sum of the suffix lengths
     int64_t h = 0, sp = 0;
     int32_t gr = 0;
-    if (dh > 0 && i1 > i0) {
+    if (dh > 0 && work > 0) {
+      pr += static_cast<unsigned long long>(work);
       if (dh > hub_dhat) {
         h = ceil_div(dh, hub_cap) * ceil_div(cost, iw_hub);
       } else if (cost + kCostPerStaged * dh > iw_wave) {
@@ -139,6 +137,8 @@ __global__ void k_pivot_classify(int32_t n, const int64_t* __restrict__ off, con
     n_split[u] = sp;
     grouped[u] = gr;
   }
+  pr = wave_sum(pr);
+  if (lane_id() == 0 && pr) atomicAdd(probes, pr);
 }
 
 // First in-edge index in [i0,i1] whose cost prefix reaches target (boundary
@@ -760,26 +760,24 @@ void ensure_plan(Csr& c, hipStream_t s, const Options& o) {
     return;
   }
   const int b = bits_for(n > 1 ? static_cast<uint64_t>(n - 1) : 1);
-  // in-edge keys (u, e) for edges with a non-empty suffix and non-empty N_u
+  // in-edge records of all m edges, sorted by pivot u (stable: by e within u)
+  const uint64_t mi = m;
   DevBuf<uint64_t> ik(m, s), ik2(m, s);
-  DevBuf<uint64_t> d_cnt(1, s);
-  compact_if<uint64_t>(m, InEdgePred{c.off.p, c.adj.p, c.src.p}, InEdgeKey{c.adj.p}, ik.get(), d_cnt.get(), s);
-  uint64_t mi = 0;
-  TC_HIP(hipMemcpyAsync(&mi, d_cnt.get(), sizeof(uint64_t), hipMemcpyDeviceToHost, s));
-  TC_HIP(hipStreamSynchronize(s));
-  uint64_t* sk = radix_sort<uint64_t>(ik.get(), ik2.get(), mi, 32, 32 + b, s);
+  DevBuf<uint32_t> il(m, s), il2(m, s);
+  k_inkeys<<<grid_for(m, kBlock, 65536), kBlock, 0, s>>>(c.off.p, c.adj.p, c.src.p, m, ik.get(), il.get());
+  TC_LAUNCH_CHECK();
+  uint32_t* sl = il.get();
+  uint64_t* sk = radix_sort_pairs<uint64_t, uint32_t>(ik.get(), ik2.get(), sl, il2.get(), mi, 32, 32 + b, s);
   P.inrec.alloc(mi, s);
-  DevBuf<int32_t> piv(mi, s);
   DevBuf<int64_t> fin(mi + 1, s);
-  if (mi > 0) {
-    k_inrec_fill<<<grid_for(mi, kBlock, 65536), kBlock, 0, s>>>(sk, mi, c.off.p, c.src.p, P.inrec.p, piv.get(), fin.get());
-    TC_LAUNCH_CHECK();
-  }
-  offsets_from_rows(piv.get(), mi, n, P.in_off.p, s);
+  k_inrec_fill<<<grid_for(mi, kBlock, 65536), kBlock, 0, s>>>(sk, sl, mi, P.inrec.p, fin.get());
+  TC_LAUNCH_CHECK();
+  offsets_from_key_rows(sk, mi, n, P.in_off.p, s);
   exclusive_scan<int64_t>(fin.get(), fin.get(), mi, s, fin.get() + mi);
   ik.release();
   ik2.release();
-  piv.release();
+  il.release();
+  il2.release();
 
   // classify pivots and count items
   const int64_t iw_wave = o.item_work > 64 ? o.item_work : 64;
@@ -787,17 +785,21 @@ void ensure_plan(Csr& c, hipStream_t s, const Options& o) {
   const int64_t cap = hub_slice_cap(kCountPerNode);
   DevBuf<int64_t> nh(static_cast<size_t>(n) + 1, s), ns(static_cast<size_t>(n) + 1, s);
   DevBuf<int32_t> grp(n, s);
+  DevBuf<unsigned long long> d_probes(1, s);
+  k_fill_words<unsigned long long><<<1, 64, 0, s>>>(d_probes.get(), 1, 0ull);
+  TC_LAUNCH_CHECK();
   k_pivot_classify<<<grid_for(n, kBlock, 65536), kBlock, 0, s>>>(n, c.off.p, P.in_off.p, fin.get(), clamp_hub(o.hub_dhat), cap,
-                                                                 iw_hub, iw_wave, nh.get(), ns.get(), grp.get());
+                                                                 iw_hub, iw_wave, nh.get(), ns.get(), grp.get(),
+                                                                 d_probes.get());
   TC_LAUNCH_CHECK();
   exclusive_scan<int64_t>(nh.get(), nh.get(), n, s, nh.get() + n);
   exclusive_scan<int64_t>(ns.get(), ns.get(), n, s, ns.get() + n);
   int64_t counts[3] = {0, 0, 0};
   TC_HIP(hipMemcpyAsync(&counts[0], nh.get() + n, sizeof(int64_t), hipMemcpyDeviceToHost, s));
   TC_HIP(hipMemcpyAsync(&counts[1], ns.get() + n, sizeof(int64_t), hipMemcpyDeviceToHost, s));
-  TC_HIP(hipMemcpyAsync(&counts[2], fin.get() + mi, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+  TC_HIP(hipMemcpyAsync(&counts[2], d_probes.get(), sizeof(int64_t), hipMemcpyDeviceToHost, s));
   TC_HIP(hipStreamSynchronize(s));
-  P.probes = static_cast<uint64_t>(counts[2]) - static_cast<uint64_t>(kCostPerRecord) * mi;
+  P.probes = static_cast<uint64_t>(counts[2]);
   P.n_hub_items = static_cast<uint64_t>(counts[0]);
   P.n_wave_items = static_cast<uint64_t>(counts[1]);
   // items: [hub items | split wave items | grouped pivots as int32 at the end]

@@ -22,15 +22,17 @@ struct Owned {
   Owned(const Owned&) = delete;
   Owned& operator=(const Owned&) = delete;
   ~Owned() { reset(); }
+  // Callers free only when no stream still uses the array (after a device
+  // synchronisation).
   void reset() {
-    if (p) (void)hipFreeAsync(p, nullptr);
+    if (p) dev_free(p, nullptr);
     p = nullptr;
     n = 0;
   }
   void alloc(size_t count, hipStream_t s = nullptr) {
     reset();
     n = count;
-    if (count) TC_HIP(hipMallocAsync(reinterpret_cast<void**>(&p), count * sizeof(T), s));
+    if (count) p = static_cast<T*>(dev_alloc(count * sizeof(T), s));
   }
   // take over a stream-ordered buffer
   void adopt(DevBuf<T>& b) {
@@ -69,7 +71,7 @@ struct PivotPlan {
   Owned<int32_t> grouped;    // small pivots served from a shared queue
   uint64_t n_grouped = 0;
   int64_t hub_dhat = 0, item_work = 0;  // options the plan was built with
-  uint64_t probes = 0;       // sum of suffix lengths |A| over in-edge records (the wedge checks P)
+  uint64_t probes = 0;       // sum of suffix lengths |A| over records whose pivot has a non-empty N_u
   uint64_t n_split_items() const { return n_wave_items; }
   void reset() {
     ready = false;
@@ -164,6 +166,8 @@ void build_sampled_csr(const tc_graph* g, double q, uint64_t seed, Csr& out, hip
 void sort_triangles(int32_t* tri, int64_t count, int bits, hipStream_t s);
 // off[r] = first index whose row is >= r, for rows sorted ascending (length m); off has n+1 entries
 void offsets_from_rows(const int32_t* row, uint64_t m, int32_t n, int64_t* off, hipStream_t s);
+// Same, for keys sorted by their high 32 bits (the row).
+void offsets_from_key_rows(const uint64_t* keys, uint64_t m, int32_t n, int64_t* off, hipStream_t s);
 // largest off[r+1]-off[r] (0 if n == 0); synchronises s
 int32_t max_row_length(const int64_t* off, int32_t n, hipStream_t s);
 

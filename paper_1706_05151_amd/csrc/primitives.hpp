@@ -3,6 +3,9 @@
 // instantiates its own kernels.
 #pragma once
 
+#include <type_traits>
+#include <utility>
+
 #include "common.hpp"
 
 namespace tc {
@@ -170,6 +173,11 @@ struct RadixKey<uint64_t> {
 };
 
 template <>
+struct RadixKey<uint32_t> {
+  __device__ __forceinline__ static uint32_t digit(uint32_t k, int shift) { return (k >> shift) & 255u; }
+};
+
+template <>
 struct RadixKey<u128> {
   __device__ __forceinline__ static uint32_t digit(const u128& k, int shift) {
     return shift < 64 ? static_cast<uint32_t>(k.lo >> shift) & 255u : static_cast<uint32_t>(k.hi >> (shift - 64)) & 255u;
@@ -180,6 +188,10 @@ template <typename K>
 struct RadixItems;
 template <>
 struct RadixItems<uint64_t> {
+  static constexpr int value = 32;
+};
+template <>
+struct RadixItems<uint32_t> {
   static constexpr int value = 32;
 };
 template <>
@@ -221,15 +233,20 @@ __device__ __forceinline__ uint32_t radix_digit_bits(int shift, int bit_hi) {
   return w >= 8 ? 255u : (1u << w) - 1u;
 }
 
-// hist[p * 256 + d] += number of keys whose pass-p digit is d.
+// hist[p * 256 + d] += number of keys whose pass-p digit is d. The block's
+// LDS counts are kept in `copies` interleaved copies (lane L adds to copy
+// L % copies), so lanes with equal digits hit different banks.
 template <typename K>
 __global__ __launch_bounds__(kSortBlock) void k_sweep_hist(const K* __restrict__ keys, uint32_t N, int bit_lo,
-                                                            int bit_hi, int passes, uint32_t* __restrict__ hist) {
+                                                            int bit_hi, int passes, int copies,
+                                                            uint32_t* __restrict__ hist) {
   constexpr int ITEMS = RadixItems<K>::value;
   constexpr int TILE = kSortBlock * ITEMS;
-  __shared__ uint32_t h[kMaxPasses * 256];
-  for (int i = threadIdx.x; i < passes * 256; i += kSortBlock) h[i] = 0;
+  extern __shared__ uint32_t h[];  // passes * 256 * copies
+  const int nh = passes * 256 * copies;
+  for (int i = threadIdx.x; i < nh; i += kSortBlock) h[i] = 0;
   __syncthreads();
+  const uint32_t c = static_cast<uint32_t>(lane_id()) & static_cast<uint32_t>(copies - 1);
   for (size_t base = static_cast<size_t>(blockIdx.x) * TILE; base < N; base += static_cast<size_t>(gridDim.x) * TILE) {
     K k[ITEMS];
 #pragma unroll
@@ -243,13 +260,16 @@ __global__ __launch_bounds__(kSortBlock) void k_sweep_hist(const K* __restrict__
 #pragma unroll
       for (int i = 0; i < ITEMS; i++) {
         const size_t idx = base + static_cast<size_t>(i) * kSortBlock + threadIdx.x;
-        if (idx < N) atomicAdd(&h[p * 256 + (RadixKey<K>::digit(k[i], shift) & dm)], 1u);
+        if (idx < N) atomicAdd(&h[(p * 256 + (RadixKey<K>::digit(k[i], shift) & dm)) * copies + c], 1u);
       }
     }
   }
   __syncthreads();
-  for (int i = threadIdx.x; i < passes * 256; i += kSortBlock)
-    if (h[i]) atomicAdd(&hist[i], h[i]);
+  for (int i = threadIdx.x; i < passes * 256; i += kSortBlock) {
+    uint32_t t = 0;
+    for (int x = 0; x < copies; x++) t += h[i * copies + x];
+    if (t) atomicAdd(&hist[i], t);
+  }
 }
 
 // In place: each pass's 256 counts become exclusive digit starts (one block per pass).
@@ -269,20 +289,28 @@ __device__ __forceinline__ void status_store(uint64_t* p, uint64_t v) {
   __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
+// Value type of a keys-only sort.
+struct NoVal {};
+
 // One pass. Wave w ranks the contiguous chunk [w*ITEMS*64, (w+1)*ITEMS*64)
 // of the tile among equal digits with wave-private counters (ballot match,
 // the lowest lane of each group updating the counter), so tile order is
 // index order and the pass is stable. ctr[0] hands out tile indices; ctr[1]
-// is set if a look-back gave up.
-template <typename K>
-__global__ __launch_bounds__(kSortBlock) void k_sweep_scatter(const K* __restrict__ in, K* __restrict__ out, uint32_t N,
-                                                               int shift, uint32_t dmask, uint64_t tag,
+// is set if a look-back gave up. With a value type V, each key's value moves
+// with it (staged through the same LDS tile after the keys are written).
+template <typename K, typename V>
+__global__ __launch_bounds__(kSortBlock) void k_sweep_scatter(const K* __restrict__ in, K* __restrict__ out,
+                                                               const V* __restrict__ vin, V* __restrict__ vout,
+                                                               uint32_t N, int shift, uint32_t dmask, uint64_t tag,
                                                                const uint32_t* __restrict__ starts,
                                                                uint64_t* __restrict__ status, uint32_t* __restrict__ ctr) {
+  constexpr bool kHasVal = !std::is_same<V, NoVal>::value;
   constexpr int ITEMS = RadixItems<K>::value;
   constexpr int TILE = kSortBlock * ITEMS;
   constexpr int CHUNK = kWave * ITEMS;
+  static_assert(!kHasVal || sizeof(V) <= sizeof(K), "values are staged in the key tile");
   __shared__ K tile[TILE];
+  __shared__ uint8_t pdig[kHasVal ? TILE : 1];
   __shared__ uint32_t wc[kSortWaves][256];
   __shared__ uint32_t dstart[256];
   __shared__ uint32_t gbase[256];
@@ -375,6 +403,25 @@ __global__ __launch_bounds__(kSortBlock) void k_sweep_scatter(const K* __restric
       const K k = tile[j];
       const uint32_t d = RadixKey<K>::digit(k, shift) & dmask;
       out[gbase[d] + (j - dstart[d])] = k;
+      if constexpr (kHasVal) pdig[j] = static_cast<uint8_t>(d);
+    }
+  }
+  if constexpr (kHasVal) {
+    __syncthreads();
+    V* vt = reinterpret_cast<V*>(tile);
+#pragma unroll
+    for (int i = 0; i < ITEMS; i++) {
+      const size_t idx = base + static_cast<size_t>(w) * CHUNK + static_cast<size_t>(i) * kWave + lane;
+      if (dg[i] < 256u) vt[dstart[dg[i]] + wc[w][dg[i]] + rk[i]] = vin[idx];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < ITEMS; i++) {
+      const uint32_t j = static_cast<uint32_t>(i * kSortBlock + tid);
+      if (j < count) {
+        const uint32_t d = pdig[j];
+        vout[gbase[d] + (j - dstart[d])] = vt[j];
+      }
     }
   }
 }
@@ -386,10 +433,13 @@ __global__ void k_fill_words(T* __restrict__ p, size_t n, T v) {
     p[i] = v;
 }
 
-// Sorts N keys ascending by bits [bit_lo, bit_hi) (8-bit digits, stable).
-// Uses `keys` and `tmp` as ping-pong buffers; returns the one holding the result.
-template <typename K>
-K* radix_sort(K* keys, K* tmp, size_t N, int bit_lo, int bit_hi, hipStream_t s) {
+// Sorts N keys ascending by bits [bit_lo, bit_hi) (8-bit digits, stable),
+// each value in `vals` moving with its key. Uses `keys`/`tmp` and
+// `vals`/`vtmp` as ping-pong buffers; returns the key buffer holding the
+// result and points `vals` at the value buffer holding the result.
+// Synchronises the stream before returning (it checks the look-back flags).
+template <typename K, typename V>
+K* radix_sort_pairs(K* keys, K* tmp, V*& vals, V* vtmp, size_t N, int bit_lo, int bit_hi, hipStream_t s) {
   if (N <= 1 || bit_hi <= bit_lo) return keys;
   if (N >= (1ull << 32)) fail(TC_E_INVAL, "radix_sort: more than 2^32 - 1 keys");
   constexpr int TILE = kSortBlock * RadixItems<K>::value;
@@ -407,32 +457,41 @@ K* radix_sort(K* keys, K* tmp, size_t N, int bit_lo, int bit_hi, hipStream_t s) 
   TC_LAUNCH_CHECK();
   uint32_t* hist = words.get();
   uint32_t* ctrs = hist + static_cast<size_t>(passes) * 256;
-  k_sweep_hist<K><<<tiles < 2048u ? tiles : 2048u, kSortBlock, 0, s>>>(keys, static_cast<uint32_t>(N), bit_lo, bit_hi,
-                                                                       passes, hist);
+  const int copies = passes <= 8 ? 8 : 4;  // LDS: passes * 256 * copies words <= 64 KiB
+  k_sweep_hist<K><<<tiles < 2048u ? tiles : 2048u, kSortBlock, static_cast<size_t>(passes) * 256 * copies * 4, s>>>(
+      keys, static_cast<uint32_t>(N), bit_lo, bit_hi, passes, copies, hist);
   TC_LAUNCH_CHECK();
   k_sweep_starts<<<passes, kSortBlock, 0, s>>>(hist);
   TC_LAUNCH_CHECK();
   K* a = keys;
   K* b = tmp;
+  V* va = vals;
+  V* vb = vtmp;
   for (int p = 0; p < passes; p++) {
     const int shift = bit_lo + 8 * p;
     const int w = bit_hi - shift;
     const uint32_t dmask = w >= 8 ? 255u : (1u << w) - 1u;
-    uint32_t* ctr = ctrs + 2 * p;
-    k_sweep_scatter<K><<<tiles, kSortBlock, 0, s>>>(a, b, static_cast<uint32_t>(N), shift, dmask,
-                                                    static_cast<uint64_t>(p + 1) << kTagShift,
-                                                    hist + static_cast<size_t>(p) * 256, status.get(), ctr);
+    k_sweep_scatter<K, V><<<tiles, kSortBlock, 0, s>>>(a, b, va, vb, static_cast<uint32_t>(N), shift, dmask,
+                                                       static_cast<uint64_t>(p + 1) << kTagShift,
+                                                       hist + static_cast<size_t>(p) * 256, status.get(), ctrs + 2 * p);
     TC_LAUNCH_CHECK();
-    K* t = a;
-    a = b;
-    b = t;
+    std::swap(a, b);
+    std::swap(va, vb);
   }
-  uint32_t h_err[2 * kMaxPasses] = {};
-  TC_HIP(hipMemcpyAsync(h_err, ctrs, 2 * passes * sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+  uint32_t h_ctr[2 * kMaxPasses] = {};
+  TC_HIP(hipMemcpyAsync(h_ctr, ctrs, 2 * passes * sizeof(uint32_t), hipMemcpyDeviceToHost, s));
   TC_HIP(hipStreamSynchronize(s));
   for (int p = 0; p < passes; p++)
-    if (h_err[2 * p + 1]) fail(TC_E_DEVICE, "radix_sort: a tile's look-back did not complete");
+    if (h_ctr[2 * p + 1]) fail(TC_E_DEVICE, "radix_sort: a tile's look-back did not complete");
+  vals = va;
   return a;
+}
+
+// Keys-only form of radix_sort_pairs.
+template <typename K>
+K* radix_sort(K* keys, K* tmp, size_t N, int bit_lo, int bit_hi, hipStream_t s) {
+  NoVal* none = nullptr;
+  return radix_sort_pairs<K, NoVal>(keys, tmp, none, nullptr, N, bit_lo, bit_hi, s);
 }
 
 }  // namespace tc
