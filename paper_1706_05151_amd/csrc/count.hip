@@ -201,14 +201,16 @@ __device__ __forceinline__ void wave_sync() {
 
 // Bucketed hash set in LDS: 2^log2b buckets of 4 int32 slots. A bucket's
 // slots fill in order and a full bucket spills into the next one, so a lookup
-// reads one 16-byte bucket and stops there unless that bucket is full.
-__device__ __forceinline__ uint32_t bucket_of(int32_t x, int log2b) {
-  return (static_cast<uint32_t>(x) * 0x9E3779B1u) >> (32 - log2b);
-}
+// reads one 16-byte bucket and stops there unless that bucket is full. One
+// multiplicative hash h = x * 0x9E3779B1 gives both the home bucket (top
+// log2b bits) and the element's filter bit in the home bucket's filter word
+// (the next 5 bits).
+__device__ __forceinline__ uint32_t hash_of(int32_t x) { return static_cast<uint32_t>(x) * 0x9E3779B1u; }
+__device__ __forceinline__ uint32_t home_bucket(uint32_t h, int log2b) { return h >> (32 - log2b); }
+__device__ __forceinline__ uint32_t filter_shift(uint32_t h, int log2b) { return (h >> (27 - log2b)) & 31u; }
 
-__device__ __forceinline__ void bt_insert(int32_t* T, int log2b, int32_t x) {
+__device__ __forceinline__ void bt_insert(int32_t* T, int log2b, uint32_t b, int32_t x) {
   const uint32_t mask = (1u << log2b) - 1u;
-  uint32_t b = bucket_of(x, log2b);
   for (;;) {
 #pragma unroll
     for (int i = 0; i < 4; i++)
@@ -217,17 +219,39 @@ __device__ __forceinline__ void bt_insert(int32_t* T, int log2b, int32_t x) {
   }
 }
 
-// Slot index of x, or -1.
-__device__ __forceinline__ int bt_find(const int32_t* T, int log2b, int32_t x) {
+// Smallest of slot ^ x over a bucket's four slots: zero iff x is in it.
+__device__ __forceinline__ uint32_t bucket_miss(const int4& q, int32_t x) {
+  const uint32_t ux = static_cast<uint32_t>(x);
+  const uint32_t a = static_cast<uint32_t>(q.x) ^ ux, b = static_cast<uint32_t>(q.y) ^ ux;
+  const uint32_t c = static_cast<uint32_t>(q.z) ^ ux, d = static_cast<uint32_t>(q.w) ^ ux;
+  return min(min(a, b), min(c, d));
+}
+
+// Slot index of x in the full buckets after b, or -1 (a bucket spills only
+// when it is full, so the search stops at the first bucket with a free slot).
+__device__ __forceinline__ int bt_find_spilled(const int32_t* T, int log2b, uint32_t b, int32_t x) {
   const uint32_t mask = (1u << log2b) - 1u;
-  uint32_t b = bucket_of(x, log2b);
   for (;;) {
+    b = (b + 1u) & mask;
     const int4 q = *reinterpret_cast<const int4*>(T + 4 * b);
     const int s = q.x == x ? 0 : q.y == x ? 1 : q.z == x ? 2 : q.w == x ? 3 : -1;
     if (s >= 0) return static_cast<int>(4 * b) + s;
     if (q.w == kEmpty) return -1;
-    b = (b + 1u) & mask;
   }
+}
+
+// Slot index of x with home bucket b, or -1 (kAnySlot if only membership is
+// asked for). The home bucket is read with one 16-byte LDS read.
+constexpr int kAnySlot = 0;
+template <bool kSlot>
+__device__ __forceinline__ int bt_find(const int32_t* T, int log2b, uint32_t b, int32_t x) {
+  const int4 q = *reinterpret_cast<const int4*>(T + 4 * b);
+  if (bucket_miss(q, x) == 0) {
+    if (!kSlot) return kAnySlot;
+    return static_cast<int>(4 * b) + (q.x == x ? 0 : q.y == x ? 1 : q.z == x ? 2 : 3);
+  }
+  if (q.w == kEmpty) return -1;
+  return bt_find_spilled(T, log2b, b, x);
 }
 
 __device__ __forceinline__ int log2_buckets(int64_t len, int load = 1) {
@@ -236,21 +260,17 @@ __device__ __forceinline__ int log2_buckets(int64_t len, int load = 1) {
   return l;
 }
 
-// A staged list: the bucket table T (4 << log2b slots), a bit filter F with
-// 8 bits per slot (16 per entry at two entries per bucket) tested before the
-// table, and per-slot tallies C (per-node mode). A probe reads one 4-byte
-// filter word; only filter hits (true hits and ~6% false positives) read the
-// 16-byte bucket.
+// A staged list: the bucket table T (4 << log2b slots), a bit filter F of one
+// 32-bit word per bucket (8 bits per slot, 16 per entry at two entries per
+// bucket) tested before the table, and per-slot tallies C (per-node mode). A
+// probe reads one 4-byte filter word; only filter hits (true hits and ~6%
+// false positives) read the 16-byte bucket.
 struct Table {
   int32_t* T;
   uint32_t* F;
   uint32_t* C;
   int log2b;
 };
-
-__device__ __forceinline__ uint32_t filter_bit(int32_t x, int log2b) {
-  return (static_cast<uint32_t>(x) * 0x85EBCA77u) >> (32 - (log2b + 5));
-}
 
 // Words of a table region of 2^log2b buckets: T, then F, then C (per-node).
 __host__ __device__ __forceinline__ int table_words(int log2b, bool per_node) {
@@ -276,15 +296,19 @@ __device__ __forceinline__ void tb_clear(const Table& t, int i0, int step) {
 }
 
 __device__ __forceinline__ void tb_insert(const Table& t, int32_t x) {
-  bt_insert(t.T, t.log2b, x);
-  const uint32_t f = filter_bit(x, t.log2b);
-  atomicOr(&t.F[f >> 5], 1u << (f & 31u));
+  const uint32_t h = hash_of(x);
+  const uint32_t b = home_bucket(h, t.log2b);
+  bt_insert(t.T, t.log2b, b, x);
+  atomicOr(&t.F[b], 1u << filter_shift(h, t.log2b));
 }
 
+// Slot of x or -1 (MODE == kCountTotal: kAnySlot for found).
+template <int MODE>
 __device__ __forceinline__ int tb_find(const Table& t, int32_t x) {
-  const uint32_t f = filter_bit(x, t.log2b);
-  if (!((t.F[f >> 5] >> (f & 31u)) & 1u)) return -1;
-  return bt_find(t.T, t.log2b, x);
+  const uint32_t h = hash_of(x);
+  const uint32_t b = home_bucket(h, t.log2b);
+  if (!((t.F[b] >> filter_shift(h, t.log2b)) & 1u)) return -1;
+  return bt_find<MODE != kCountTotal>(t.T, t.log2b, b, x);
 }
 
 struct KernelArgs {
@@ -345,7 +369,7 @@ struct BatchLds {
 template <int MODE>
 __device__ __forceinline__ uint32_t probe_one(const KernelArgs& a, int32_t u, int32_t x, const Table& tab,
                                               uint32_t* hit_rec, uint32_t rec_begin) {
-  const int s = tb_find(tab, x);
+  const int s = tb_find<MODE>(tab, x);
   if (s < 0) return 0u;
   if (MODE == kCountPerNode) {
     atomicAdd(&tab.C[s], 1u);

@@ -10,10 +10,9 @@
 
 namespace tc {
 
-// Device arrays owned by a graph, taken from the stream-ordered pool on the
-// building stream and returned on the null stream, which orders the free
-// after the work of every blocking stream (graphs are freed after a device
-// synchronisation).
+// Device arrays owned by a graph, taken from the library's block cache on the
+// building stream. They are freed only after a device synchronisation, so the
+// free is recorded on the null stream.
 template <typename T>
 struct Owned {
   T* p = nullptr;
