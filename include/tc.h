@@ -157,7 +157,10 @@ tc_status tc_graph_oriented(tc_graph* g, void* stream, int64_t* off_dev, int32_t
  *                          fewer than 16 per edge, else pivot-staged),
  *                          1 plain merge, 2 pivot-staged
  *   TC_OPT_HUB_DHAT      : lists longer than this use the block-per-pivot path
- *   TC_OPT_ITEM_WORK     : target probes per work item of the partitioner
+ *                          (default 256, the largest per-wave table)
+ *   TC_OPT_ITEM_WORK     : target probes per work item of the partitioner;
+ *                          0 (default) derives it from the graph: about 8
+ *                          items per resident wave, within [4096, 65536]
  *   TC_OPT_BLOCKS_PER_CU : blocks per compute unit of the persistent launch
  *   TC_OPT_HUB_BUCKET_LOAD : target list entries per 4-slot LDS hash bucket
  *                          of the block path (1 or 2)

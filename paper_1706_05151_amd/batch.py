@@ -23,8 +23,8 @@ AUTOTUNE_FILE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "autotu
 
 # candidate (hub_dhat, item_work, blocks_per_cu, hub_bucket_load)
 DEFAULT_CANDIDATES = [
-    (128, 16384, 4, 2), (64, 16384, 4, 2), (256, 16384, 4, 2), (32, 4096, 4, 2),
-    (128, 4096, 4, 2), (128, 65536, 4, 2), (128, 16384, 3, 1), (256, 65536, 4, 2),
+    (256, 0, 4, 2), (128, 0, 4, 2), (256, 16384, 4, 2), (256, 65536, 4, 2),
+    (128, 16384, 4, 2), (64, 4096, 4, 2), (32, 4096, 4, 2), (256, 0, 3, 1),
 ]
 _KEYS = (tc.OPT_HUB_DHAT, tc.OPT_ITEM_WORK, tc.OPT_BLOCKS_PER_CU, tc.OPT_HUB_BUCKET_LOAD)
 

@@ -15,7 +15,7 @@ namespace tc {
 namespace {
 
 thread_local std::string g_last_error;
-std::atomic<int64_t> g_opt_kernel{0}, g_opt_hub{128}, g_opt_iw{16384}, g_opt_bpc{4}, g_opt_load{2}, g_opt_order{0};
+std::atomic<int64_t> g_opt_kernel{0}, g_opt_hub{256}, g_opt_iw{0}, g_opt_bpc{4}, g_opt_load{2}, g_opt_order{0};
 
 template <typename F>
 tc_status guarded(F&& f) {

@@ -803,8 +803,18 @@ void ensure_plan(Csr& c, hipStream_t s, const Options& o) {
   il.release();
   il2.release();
 
-  // classify pivots and count items
-  const int64_t iw_wave = o.item_work > 64 ? o.item_work : 64;
+  // classify pivots and count items; item_work 0: about 8 items per resident
+  // wave, between 4096 and 65536 probe-equivalents
+  int64_t total_cost = 0;
+  TC_HIP(hipMemcpyAsync(&total_cost, fin.get() + mi, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+  TC_HIP(hipStreamSynchronize(s));
+  int64_t iw_wave = o.item_work;
+  if (iw_wave <= 0) {
+    const int64_t waves = static_cast<int64_t>(device_cus()) * 4 * kPivotWaves;
+    iw_wave = total_cost / (8 * waves);
+    iw_wave = iw_wave < 4096 ? 4096 : iw_wave > 65536 ? 65536 : iw_wave;
+  }
+  if (iw_wave < 64) iw_wave = 64;
   const int64_t iw_hub = 8 * iw_wave;
   const int64_t cap = hub_slice_cap(kCountPerNode);
   DevBuf<int64_t> nh(static_cast<size_t>(n) + 1, s), ns(static_cast<size_t>(n) + 1, s);

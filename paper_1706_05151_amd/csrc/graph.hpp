@@ -125,8 +125,8 @@ namespace tc {
 
 struct Options {
   int64_t kernel = 0;        // 0 auto, 1 plain, 2 pivot
-  int64_t hub_dhat = 128;    // pivots with |N_u| > hub_dhat use the block path
-  int64_t item_work = 4096;  // target probes per work item
+  int64_t hub_dhat = 256;    // pivots with |N_u| > hub_dhat use the block path
+  int64_t item_work = 0;     // target probes per work item (0: from the graph's total)
   int64_t blocks_per_cu = 8; // persistent launch occupancy
   int64_t hub_bucket_load = 2;  // entries per 4-slot bucket of a hub table (1 or 2)
   int64_t order = 0;            // total order of the orientation (0 degree, 1 id, 2 random, 3 degree descending)
