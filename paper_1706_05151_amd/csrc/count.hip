@@ -265,11 +265,17 @@ __device__ __forceinline__ int log2_buckets(int64_t len, int load = 1) {
 // bucket) tested before the table, and per-slot tallies C (per-node mode). A
 // probe reads one 4-byte filter word; only filter hits (true hits and ~6%
 // false positives) read the 16-byte bucket.
+//
+// Bitmap form (counts and listing): when the staged entries lie in a short
+// range [lo, lo + span), the region holds one bit per value of the range
+// instead; a probe is a range check and one 4-byte LDS read, exact.
 struct Table {
   int32_t* T;
   uint32_t* F;
   uint32_t* C;
   int log2b;
+  int32_t lo;     // bitmap form: smallest staged entry
+  uint32_t span;  // bitmap form: entries lie in [lo, lo + span); 0 for the hash form
 };
 
 // Words of a table region of 2^log2b buckets: T, then F, then C (per-node).
@@ -283,10 +289,35 @@ __device__ __forceinline__ Table table_at(int32_t* base, int log2b, bool per_nod
   t.T = base;
   t.F = reinterpret_cast<uint32_t*>(base + (4 << log2b));
   t.C = per_node ? reinterpret_cast<uint32_t*>(base + (4 << log2b) + (1 << log2b)) : nullptr;
+  t.lo = 0;
+  t.span = 0;
   return t;
 }
 
+// The table for the sorted entries list[0..len) in a region of `words`
+// 32-bit words: the bitmap form if the mode needs no slot tallies and the
+// entries' range fits the region, else the hash form with 2^log2b buckets.
+template <int MODE>
+__device__ __forceinline__ Table table_for(int32_t* base, const int32_t* list, uint32_t len, int log2b, uint32_t words) {
+  if (MODE != kCountPerNode && len > 0) {
+    const int32_t lo = __builtin_amdgcn_readfirstlane(list[0]);
+    const uint32_t span = static_cast<uint32_t>(__builtin_amdgcn_readfirstlane(list[len - 1]) - lo) + 1u;
+    if (span <= 32u * words) {
+      Table t = table_at(base, log2b, false);
+      t.lo = lo;
+      t.span = span;
+      return t;
+    }
+  }
+  return table_at(base, log2b, MODE == kCountPerNode);
+}
+
 __device__ __forceinline__ void tb_clear(const Table& t, int i0, int step) {
+  if (t.span) {
+    const int words = static_cast<int>((t.span + 31u) >> 5);
+    for (int w = i0; w < words; w += step) t.T[w] = 0;
+    return;
+  }
   const int S = 4 << t.log2b;
   for (int s = i0; s < S; s += step) {
     t.T[s] = kEmpty;
@@ -296,6 +327,11 @@ __device__ __forceinline__ void tb_clear(const Table& t, int i0, int step) {
 }
 
 __device__ __forceinline__ void tb_insert(const Table& t, int32_t x) {
+  if (t.span) {
+    const uint32_t d = static_cast<uint32_t>(x - t.lo);
+    atomicOr(reinterpret_cast<uint32_t*>(t.T) + (d >> 5), 1u << (d & 31u));
+    return;
+  }
   const uint32_t h = hash_of(x);
   const uint32_t b = home_bucket(h, t.log2b);
   bt_insert(t.T, t.log2b, b, x);
@@ -305,6 +341,11 @@ __device__ __forceinline__ void tb_insert(const Table& t, int32_t x) {
 // Slot of x or -1 (MODE == kCountTotal: kAnySlot for found).
 template <int MODE>
 __device__ __forceinline__ int tb_find(const Table& t, int32_t x) {
+  if (MODE != kCountPerNode && t.span) {
+    const uint32_t d = static_cast<uint32_t>(x - t.lo);
+    if (d >= t.span) return -1;
+    return (reinterpret_cast<const uint32_t*>(t.T)[d >> 5] >> (d & 31u)) & 1u ? kAnySlot : -1;
+  }
   const uint32_t h = hash_of(x);
   const uint32_t b = home_bucket(h, t.log2b);
   if (!((t.F[b] >> filter_shift(h, t.log2b)) & 1u)) return -1;
@@ -515,7 +556,7 @@ __device__ __forceinline__ unsigned long long wave_pivot(const KernelArgs& a, in
   const uint32_t nlen = static_cast<uint32_t>(a.off[u + 1] - nb);
   int log2b = log2_buckets(nlen);
   if (log2b > kWaveLog2b) log2b = kWaveLog2b;  // >= 2 slots per entry
-  const Table tab = table_at(region, log2b, MODE == kCountPerNode);
+  const Table tab = table_for<MODE>(region, a.adj + nb, nlen, log2b, table_words(kWaveLog2b, MODE == kCountPerNode));
   tb_clear(tab, lane, kWave);
   wave_sync();
   for (uint32_t k = lane; k < nlen; k += kWave) tb_insert(tab, a.adj[nb + k]);
@@ -541,15 +582,15 @@ __device__ __forceinline__ unsigned long long wave_pivot(const KernelArgs& a, in
 // item's triangle count (valid in thread 0).
 template <int MODE>
 __device__ __forceinline__ unsigned long long hub_item(const KernelArgs& a, const PivotItem& item, int32_t* region,
-                                                       BatchLds<kPivotBlock>& bl, uint32_t* scan_tmp,
-                                                       unsigned long long* red) {
+                                                       uint32_t region_words, BatchLds<kPivotBlock>& bl,
+                                                       uint32_t* scan_tmp, unsigned long long* red) {
   const int tid = threadIdx.x, w = tid / kWave, lane = lane_id();
   constexpr bool per_node = MODE == kCountPerNode;
   const int log2b = log2_buckets(item.nlen, a.bucket_load);
-  const Table tab = table_at(region, log2b, per_node);
+  const int64_t nb = a.off[item.u] + item.nbeg_rel;
+  const Table tab = table_for<MODE>(region, a.adj + nb, item.nlen, log2b, region_words);
   tb_clear(tab, tid, kPivotBlock);
   __syncthreads();
-  const int64_t nb = a.off[item.u] + item.nbeg_rel;
   for (uint32_t k = tid; k < item.nlen; k += kPivotBlock) tb_insert(tab, a.adj[nb + k]);
   __syncthreads();
   uint32_t cnt = 0;
@@ -645,6 +686,10 @@ __global__ __launch_bounds__(kPivotBlock, TC_PIVOT_MIN_WAVES) void k_pivot(
   const int tid = threadIdx.x, w = tid / kWave, lane = lane_id();
   constexpr bool per_node = MODE == kCountPerNode;
   unsigned long long acc = 0;
+  // the dynamic region holds the larger of one hub table and the wave tables
+  const uint32_t hub_words = static_cast<uint32_t>(table_words(hub_log2b, per_node));
+  const uint32_t wave_words = static_cast<uint32_t>(kPivotWaves * table_words(kWaveLog2b, per_node));
+  const uint32_t region_words = hub_words > wave_words ? hub_words : wave_words;
 
   // ---- phase 1: hub items, one block each
   {
@@ -656,9 +701,10 @@ __global__ __launch_bounds__(kPivotBlock, TC_PIVOT_MIN_WAVES) void k_pivot(
       if (MULTI) {
         const int32_t g = job_of(jobs.pre, jobs.k, it);
         const GraphDesc d = jobs.descs[g];
-        acc += hub_item<MODE>(job_args(a, d, g), d.hub[it - jobs.pre[g]], smem, rl.block, scan_tmp, red);
+        acc += hub_item<MODE>(job_args(a, d, g), d.hub[it - jobs.pre[g]], smem, region_words, rl.block, scan_tmp,
+                              red);
       } else {
-        acc += hub_item<MODE>(a, hub_items[it], smem, rl.block, scan_tmp, red);
+        acc += hub_item<MODE>(a, hub_items[it], smem, region_words, rl.block, scan_tmp, red);
       }
     }
   }
