@@ -546,17 +546,28 @@ __device__ __forceinline__ uint32_t probe_batch_wave(const KernelArgs& a, int32_
 }
 
 constexpr int kWaveLog2b = 7;  // per-wave tables: 128 buckets (kWaveSlots slots), lists up to 256 entries
+constexpr int kRegionWords = 7680;  // least dynamic LDS of a pivot block (32-bit words; 30 KiB, 4 blocks per CU)
+
+// Dynamic LDS words of a pivot block: one hub table of 2^hub_log2b buckets
+// in phase 1, kPivotWaves equal wave regions in phase 2.
+__host__ __device__ __forceinline__ uint32_t pivot_region_words(int hub_log2b, bool per_node) {
+  const uint32_t hub = static_cast<uint32_t>(table_words(hub_log2b, per_node));
+  const uint32_t wave = static_cast<uint32_t>(kPivotWaves * table_words(kWaveLog2b, per_node));
+  uint32_t r = hub > wave ? hub : wave;
+  if (r < static_cast<uint32_t>(kRegionWords)) r = kRegionWords;
+  return (r + kPivotWaves * 4 - 1) / (kPivotWaves * 4) * (kPivotWaves * 4);  // whole 16-byte rows per wave
+}
 
 // Per-wave staging of one small pivot (|N_u| <= 256) into the wave's region.
 template <int MODE>
 __device__ __forceinline__ unsigned long long wave_pivot(const KernelArgs& a, int32_t u, uint32_t ibeg, uint32_t iend,
-                                                         int32_t* region, BatchLds<kWave>& B) {
+                                                         int32_t* region, uint32_t region_words, BatchLds<kWave>& B) {
   const int lane = lane_id();
   const int64_t nb = a.off[u];
   const uint32_t nlen = static_cast<uint32_t>(a.off[u + 1] - nb);
   int log2b = log2_buckets(nlen);
   if (log2b > kWaveLog2b) log2b = kWaveLog2b;  // >= 2 slots per entry
-  const Table tab = table_for<MODE>(region, a.adj + nb, nlen, log2b, table_words(kWaveLog2b, MODE == kCountPerNode));
+  const Table tab = table_for<MODE>(region, a.adj + nb, nlen, log2b, region_words);
   tb_clear(tab, lane, kWave);
   wave_sync();
   for (uint32_t k = lane; k < nlen; k += kWave) tb_insert(tab, a.adj[nb + k]);
@@ -686,10 +697,7 @@ __global__ __launch_bounds__(kPivotBlock, TC_PIVOT_MIN_WAVES) void k_pivot(
   const int tid = threadIdx.x, w = tid / kWave, lane = lane_id();
   constexpr bool per_node = MODE == kCountPerNode;
   unsigned long long acc = 0;
-  // the dynamic region holds the larger of one hub table and the wave tables
-  const uint32_t hub_words = static_cast<uint32_t>(table_words(hub_log2b, per_node));
-  const uint32_t wave_words = static_cast<uint32_t>(kPivotWaves * table_words(kWaveLog2b, per_node));
-  const uint32_t region_words = hub_words > wave_words ? hub_words : wave_words;
+  const uint32_t region_words = pivot_region_words(hub_log2b, per_node);
 
   // ---- phase 1: hub items, one block each
   {
@@ -711,7 +719,8 @@ __global__ __launch_bounds__(kPivotBlock, TC_PIVOT_MIN_WAVES) void k_pivot(
 
   // ---- phase 2: split items and grouped small pivots, one wave each
   {
-    int32_t* region = smem + w * table_words(kWaveLog2b, per_node);
+    const uint32_t wave_words = region_words / kPivotWaves;
+    int32_t* region = smem + w * wave_words;
     for (;;) {
       unsigned long long it = 0;
       if (lane == 0) it = n_split ? atomicAdd(&queues[1], 1ull) : 0ull;
@@ -722,10 +731,10 @@ __global__ __launch_bounds__(kPivotBlock, TC_PIVOT_MIN_WAVES) void k_pivot(
         const int32_t g = job_of(pre, jobs.k, it);
         const GraphDesc d = jobs.descs[g];
         const PivotItem item = d.split[it - pre[g]];
-        acc += wave_pivot<MODE>(job_args(a, d, g), item.u, item.ibeg, item.iend, region, rl.wave[w]);
+        acc += wave_pivot<MODE>(job_args(a, d, g), item.u, item.ibeg, item.iend, region, wave_words, rl.wave[w]);
       } else {
         const PivotItem item = split_items[it];
-        acc += wave_pivot<MODE>(a, item.u, item.ibeg, item.iend, region, rl.wave[w]);
+        acc += wave_pivot<MODE>(a, item.u, item.ibeg, item.iend, region, wave_words, rl.wave[w]);
       }
     }
     for (;;) {
@@ -750,7 +759,7 @@ __global__ __launch_bounds__(kPivotBlock, TC_PIVOT_MIN_WAVES) void k_pivot(
       for (uint64_t x = g0; x < g1; x++) {
         const int32_t u = glist[x];
         acc += wave_pivot<MODE>(ga, u, static_cast<uint32_t>(ga.in_off[u]), static_cast<uint32_t>(ga.in_off[u + 1]),
-                                region, rl.wave[w]);
+                                region, wave_words, rl.wave[w]);
       }
     }
   }
@@ -947,9 +956,7 @@ void count_pivot(Csr& c, const CountArgs& ca, hipStream_t s, const Options& o, b
     const int64_t maxlen = c.dhat_max < cap ? c.dhat_max : cap;
     while ((1ll << hub_log2b) * o.hub_bucket_load < maxlen) hub_log2b++;
   }
-  const size_t hub_lds = static_cast<size_t>(table_words(hub_log2b, per_node)) * sizeof(int32_t);
-  const size_t wave_lds = static_cast<size_t>(kPivotWaves) * table_words(kWaveLog2b, per_node) * sizeof(int32_t);
-  const size_t lds = hub_lds > wave_lds ? hub_lds : wave_lds;
+  const size_t lds = static_cast<size_t>(pivot_region_words(hub_log2b, per_node)) * sizeof(int32_t);
   const uint64_t wave_units = P.n_split_items() + (P.n_grouped + kGroupChunk - 1) / kGroupChunk;
   const uint64_t blocks_needed = P.n_hub_items + (wave_units + kPivotWaves - 1) / kPivotWaves;
   if (blocks_needed == 0) return;
@@ -1006,9 +1013,7 @@ void count_multi(const std::vector<Csr*>& gs, const std::vector<unsigned long lo
   const int64_t cap = hub_slice_cap(kCountPerNode);
   const int64_t maxlen = dmax < cap ? dmax : cap;
   while ((1ll << hub_log2b) * o.hub_bucket_load < maxlen) hub_log2b++;
-  const size_t hub_lds = static_cast<size_t>(table_words(hub_log2b, per_node)) * sizeof(int32_t);
-  const size_t wave_lds = static_cast<size_t>(kPivotWaves) * table_words(kWaveLog2b, per_node) * sizeof(int32_t);
-  const size_t lds = hub_lds > wave_lds ? hub_lds : wave_lds;
+  const size_t lds = static_cast<size_t>(pivot_region_words(hub_log2b, per_node)) * sizeof(int32_t);
   const unsigned cus = static_cast<unsigned>(device_cus());
   const unsigned bpc = static_cast<unsigned>(o.blocks_per_cu > 0 ? o.blocks_per_cu : 4);
   const uint64_t blocks_needed = n_hub + (n_split + n_chunks + kPivotWaves - 1) / kPivotWaves;
