@@ -342,9 +342,11 @@ __device__ __forceinline__ void tb_insert(const Table& t, int32_t x) {
 template <int MODE>
 __device__ __forceinline__ int tb_find(const Table& t, int32_t x) {
   if (MODE != kCountPerNode && t.span) {
+    // branch-free: out-of-range values read word 0 and are masked off
     const uint32_t d = static_cast<uint32_t>(x - t.lo);
-    if (d >= t.span) return -1;
-    return (reinterpret_cast<const uint32_t*>(t.T)[d >> 5] >> (d & 31u)) & 1u ? kAnySlot : -1;
+    const bool in = d < t.span;
+    const uint32_t w = reinterpret_cast<const uint32_t*>(t.T)[in ? d >> 5 : 0u];
+    return (in && ((w >> (d & 31u)) & 1u)) ? kAnySlot : -1;
   }
   const uint32_t h = hash_of(x);
   const uint32_t b = home_bucket(h, t.log2b);
@@ -434,7 +436,19 @@ __device__ __forceinline__ uint32_t probe_long(const KernelArgs& a, int32_t u, c
     const uint32_t len = __builtin_amdgcn_readfirstlane(B.len[j]);
     if (len < kLongMin) continue;
     const uint32_t beg = __builtin_amdgcn_readfirstlane(B.beg[j]);
-    for (uint32_t k0 = 0; k0 < len; k0 += kSeg) {
+    uint32_t k0 = 0;
+    // full windows: unguarded loads from a wave-uniform base
+    for (; k0 + kSeg <= len; k0 += kSeg) {
+      const int32_t* wbase = a.adj + beg + k0;
+      int32_t x[kPerLane];
+#pragma unroll
+      for (int i = 0; i < kPerLane; i++) x[i] = wbase[lane + kWave * i];
+      uint32_t h = 0;
+#pragma unroll
+      for (int i = 0; i < kPerLane; i++) h += probe_one<MODE>(a, u, x[i], tab, &hits[j], beg);
+      cnt += h;
+    }
+    if (k0 < len) {
       const uint32_t rem = len - k0;
       int32_t x[kPerLane];
 #pragma unroll

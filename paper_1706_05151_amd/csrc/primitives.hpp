@@ -202,11 +202,12 @@ struct RadixItems<u128> {
 constexpr int kSortBlock = 256;
 constexpr int kSortWaves = kSortBlock / kWave;
 
-// Mask of the lanes whose 9-bit value equals this lane's (all 64 lanes active).
-__device__ __forceinline__ uint64_t match_any9(uint32_t d) {
+// Mask of the lanes whose BITS-bit value equals this lane's (all 64 lanes active).
+template <int BITS>
+__device__ __forceinline__ uint64_t match_any(uint32_t d) {
   uint64_t peers = ~0ull;
 #pragma unroll
-  for (int b = 0; b < 9; b++) {
+  for (int b = 0; b < BITS; b++) {
     const bool bit = (d >> b) & 1u;
     const uint64_t bb = __ballot(bit);
     peers &= bit ? bb : ~bb;
@@ -327,19 +328,11 @@ __global__ __launch_bounds__(kSortBlock) void k_sweep_scatter(const K* __restric
   K key[ITEMS];
   uint32_t rk[ITEMS];
   uint32_t dg[ITEMS];
-#pragma unroll
-  for (int i = 0; i < ITEMS; i++) {
-    const size_t idx = base + static_cast<size_t>(w) * CHUNK + static_cast<size_t>(i) * kWave + lane;
-    key[i] = K{};
-    if (idx < N) key[i] = in[idx];
-  }
   uint32_t* cnt = wc[w];
-#pragma unroll
-  for (int i = 0; i < ITEMS; i++) {
-    const size_t idx = base + static_cast<size_t>(w) * CHUNK + static_cast<size_t>(i) * kWave + lane;
-    const bool valid = idx < N;
-    const uint32_t d = valid ? (RadixKey<K>::digit(key[i], shift) & dmask) : 256u;
-    const uint64_t peers = match_any9(d);
+  // Rank of each key among the equal digits of its wave chunk so far; lanes
+  // with equal digits are matched by ballots over the digit bits (plus a
+  // validity bit in a partial tile).
+  auto rank_item = [&](int i, uint32_t d, uint64_t peers, bool valid) {
     const uint32_t lr = static_cast<uint32_t>(__popcll(peers & lanemask_lt()));
     const int leader = __ffsll(static_cast<long long>(peers)) - 1;
     uint32_t old = 0;
@@ -351,6 +344,30 @@ __global__ __launch_bounds__(kSortBlock) void k_sweep_scatter(const K* __restric
     dg[i] = d;
     rk[i] = old + lr;
     __builtin_amdgcn_wave_barrier();
+  };
+  const K* chunk = in + base + static_cast<size_t>(w) * CHUNK;
+  if (base + TILE <= N) {  // full tile (wave-uniform): no bounds checks, 8 ballots
+#pragma unroll
+    for (int i = 0; i < ITEMS; i++) key[i] = chunk[i * kWave + lane];
+#pragma unroll
+    for (int i = 0; i < ITEMS; i++) {
+      const uint32_t d = RadixKey<K>::digit(key[i], shift) & dmask;
+      rank_item(i, d, match_any<8>(d), true);
+    }
+  } else {
+#pragma unroll
+    for (int i = 0; i < ITEMS; i++) {
+      const size_t idx = base + static_cast<size_t>(w) * CHUNK + static_cast<size_t>(i) * kWave + lane;
+      key[i] = K{};
+      if (idx < N) key[i] = chunk[i * kWave + lane];
+    }
+#pragma unroll
+    for (int i = 0; i < ITEMS; i++) {
+      const size_t idx = base + static_cast<size_t>(w) * CHUNK + static_cast<size_t>(i) * kWave + lane;
+      const bool valid = idx < N;
+      const uint32_t d = valid ? (RadixKey<K>::digit(key[i], shift) & dmask) : 256u;
+      rank_item(i, d, match_any<9>(d), valid);
+    }
   }
   __syncthreads();
   // thread tid owns digit tid: per-wave offsets inside the digit, and the tile's count
