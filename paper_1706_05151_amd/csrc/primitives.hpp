@@ -202,6 +202,15 @@ struct RadixItems<u128> {
 constexpr int kSortBlock = 256;
 constexpr int kSortWaves = kSortBlock / kWave;
 
+// Scatter passes run 512-thread blocks over the same tiles (keys per thread
+// halved), which doubles the resident waves at the same LDS per tile.
+constexpr int kScatterBlock = 512;
+constexpr int kScatterWaves = kScatterBlock / kWave;
+template <typename K>
+struct ScatterItems {
+  static constexpr int value = RadixItems<K>::value * kSortBlock / kScatterBlock;
+};
+
 // Mask of the lanes whose BITS-bit value equals this lane's (all 64 lanes active).
 template <int BITS>
 __device__ __forceinline__ uint64_t match_any(uint32_t d) {
@@ -300,27 +309,32 @@ struct NoVal {};
 // is set if a look-back gave up. With a value type V, each key's value moves
 // with it (staged through the same LDS tile after the keys are written).
 template <typename K, typename V>
-__global__ __launch_bounds__(kSortBlock) void k_sweep_scatter(const K* __restrict__ in, K* __restrict__ out,
+__global__ __launch_bounds__(kScatterBlock) void k_sweep_scatter(const K* __restrict__ in, K* __restrict__ out,
                                                                const V* __restrict__ vin, V* __restrict__ vout,
                                                                uint32_t N, int shift, uint32_t dmask, uint64_t tag,
                                                                const uint32_t* __restrict__ starts,
                                                                uint64_t* __restrict__ status, uint32_t* __restrict__ ctr) {
   constexpr bool kHasVal = !std::is_same<V, NoVal>::value;
-  constexpr int ITEMS = RadixItems<K>::value;
-  constexpr int TILE = kSortBlock * ITEMS;
+  constexpr int ITEMS = ScatterItems<K>::value;
+  constexpr int TILE = kScatterBlock * ITEMS;
   constexpr int CHUNK = kWave * ITEMS;
   static_assert(!kHasVal || sizeof(V) <= sizeof(K), "values are staged in the key tile");
   __shared__ K tile[TILE];
-  __shared__ uint8_t pdig[kHasVal ? TILE : 1];
-  __shared__ uint32_t wc[kSortWaves][256];
+  // per-wave digit counts while ranking; afterwards (values only) the digit of each staged position
+  __shared__ union {
+    uint32_t wc[kScatterWaves][256];
+    uint8_t pdig[kHasVal ? TILE : 1];
+  } u;
+  auto& wc = u.wc;
+  auto& pdig = u.pdig;
   __shared__ uint32_t dstart[256];
   __shared__ uint32_t gbase[256];
-  __shared__ uint32_t scan_tmp[kSortWaves];
+  __shared__ uint32_t scan_tmp[kScatterWaves];
   __shared__ uint32_t s_tile;
   const int tid = threadIdx.x, w = tid / kWave, lane = lane_id();
+  const bool owner = tid < 256;  // thread tid owns digit tid
   if (tid == 0) s_tile = atomicAdd(&ctr[0], 1u);
-#pragma unroll
-  for (int x = 0; x < kSortWaves; x++) wc[x][tid] = 0;
+  for (int i = tid; i < kScatterWaves * 256; i += kScatterBlock) (&wc[0][0])[i] = 0;
   __syncthreads();
   const uint32_t t = s_tile;
   const size_t base = static_cast<size_t>(t) * TILE;
@@ -370,52 +384,60 @@ __global__ __launch_bounds__(kSortBlock) void k_sweep_scatter(const K* __restric
     }
   }
   __syncthreads();
-  // thread tid owns digit tid: per-wave offsets inside the digit, and the tile's count
+  // digit owners: per-wave offsets inside the digit, and the tile's count
   uint32_t tot = 0;
-#pragma unroll
-  for (int x = 0; x < kSortWaves; x++) {
-    const uint32_t c = wc[x][tid];
-    wc[x][tid] = tot;
-    tot += c;
-  }
-  uint64_t* mine = status + static_cast<size_t>(t) * 256 + tid;
   uint64_t excl = 0;
-  if (t == 0) {
-    status_store(mine, kKindInc | tag | tot);
-  } else {
-    status_store(mine, kKindAgg | tag | tot);
-    uint32_t j = t - 1;
-    uint32_t polls = 0;
-    for (;;) {
-      const uint64_t v = status_load(status + static_cast<size_t>(j) * 256 + tid);
-      const uint64_t kind = v & kKindMask;
-      if (kind == 0 || (v & ~kKindMask & ~kValMask) != tag) {
-        if (++polls > kSpinLimit) {
-          atomicOr(&ctr[1], 1u);
-          break;
-        }
-        __builtin_amdgcn_s_sleep(1);
-        continue;
-      }
-      excl += v & kValMask;
-      if (kind == kKindInc || j == 0) break;
-      --j;
+  if (owner) {
+#pragma unroll
+    for (int x = 0; x < kScatterWaves; x++) {
+      const uint32_t c = wc[x][tid];
+      wc[x][tid] = tot;
+      tot += c;
     }
-    status_store(mine, kKindInc | tag | (excl + tot));
+    uint64_t* mine = status + static_cast<size_t>(t) * 256 + tid;
+    if (t == 0) {
+      status_store(mine, kKindInc | tag | tot);
+    } else {
+      status_store(mine, kKindAgg | tag | tot);
+      uint32_t j = t - 1;
+      uint32_t polls = 0;
+      for (;;) {
+        const uint64_t v = status_load(status + static_cast<size_t>(j) * 256 + tid);
+        const uint64_t kind = v & kKindMask;
+        if (kind == 0 || (v & ~kKindMask & ~kValMask) != tag) {
+          if (++polls > kSpinLimit) {
+            atomicOr(&ctr[1], 1u);
+            break;
+          }
+          __builtin_amdgcn_s_sleep(1);
+          continue;
+        }
+        excl += v & kValMask;
+        if (kind == kKindInc || j == 0) break;
+        --j;
+      }
+      status_store(mine, kKindInc | tag | (excl + tot));
+    }
   }
   uint32_t all;
-  const uint32_t ds = block_excl_scan<uint32_t, kSortBlock>(tot, scan_tmp, all);
-  dstart[tid] = ds;
-  gbase[tid] = starts[tid] + static_cast<uint32_t>(excl);
+  const uint32_t ds = block_excl_scan<uint32_t, kScatterBlock>(tot, scan_tmp, all);
+  if (owner) {
+    dstart[tid] = ds;
+    gbase[tid] = starts[tid] + static_cast<uint32_t>(excl);
+  }
   __syncthreads();
 #pragma unroll
-  for (int i = 0; i < ITEMS; i++)
-    if (dg[i] < 256u) tile[dstart[dg[i]] + wc[w][dg[i]] + rk[i]] = key[i];
+  for (int i = 0; i < ITEMS; i++) {
+    if (dg[i] < 256u) {
+      rk[i] += dstart[dg[i]] + wc[w][dg[i]];  // the key's position in the staged tile
+      tile[rk[i]] = key[i];
+    }
+  }
   __syncthreads();
   const uint32_t count = static_cast<uint32_t>(N - base < static_cast<size_t>(TILE) ? N - base : TILE);
 #pragma unroll
   for (int i = 0; i < ITEMS; i++) {
-    const uint32_t j = static_cast<uint32_t>(i * kSortBlock + tid);
+    const uint32_t j = static_cast<uint32_t>(i * kScatterBlock + tid);
     if (j < count) {
       const K k = tile[j];
       const uint32_t d = RadixKey<K>::digit(k, shift) & dmask;
@@ -429,12 +451,12 @@ __global__ __launch_bounds__(kSortBlock) void k_sweep_scatter(const K* __restric
 #pragma unroll
     for (int i = 0; i < ITEMS; i++) {
       const size_t idx = base + static_cast<size_t>(w) * CHUNK + static_cast<size_t>(i) * kWave + lane;
-      if (dg[i] < 256u) vt[dstart[dg[i]] + wc[w][dg[i]] + rk[i]] = vin[idx];
+      if (dg[i] < 256u) vt[rk[i]] = vin[idx];
     }
     __syncthreads();
 #pragma unroll
     for (int i = 0; i < ITEMS; i++) {
-      const uint32_t j = static_cast<uint32_t>(i * kSortBlock + tid);
+      const uint32_t j = static_cast<uint32_t>(i * kScatterBlock + tid);
       if (j < count) {
         const uint32_t d = pdig[j];
         vout[gbase[d] + (j - dstart[d])] = vt[j];
@@ -459,7 +481,7 @@ template <typename K, typename V>
 K* radix_sort_pairs(K* keys, K* tmp, V*& vals, V* vtmp, size_t N, int bit_lo, int bit_hi, hipStream_t s) {
   if (N <= 1 || bit_hi <= bit_lo) return keys;
   if (N >= (1ull << 32)) fail(TC_E_INVAL, "radix_sort: more than 2^32 - 1 keys");
-  constexpr int TILE = kSortBlock * RadixItems<K>::value;
+  constexpr int TILE = kScatterBlock * ScatterItems<K>::value;
   const int passes = (bit_hi - bit_lo + 7) / 8;
   if (passes > kMaxPasses) fail(TC_E_INVAL, "radix_sort: bit range too wide");
   const uint32_t tiles = static_cast<uint32_t>((N + TILE - 1) / TILE);
@@ -488,7 +510,7 @@ K* radix_sort_pairs(K* keys, K* tmp, V*& vals, V* vtmp, size_t N, int bit_lo, in
     const int shift = bit_lo + 8 * p;
     const int w = bit_hi - shift;
     const uint32_t dmask = w >= 8 ? 255u : (1u << w) - 1u;
-    k_sweep_scatter<K, V><<<tiles, kSortBlock, 0, s>>>(a, b, va, vb, static_cast<uint32_t>(N), shift, dmask,
+    k_sweep_scatter<K, V><<<tiles, kScatterBlock, 0, s>>>(a, b, va, vb, static_cast<uint32_t>(N), shift, dmask,
                                                        static_cast<uint64_t>(p + 1) << kTagShift,
                                                        hist + static_cast<size_t>(p) * 256, status.get(), ctrs + 2 * p);
     TC_LAUNCH_CHECK();
