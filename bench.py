@@ -181,7 +181,12 @@ def run_graph_bench(args):
     out["roofline"] = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                        "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                        "kernel": "k_pivot (one launch per tc_count)",
-                       "algorithmic_bytes": b_alg, "model": "4*W + 24*m bytes per count (merge model)"}
+                       "algorithmic_bytes": b_alg, "model": "4*W + 24*m bytes per count (merge model)",
+                       "probe_bytes_4P": 4 * P}
+    if traffic:
+        # measured HBM bytes of one launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, calibrated) over this run's time
+        out["roofline"]["traffic_gbs"] = traffic / (cm / 1e3) / 1e9
+        out["roofline"]["traffic_frac"] = out["roofline"]["traffic_gbs"] / HBM_PEAK_GBS
     if not args.no_plain:
         ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
         ev[0].record(stream)
