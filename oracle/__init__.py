@@ -13,7 +13,8 @@ Routes (each function cites the passage it follows):
     Section 9 local-count figure, listing as in the Section 8 figure);
   * NodeIterator++ of Section 3 — ``count_nodeiterpp``;
   * clustering coefficients of Section 2 — ``clustering``;
-  * sparsification of Section 7 — ``sparsify`` and ``estimate``.
+  * sparsification of Section 7 — ``sparsify`` and ``estimate``;
+  * the k-core order of Section 4 — ``coreness``.
 """
 from __future__ import annotations
 
@@ -68,6 +69,7 @@ def _load():
         "orc_estimate": ([u64, dbl], dbl),
         "orc_sampled_local": ([vp, vp, i64, i32, vp, i32, vp, vp], ctypes.c_int),
         "orc_num_threads": ([], ctypes.c_int),
+        "orc_coreness": ([vp, vp, i32, vp], None),
     }
     for name, (args, res) in sig.items():
         f = getattr(L, name)
@@ -117,6 +119,14 @@ def full_adjacency(lo, hi, n: int):
     nbr = np.empty(max(2 * lo.shape[0], 1), np.int32)
     _load().orc_full_adjacency(_p(lo), _p(hi), lo.shape[0], n, _p(off), _p(nbr))
     return off, nbr[: 2 * lo.shape[0]]
+
+
+def coreness(off, nbr, n: int) -> np.ndarray:
+    """Coreness of every vertex (the k-core order of Section 4) from the full
+    adjacency, by bucket peeling; int32[n]."""
+    core = np.zeros(max(n, 1), np.int32)
+    _load().orc_coreness(_p(off), _p(nbr), n, _p(core))
+    return core[:n]
 
 
 def local_counts_def(off, nbr, n: int):

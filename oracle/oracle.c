@@ -109,6 +109,60 @@ void orc_full_adjacency(const int32_t* lo, const int32_t* hi, int64_t m, int32_t
   free(pos);
 }
 
+/*
+ * Coreness (the k-core order of Section 4, "An Optimal Node Ordering"): the
+ * k-core is the largest subgraph in which every vertex has degree >= k, and
+ * the coreness of v is the largest k whose k-core contains v. Computed by
+ * peeling in degree buckets (Batagelj and Zaversnik, 2003): repeatedly remove
+ * a vertex of smallest remaining degree; its remaining degree at removal,
+ * raised to the running maximum, is its coreness. off/nbr: full adjacency.
+ */
+void orc_coreness(const int64_t* off, const int32_t* nbr, int32_t n, int32_t* core) {
+  if (n <= 0) return;
+  int32_t maxd = 0;
+  int32_t* d = (int32_t*)malloc(sizeof(int32_t) * (size_t)n);
+  for (int32_t v = 0; v < n; v++) {
+    d[v] = (int32_t)(off[v + 1] - off[v]);
+    if (d[v] > maxd) maxd = d[v];
+  }
+  /* bin[k] = first position of degree k in vert[]; vert sorted by degree; pos = inverse */
+  int32_t* bin = (int32_t*)calloc((size_t)maxd + 2, sizeof(int32_t));
+  int32_t* vert = (int32_t*)malloc(sizeof(int32_t) * (size_t)n);
+  int32_t* pos = (int32_t*)malloc(sizeof(int32_t) * (size_t)n);
+  for (int32_t v = 0; v < n; v++) bin[d[v]]++;
+  int32_t start = 0;
+  for (int32_t k = 0; k <= maxd; k++) {
+    int32_t c = bin[k];
+    bin[k] = start;
+    start += c;
+  }
+  for (int32_t v = 0; v < n; v++) {
+    pos[v] = bin[d[v]];
+    vert[pos[v]] = v;
+    bin[d[v]]++;
+  }
+  for (int32_t k = maxd; k > 0; k--) bin[k] = bin[k - 1];
+  bin[0] = 0;
+  for (int32_t i = 0; i < n; i++) {
+    int32_t v = vert[i];
+    core[v] = d[v];
+    for (int64_t j = off[v]; j < off[v + 1]; j++) {
+      int32_t u = nbr[j];
+      if (d[u] > d[v]) {
+        /* move u to the front of its degree bucket, then shrink the bucket */
+        int32_t du = d[u], pu = pos[u], pw = bin[du], w = vert[pw];
+        if (u != w) {
+          pos[u] = pw; vert[pw] = u;
+          pos[w] = pu; vert[pu] = w;
+        }
+        bin[du]++;
+        d[u]--;
+      }
+    }
+  }
+  free(d); free(bin); free(vert); free(pos);
+}
+
 /* ----------------------------------------------- route (1): definitions --- */
 
 /*

@@ -389,3 +389,72 @@ def test_sampled_local_matches_full():
     t, d = oracle.sampled_local(g.src, g.dst, g.n, sample)
     np.testing.assert_array_equal(t, r.t[sample])
     np.testing.assert_array_equal(d, r.deg[sample])
+
+
+# ------------------------------------------------------------ coreness pins
+
+def _core_of(g):
+    lo, hi = oracle.simple(g.src, g.dst, g.n)
+    off, nbr = oracle.full_adjacency(lo, hi, g.n)
+    return oracle.coreness(off, nbr, g.n)
+
+
+def _core_by_definition(n, lo, hi):
+    """Largest k whose k-core (repeatedly delete vertices of degree < k) holds v."""
+    adj = [set() for _ in range(n)]
+    for a, b in zip(lo.tolist(), hi.tolist()):
+        adj[a].add(b)
+        adj[b].add(a)
+    core = [0] * n
+    k = 1
+    while True:
+        alive = set(range(n))
+        changed = True
+        while changed:
+            changed = False
+            for v in list(alive):
+                if len(adj[v] & alive) < k:
+                    alive.discard(v)
+                    changed = True
+        if not alive:
+            return np.array(core, np.int32)
+        for v in alive:
+            core[v] = k
+        k += 1
+
+
+@pytest.mark.parametrize("g,expect", [
+    (synth.complete(9), lambda v: 8), (synth.cycle(17), lambda v: 2), (synth.path(12), lambda v: 1),
+    (synth.star(25), lambda v: 1), (synth.wheel(11), lambda v: 3), (synth.hypercube(5), lambda v: 5),
+    (synth.grid(6, 8), lambda v: 2), (synth.complete_bipartite(4, 9), lambda v: 4),
+    (synth.complete_tripartite(3, 4, 6), lambda v: 7), (synth.friendship(7), lambda v: 2),
+    (synth.random_tree(150, 4), lambda v: 1), (synth.empty(6), lambda v: 0),
+])
+def test_coreness_closed_forms(g, expect):
+    """Coreness of regular and structured families (the k-core order of Section 4)."""
+    core = _core_of(g)
+    assert core.tolist() == [expect(v) for v in range(g.n)]
+
+
+@pytest.mark.parametrize("seed", range(10))
+def test_coreness_matches_definition(seed):
+    rng = np.random.default_rng(300 + seed)
+    n = int(rng.integers(1, 40))
+    src, dst = messy_random_graph(n, int(rng.integers(0, 5 * n + 1)), seed)
+    lo, hi = oracle.simple(src, dst, n)
+    off, nbr = oracle.full_adjacency(lo, hi, n)
+    np.testing.assert_array_equal(oracle.coreness(off, nbr, n), _core_by_definition(n, lo, hi))
+
+
+def test_coreness_bounds_on_rmat():
+    """0 <= core <= degree; the max-core vertices induce a subgraph of min degree = max core."""
+    g = synth.rmat(12, 16, 5)
+    lo, hi = oracle.simple(g.src, g.dst, g.n)
+    off, nbr = oracle.full_adjacency(lo, hi, g.n)
+    deg = oracle.degrees(lo, hi, g.n)
+    core = oracle.coreness(off, nbr, g.n)
+    assert (core >= 0).all() and (core <= deg).all()
+    kmax = int(core.max())
+    top = set(np.nonzero(core == kmax)[0].tolist())
+    for v in top:
+        assert sum(1 for u in nbr[off[v]:off[v + 1]].tolist() if u in top) >= kmax
