@@ -139,6 +139,15 @@ tc_status tc_graph_work(tc_graph* g, void* stream, uint64_t* W, uint64_t* P);
 tc_status tc_graph_order_cost(tc_graph* g, void* stream, uint64_t* cost, int32_t* order_kind);
 
 /*
+ * Coreness of every vertex in the caller's ids (the k-core order compared in
+ * Section 4, "An Optimal Node Ordering"): core_dev int32[n] gets the largest k
+ * such that v lies in a subgraph whose vertices all have degree >= k, computed
+ * on the device by level-synchronous peeling. core_dev is caller-owned device
+ * memory. TC_E_INVAL on a sampled graph or NULL arguments. Synchronises `stream`.
+ */
+tc_status tc_graph_coreness(tc_graph* g, void* stream, int32_t* core_dev);
+
+/*
  * Export the degree data in the caller's ids: deg_dev int32[n] = d_v and
  * dhat_dev int32[n] = |N_v| (effective degree, Section 3). Either may be NULL.
  */
@@ -166,7 +175,9 @@ tc_status tc_graph_oriented(tc_graph* g, void* stream, int64_t* off_dev, int32_t
  *                          of the block path (1 or 2)
  *   TC_OPT_ORDER         : total order used by graphs built afterwards:
  *                          0 degree (Eq. (1), the default), 1 id, 2 a fixed
- *                          pseudo-random permutation, 3 degree descending
+ *                          pseudo-random permutation, 3 degree descending,
+ *                          4 coreness (ties by id; the build first orients by
+ *                          degree to compute the coreness, then rebuilds)
  *                          (the orderings compared in Section 4)
  * Options change speed only, never results (Theorem 1: any total order counts
  * each triangle once). Returns TC_E_INVAL for an unknown key or an

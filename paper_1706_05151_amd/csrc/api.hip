@@ -3,6 +3,7 @@
 // clustering coefficients).
 #include <atomic>
 #include <cmath>
+#include <memory>
 #include <new>
 #include <string>
 #include <vector>
@@ -145,6 +146,40 @@ using namespace tc;
 
 extern "C" {
 
+// Coreness by caller id of a built graph (the plan must exist).
+__global__ void k_i32_by_order(const int32_t* __restrict__ by_rank, const int32_t* __restrict__ order, int32_t n,
+                               int32_t* __restrict__ by_id) {
+  for (int32_t r = blockIdx.x * blockDim.x + threadIdx.x; r < n; r += gridDim.x * blockDim.x) by_id[order[r]] = by_rank[r];
+}
+
+static void coreness_by_id(tc_graph* g, hipStream_t s, int32_t* core_id) {
+  if (g->n <= 0) return;
+  DevBuf<int32_t> cr(g->n, s);
+  coreness_rank(g->csr, s, cr.get());
+  k_i32_by_order<<<grid_for(g->n, kBlock, 65536), kBlock, 0, s>>>(cr.get(), g->order.p, g->n, core_id);
+  TC_LAUNCH_CHECK();
+}
+
+// Builds g (and its plan) in the order of the TC_OPT_ORDER option. The
+// coreness order first builds the graph in degree order, takes its coreness
+// and builds again with the coreness as the order key.
+static void build_in_order(const int32_t* src, const int32_t* dst, int64_t E, int32_t n, const int64_t* edge_off,
+                           const int32_t* n_per_graph, int32_t G, bool on_device, hipStream_t s, tc_graph* g) {
+  const Options o = get_options();
+  if (o.order == 4) {
+    std::unique_ptr<tc_graph> g0(new tc_graph());
+    build_graph(src, dst, E, n, edge_off, n_per_graph, G, on_device, s, g0.get(), 0, nullptr);
+    ensure_plan(g0->csr, s, o);
+    DevBuf<int32_t> core(static_cast<size_t>(n), s);
+    coreness_by_id(g0.get(), s, core.get());
+    build_graph(src, dst, E, n, edge_off, n_per_graph, G, on_device, s, g, 4, core.get());
+    TC_HIP(hipStreamSynchronize(s));
+  } else {
+    build_graph(src, dst, E, n, edge_off, n_per_graph, G, on_device, s, g, static_cast<int>(o.order), nullptr);
+  }
+  ensure_plan(g->csr, s, o);  // work plan of the intersection kernel
+}
+
 tc_status tc_build_csr(const int32_t* src, const int32_t* dst, int64_t num_edges, int32_t n, uint32_t flags,
                        void* stream, tc_graph** out) {
   return guarded([&] {
@@ -152,8 +187,7 @@ tc_status tc_build_csr(const int32_t* src, const int32_t* dst, int64_t num_edges
     *out = nullptr;
     auto* g = new tc_graph();
     try {
-      build_graph(src, dst, num_edges, n, nullptr, nullptr, 1, (flags & TC_IN_DEVICE) != 0, as_stream(stream), g);
-      ensure_plan(g->csr, as_stream(stream), get_options());  // work plan of the intersection kernel
+      build_in_order(src, dst, num_edges, n, nullptr, nullptr, 1, (flags & TC_IN_DEVICE) != 0, as_stream(stream), g);
       TC_HIP(hipStreamSynchronize(as_stream(stream)));
     } catch (...) {
       (void)hipStreamSynchronize(as_stream(stream));
@@ -177,9 +211,8 @@ tc_status tc_batch_build(const int32_t* src, const int32_t* dst, const int64_t* 
     const hipStream_t s = as_stream(stream);
     auto* g = new tc_graph();
     try {
-      build_graph(src, dst, edge_off[num_graphs], static_cast<int32_t>(ntot), edge_off, n_per_graph, num_graphs,
-                  (flags & TC_IN_DEVICE) != 0, s, g);
-      ensure_plan(g->csr, s, get_options());
+      build_in_order(src, dst, edge_off[num_graphs], static_cast<int32_t>(ntot), edge_off, n_per_graph, num_graphs,
+                     (flags & TC_IN_DEVICE) != 0, s, g);
       g->workspace.alloc((3 + static_cast<size_t>(g->n)) * sizeof(unsigned long long), s);
       TC_HIP(hipStreamSynchronize(s));
     } catch (...) {
@@ -324,6 +357,19 @@ tc_status tc_sparsify_count(tc_graph* g, double q, uint64_t seed, void* stream, 
     if (T_sampled) *T_sampled = Ts;
     if (m_kept) *m_kept = sampled.m;
     if (estimate) *estimate = static_cast<double>(Ts) / ((q * q) * q);
+  });
+}
+
+tc_status tc_graph_coreness(tc_graph* g, void* stream, int32_t* core_dev) {
+  return guarded([&] {
+    require(g != nullptr && core_dev != nullptr, TC_E_INVAL, "NULL argument");
+    require(!g->sampled, TC_E_INVAL, "coreness is not available on a sampled graph");
+    DeviceScope ds(g->device);
+    const hipStream_t s = as_stream(stream);
+    std::lock_guard<std::mutex> lk(g->mu);
+    ensure_plan(g->csr, s, get_options());
+    coreness_by_id(g, s, core_dev);
+    TC_HIP(hipStreamSynchronize(s));
   });
 }
 
@@ -527,7 +573,8 @@ tc_status tc_set_option(tc_option key, int64_t value) {
         g_opt_load = value;
         break;
       case TC_OPT_ORDER:
-        require(value <= 3, TC_E_INVAL, "order must be 0 (degree), 1 (id), 2 (random) or 3 (degree descending)");
+        require(value <= 4, TC_E_INVAL,
+                "order must be 0 (degree), 1 (id), 2 (random), 3 (degree descending) or 4 (coreness)");
         g_opt_order = value;
         break;
       default: fail(TC_E_INVAL, "unknown option");

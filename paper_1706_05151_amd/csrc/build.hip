@@ -104,7 +104,8 @@ __global__ __launch_bounds__(kBlock) void k_larger_ends(const uint64_t* __restri
 
 // Rank key of a vertex: graph index (hi word), then the order key, then id.
 // order 0: degree (Eq. (1)); 1: id; 2: a fixed pseudo-random permutation;
-// 3: degree descending. Any total order counts each triangle once (Theorem 1).
+// 3: degree descending; a coreness order passes the coreness as `d` with
+// order 0. Any total order counts each triangle once (Theorem 1).
 __device__ __forceinline__ uint64_t order_key(int order, int32_t v, int32_t d, int b) {
   const uint64_t mask = (1ull << b) - 1;
   switch (order) {
@@ -238,7 +239,8 @@ int32_t max_row_length(const int64_t* off, int32_t n, hipStream_t s) {
 }
 
 void build_graph(const int32_t* src, const int32_t* dst, int64_t E, int32_t n, const int64_t* edge_off_host,
-                 const int32_t* n_per_graph_host, int32_t G, bool on_device, hipStream_t s, tc_graph* g) {
+                 const int32_t* n_per_graph_host, int32_t G, bool on_device, hipStream_t s, tc_graph* g, int order,
+                 const int32_t* key_by_id) {
   if (E < 0 || n < 0) fail(TC_E_RANGE, "negative edge or vertex count");
   if (E >= (1ll << 32) - 1) fail(TC_E_INVAL, "more than 2^32 - 2 edge records");
   if (E > 0 && (!src || !dst)) fail(TC_E_INVAL, "NULL edge array");
@@ -261,7 +263,7 @@ void build_graph(const int32_t* src, const int32_t* dst, int64_t E, int32_t n, c
   }
   const int b = bits_for(n > 1 ? static_cast<uint64_t>(n - 1) : 1);
   g->bits = b;
-  g->order_kind = static_cast<int>(get_options().order);
+  g->order_kind = order;
   const int gbits = G > 1 ? bits_for(static_cast<uint64_t>(G - 1)) : 0;
 
   // ---- inputs on the device
@@ -339,8 +341,9 @@ void build_graph(const int32_t* src, const int32_t* dst, int64_t E, int32_t n, c
   if (G > 1) g->graph_of_rank.alloc(n, s);
   if (n > 0) {
     DevBuf<u128> rk(n, s), rk2(n, s);
-    k_rank_keys<<<grid_for(n, kBlock, 65536), kBlock, 0, s>>>(n, b, g->deg.p, d_vbase.get(), G,
-                                                               static_cast<int>(get_options().order), rk.get());
+    // a caller-supplied key (coreness) orders like the degree: ascending, ties by id
+    k_rank_keys<<<grid_for(n, kBlock, 65536), kBlock, 0, s>>>(n, b, key_by_id ? key_by_id : g->deg.p, d_vbase.get(),
+                                                               G, key_by_id ? 0 : order, rk.get());
     TC_LAUNCH_CHECK();
     u128* r1 = radix_sort<u128>(rk.get(), rk2.get(), n, 0, 2 * b, s);
     u128* r2 = r1;

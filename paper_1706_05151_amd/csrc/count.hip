@@ -941,6 +941,119 @@ __global__ void k_fill_u64(unsigned long long* __restrict__ p, size_t n, unsigne
 }  // namespace
 
 // A fill kernel rather than hipMemsetAsync so that captured graphs hold no memset node.
+// ---------------------------------------------------------------- coreness
+//
+// The k-core order of Section 4: the coreness of v is the largest k such that
+// v lies in a subgraph whose vertices all have degree >= k. Level-synchronous
+// peeling in rank space: at level k every live vertex with remaining degree
+// <= k is removed with coreness k, its live neighbours lose one degree each,
+// and a neighbour whose remaining degree falls from k+1 to k joins the next
+// round of the same level. A level starts at the smallest remaining degree.
+
+__global__ void k_core_init(const int64_t* __restrict__ off, const int64_t* __restrict__ in_off, int32_t n,
+                            int32_t* __restrict__ cd, int32_t* __restrict__ core) {
+  for (int32_t r = blockIdx.x * blockDim.x + threadIdx.x; r < n; r += gridDim.x * blockDim.x) {
+    cd[r] = static_cast<int32_t>((off[r + 1] - off[r]) + (in_off[r + 1] - in_off[r]));
+    core[r] = -1;
+  }
+}
+
+__global__ void k_core_min(const int32_t* __restrict__ cd, const int32_t* __restrict__ core, int32_t n,
+                           int32_t* __restrict__ out) {
+  int32_t best = INT32_MAX;
+  for (int32_t r = blockIdx.x * blockDim.x + threadIdx.x; r < n; r += gridDim.x * blockDim.x)
+    if (core[r] < 0 && cd[r] < best) best = cd[r];
+#pragma unroll
+  for (int d = kWave / 2; d > 0; d >>= 1) {
+    const int32_t o = __shfl_xor(best, d, kWave);
+    best = o < best ? o : best;
+  }
+  if (lane_id() == 0 && best != INT32_MAX) atomicMin(out, best);
+}
+
+struct CoreFrontierPred {
+  const int32_t* cd;
+  const int32_t* core;
+  int32_t k;
+  __device__ bool operator()(size_t r) const { return core[r] < 0 && cd[r] <= k; }
+};
+struct IndexI32 {
+  __device__ int32_t operator()(size_t r) const { return static_cast<int32_t>(r); }
+};
+
+__global__ void k_core_mark(const int32_t* __restrict__ f, uint32_t nf, int32_t k, int32_t* __restrict__ core) {
+  for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < nf; i += gridDim.x * blockDim.x) core[f[i]] = k;
+}
+
+// One wave per removed vertex: its out-entries and in-edge records name its neighbours.
+__global__ __launch_bounds__(kBlock) void k_core_peel(const int32_t* __restrict__ f, uint32_t nf, int32_t k,
+                                                      const int64_t* __restrict__ off, const int32_t* __restrict__ adj,
+                                                      const int64_t* __restrict__ in_off,
+                                                      const InRec* __restrict__ rec, const int32_t* __restrict__ src,
+                                                      const int32_t* __restrict__ core, int32_t* __restrict__ cd,
+                                                      int32_t* __restrict__ next, uint32_t* __restrict__ n_next) {
+  const uint32_t waves = gridDim.x * (blockDim.x / kWave);
+  const int lane = lane_id();
+  auto drop = [&](int32_t w) {
+    if (core[w] >= 0) return;  // already removed (this round's vertices are marked before the round)
+    const int32_t old = atomicSub(&cd[w], 1);
+    if (old == k + 1) next[atomicAdd(n_next, 1u)] = w;
+  };
+  for (uint32_t i = blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave; i < nf; i += waves) {
+    const int32_t r = f[i];
+    for (int64_t j = off[r] + lane; j < off[r + 1]; j += kWave) drop(adj[j]);
+    for (int64_t j = in_off[r] + lane; j < in_off[r + 1]; j += kWave) drop(src[rec[j].a_begin - 1]);
+  }
+}
+
+void coreness_rank(const Csr& c, hipStream_t s, int32_t* core) {
+  const int32_t n = c.n;
+  if (n <= 0) return;
+  if (!c.plan.ready) fail(TC_E_INVAL, "coreness needs the work plan");
+  const PivotPlan& P = c.plan;
+  DevBuf<int32_t> cd(n, s), fa(n, s), fb(n, s), dmin(1, s);
+  DevBuf<uint32_t> dnext(1, s);
+  DevBuf<uint64_t> dcnt(1, s);
+  k_core_init<<<grid_for(n, kBlock, 65536), kBlock, 0, s>>>(c.off.p, P.in_off.p, n, cd.get(), core);
+  TC_LAUNCH_CHECK();
+  int64_t alive = n;
+  int32_t k = 0;
+  int32_t* f = fa.get();
+  int32_t* g = fb.get();
+  while (alive > 0) {
+    k_fill_words<int32_t><<<1, 64, 0, s>>>(dmin.get(), 1, INT32_MAX);
+    TC_LAUNCH_CHECK();
+    k_core_min<<<grid_for(n, kBlock, 4096), kBlock, 0, s>>>(cd.get(), core, n, dmin.get());
+    TC_LAUNCH_CHECK();
+    int32_t lo = 0;
+    TC_HIP(hipMemcpyAsync(&lo, dmin.get(), sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    TC_HIP(hipStreamSynchronize(s));
+    if (lo == INT32_MAX) fail(TC_E_DEVICE, "coreness: live vertices without a degree");
+    if (lo > k) k = lo;
+    compact_if<int32_t>(static_cast<size_t>(n), CoreFrontierPred{cd.get(), core, k}, IndexI32{}, f, dcnt.get(), s);
+    uint64_t nf = 0;
+    TC_HIP(hipMemcpyAsync(&nf, dcnt.get(), sizeof(uint64_t), hipMemcpyDeviceToHost, s));
+    TC_HIP(hipStreamSynchronize(s));
+    if (nf == 0) fail(TC_E_DEVICE, "coreness: empty level");
+    while (nf > 0) {
+      const uint32_t nfu = static_cast<uint32_t>(nf);
+      k_core_mark<<<grid_for(nf, kBlock, 65536), kBlock, 0, s>>>(f, nfu, k, core);
+      TC_LAUNCH_CHECK();
+      alive -= static_cast<int64_t>(nf);
+      k_fill_words<uint32_t><<<1, 64, 0, s>>>(dnext.get(), 1, 0u);
+      TC_LAUNCH_CHECK();
+      k_core_peel<<<grid_for(static_cast<uint64_t>(nf) * kWave, kBlock, 65536), kBlock, 0, s>>>(
+          f, nfu, k, c.off.p, c.adj.p, P.in_off.p, P.inrec.p, c.src.p, core, cd.get(), g, dnext.get());
+      TC_LAUNCH_CHECK();
+      uint32_t nn = 0;
+      TC_HIP(hipMemcpyAsync(&nn, dnext.get(), sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+      TC_HIP(hipStreamSynchronize(s));
+      nf = nn;
+      std::swap(f, g);
+    }
+  }
+}
+
 void fill_u64(unsigned long long* p, size_t n, unsigned long long v, hipStream_t s) {
   if (n == 0) return;
   k_fill_u64<<<grid_for(n, kBlock, 65536), kBlock, 0, s>>>(p, n, v);

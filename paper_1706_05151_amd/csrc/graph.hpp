@@ -129,13 +129,16 @@ struct Options {
   int64_t item_work = 0;     // target probes per work item (0: from the graph's total)
   int64_t blocks_per_cu = 8; // persistent launch occupancy
   int64_t hub_bucket_load = 2;  // entries per 4-slot bucket of a hub table (1 or 2)
-  int64_t order = 0;            // total order of the orientation (0 degree, 1 id, 2 random, 3 degree descending)
+  int64_t order = 0;            // total order of the orientation (0 degree, 1 id, 2 random, 3 degree descending, 4 coreness)
 };
 Options get_options();
 
 // build.hip
+// order: TC_OPT_ORDER value recorded on the graph; key_by_id (device, optional)
+// replaces the degree as the ascending order key (ties by id)
 void build_graph(const int32_t* src, const int32_t* dst, int64_t E, int32_t n, const int64_t* edge_off_host,
-                 const int32_t* n_per_graph_host, int32_t num_graphs, bool on_device, hipStream_t s, tc_graph* g);
+                 const int32_t* n_per_graph_host, int32_t num_graphs, bool on_device, hipStream_t s, tc_graph* g,
+                 int order, const int32_t* key_by_id);
 
 // count.hip
 enum CountMode { kCountTotal = 0, kCountPerNode = 1, kCountList = 2 };
@@ -161,6 +164,8 @@ void count_plain(const Csr& c, unsigned long long* total, hipStream_t s);
 void graph_work(const Csr& c, unsigned long long* W, unsigned long long* P, hipStream_t s);
 // sum_v d_v * dhat_v (the objective of Theorem 3); deg by caller id, order rank -> id
 void order_cost(const Csr& c, const int32_t* deg, const int32_t* order, unsigned long long* out, hipStream_t s);
+// coreness of every rank of the CSR (neighbours: out-entries and in-edge records; needs the plan)
+void coreness_rank(const Csr& c, hipStream_t s, int32_t* core);
 void build_sampled_csr(const tc_graph* g, double q, uint64_t seed, Csr& out, hipStream_t s);
 void sort_triangles(int32_t* tri, int64_t count, int bits, hipStream_t s);
 // off[r] = first index whose row is >= r, for rows sorted ascending (length m); off has n+1 entries

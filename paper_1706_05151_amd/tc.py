@@ -18,7 +18,7 @@ LIB_PATH = os.path.join(_HERE, "libtc.so")
 TC_OK, TC_E_INVAL, TC_E_NOMEM, TC_E_DEVICE, TC_E_RANGE, TC_E_TRUNC = 0, -1, -2, -3, -4, -5
 TC_IN_DEVICE = 1
 OPT_KERNEL, OPT_HUB_DHAT, OPT_ITEM_WORK, OPT_BLOCKS_PER_CU, OPT_HUB_BUCKET_LOAD, OPT_ORDER = 0, 1, 2, 3, 4, 5
-ORDER_DEGREE, ORDER_ID, ORDER_RANDOM, ORDER_DEGREE_DESC = 0, 1, 2, 3
+ORDER_DEGREE, ORDER_ID, ORDER_RANDOM, ORDER_DEGREE_DESC, ORDER_CORE = 0, 1, 2, 3, 4
 
 # (name, argtypes, restype) for every symbol include/tc.h declares
 _vp, _i32, _i64, _u32, _u64, _dbl = (ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_uint32,
@@ -37,6 +37,7 @@ SIGNATURES = {
     "tc_graph_work": ([_vp, _vp, _P(_u64), _P(_u64)], ctypes.c_int),
     "tc_graph_degrees": ([_vp, _vp, _vp, _vp], ctypes.c_int),
     "tc_graph_order_cost": ([_vp, _vp, _P(_u64), _P(_i32)], ctypes.c_int),
+    "tc_graph_coreness": ([_vp, _vp, _vp], ctypes.c_int),
     "tc_graph_oriented": ([_vp, _vp, _vp, _vp], ctypes.c_int),
     "tc_set_option": ([ctypes.c_int, _i64], ctypes.c_int),
     "tc_get_option": ([ctypes.c_int], _i64),
@@ -221,6 +222,13 @@ class Graph:
         _check(lib().tc_graph_order_cost(self._h, _stream(stream), ctypes.byref(c), ctypes.byref(k)),
                "tc_graph_order_cost")
         return c.value, k.value
+
+    def coreness(self, stream=None):
+        """Coreness of every vertex by caller id (k-core order of Section 4): int32[n] on the device."""
+        torch = _torch()
+        core = torch.empty(max(self.n, 1), dtype=torch.int32, device="cuda")
+        _check(lib().tc_graph_coreness(self._h, _stream(stream), _dptr(core)), "tc_graph_coreness")
+        return core[: self.n]
 
     def degrees(self, stream=None):
         torch = _torch()

@@ -283,7 +283,7 @@ def test_config_ba22(tc):
 
 # ----------------------------------------------------------------- orders ---
 
-@pytest.mark.parametrize("order", [0, 1, 2, 3])
+@pytest.mark.parametrize("order", [0, 1, 2, 3, 4])
 def test_orders_count_each_triangle_once(tc, order):
     """Theorem 1: every total order gives the same exact outputs; Theorem 3:
     the degree order has the smallest sum_v d_v * dhat_v."""
@@ -305,8 +305,11 @@ def test_orders_count_each_triangle_once(tc, order):
             assert kind == order and cost >= best
             if order == 0:
                 assert cost == best
-            if order in (1, 3):  # orders the oracle can reproduce: id, degree descending (ties by id)
-                key = np.zeros(el.n, np.int64) if order == 1 else -ref.deg
+            if order in (1, 3, 4):  # orders the oracle can reproduce: id, degree descending, coreness (ties by id)
+                if order == 4:
+                    key = oracle.coreness(*oracle.full_adjacency(lo, hi, el.n), el.n).astype(np.int64)
+                else:
+                    key = np.zeros(el.n, np.int64) if order == 1 else -ref.deg
                 off, adj = oracle.orient_by_key(lo, hi, key, el.n)
                 goff, gadj = g.oriented()
                 np.testing.assert_array_equal(goff.cpu().numpy(), off)
@@ -316,3 +319,62 @@ def test_orders_count_each_triangle_once(tc, order):
             assert (Ts, mk) == oracle.sparsified_count(lo, hi, ref.deg, el.n, 0.3, 4)[:2]
     finally:
         tc.set_option(tc.OPT_ORDER, old)
+
+
+# --------------------------------------------------------------- coreness ---
+
+def _messy_el(n, m, seed):
+    """Random raw edge list with loops, repeats and both directions."""
+    rng = np.random.default_rng(seed)
+    src = rng.integers(0, n, m).astype(np.int32)
+    dst = rng.integers(0, n, m).astype(np.int32)
+    src = np.concatenate([src, dst[: m // 4], np.arange(5, dtype=np.int32)])
+    dst = np.concatenate([dst, src[: m // 4], np.arange(5, dtype=np.int32)])
+    return synth.EdgeList(n, src, dst, f"messy{seed}")
+
+
+def _core_ref(el):
+    lo, hi = oracle.simple(el.src, el.dst, el.n)
+    return oracle.coreness(*oracle.full_adjacency(lo, hi, el.n), el.n)
+
+
+@pytest.mark.parametrize("name", ["complete", "wheel", "hypercube", "grid", "bipartite", "tripartite", "friendship",
+                                  "star", "cycle", "tree", "messy", "rmat", "er", "ba", "empty"])
+def test_coreness_matches_oracle(tc, name):
+    """Coreness (the k-core order of Section 4) equals the oracle's bucket peeling exactly."""
+    el = {
+        "complete": lambda: synth.complete(30), "wheel": lambda: synth.wheel(40), "hypercube": lambda: synth.hypercube(7),
+        "grid": lambda: synth.grid(17, 23), "bipartite": lambda: synth.complete_bipartite(9, 31),
+        "tripartite": lambda: synth.complete_tripartite(5, 8, 13), "friendship": lambda: synth.friendship(25),
+        "star": lambda: synth.star(500), "cycle": lambda: synth.cycle(1001), "tree": lambda: synth.random_tree(3000, 8),
+        "messy": lambda: _messy_el(700, 5000, 3), "rmat": lambda: synth.rmat(15, 16, 23),
+        "er": lambda: synth.er(20000, 0.0008, 6), "ba": lambda: synth.ba(30000, 6, 7), "empty": lambda: synth.empty(50),
+    }[name]()
+    s, d = to_dev(el)
+    with tc.Graph.build(s, d, el.n) as g:
+        say(f"[parity] coreness {name} n={el.n}")
+        np.testing.assert_array_equal(g.coreness().cpu().numpy(), _core_ref(el))
+
+
+def test_coreness_of_a_batch(tc):
+    """In a disjoint union each graph keeps its own coreness."""
+    els = [synth.rmat(11, 8, 30 + i) for i in range(3)] + [synth.wheel(50), synth.complete(12), synth.empty(7)]
+    from paper_1706_05151_amd import batch
+    packed = batch.pack(els)
+    s, d = to_dev(synth.EdgeList(int(packed["n_per_graph"].sum()), packed["src"], packed["dst"], "batch"))
+    with tc.Graph.build_batch(s, d, packed["edge_off"], packed["n_per_graph"]) as g:
+        core = g.coreness().cpu().numpy()
+    ref = np.concatenate([_core_ref(el) for el in els])
+    np.testing.assert_array_equal(core, ref)
+
+
+def test_coreness_refused_on_sample(tc):
+    el = synth.rmat(10, 8, 2)
+    s, d = to_dev(el)
+    with tc.Graph.build(s, d, el.n) as g:
+        h = g.sparsify_build(0.5, 1)
+        try:
+            with pytest.raises(tc.TCError):
+                h.coreness()
+        finally:
+            h.close()
