@@ -14,7 +14,8 @@ Routes (each function cites the passage it follows):
   * NodeIterator++ of Section 3 — ``count_nodeiterpp``;
   * clustering coefficients of Section 2 — ``clustering``;
   * sparsification of Section 7 — ``sparsify`` and ``estimate``;
-  * the k-core order of Section 4 — ``coreness``.
+  * the k-core order of Section 4 — ``coreness``;
+  * the load-balancing schemes of Sections 5 and 6 — ``partition_work``.
 """
 from __future__ import annotations
 
@@ -70,6 +71,7 @@ def _load():
         "orc_sampled_local": ([vp, vp, i64, i32, vp, i32, vp, vp], ctypes.c_int),
         "orc_num_threads": ([], ctypes.c_int),
         "orc_coreness": ([vp, vp, i32, vp], None),
+        "orc_partition_work": ([vp, vp, vp, i32, ctypes.c_int, i32, vp, vp], None),
     }
     for name, (args, res) in sig.items():
         f = getattr(L, name)
@@ -127,6 +129,20 @@ def coreness(off, nbr, n: int) -> np.ndarray:
     core = np.zeros(max(n, 1), np.int32)
     _load().orc_coreness(_p(off), _p(nbr), n, _p(core))
     return core[:n]
+
+
+PARTITION_SCHEMES = ("N", "D", "DH", "DDH", "DH2", "DPD", "ANOP")
+
+
+def partition_work(off, adj, deg, n: int, scheme: int, parts: int):
+    """Section 5 load balancing (cost-function table) and the Section 6 cost:
+    boundary nodes x_j = argmin F(v) >= j*alpha over ids, and the NodeIteratorN
+    merge work of each partition. Returns (bounds int64[parts+1], work uint64[parts])."""
+    bounds = np.zeros(parts + 1, np.int64)
+    work = np.zeros(parts, np.uint64)
+    deg = np.ascontiguousarray(deg, dtype=np.int64)
+    _load().orc_partition_work(_p(off), _p(adj), _p(deg), n, scheme, parts, _p(bounds), _p(work))
+    return bounds, work
 
 
 def local_counts_def(off, nbr, n: int):

@@ -163,6 +163,65 @@ void orc_coreness(const int64_t* off, const int32_t* nbr, int32_t n, int32_t* co
   free(d); free(bin); free(vert); free(pos);
 }
 
+/*
+ * Load-balancing schemes of Section 5 (the cost-function table) and the cost
+ * of the space-efficient algorithm of Section 6: f(v) for each vertex from the
+ * oriented lists (rows by id, d^_v = |N_v|), the prefix F(t) = sum_{v<=t} f(v),
+ * and the boundary nodes x_j = argmin_v F(v) >= j*alpha with alpha = F(n-1)/p
+ * (compared exactly as F(v)*p >= j*F(n-1)); partition j holds the core nodes
+ * [x_j, x_{j+1}). work[j] = sum over its core nodes v of the NodeIteratorN
+ * merge cost sum_{u in N_v} (d^_v + d^_u) (Theorem 2).
+ * scheme: 0 f=1, 1 f=d_v, 2 f=d^_v, 3 f=d_v*d^_v, 4 f=d^_v^2,
+ *         5 f=sum_{u in N_v}(d^_v+d^_u), 6 f=sum_{u in Nfull_v - N_v}(d^_v+d^_u).
+ */
+void orc_partition_work(const int64_t* off, const int32_t* adj, const int64_t* deg, int32_t n, int scheme,
+                        int32_t parts, int64_t* bounds, uint64_t* work) {
+  uint64_t* f = (uint64_t*)calloc((size_t)(n > 0 ? n : 1), sizeof(uint64_t));
+  uint64_t* cost = (uint64_t*)calloc((size_t)(n > 0 ? n : 1), sizeof(uint64_t));
+  uint64_t* insum = (uint64_t*)calloc((size_t)(n > 0 ? n : 1), sizeof(uint64_t));
+  for (int32_t u = 0; u < n; u++) {
+    uint64_t du = (uint64_t)(off[u + 1] - off[u]);
+    for (int64_t j = off[u]; j < off[u + 1]; j++) {
+      int32_t v = adj[j];
+      uint64_t dv = (uint64_t)(off[v + 1] - off[v]);
+      cost[u] += du + dv;   /* u's merge against N_v */
+      insum[v] += dv + du;  /* u is an in-neighbour of v */
+    }
+  }
+  for (int32_t v = 0; v < n; v++) {
+    uint64_t d = (uint64_t)deg[v], dh = (uint64_t)(off[v + 1] - off[v]);
+    switch (scheme) {
+      case 0: f[v] = 1; break;
+      case 1: f[v] = d; break;
+      case 2: f[v] = dh; break;
+      case 3: f[v] = d * dh; break;
+      case 4: f[v] = dh * dh; break;
+      case 5: f[v] = cost[v]; break;
+      default: f[v] = insum[v]; break;
+    }
+  }
+  uint64_t total = 0;
+  for (int32_t v = 0; v < n; v++) total += f[v];
+  bounds[0] = 0;
+  bounds[parts] = n;
+  for (int32_t j = 1; j < parts; j++) {
+    /* first v with F(v) * parts >= j * total */
+    uint64_t F = 0;
+    int32_t x = n;
+    for (int32_t v = 0; v < n; v++) {
+      F += f[v];
+      if ((unsigned __int128)F * (unsigned)parts >= (unsigned __int128)total * (unsigned)j) { x = v; break; }
+    }
+    bounds[j] = x;
+  }
+  for (int32_t j = 0; j < parts; j++) {
+    uint64_t w = 0;
+    for (int64_t v = bounds[j]; v < bounds[j + 1]; v++) w += cost[v];
+    work[j] = w;
+  }
+  free(f); free(cost); free(insum);
+}
+
 /* ----------------------------------------------- route (1): definitions --- */
 
 /*

@@ -458,3 +458,51 @@ def test_coreness_bounds_on_rmat():
     top = set(np.nonzero(core == kmax)[0].tolist())
     for v in top:
         assert sum(1 for u in nbr[off[v]:off[v + 1]].tolist() if u in top) >= kmax
+
+
+# ------------------------------------------- load-balancing scheme pins
+
+def _oriented(g):
+    lo, hi = oracle.simple(g.src, g.dst, g.n)
+    deg = oracle.degrees(lo, hi, g.n)
+    off, adj = oracle.orient(lo, hi, deg, g.n)
+    return off, adj, deg
+
+
+@pytest.mark.parametrize("scheme", range(7))
+def test_partition_work_sums_to_W_and_bounds_cover(scheme):
+    """Every scheme splits the ids into contiguous parts whose merge work adds up to W (Theorem 2)."""
+    g = synth.rmat(12, 16, 44)
+    off, adj, deg = _oriented(g)
+    bounds, work = oracle.partition_work(off, adj, deg, g.n, scheme, 37)
+    assert bounds[0] == 0 and bounds[-1] == g.n and (np.diff(bounds) >= 0).all()
+    assert int(work.sum()) == oracle.work(off, adj, g.n)
+
+
+def test_partition_scheme_N_closed_form():
+    """f = 1: F(v) = v + 1, so the j-th boundary is the first v with (v+1) p >= j n, i.e. j n / p - 1."""
+    g = synth.cycle(960)
+    off, adj, deg = _oriented(g)
+    p = 12
+    bounds, _ = oracle.partition_work(off, adj, deg, g.n, 0, p)
+    assert bounds.tolist() == [0] + [j * g.n // p - 1 for j in range(1, p)] + [g.n]
+
+
+@pytest.mark.parametrize("scheme", [1, 3, 4, 5, 6])
+def test_partition_boundary_rule_by_search(scheme):
+    """Boundary nodes agree with a search on the cumulative cost: F(x_j - 1) < j F / p <= F(x_j)."""
+    g = synth.ba(3000, 5, 9)
+    off, adj, deg = _oriented(g)
+    dh = np.diff(off).astype(np.int64)
+    src = np.repeat(np.arange(g.n), np.diff(off))
+    merge = np.bincount(src, weights=(dh[src] + dh[adj]).astype(np.float64), minlength=g.n).astype(np.int64)
+    insum = np.bincount(adj, weights=(dh[src] + dh[adj]).astype(np.float64), minlength=g.n).astype(np.int64)
+    f = {1: deg, 3: deg * dh, 4: dh * dh, 5: merge, 6: insum}[scheme].astype(np.int64)
+    F = np.cumsum(f)
+    p = 23
+    bounds, work = oracle.partition_work(off, adj, deg, g.n, scheme, p)
+    for j in range(1, p):
+        x = int(bounds[j])
+        assert F[x] * p >= j * F[-1]
+        assert x == 0 or F[x - 1] * p < j * F[-1]
+    np.testing.assert_array_equal(work, [int(merge[bounds[j]:bounds[j + 1]].sum()) for j in range(p)])
