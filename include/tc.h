@@ -139,6 +139,24 @@ tc_status tc_graph_work(tc_graph* g, void* stream, uint64_t* W, uint64_t* P);
 tc_status tc_graph_order_cost(tc_graph* g, void* stream, uint64_t* cost, int32_t* order_kind);
 
 /*
+ * The static load balancing of Section 5, counted on the device: core nodes
+ * in id order are split into `parts` contiguous ranges by the boundary rule
+ * x_j = argmin_v F(v) >= j*alpha, alpha = F(n-1)/parts (compared exactly as
+ * F(v)*parts >= j*F(n-1)), where F is the prefix sum of the cost f(v) of
+ * `scheme`: 0 f = 1, 1 f = d_v, 2 f = dhat_v, 3 f = d_v*dhat_v, 4 f = dhat_v^2,
+ * 5 f = sum_{u in N_v} (dhat_v + dhat_u) (the cost-function table), 6 f =
+ * sum over the lower-ordered neighbours u of (dhat_v + dhat_u) (the cost of
+ * the space-efficient algorithm, Section 6). Each range is counted by one
+ * workgroup with the NodeIteratorN merge. Outputs: *T (host) the exact total;
+ * bounds_dev int64[parts+1] the boundary nodes (0 and n at the ends);
+ * work_dev uint64[parts] each range's merge work sum_v sum_{u in N_v}
+ * (dhat_v + dhat_u) (Theorem 2). Either device array may be NULL. TC_E_INVAL
+ * for an unknown scheme, parts < 1 or a sampled graph. Synchronises `stream`.
+ */
+tc_status tc_count_partitioned(tc_graph* g, void* stream, int32_t scheme, int32_t parts, uint64_t* T,
+                               int64_t* bounds_dev, uint64_t* work_dev);
+
+/*
  * Coreness of every vertex in the caller's ids (the k-core order compared in
  * Section 4, "An Optimal Node Ordering"): core_dev int32[n] gets the largest k
  * such that v lies in a subgraph whose vertices all have degree >= k, computed

@@ -360,6 +360,37 @@ tc_status tc_sparsify_count(tc_graph* g, double q, uint64_t seed, void* stream, 
   });
 }
 
+tc_status tc_count_partitioned(tc_graph* g, void* stream, int32_t scheme, int32_t parts, uint64_t* T,
+                               int64_t* bounds_dev, uint64_t* work_dev) {
+  return guarded([&] {
+    require(g != nullptr && T != nullptr, TC_E_INVAL, "NULL argument");
+    require(scheme >= 0 && scheme <= 6, TC_E_INVAL, "scheme must be 0..6");
+    require(parts >= 1, TC_E_INVAL, "parts < 1");
+    require(!g->sampled, TC_E_INVAL, "partitioned counts are not available on a sampled graph");
+    DeviceScope ds(g->device);
+    const hipStream_t s = as_stream(stream);
+    std::lock_guard<std::mutex> lk(g->mu);
+    ensure_plan(g->csr, s, get_options());
+    DevBuf<int64_t> bb;
+    DevBuf<unsigned long long> ww, tt(1, s);
+    int64_t* b = bounds_dev;
+    unsigned long long* w = reinterpret_cast<unsigned long long*>(work_dev);
+    if (!b) {
+      bb.alloc(static_cast<size_t>(parts) + 1, s);
+      b = bb.get();
+    }
+    if (!w) {
+      ww.alloc(static_cast<size_t>(parts), s);
+      w = ww.get();
+    }
+    count_partitioned(g->csr, g->order.p, g->rank.p, g->deg.p, scheme, parts, tt.get(), b, w, s);
+    unsigned long long h = 0;
+    TC_HIP(hipMemcpyAsync(&h, tt.get(), sizeof(h), hipMemcpyDeviceToHost, s));
+    TC_HIP(hipStreamSynchronize(s));
+    *T = h;
+  });
+}
+
 tc_status tc_graph_coreness(tc_graph* g, void* stream, int32_t* core_dev) {
   return guarded([&] {
     require(g != nullptr && core_dev != nullptr, TC_E_INVAL, "NULL argument");

@@ -1054,6 +1054,133 @@ void coreness_rank(const Csr& c, hipStream_t s, int32_t* core) {
   }
 }
 
+// ------------------------------------------------- load-balancing schemes
+//
+// The partitioning of Section 5: core nodes in id order are split into
+// contiguous ranges by the boundary rule x_j = argmin F(v) >= j*alpha over
+// the prefix F of a cost f (the cost-function table of Section 5; scheme 6 is
+// the cost of the space-efficient algorithm of Section 6), and each range is
+// counted by one workgroup with the NodeIteratorN merge, so the slowest range
+// sets the time.
+
+__global__ void k_vertex_costs(const int64_t* __restrict__ off, const int32_t* __restrict__ adj,
+                               const int64_t* __restrict__ in_off, const InRec* __restrict__ rec,
+                               const int32_t* __restrict__ src, const int32_t* __restrict__ order,
+                               const int32_t* __restrict__ deg, int32_t n, int scheme,
+                               unsigned long long* __restrict__ f_id, unsigned long long* __restrict__ cost_id) {
+  for (int32_t r = blockIdx.x * blockDim.x + threadIdx.x; r < n; r += gridDim.x * blockDim.x) {
+    const unsigned long long dh = static_cast<unsigned long long>(off[r + 1] - off[r]);
+    unsigned long long merge = 0, in = 0;
+    for (int64_t j = off[r]; j < off[r + 1]; j++) {
+      const int32_t u = adj[j];
+      merge += dh + static_cast<unsigned long long>(off[u + 1] - off[u]);
+    }
+    if (scheme == 6) {
+      for (int64_t j = in_off[r]; j < in_off[r + 1]; j++) {
+        const int32_t u = src[rec[j].a_begin - 1];
+        in += dh + static_cast<unsigned long long>(off[u + 1] - off[u]);
+      }
+    }
+    const int32_t v = order[r];
+    const unsigned long long d = static_cast<unsigned long long>(deg[v]);
+    unsigned long long f;
+    switch (scheme) {
+      case 0: f = 1; break;
+      case 1: f = d; break;
+      case 2: f = dh; break;
+      case 3: f = d * dh; break;
+      case 4: f = dh * dh; break;
+      case 5: f = merge; break;
+      default: f = in; break;
+    }
+    f_id[v] = f;
+    cost_id[v] = merge;
+  }
+}
+
+// bounds[j] = first v with F(v) * parts >= j * total (F inclusive; Fx = exclusive prefix).
+__global__ void k_part_bounds(const unsigned long long* __restrict__ Fx, const unsigned long long* __restrict__ f,
+                              int32_t n, const unsigned long long* __restrict__ total, int32_t parts,
+                              int64_t* __restrict__ bounds) {
+  for (int32_t j = blockIdx.x * blockDim.x + threadIdx.x; j <= parts; j += gridDim.x * blockDim.x) {
+    if (j == 0) { bounds[0] = 0; continue; }
+    if (j == parts) { bounds[parts] = n; continue; }
+    const unsigned __int128 goal = static_cast<unsigned __int128>(*total) * static_cast<unsigned>(j);
+    int32_t lo = 0, hi = n;  // first v in [0, n) with F(v) * parts >= goal, n if none
+    while (lo < hi) {
+      const int32_t mid = lo + (hi - lo) / 2;
+      const unsigned __int128 F = static_cast<unsigned __int128>(Fx[mid] + f[mid]) * static_cast<unsigned>(parts);
+      if (F >= goal) hi = mid;
+      else lo = mid + 1;
+    }
+    bounds[j] = lo;
+  }
+}
+
+__global__ void k_part_work(const unsigned long long* __restrict__ Cx, const int64_t* __restrict__ bounds,
+                            int32_t parts, unsigned long long* __restrict__ work) {
+  for (int32_t j = blockIdx.x * blockDim.x + threadIdx.x; j < parts; j += gridDim.x * blockDim.x)
+    work[j] = Cx[bounds[j + 1]] - Cx[bounds[j]];
+}
+
+// Workgroup j counts the triangles of its core nodes [bounds[j], bounds[j+1])
+// (ids): wave w takes every 4th node, its lanes take the node's oriented
+// edges and merge the two full lists.
+constexpr int kPartBlock = 256;
+__global__ __launch_bounds__(kPartBlock) void k_count_parts(const int64_t* __restrict__ off,
+                                                            const int32_t* __restrict__ adj,
+                                                            const int32_t* __restrict__ rank,
+                                                            const int64_t* __restrict__ bounds,
+                                                            unsigned long long* __restrict__ total) {
+  const int64_t v0 = bounds[blockIdx.x], v1 = bounds[blockIdx.x + 1];
+  const int w = threadIdx.x / kWave, lane = lane_id();
+  unsigned long long cnt = 0;
+  for (int64_t v = v0 + w; v < v1; v += kPartBlock / kWave) {
+    const int32_t r = rank[v];
+    const int64_t a0 = off[r], a1 = off[r + 1];
+    for (int64_t e = a0 + lane; e < a1; e += kWave) {
+      const int32_t u = adj[e];
+      int64_t i = a0, j = off[u];
+      const int64_t j1 = off[u + 1];
+      while (i < a1 && j < j1) {
+        const int32_t x = adj[i], y = adj[j];
+        cnt += x == y;
+        i += x <= y;
+        j += y <= x;
+      }
+    }
+  }
+  cnt = wave_sum(cnt);
+  if (lane == 0 && cnt) atomicAdd(total, cnt);
+}
+
+void count_partitioned(const Csr& c, const int32_t* order, const int32_t* rank, const int32_t* deg, int scheme,
+                       int32_t parts, unsigned long long* T_dev, int64_t* bounds, unsigned long long* work,
+                       hipStream_t s) {
+  const int32_t n = c.n;
+  if (!c.plan.ready) fail(TC_E_INVAL, "no work plan on this graph");
+  fill_u64(T_dev, 1, 0ull, s);
+  DevBuf<unsigned long long> f(static_cast<size_t>(n) + 1, s), cost(static_cast<size_t>(n) + 1, s);
+  DevBuf<unsigned long long> Fx(static_cast<size_t>(n) + 1, s), Cx(static_cast<size_t>(n) + 1, s);
+  if (n > 0) {
+    k_vertex_costs<<<grid_for(n, kBlock, 65536), kBlock, 0, s>>>(c.off.p, c.adj.p, c.plan.in_off.p, c.plan.inrec.p,
+                                                                 c.src.p, order, deg, n, scheme, f.get(), cost.get());
+    TC_LAUNCH_CHECK();
+  }
+  exclusive_scan<unsigned long long>(f.get(), Fx.get(), static_cast<size_t>(n), s, Fx.get() + n);
+  exclusive_scan<unsigned long long>(cost.get(), Cx.get(), static_cast<size_t>(n), s, Cx.get() + n);
+  k_part_bounds<<<grid_for(static_cast<uint64_t>(parts) + 1, kBlock, 4096), kBlock, 0, s>>>(Fx.get(), f.get(), n,
+                                                                                              Fx.get() + n, parts,
+                                                                                              bounds);
+  TC_LAUNCH_CHECK();
+  k_part_work<<<grid_for(static_cast<uint64_t>(parts), kBlock, 4096), kBlock, 0, s>>>(Cx.get(), bounds, parts, work);
+  TC_LAUNCH_CHECK();
+  if (n > 0 && c.m > 0) {
+    k_count_parts<<<static_cast<unsigned>(parts), kPartBlock, 0, s>>>(c.off.p, c.adj.p, rank, bounds, T_dev);
+    TC_LAUNCH_CHECK();
+  }
+}
+
 void fill_u64(unsigned long long* p, size_t n, unsigned long long v, hipStream_t s) {
   if (n == 0) return;
   k_fill_u64<<<grid_for(n, kBlock, 65536), kBlock, 0, s>>>(p, n, v);

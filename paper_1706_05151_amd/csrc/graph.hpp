@@ -164,6 +164,11 @@ void count_plain(const Csr& c, unsigned long long* total, hipStream_t s);
 void graph_work(const Csr& c, unsigned long long* W, unsigned long long* P, hipStream_t s);
 // sum_v d_v * dhat_v (the objective of Theorem 3); deg by caller id, order rank -> id
 void order_cost(const Csr& c, const int32_t* deg, const int32_t* order, unsigned long long* out, hipStream_t s);
+// Section 5 partitioning by a cost scheme (0..6) into `parts` id ranges, each
+// counted by one workgroup; bounds int64[parts+1], work uint64[parts] (merge cost)
+void count_partitioned(const Csr& c, const int32_t* order, const int32_t* rank, const int32_t* deg, int scheme,
+                       int32_t parts, unsigned long long* T_dev, int64_t* bounds, unsigned long long* work,
+                       hipStream_t s);
 // coreness of every rank of the CSR (neighbours: out-entries and in-edge records; needs the plan)
 void coreness_rank(const Csr& c, hipStream_t s, int32_t* core);
 void build_sampled_csr(const tc_graph* g, double q, uint64_t seed, Csr& out, hipStream_t s);

@@ -19,6 +19,7 @@ TC_OK, TC_E_INVAL, TC_E_NOMEM, TC_E_DEVICE, TC_E_RANGE, TC_E_TRUNC = 0, -1, -2, 
 TC_IN_DEVICE = 1
 OPT_KERNEL, OPT_HUB_DHAT, OPT_ITEM_WORK, OPT_BLOCKS_PER_CU, OPT_HUB_BUCKET_LOAD, OPT_ORDER = 0, 1, 2, 3, 4, 5
 ORDER_DEGREE, ORDER_ID, ORDER_RANDOM, ORDER_DEGREE_DESC, ORDER_CORE = 0, 1, 2, 3, 4
+SCHEME_N, SCHEME_D, SCHEME_DH, SCHEME_DDH, SCHEME_DH2, SCHEME_DPD, SCHEME_ANOP = range(7)
 
 # (name, argtypes, restype) for every symbol include/tc.h declares
 _vp, _i32, _i64, _u32, _u64, _dbl = (ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_uint32,
@@ -38,6 +39,7 @@ SIGNATURES = {
     "tc_graph_degrees": ([_vp, _vp, _vp, _vp], ctypes.c_int),
     "tc_graph_order_cost": ([_vp, _vp, _P(_u64), _P(_i32)], ctypes.c_int),
     "tc_graph_coreness": ([_vp, _vp, _vp], ctypes.c_int),
+    "tc_count_partitioned": ([_vp, _vp, _i32, _i32, _P(_u64), _vp, _vp], ctypes.c_int),
     "tc_graph_oriented": ([_vp, _vp, _vp, _vp], ctypes.c_int),
     "tc_set_option": ([ctypes.c_int, _i64], ctypes.c_int),
     "tc_get_option": ([ctypes.c_int], _i64),
@@ -222,6 +224,17 @@ class Graph:
         _check(lib().tc_graph_order_cost(self._h, _stream(stream), ctypes.byref(c), ctypes.byref(k)),
                "tc_graph_order_cost")
         return c.value, k.value
+
+    def count_partitioned(self, scheme: int, parts: int, stream=None):
+        """Section 5 static load balancing by cost scheme (0 N, 1 D, 2 DH, 3 DDH, 4 DH^2, 5 DPD,
+        6 the Section 6 cost): (T, bounds int64[parts+1], work uint64[parts] as int64) on the device."""
+        torch = _torch()
+        T = _u64()
+        bounds = torch.empty(parts + 1, dtype=torch.int64, device="cuda")
+        work = torch.empty(parts, dtype=torch.int64, device="cuda")
+        _check(lib().tc_count_partitioned(self._h, _stream(stream), int(scheme), int(parts), ctypes.byref(T),
+                                          _dptr(bounds), _dptr(work)), "tc_count_partitioned")
+        return T.value, bounds, work
 
     def coreness(self, stream=None):
         """Coreness of every vertex by caller id (k-core order of Section 4): int32[n] on the device."""

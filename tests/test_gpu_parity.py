@@ -378,3 +378,36 @@ def test_coreness_refused_on_sample(tc):
                 h.coreness()
         finally:
             h.close()
+
+
+# ------------------------------------------------- load-balancing schemes ---
+
+@pytest.mark.parametrize("scheme", range(7))
+def test_partitioned_count_matches_oracle(tc, scheme):
+    """Section 5 partitioning: boundaries and per-range merge work equal the oracle's, T is exact."""
+    for el, parts in ((synth.rmat(12, 16, 52), 64), (synth.ba(20000, 5, 53), 200), (synth.er(5000, 0.004, 54), 7),
+                      (synth.wheel(300), 5)):
+        lo, hi = oracle.simple(el.src, el.dst, el.n)
+        deg = oracle.degrees(lo, hi, el.n)
+        off, adj = oracle.orient(lo, hi, deg, el.n)
+        T_ref = oracle.count_nin(off, adj, el.n)[0]
+        bounds, work = oracle.partition_work(off, adj, deg, el.n, scheme, parts)
+        s, d = to_dev(el)
+        with tc.Graph.build(s, d, el.n) as g:
+            say(f"[parity] scheme {scheme} {el.name} parts {parts}")
+            T, gb, gw = g.count_partitioned(scheme, parts)
+            assert T == T_ref
+            np.testing.assert_array_equal(gb.cpu().numpy(), bounds)
+            np.testing.assert_array_equal(gw.cpu().numpy().astype(np.uint64), work)
+
+
+def test_partitioned_count_errors(tc):
+    el = synth.rmat(9, 8, 1)
+    s, d = to_dev(el)
+    with tc.Graph.build(s, d, el.n) as g:
+        with pytest.raises(tc.TCError):
+            g.count_partitioned(7, 4)
+        with pytest.raises(tc.TCError):
+            g.count_partitioned(0, 0)
+        T, b, w = g.count_partitioned(5, 1)  # one range: the whole graph
+        assert T == g.count() and b.cpu().tolist() == [0, el.n]
