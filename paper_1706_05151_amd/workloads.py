@@ -242,9 +242,64 @@ def run_orders(args):
             "table": table}
 
 
+def run_schemes(args):
+    """Load-balancing study (Section 5, the cost-function table, and the Section
+    6 cost): the same graphs partitioned into `parts` id ranges by each cost
+    scheme and counted one range per workgroup. Reports the time of the
+    partitioned count (costs, prefix, boundaries and the count), the spread of
+    the per-range merge work (max / mean) and checks T against tc_count."""
+    import torch
+
+    import synth
+
+    torch.cuda.set_device(0)
+    names = ("N", "D", "DH", "DDH", "DH2", "DPD", "ANOP")
+    parts = int(getattr(args, "parts", 1024) or 1024)
+    graphs = [("er", synth.er(1 << 20, 16.0 / ((1 << 20) - 1), 11)), ("ba", synth.ba(1 << 20, 8, 12)),
+              ("rmat", synth.rmat(args.scale if args.scale <= 22 else 22, 16, 3))]
+    table = []
+    for gname, el in graphs:
+        s = torch.from_numpy(el.src).cuda()
+        d = torch.from_numpy(el.dst).cuda()
+        g = tc.Graph.build(s, d, el.n)
+        T = g.count()
+        cost, _ = g.order_cost()
+        for sc, name in enumerate(names):
+            g.count_partitioned(sc, parts)  # warm-up
+            best = float("inf")
+            for _ in range(3):
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                Tp, _, work = g.count_partitioned(sc, parts)
+                torch.cuda.synchronize()
+                best = min(best, time.perf_counter() - t0)
+                assert Tp == T, "partitioned count disagrees"
+            w = work.double()
+            row = {"graph": gname, "scheme": name, "parts": parts, "n": g.n, "m": g.m, "T": T, "sum_d_dhat": cost,
+                   "time_ms": 1e3 * best, "work_max_over_mean": float(w.max() / w.mean()) if w.mean() > 0 else None,
+                   "work_max": int(work.max()), "empty_parts": int((work == 0).sum())}
+            _log(f"[schemes] {row}")
+            table.append(row)
+        g.close()
+        del s, d
+        torch.cuda.empty_cache()
+    rm = {r["scheme"]: r for r in table if r["graph"] == "rmat"}
+    best = min(rm.values(), key=lambda r: r["time_ms"])
+    return {"metric": METRIC, "value": rm["N"]["m"] / (best["time_ms"] / 1e3), "unit": "oriented edges/s",
+            "n_gpus": 1, "steps": 3, "warmup": 1, "ms_per_step": best["time_ms"], "higher_is_better": True,
+            "scaling": "weak", "vs_baseline": None, "dtype": "int32", "data": "synthetic",
+            "config": {"workload": "load-balancing-schemes", "parts": parts,
+                       "graphs": "ER 2^20 deg 16, PA 2^20 k=8, R-MAT scale 22 ef 16", "parallelism": "single GPU"},
+            "rmat_time_ms_by_scheme": {k: v["time_ms"] for k, v in rm.items()},
+            "rmat_spread_by_scheme": {k: v["work_max_over_mean"] for k, v in rm.items()},
+            "table": table}
+
+
 def run(args):
     if args.workload == "batch":
         return run_batch(args)
     if args.workload == "orders":
         return run_orders(args)
+    if args.workload == "schemes":
+        return run_schemes(args)
     return run_serve(args)
