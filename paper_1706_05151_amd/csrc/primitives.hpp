@@ -162,28 +162,34 @@ struct u128 {
   uint64_t lo, hi;
 };
 
+// 9-bit digits: 512 bins, one per thread of a scatter block.
+constexpr int kRadixBits = 9;
+constexpr uint32_t kBins = 1u << kRadixBits;
+
+// The key's bits from `shift` up (the caller masks the digit width).
 template <typename K>
 struct RadixKey;
 
 template <>
 struct RadixKey<uint64_t> {
-  __device__ __forceinline__ static uint32_t digit(uint64_t k, int shift) {
-    return static_cast<uint32_t>(k >> shift) & 255u;
-  }
+  __device__ __forceinline__ static uint32_t bits(uint64_t k, int shift) { return static_cast<uint32_t>(k >> shift); }
 };
 
 template <>
 struct RadixKey<uint32_t> {
-  __device__ __forceinline__ static uint32_t digit(uint32_t k, int shift) { return (k >> shift) & 255u; }
+  __device__ __forceinline__ static uint32_t bits(uint32_t k, int shift) { return k >> shift; }
 };
 
 template <>
 struct RadixKey<u128> {
-  __device__ __forceinline__ static uint32_t digit(const u128& k, int shift) {
-    return shift < 64 ? static_cast<uint32_t>(k.lo >> shift) & 255u : static_cast<uint32_t>(k.hi >> (shift - 64)) & 255u;
+  __device__ __forceinline__ static uint32_t bits(const u128& k, int shift) {
+    if (shift >= 64) return static_cast<uint32_t>(k.hi >> (shift - 64));
+    if (shift == 0) return static_cast<uint32_t>(k.lo);
+    return static_cast<uint32_t>((k.lo >> shift) | (k.hi << (64 - shift)));
   }
 };
 
+// Keys per thread of the histogram pass (256 threads) and of a scatter tile.
 template <typename K>
 struct RadixItems;
 template <>
@@ -202,10 +208,11 @@ struct RadixItems<u128> {
 constexpr int kSortBlock = 256;
 constexpr int kSortWaves = kSortBlock / kWave;
 
-// Scatter passes run 512-thread blocks over the same tiles (keys per thread
-// halved), which doubles the resident waves at the same LDS per tile.
+// Scatter passes run 512-thread blocks (thread d owns digit d) over tiles of
+// 256 * RadixItems keys.
 constexpr int kScatterBlock = 512;
 constexpr int kScatterWaves = kScatterBlock / kWave;
+static_assert(kScatterBlock == static_cast<int>(kBins), "one digit per scatter thread");
 template <typename K>
 struct ScatterItems {
   static constexpr int value = RadixItems<K>::value * kSortBlock / kScatterBlock;
@@ -238,12 +245,12 @@ constexpr int kTagShift = 56;               // bits 56..61 hold the pass number 
 constexpr uint64_t kValMask = (1ull << kTagShift) - 1;
 constexpr uint32_t kSpinLimit = 1u << 22;   // polls of a not-yet-published word before giving up
 
-__device__ __forceinline__ uint32_t radix_digit_bits(int shift, int bit_hi) {
+__host__ __device__ __forceinline__ uint32_t radix_digit_mask(int shift, int bit_hi) {
   const int w = bit_hi - shift;
-  return w >= 8 ? 255u : (1u << w) - 1u;
+  return w >= kRadixBits ? kBins - 1u : (1u << w) - 1u;
 }
 
-// hist[p * 256 + d] += number of keys whose pass-p digit is d. The block's
+// hist[p * kBins + d] += number of keys whose pass-p digit is d. The block's
 // LDS counts are kept in `copies` interleaved copies (lane L adds to copy
 // L % copies), so lanes with equal digits hit different banks.
 template <typename K>
@@ -252,8 +259,8 @@ __global__ __launch_bounds__(kSortBlock) void k_sweep_hist(const K* __restrict__
                                                             uint32_t* __restrict__ hist) {
   constexpr int ITEMS = RadixItems<K>::value;
   constexpr int TILE = kSortBlock * ITEMS;
-  extern __shared__ uint32_t h[];  // passes * 256 * copies
-  const int nh = passes * 256 * copies;
+  extern __shared__ uint32_t h[];  // passes * kBins * copies
+  const int nh = passes * static_cast<int>(kBins) * copies;
   for (int i = threadIdx.x; i < nh; i += kSortBlock) h[i] = 0;
   __syncthreads();
   const uint32_t c = static_cast<uint32_t>(lane_id()) & static_cast<uint32_t>(copies - 1);
@@ -265,30 +272,30 @@ __global__ __launch_bounds__(kSortBlock) void k_sweep_hist(const K* __restrict__
       if (idx < N) k[i] = keys[idx];
     }
     for (int p = 0; p < passes; p++) {
-      const int shift = bit_lo + 8 * p;
-      const uint32_t dm = radix_digit_bits(shift, bit_hi);
+      const int shift = bit_lo + kRadixBits * p;
+      const uint32_t dm = radix_digit_mask(shift, bit_hi);
 #pragma unroll
       for (int i = 0; i < ITEMS; i++) {
         const size_t idx = base + static_cast<size_t>(i) * kSortBlock + threadIdx.x;
-        if (idx < N) atomicAdd(&h[(p * 256 + (RadixKey<K>::digit(k[i], shift) & dm)) * copies + c], 1u);
+        if (idx < N) atomicAdd(&h[(p * kBins + (RadixKey<K>::bits(k[i], shift) & dm)) * copies + c], 1u);
       }
     }
   }
   __syncthreads();
-  for (int i = threadIdx.x; i < passes * 256; i += kSortBlock) {
+  for (int i = threadIdx.x; i < passes * static_cast<int>(kBins); i += kSortBlock) {
     uint32_t t = 0;
     for (int x = 0; x < copies; x++) t += h[i * copies + x];
     if (t) atomicAdd(&hist[i], t);
   }
 }
 
-// In place: each pass's 256 counts become exclusive digit starts (one block per pass).
-static __global__ __launch_bounds__(kSortBlock) void k_sweep_starts(uint32_t* __restrict__ hist) {
-  __shared__ uint32_t tmp[kSortWaves];
-  uint32_t* h = hist + static_cast<size_t>(blockIdx.x) * 256;
+// In place: each pass's kBins counts become exclusive digit starts (one block per pass).
+static __global__ __launch_bounds__(kBins) void k_sweep_starts(uint32_t* __restrict__ hist) {
+  __shared__ uint32_t tmp[kBins / kWave];
+  uint32_t* h = hist + static_cast<size_t>(blockIdx.x) * kBins;
   const uint32_t x = h[threadIdx.x];
   uint32_t all;
-  const uint32_t ex = block_excl_scan<uint32_t, kSortBlock>(x, tmp, all);
+  const uint32_t ex = block_excl_scan<uint32_t, kBins>(x, tmp, all);
   h[threadIdx.x] = ex;
 }
 
@@ -303,38 +310,33 @@ __device__ __forceinline__ void status_store(uint64_t* p, uint64_t v) {
 struct NoVal {};
 
 // One pass. Wave w ranks the contiguous chunk [w*ITEMS*64, (w+1)*ITEMS*64)
-// of the tile among equal digits with wave-private counters (ballot match,
-// the lowest lane of each group updating the counter), so tile order is
+// of the tile among equal digits with wave-private 16-bit counters (ballot
+// match, the lowest lane of each group updating the counter), so tile order is
 // index order and the pass is stable. ctr[0] hands out tile indices; ctr[1]
 // is set if a look-back gave up. With a value type V, each key's value moves
 // with it (staged through the same LDS tile after the keys are written).
 template <typename K, typename V>
 __global__ __launch_bounds__(kScatterBlock) void k_sweep_scatter(const K* __restrict__ in, K* __restrict__ out,
-                                                               const V* __restrict__ vin, V* __restrict__ vout,
-                                                               uint32_t N, int shift, uint32_t dmask, uint64_t tag,
-                                                               const uint32_t* __restrict__ starts,
-                                                               uint64_t* __restrict__ status, uint32_t* __restrict__ ctr) {
+                                                                 const V* __restrict__ vin, V* __restrict__ vout,
+                                                                 uint32_t N, int shift, uint32_t dmask, uint64_t tag,
+                                                                 const uint32_t* __restrict__ starts,
+                                                                 uint64_t* __restrict__ status,
+                                                                 uint32_t* __restrict__ ctr) {
   constexpr bool kHasVal = !std::is_same<V, NoVal>::value;
   constexpr int ITEMS = ScatterItems<K>::value;
   constexpr int TILE = kScatterBlock * ITEMS;
   constexpr int CHUNK = kWave * ITEMS;
+  static_assert(CHUNK < 65536 && TILE < 65536, "16-bit tile counters");
   static_assert(!kHasVal || sizeof(V) <= sizeof(K), "values are staged in the key tile");
   __shared__ K tile[TILE];
-  // per-wave digit counts while ranking; afterwards (values only) the digit of each staged position
-  __shared__ union {
-    uint32_t wc[kScatterWaves][256];
-    uint8_t pdig[kHasVal ? TILE : 1];
-  } u;
-  auto& wc = u.wc;
-  auto& pdig = u.pdig;
-  __shared__ uint32_t dstart[256];
-  __shared__ uint32_t gbase[256];
+  __shared__ uint16_t wc[kScatterWaves][kBins];  // per-wave digit counts, then per-wave offsets inside a digit
+  __shared__ uint32_t dstart[kBins];
+  __shared__ uint32_t gbase[kBins];
   __shared__ uint32_t scan_tmp[kScatterWaves];
   __shared__ uint32_t s_tile;
   const int tid = threadIdx.x, w = tid / kWave, lane = lane_id();
-  const bool owner = tid < 256;  // thread tid owns digit tid
   if (tid == 0) s_tile = atomicAdd(&ctr[0], 1u);
-  for (int i = tid; i < kScatterWaves * 256; i += kScatterBlock) (&wc[0][0])[i] = 0;
+  for (int i = tid; i < kScatterWaves * static_cast<int>(kBins); i += kScatterBlock) (&wc[0][0])[i] = 0;
   __syncthreads();
   const uint32_t t = s_tile;
   const size_t base = static_cast<size_t>(t) * TILE;
@@ -342,17 +344,14 @@ __global__ __launch_bounds__(kScatterBlock) void k_sweep_scatter(const K* __rest
   K key[ITEMS];
   uint32_t rk[ITEMS];
   uint32_t dg[ITEMS];
-  uint32_t* cnt = wc[w];
-  // Rank of each key among the equal digits of its wave chunk so far; lanes
-  // with equal digits are matched by ballots over the digit bits (plus a
-  // validity bit in a partial tile).
+  uint16_t* cnt = wc[w];
   auto rank_item = [&](int i, uint32_t d, uint64_t peers, bool valid) {
     const uint32_t lr = static_cast<uint32_t>(__popcll(peers & lanemask_lt()));
     const int leader = __ffsll(static_cast<long long>(peers)) - 1;
     uint32_t old = 0;
     if (valid && lr == 0) {
       old = cnt[d];
-      cnt[d] = old + static_cast<uint32_t>(__popcll(peers));
+      cnt[d] = static_cast<uint16_t>(old + static_cast<uint32_t>(__popcll(peers)));
     }
     old = __shfl(old, leader, kWave);
     dg[i] = d;
@@ -360,15 +359,15 @@ __global__ __launch_bounds__(kScatterBlock) void k_sweep_scatter(const K* __rest
     __builtin_amdgcn_wave_barrier();
   };
   const K* chunk = in + base + static_cast<size_t>(w) * CHUNK;
-  if (base + TILE <= N) {  // full tile (wave-uniform): no bounds checks, 8 ballots
+  if (base + TILE <= N) {  // full tile (wave-uniform): no bounds checks, one ballot per digit bit
 #pragma unroll
     for (int i = 0; i < ITEMS; i++) key[i] = chunk[i * kWave + lane];
 #pragma unroll
     for (int i = 0; i < ITEMS; i++) {
-      const uint32_t d = RadixKey<K>::digit(key[i], shift) & dmask;
-      rank_item(i, d, match_any<8>(d), true);
+      const uint32_t d = RadixKey<K>::bits(key[i], shift) & dmask;
+      rank_item(i, d, match_any<kRadixBits>(d), true);
     }
-  } else {
+  } else {  // partial tile: a validity bit joins the match
 #pragma unroll
     for (int i = 0; i < ITEMS; i++) {
       const size_t idx = base + static_cast<size_t>(w) * CHUNK + static_cast<size_t>(i) * kWave + lane;
@@ -379,70 +378,68 @@ __global__ __launch_bounds__(kScatterBlock) void k_sweep_scatter(const K* __rest
     for (int i = 0; i < ITEMS; i++) {
       const size_t idx = base + static_cast<size_t>(w) * CHUNK + static_cast<size_t>(i) * kWave + lane;
       const bool valid = idx < N;
-      const uint32_t d = valid ? (RadixKey<K>::digit(key[i], shift) & dmask) : 256u;
-      rank_item(i, d, match_any<9>(d), valid);
+      const uint32_t d = valid ? (RadixKey<K>::bits(key[i], shift) & dmask) : kBins;
+      rank_item(i, d, match_any<kRadixBits + 1>(d), valid);
     }
   }
   __syncthreads();
-  // digit owners: per-wave offsets inside the digit, and the tile's count
+  // thread tid owns digit tid: per-wave offsets inside the digit, and the tile's count
   uint32_t tot = 0;
   uint64_t excl = 0;
-  if (owner) {
 #pragma unroll
-    for (int x = 0; x < kScatterWaves; x++) {
-      const uint32_t c = wc[x][tid];
-      wc[x][tid] = tot;
-      tot += c;
-    }
-    uint64_t* mine = status + static_cast<size_t>(t) * 256 + tid;
-    if (t == 0) {
-      status_store(mine, kKindInc | tag | tot);
-    } else {
-      status_store(mine, kKindAgg | tag | tot);
-      uint32_t j = t - 1;
-      uint32_t polls = 0;
-      for (;;) {
-        const uint64_t v = status_load(status + static_cast<size_t>(j) * 256 + tid);
-        const uint64_t kind = v & kKindMask;
-        if (kind == 0 || (v & ~kKindMask & ~kValMask) != tag) {
-          if (++polls > kSpinLimit) {
-            atomicOr(&ctr[1], 1u);
-            break;
-          }
-          __builtin_amdgcn_s_sleep(1);
-          continue;
+  for (int x = 0; x < kScatterWaves; x++) {
+    const uint32_t c = wc[x][tid];
+    wc[x][tid] = static_cast<uint16_t>(tot);
+    tot += c;
+  }
+  uint64_t* mine = status + static_cast<size_t>(t) * kBins + tid;
+  if (t == 0) {
+    status_store(mine, kKindInc | tag | tot);
+  } else {
+    status_store(mine, kKindAgg | tag | tot);
+    uint32_t j = t - 1;
+    uint32_t polls = 0;
+    for (;;) {
+      const uint64_t v = status_load(status + static_cast<size_t>(j) * kBins + tid);
+      const uint64_t kind = v & kKindMask;
+      if (kind == 0 || (v & ~kKindMask & ~kValMask) != tag) {
+        if (++polls > kSpinLimit) {
+          atomicOr(&ctr[1], 1u);
+          break;
         }
-        excl += v & kValMask;
-        if (kind == kKindInc || j == 0) break;
-        --j;
+        __builtin_amdgcn_s_sleep(1);
+        continue;
       }
-      status_store(mine, kKindInc | tag | (excl + tot));
+      excl += v & kValMask;
+      if (kind == kKindInc || j == 0) break;
+      --j;
     }
+    status_store(mine, kKindInc | tag | (excl + tot));
   }
   uint32_t all;
   const uint32_t ds = block_excl_scan<uint32_t, kScatterBlock>(tot, scan_tmp, all);
-  if (owner) {
-    dstart[tid] = ds;
-    gbase[tid] = starts[tid] + static_cast<uint32_t>(excl);
-  }
+  dstart[tid] = ds;
+  gbase[tid] = starts[tid] + static_cast<uint32_t>(excl);
   __syncthreads();
 #pragma unroll
   for (int i = 0; i < ITEMS; i++) {
-    if (dg[i] < 256u) {
+    if (dg[i] < kBins) {
       rk[i] += dstart[dg[i]] + wc[w][dg[i]];  // the key's position in the staged tile
       tile[rk[i]] = key[i];
     }
   }
   __syncthreads();
   const uint32_t count = static_cast<uint32_t>(N - base < static_cast<size_t>(TILE) ? N - base : TILE);
+  uint32_t gpos[kHasVal ? ITEMS : 1];  // output position of staged position i * kScatterBlock + tid
 #pragma unroll
   for (int i = 0; i < ITEMS; i++) {
     const uint32_t j = static_cast<uint32_t>(i * kScatterBlock + tid);
     if (j < count) {
       const K k = tile[j];
-      const uint32_t d = RadixKey<K>::digit(k, shift) & dmask;
-      out[gbase[d] + (j - dstart[d])] = k;
-      if constexpr (kHasVal) pdig[j] = static_cast<uint8_t>(d);
+      const uint32_t d = RadixKey<K>::bits(k, shift) & dmask;
+      const uint32_t g = gbase[d] + (j - dstart[d]);
+      out[g] = k;
+      if constexpr (kHasVal) gpos[i] = g;
     }
   }
   if constexpr (kHasVal) {
@@ -451,16 +448,13 @@ __global__ __launch_bounds__(kScatterBlock) void k_sweep_scatter(const K* __rest
 #pragma unroll
     for (int i = 0; i < ITEMS; i++) {
       const size_t idx = base + static_cast<size_t>(w) * CHUNK + static_cast<size_t>(i) * kWave + lane;
-      if (dg[i] < 256u) vt[rk[i]] = vin[idx];
+      if (dg[i] < kBins) vt[rk[i]] = vin[idx];
     }
     __syncthreads();
 #pragma unroll
     for (int i = 0; i < ITEMS; i++) {
       const uint32_t j = static_cast<uint32_t>(i * kScatterBlock + tid);
-      if (j < count) {
-        const uint32_t d = pdig[j];
-        vout[gbase[d] + (j - dstart[d])] = vt[j];
-      }
+      if (j < count) vout[gpos[i]] = vt[j];
     }
   }
 }
@@ -472,7 +466,7 @@ __global__ void k_fill_words(T* __restrict__ p, size_t n, T v) {
     p[i] = v;
 }
 
-// Sorts N keys ascending by bits [bit_lo, bit_hi) (8-bit digits, stable),
+// Sorts N keys ascending by bits [bit_lo, bit_hi) (9-bit digits, stable),
 // each value in `vals` moving with its key. Uses `keys`/`tmp` and
 // `vals`/`vtmp` as ping-pong buffers; returns the key buffer holding the
 // result and points `vals` at the value buffer holding the result.
@@ -482,37 +476,37 @@ K* radix_sort_pairs(K* keys, K* tmp, V*& vals, V* vtmp, size_t N, int bit_lo, in
   if (N <= 1 || bit_hi <= bit_lo) return keys;
   if (N >= (1ull << 32)) fail(TC_E_INVAL, "radix_sort: more than 2^32 - 1 keys");
   constexpr int TILE = kScatterBlock * ScatterItems<K>::value;
-  const int passes = (bit_hi - bit_lo + 7) / 8;
+  const int passes = (bit_hi - bit_lo + kRadixBits - 1) / kRadixBits;
   if (passes > kMaxPasses) fail(TC_E_INVAL, "radix_sort: bit range too wide");
   const uint32_t tiles = static_cast<uint32_t>((N + TILE - 1) / TILE);
-  // words: passes*256 histogram/starts, then per pass {tile counter, look-back failure flag}
-  const size_t nwords = static_cast<size_t>(passes) * 256 + 2 * passes;
+  // words: passes*kBins histogram/starts, then per pass {tile counter, look-back failure flag}
+  const size_t nwords = static_cast<size_t>(passes) * kBins + 2 * passes;
   DevBuf<uint32_t> words(nwords, s);
-  DevBuf<uint64_t> status(static_cast<size_t>(tiles) * 256, s);
+  DevBuf<uint64_t> status(static_cast<size_t>(tiles) * kBins, s);
   k_fill_words<uint32_t><<<grid_for(nwords, 256, 64), 256, 0, s>>>(words.get(), nwords, 0u);
   TC_LAUNCH_CHECK();
-  k_fill_words<uint64_t><<<grid_for(static_cast<uint64_t>(tiles) * 256, 256, 8192), 256, 0, s>>>(
-      status.get(), static_cast<size_t>(tiles) * 256, 0ull);
+  k_fill_words<uint64_t><<<grid_for(static_cast<uint64_t>(tiles) * kBins, 256, 8192), 256, 0, s>>>(
+      status.get(), static_cast<size_t>(tiles) * kBins, 0ull);
   TC_LAUNCH_CHECK();
   uint32_t* hist = words.get();
-  uint32_t* ctrs = hist + static_cast<size_t>(passes) * 256;
-  const int copies = passes <= 8 ? 8 : 4;  // LDS: passes * 256 * copies words <= 64 KiB
-  k_sweep_hist<K><<<tiles < 2048u ? tiles : 2048u, kSortBlock, static_cast<size_t>(passes) * 256 * copies * 4, s>>>(
+  uint32_t* ctrs = hist + static_cast<size_t>(passes) * kBins;
+  const int copies = passes <= 8 ? 4 : 2;  // LDS: passes * kBins * copies words <= 64 KiB
+  k_sweep_hist<K><<<tiles < 2048u ? tiles : 2048u, kSortBlock, static_cast<size_t>(passes) * kBins * copies * 4, s>>>(
       keys, static_cast<uint32_t>(N), bit_lo, bit_hi, passes, copies, hist);
   TC_LAUNCH_CHECK();
-  k_sweep_starts<<<passes, kSortBlock, 0, s>>>(hist);
+  k_sweep_starts<<<passes, kBins, 0, s>>>(hist);
   TC_LAUNCH_CHECK();
   K* a = keys;
   K* b = tmp;
   V* va = vals;
   V* vb = vtmp;
   for (int p = 0; p < passes; p++) {
-    const int shift = bit_lo + 8 * p;
-    const int w = bit_hi - shift;
-    const uint32_t dmask = w >= 8 ? 255u : (1u << w) - 1u;
-    k_sweep_scatter<K, V><<<tiles, kScatterBlock, 0, s>>>(a, b, va, vb, static_cast<uint32_t>(N), shift, dmask,
-                                                       static_cast<uint64_t>(p + 1) << kTagShift,
-                                                       hist + static_cast<size_t>(p) * 256, status.get(), ctrs + 2 * p);
+    const int shift = bit_lo + kRadixBits * p;
+    k_sweep_scatter<K, V><<<tiles, kScatterBlock, 0, s>>>(a, b, va, vb, static_cast<uint32_t>(N), shift,
+                                                          radix_digit_mask(shift, bit_hi),
+                                                          static_cast<uint64_t>(p + 1) << kTagShift,
+                                                          hist + static_cast<size_t>(p) * kBins, status.get(),
+                                                          ctrs + 2 * p);
     TC_LAUNCH_CHECK();
     std::swap(a, b);
     std::swap(va, vb);
