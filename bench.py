@@ -15,7 +15,11 @@ Other workloads (--workload): er10k (G(10^4, 0.0016) seed 1), ba22 (PA n=2^22,
 k=8, seed 2; count + per-node + clustering + list), batch (4096 mixed small
 graphs in one launch), serve (open-loop Poisson serving), orders (the same
 graphs oriented by degree, id, random, reversed degree and coreness), schemes
-(the Section 5 load-balancing cost schemes, one id range per workgroup).
+(the Section 5 load-balancing cost schemes, one id range per workgroup), shards
+(the R-MAT graph's core nodes in --shards ranges, each counted with its own
+plan: one GPU's share of a sharded count), sampling (one sample against
+independent per-shard samples, Section 7), streamed (the rank-space CSR in
+pinned host memory counted under device-memory budgets, Section 6 partitions).
 """
 from __future__ import annotations
 
@@ -239,8 +243,10 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="rmat",
-                    choices=["rmat", "ba22", "er10k", "batch", "serve", "orders", "schemes"])
+                    choices=["rmat", "ba22", "er10k", "batch", "serve", "orders", "schemes", "shards", "sampling",
+                             "streamed"])
     ap.add_argument("--parts", type=int, default=1024, help="id ranges for --workload schemes")
+    ap.add_argument("--shards", type=int, default=8, help="core-node shards for --workload shards / sampling")
     ap.add_argument("--scale", type=int, default=26, help="R-MAT scale for --workload rmat")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -263,7 +269,7 @@ def main():
         log(f"[bench] calibration copy of {nbytes} bytes done")
         del a, b
         torch.cuda.empty_cache()
-    if args.workload in ("batch", "serve", "orders", "schemes"):
+    if args.workload in ("batch", "serve", "orders", "schemes", "shards", "sampling", "streamed"):
         from paper_1706_05151_amd import workloads
 
         out = workloads.run(args)

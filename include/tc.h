@@ -166,6 +166,94 @@ tc_status tc_count_partitioned(tc_graph* g, void* stream, int32_t scheme, int32_
 tc_status tc_graph_coreness(tc_graph* g, void* stream, int32_t* core_dev);
 
 /*
+ * The orientation order as positions: order_dev int32[n] gets, at position r,
+ * the caller id of the vertex ranked r-th (0 first) in the total order the
+ * graph was oriented by (Eq. (1) for the degree order). Caller-owned device
+ * memory. Synchronises `stream`.
+ */
+tc_status tc_graph_order(tc_graph* g, void* stream, int32_t* order_dev);
+
+/*
+ * One GPU's share of a sharded count (the overlapping partitions of Section 5
+ * with the whole oriented graph resident): shard j holds the core nodes with
+ * positions [bounds[j], bounds[j+1]) in the orientation order. The boundaries
+ * follow the rule x_j = argmin_v F(v) >= j*alpha, alpha = F(n-1)/k (compared
+ * exactly as F(v)*k >= j*F(n-1)), over positions, with F the prefix sum of
+ * f(v) = sum_{u in N_v} (dhat_v + dhat_u) (the cost-function table of
+ * Section 5, the merge cost of Theorem 2). bounds is host int32[k+1], with
+ * bounds[0] = 0 and bounds[k] = n. TC_E_INVAL for k < 1 or NULL arguments.
+ * Synchronises `stream`.
+ */
+tc_status tc_shard_bounds(tc_graph* g, void* stream, int32_t k, int32_t* bounds);
+
+/*
+ * The triangles counted by the shard whose core nodes have positions [lo, hi)
+ * in the orientation order: sum over those v of sum_{u in N_v} |N_v ∩ N_u|
+ * (NodeIteratorN restricted to the core nodes, each triangle counted at its
+ * lowest vertex, Theorem 1), into *T (host). The shards of tc_shard_bounds
+ * add up to tc_count. The shard's work plan (its in-edge records and items)
+ * is built on the first call for a range and kept on the graph until a call
+ * for another range. TC_E_RANGE unless 0 <= lo <= hi <= n. Works on sampled
+ * graphs. Synchronises `stream`.
+ */
+tc_status tc_count_shard(tc_graph* g, void* stream, int32_t lo, int32_t hi, uint64_t* T);
+
+/*
+ * Sparsification with overlapping partitions (Section 7, parallel
+ * sparsification; Eq. var2): the core nodes are split into `parts` shards as
+ * in tc_shard_bounds, and shard i keeps each edge it uses independently of the
+ * other shards, with the keep rule of tc_sparsify_count under the seed
+ * seed_i = output i+1 of SplitMix64 started at `seed` (seed + (i+1)*
+ * 0x9E3779B97F4A7C15, then the SplitMix64 finaliser). Shard i counts the
+ * triangles of its own sample whose lowest vertex is one of its core nodes.
+ * The estimate sum_i T_i / q^3 is unbiased; its variance is
+ * (1/q^3 - 1) T + 2 k' (1/q - 1) with k' the pairs of triangles sharing an
+ * edge whose lowest vertices lie in one shard. Outputs (each may be NULL):
+ * T_parts host uint64[parts], bounds host int32[parts+1], *T_sampled the sum,
+ * *estimate. parts = 1 gives the same sample as tc_sparsify_count with seed
+ * seed_0. TC_E_RANGE for q outside (0,1]; TC_E_INVAL for parts < 1 or a
+ * sampled graph. Synchronises `stream`.
+ */
+tc_status tc_sparsify_count_partitioned(tc_graph* g, double q, uint64_t seed, int32_t parts, void* stream,
+                                        uint64_t* T_parts, int32_t* bounds, uint64_t* T_sampled, double* estimate);
+
+/*
+ * The oriented CSR in rank space, the input of tc_count_streamed: off int64[n+1]
+ * and adj int32[m], row r holding the ranks after r adjacent to the r-th vertex
+ * of the orientation order, ascending. Either pointer may be NULL; each may be
+ * host or device memory (copied with hipMemcpyDefault). For a batch, the
+ * ranks of all graphs together. Synchronises `stream`.
+ */
+tc_status tc_graph_export_csr(tc_graph* g, void* stream, int64_t* off, int32_t* adj);
+
+/*
+ * Exact T of an oriented CSR kept in host memory, streamed through the GPU
+ * under a device-memory budget (the non-overlapping partitions of Section 6,
+ * with the surrogate pairing). The rows are split into pivot partitions V_j
+ * and source chunks, each sized to about half of budget_bytes. The rows of
+ * each V_j are loaded once. Every chunk of rows that start before the end of
+ * V_j is then shipped to it once (N_v goes to the owner of u once per chunk,
+ * not once per edge). There the in-edge records (v,u), u in V_j, count
+ * |N_v after u ∩ N_u| with the pivot kernel. Each triangle is counted once,
+ * at the partition of its middle vertex. The next chunk is copied in while
+ * the current one is counted.
+ *
+ * Input: off host int64[n+1] with off[0] = 0 and off[n] = m; adj int32[m]
+ * (host, pinned for full copy speed, or device memory). Row r must hold
+ * strictly ascending values in (r, n): a rank-space CSR such as
+ * tc_graph_export_csr writes. The offsets are checked on the host and the
+ * rows on the device before they are counted. A violation gives TC_E_INVAL,
+ * as do off in device memory, NULL
+ * arguments and budget_bytes < 4096. TC_E_NOMEM if one row alone does not fit
+ * half the budget. The budget covers the copies, records and plans; the
+ * kernel's counters come on top. Output: *T. info (may be NULL) gets uint64[4]:
+ * pivot partitions, chunks, (partition, chunk) pairs visited, bytes copied to
+ * the device. Runs on the current device. Synchronises `stream`.
+ */
+tc_status tc_count_streamed(const int64_t* off, const int32_t* adj, int32_t n, int64_t m, uint64_t budget_bytes,
+                            void* stream, uint64_t* T, uint64_t* info);
+
+/*
  * Export the degree data in the caller's ids: deg_dev int32[n] = d_v and
  * dhat_dev int32[n] = |N_v| (effective degree, Section 3). Either may be NULL.
  */

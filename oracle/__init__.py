@@ -15,7 +15,11 @@ Routes (each function cites the passage it follows):
   * clustering coefficients of Section 2 — ``clustering``;
   * sparsification of Section 7 — ``sparsify`` and ``estimate``;
   * the k-core order of Section 4 — ``coreness``;
-  * the load-balancing schemes of Sections 5 and 6 — ``partition_work``.
+  * the load-balancing schemes of Sections 5 and 6 — ``partition_work``;
+  * core-node shards over the orientation order (Section 5 partitions) —
+    ``order_positions``, ``shard_bounds``, ``count_nin_pos_range``;
+  * sparsification with independent per-shard samples (Section 7, Eq. var2) —
+    ``partition_seed``, ``sparsified_count_partitioned``.
 """
 from __future__ import annotations
 
@@ -72,6 +76,10 @@ def _load():
         "orc_num_threads": ([], ctypes.c_int),
         "orc_coreness": ([vp, vp, i32, vp], None),
         "orc_partition_work": ([vp, vp, vp, i32, ctypes.c_int, i32, vp, vp], None),
+        "orc_order_positions": ([vp, i32, vp], None),
+        "orc_shard_bounds": ([vp, vp, i32, vp, i32, vp], None),
+        "orc_count_nin_pos_range": ([vp, vp, i32, vp, i32, i32], u64),
+        "orc_partition_seed": ([u64, i32], u64),
     }
     for name, (args, res) in sig.items():
         f = getattr(L, name)
@@ -198,6 +206,34 @@ def count_nin_range(off, adj, v0: int, v1: int) -> int:
     return int(_load().orc_count_nin_range(_p(off), _p(adj), v0, v1))
 
 
+def order_positions(key, n: int) -> np.ndarray:
+    """Position of every vertex in the total order by (key, id) ascending (Eq. (1) with key = degree); int32[n]."""
+    key = np.ascontiguousarray(key, dtype=np.int64)
+    pos = np.zeros(max(n, 1), np.int32)
+    _load().orc_order_positions(_p(key), n, _p(pos))
+    return pos[:n]
+
+
+def shard_bounds(off, adj, n: int, pos, k: int) -> np.ndarray:
+    """Boundary positions of k core-node shards: the rule x_j = argmin F >= j*alpha over positions,
+    f(v) = sum_{u in N_v} (dhat_v + dhat_u) (Section 5 cost-function table); int64[k+1]."""
+    pos = _i32(pos)
+    bounds = np.zeros(k + 1, np.int64)
+    _load().orc_shard_bounds(_p(off), _p(adj), n, _p(pos), k, _p(bounds))
+    return bounds
+
+
+def count_nin_pos_range(off, adj, n: int, pos, p0: int, p1: int) -> int:
+    """NodeIteratorN over the core nodes whose position lies in [p0, p1) (triangles by lowest vertex)."""
+    pos = _i32(pos)
+    return int(_load().orc_count_nin_pos_range(_p(off), _p(adj), n, _p(pos), p0, p1))
+
+
+def partition_seed(seed: int, i: int) -> int:
+    """Output i+1 of SplitMix64 started at seed: the seed of shard i's sample."""
+    return int(_load().orc_partition_seed(int(seed) & (2 ** 64 - 1), i))
+
+
 def work(off, adj, n: int) -> int:
     """W = sum over oriented edges (v,u) of (dhat_v + dhat_u) (Theorem 2)."""
     return int(_load().orc_work(_p(off), _p(adj), n))
@@ -297,3 +333,20 @@ def sparsified_count(lo, hi, deg, n: int, q: float, seed: int):
     off, adj = orient(klo, khi, deg, n)
     Ts, _, _ = count_nin(off, adj, n)
     return Ts, int(klo.shape[0]), estimate(Ts, q)
+
+
+def sparsified_count_partitioned(lo, hi, deg, n: int, q: float, seed: int, parts: int):
+    """Section 7 sparsification with overlapping partitions: the core nodes are split into
+    `parts` shards (``shard_bounds`` on the degree-ordered graph); shard i keeps each edge
+    independently under ``partition_seed(seed, i)`` and counts the triangles of its sample
+    whose lowest vertex is one of its core nodes. Returns (T_parts, bounds, sum, estimate)."""
+    off, adj = orient(lo, hi, deg, n)
+    pos = order_positions(deg, n)
+    bounds = shard_bounds(off, adj, n, pos, parts)
+    T_parts = []
+    for i in range(parts):
+        klo, khi = sparsify(lo, hi, q, partition_seed(seed, i))
+        soff, sadj = orient(klo, khi, deg, n)
+        T_parts.append(count_nin_pos_range(soff, sadj, n, pos, int(bounds[i]), int(bounds[i + 1])))
+    Ts = sum(T_parts)
+    return T_parts, bounds, Ts, estimate(Ts, q)

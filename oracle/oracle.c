@@ -354,6 +354,81 @@ uint64_t orc_count_nin_range(const int64_t* off, const int32_t* adj, int32_t v0,
   return T;
 }
 
+/* ------------------------------------------------------------- shards --- */
+
+static const int64_t* g_pos_key; /* key of the qsort below (single-threaded use) */
+static int cmp_by_key_then_id(const void* a, const void* b) {
+  int32_t x = *(const int32_t*)a, y = *(const int32_t*)b;
+  if (g_pos_key[x] != g_pos_key[y]) return g_pos_key[x] < g_pos_key[y] ? -1 : 1;
+  return (x > y) - (x < y);
+}
+
+/*
+ * Positions in a total order given by a key per vertex, ties by smaller id
+ * (Eq. (1) when the key is the degree): pos[v] = number of vertices that
+ * precede v.
+ */
+void orc_order_positions(const int64_t* key, int32_t n, int32_t* pos) {
+  int32_t* ids = (int32_t*)malloc(sizeof(int32_t) * (size_t)(n > 0 ? n : 1));
+  for (int32_t v = 0; v < n; v++) ids[v] = v;
+  g_pos_key = key;
+  qsort(ids, (size_t)n, sizeof(int32_t), cmp_by_key_then_id);
+  for (int32_t r = 0; r < n; r++) pos[ids[r]] = r;
+  free(ids);
+}
+
+/*
+ * Core-node shards over positions (the overlapping partitions of Section 5
+ * with the partitioning done on the orientation order): f at position pos[v]
+ * is sum_{u in N_v} (dhat_v + dhat_u) (cost-function table), F its inclusive
+ * prefix over positions, and bounds[j] (0 < j < k) the first position p with
+ * F(p)*k >= j*F(n-1) (the boundary rule x_j = argmin F >= j*alpha, exactly);
+ * bounds[0] = 0, bounds[k] = n.
+ */
+void orc_shard_bounds(const int64_t* off, const int32_t* adj, int32_t n, const int32_t* pos, int32_t k,
+                      int64_t* bounds) {
+  uint64_t* f = (uint64_t*)calloc((size_t)(n > 0 ? n : 1), sizeof(uint64_t));
+  for (int32_t v = 0; v < n; v++) {
+    uint64_t dv = (uint64_t)(off[v + 1] - off[v]), x = 0;
+    for (int64_t j = off[v]; j < off[v + 1]; j++) {
+      int32_t u = adj[j];
+      x += dv + (uint64_t)(off[u + 1] - off[u]);
+    }
+    f[pos[v]] = x;
+  }
+  uint64_t total = 0;
+  for (int32_t p = 0; p < n; p++) total += f[p];
+  bounds[0] = 0;
+  bounds[k] = n;
+  for (int32_t j = 1; j < k; j++) {
+    uint64_t F = 0;
+    int32_t x = n;
+    for (int32_t p = 0; p < n; p++) {
+      F += f[p];
+      if ((unsigned __int128)F * (unsigned)k >= (unsigned __int128)total * (unsigned)j) { x = p; break; }
+    }
+    bounds[j] = x;
+  }
+  free(f);
+}
+
+/*
+ * The counting loop of NodeIteratorN over the core nodes v whose position
+ * lies in [p0, p1): each triangle is counted once, at its lowest vertex.
+ */
+uint64_t orc_count_nin_pos_range(const int64_t* off, const int32_t* adj, int32_t n, const int32_t* pos,
+                                 int32_t p0, int32_t p1) {
+  uint64_t T = 0;
+  for (int32_t v = 0; v < n; v++) {
+    if (pos[v] < p0 || pos[v] >= p1) continue;
+    for (int64_t k = off[v]; k < off[v + 1]; k++) {
+      int32_t u = adj[k];
+      T += (uint64_t)merge_count(adj + off[v], off[v + 1] - off[v], adj + off[u], off[u + 1] - off[u]);
+    }
+  }
+  return T;
+}
+
 /* Merge work of Theorem 2: W = sum over oriented edges (v,u) of (dhat_v + dhat_u). */
 uint64_t orc_work(const int64_t* off, const int32_t* adj, int32_t n) {
   uint64_t W = 0;
@@ -434,6 +509,15 @@ int orc_keep(int32_t a, int32_t b, double q, uint64_t seed) {
   uint64_t h = orc_splitmix64_finalizer(orc_splitmix64_finalizer(seed ^ ORC_SPARSIFY_DOMAIN) ^
                                         (((uint64_t)(uint32_t)a << 32) | (uint32_t)b));
   return h < orc_keep_threshold(q);
+}
+
+/*
+ * Seed of shard i's independent sample: output i+1 of the SplitMix64
+ * generator (Steele, Lea and Flood, 2014) started at `seed`, i.e. the
+ * finaliser applied to seed + (i+1) * 0x9E3779B97F4A7C15.
+ */
+uint64_t orc_partition_seed(uint64_t seed, int32_t i) {
+  return orc_splitmix64_finalizer(seed + (uint64_t)(i + 1) * 0x9E3779B97F4A7C15ULL);
 }
 
 /* Retained subset of the unique edges lo<hi; returns m'. */

@@ -10,7 +10,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OUT_DIR = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libtc.so")
-SOURCES = ["build.hip", "count.hip", "api.hip", "memory.hip"]
+SOURCES = ["build.hip", "count.hip", "stream.hip", "api.hip", "memory.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"

@@ -404,6 +404,123 @@ tc_status tc_graph_coreness(tc_graph* g, void* stream, int32_t* core_dev) {
   });
 }
 
+tc_status tc_shard_bounds(tc_graph* g, void* stream, int32_t k, int32_t* bounds) {
+  return guarded([&] {
+    require(g != nullptr && bounds != nullptr, TC_E_INVAL, "NULL argument");
+    require(k >= 1, TC_E_INVAL, "k < 1");
+    DeviceScope ds(g->device);
+    const hipStream_t s = as_stream(stream);
+    DevBuf<int64_t> b(static_cast<size_t>(k) + 1, s);
+    shard_bounds(g->csr, k, b.get(), s);
+    std::vector<int64_t> h(static_cast<size_t>(k) + 1);
+    TC_HIP(hipMemcpyAsync(h.data(), b.get(), h.size() * sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    TC_HIP(hipStreamSynchronize(s));
+    for (int32_t j = 0; j <= k; j++) bounds[j] = static_cast<int32_t>(h[j]);
+  });
+}
+
+tc_status tc_count_shard(tc_graph* g, void* stream, int32_t lo, int32_t hi, uint64_t* T) {
+  return guarded([&] {
+    require(g != nullptr && T != nullptr, TC_E_INVAL, "NULL argument");
+    require(lo >= 0 && lo <= hi && hi <= g->n, TC_E_RANGE, "rank range outside [0, n]");
+    DeviceScope ds(g->device);
+    const hipStream_t s = as_stream(stream);
+    DevBuf<unsigned long long> tot(1, s);
+    fill_u64(tot.get(), 1, 0ull, s);
+    {
+      std::lock_guard<std::mutex> lk(g->mu);
+      count_shard(g->csr, lo, hi, tot.get(), s, get_options());
+    }
+    unsigned long long h = 0;
+    TC_HIP(hipMemcpyAsync(&h, tot.get(), sizeof(h), hipMemcpyDeviceToHost, s));
+    TC_HIP(hipStreamSynchronize(s));
+    *T = h;
+  });
+}
+
+// Output i + 1 of the SplitMix64 generator (Steele, Lea and Flood, 2014)
+// started at `seed`: the seed of partition i's sample.
+static uint64_t partition_seed(uint64_t seed, int32_t i) {
+  uint64_t z = seed + static_cast<uint64_t>(i + 1) * 0x9E3779B97F4A7C15ull;
+  z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ull;
+  z = (z ^ (z >> 27)) * 0x94d049bb133111ebull;
+  return z ^ (z >> 31);
+}
+
+tc_status tc_sparsify_count_partitioned(tc_graph* g, double q, uint64_t seed, int32_t parts, void* stream,
+                                        uint64_t* T_parts, int32_t* bounds, uint64_t* T_sampled, double* estimate) {
+  return guarded([&] {
+    require(g != nullptr, TC_E_INVAL, "graph is NULL");
+    require(!g->sampled, TC_E_INVAL, "cannot sample a sampled graph");
+    require(q > 0.0 && q <= 1.0, TC_E_RANGE, "q outside (0, 1]");
+    require(parts >= 1, TC_E_INVAL, "parts < 1");
+    DeviceScope ds(g->device);
+    const hipStream_t s = as_stream(stream);
+    const Options o = get_options();
+    std::vector<int64_t> hb(static_cast<size_t>(parts) + 1);
+    {
+      DevBuf<int64_t> b(hb.size(), s);
+      shard_bounds(g->csr, parts, b.get(), s);
+      TC_HIP(hipMemcpyAsync(hb.data(), b.get(), hb.size() * sizeof(int64_t), hipMemcpyDeviceToHost, s));
+      TC_HIP(hipStreamSynchronize(s));
+    }
+    DevBuf<unsigned long long> t(static_cast<size_t>(parts), s);
+    fill_u64(t.get(), static_cast<size_t>(parts), 0ull, s);
+    for (int32_t i = 0; i < parts; i++) {
+      const int32_t lo = static_cast<int32_t>(hb[i]), hi = static_cast<int32_t>(hb[i + 1]);
+      if (lo == hi) continue;
+      // partition i samples every edge it can reach on its own: the rows of
+      // ranks >= lo (its core nodes and all later vertices)
+      Csr sampled;
+      build_sampled_csr(g, q, partition_seed(seed, i), sampled, s, lo);
+      count_shard(sampled, lo, hi, t.get() + i, s, o);
+      TC_HIP(hipStreamSynchronize(s));
+    }
+    std::vector<unsigned long long> ht(static_cast<size_t>(parts));
+    TC_HIP(hipMemcpyAsync(ht.data(), t.get(), ht.size() * sizeof(unsigned long long), hipMemcpyDeviceToHost, s));
+    TC_HIP(hipStreamSynchronize(s));
+    unsigned long long sum = 0;
+    for (int32_t i = 0; i < parts; i++) {
+      sum += ht[i];
+      if (T_parts) T_parts[i] = ht[i];
+    }
+    if (bounds)
+      for (int32_t j = 0; j <= parts; j++) bounds[j] = static_cast<int32_t>(hb[j]);
+    if (T_sampled) *T_sampled = sum;
+    if (estimate) *estimate = static_cast<double>(sum) / ((q * q) * q);
+  });
+}
+
+tc_status tc_count_streamed(const int64_t* off, const int32_t* adj, int32_t n, int64_t m, uint64_t budget_bytes,
+                            void* stream, uint64_t* T, uint64_t* info) {
+  return guarded([&] {
+    require(off != nullptr && T != nullptr && (adj != nullptr || m == 0), TC_E_INVAL, "NULL argument");
+    require(n >= 0 && m >= 0, TC_E_INVAL, "negative size");
+    require(budget_bytes >= 4096, TC_E_INVAL, "budget below 4096 bytes");
+    hipPointerAttribute_t at{};
+    if (hipPointerGetAttributes(&at, off) == hipSuccess && at.type == hipMemoryTypeDevice)
+      fail(TC_E_INVAL, "row offsets must be in host memory");
+    (void)hipGetLastError();
+    require(off[0] == 0 && off[n] == m, TC_E_INVAL, "row offsets must run from 0 to m");
+    for (int32_t r = 0; r < n; r++) require(off[r] <= off[r + 1], TC_E_INVAL, "row offsets must not decrease");
+    uint64_t local[4];
+    *T = count_streamed(off, adj, n, m, budget_bytes, as_stream(stream), get_options(), info ? info : local);
+  });
+}
+
+tc_status tc_graph_export_csr(tc_graph* g, void* stream, int64_t* off, int32_t* adj) {
+  return guarded([&] {
+    require(g != nullptr, TC_E_INVAL, "graph is NULL");
+    DeviceScope ds(g->device);
+    const hipStream_t s = as_stream(stream);
+    if (off) TC_HIP(hipMemcpyAsync(off, g->csr.off.p, (static_cast<size_t>(g->csr.n) + 1) * sizeof(int64_t),
+                                   hipMemcpyDefault, s));
+    if (adj && g->csr.m > 0)
+      TC_HIP(hipMemcpyAsync(adj, g->csr.adj.p, static_cast<size_t>(g->csr.m) * sizeof(int32_t), hipMemcpyDefault, s));
+    TC_HIP(hipStreamSynchronize(s));
+  });
+}
+
 tc_status tc_graph_work(tc_graph* g, void* stream, uint64_t* W, uint64_t* P) {
   return guarded([&] {
     require(g != nullptr, TC_E_INVAL, "graph is NULL");
@@ -449,6 +566,17 @@ tc_status tc_graph_degrees(tc_graph* g, void* stream, int32_t* deg_dev, int32_t*
       k_dhat_by_id<<<grid_for(g->n, kBlock, 65536), kBlock, 0, s>>>(g->csr.off.p, g->order.p, g->n, dhat_dev);
       TC_LAUNCH_CHECK();
     }
+    TC_HIP(hipStreamSynchronize(s));
+  });
+}
+
+tc_status tc_graph_order(tc_graph* g, void* stream, int32_t* order_dev) {
+  return guarded([&] {
+    require(g != nullptr && order_dev != nullptr, TC_E_INVAL, "NULL argument");
+    require(!g->sampled, TC_E_INVAL, "not available on a sampled graph");
+    DeviceScope ds(g->device);
+    const hipStream_t s = as_stream(stream);
+    if (g->n > 0) TC_HIP(hipMemcpyAsync(order_dev, g->order.p, g->n * sizeof(int32_t), hipMemcpyDeviceToDevice, s));
     TC_HIP(hipStreamSynchronize(s));
   });
 }

@@ -85,23 +85,27 @@ __global__ __launch_bounds__(kBlock) void k_work(const int64_t* __restrict__ off
 // and the length of the suffix of N_v after u. Pivots with an empty N_u and
 // records with an empty suffix stay in the list; they are given no work.
 __global__ __launch_bounds__(kBlock) void k_inkeys(const int64_t* __restrict__ off, const int32_t* __restrict__ adj,
-                                                   const int32_t* __restrict__ src, uint64_t m,
+                                                   const int32_t* __restrict__ src, uint64_t e0, uint64_t cnt,
                                                    uint64_t* __restrict__ keys, uint32_t* __restrict__ lens) {
-  for (uint64_t e = static_cast<uint64_t>(blockIdx.x) * blockDim.x + threadIdx.x; e < m;
-       e += static_cast<uint64_t>(gridDim.x) * blockDim.x) {
-    keys[e] = (static_cast<uint64_t>(static_cast<uint32_t>(adj[e])) << 32) | e;
-    lens[e] = static_cast<uint32_t>(off[src[e] + 1] - static_cast<int64_t>(e) - 1);
+  for (uint64_t i = static_cast<uint64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < cnt;
+       i += static_cast<uint64_t>(gridDim.x) * blockDim.x) {
+    const uint64_t e = e0 + i;
+    keys[i] = (static_cast<uint64_t>(static_cast<uint32_t>(adj[e])) << 32) | e;
+    lens[i] = static_cast<uint32_t>(off[src[e] + 1] - static_cast<int64_t>(e) - 1);
   }
 }
 
-// Records in pivot order from the sorted keys and their suffix lengths.
+// Records in pivot order from the sorted keys and their suffix lengths (taken
+// from the CSR when lens is null).
 __global__ __launch_bounds__(kBlock) void k_inrec_fill(const uint64_t* __restrict__ ikeys,
-                                                       const uint32_t* __restrict__ lens, uint64_t mi,
+                                                       const uint32_t* __restrict__ lens,
+                                                       const int64_t* __restrict__ off,
+                                                       const int32_t* __restrict__ src, uint64_t mi,
                                                        InRec* __restrict__ rec, int64_t* __restrict__ cost) {
   for (uint64_t i = static_cast<uint64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < mi;
        i += static_cast<uint64_t>(gridDim.x) * blockDim.x) {
     const uint32_t e = static_cast<uint32_t>(ikeys[i] & 0xffffffffu);
-    const uint32_t len = lens[i];
+    const uint32_t len = lens ? lens[i] : static_cast<uint32_t>(off[src[e] + 1] - static_cast<int64_t>(e) - 1);
     rec[i] = InRec{e + 1, len};
     cost[i] = static_cast<int64_t>(len) + kCostPerRecord;
   }
@@ -837,15 +841,16 @@ void order_cost(const Csr& c, const int32_t* deg, const int32_t* order, unsigned
 // serves the total-only mode.
 static int64_t clamp_hub(int64_t h) { return h < 0 ? 0 : (h > kWaveSlots / 2 ? kWaveSlots / 2 : h); }
 
-void ensure_plan(Csr& c, hipStream_t s, const Options& o) {
-  PivotPlan& P = c.plan;
-  if (P.ready && P.hub_dhat == clamp_hub(o.hub_dhat) && P.item_work == o.item_work) return;
-  if (P.ready) TC_HIP(hipDeviceSynchronize());  // launches on other streams may still read the old plan
+namespace {
+
+// The records of the oriented edges at CSR entries [e0, e1) grouped by pivot,
+// and the work items over them.
+void build_plan(Csr& c, PivotPlan& P, uint64_t e0, uint64_t e1, hipStream_t s, const Options& o) {
   P.reset();
   const int32_t n = c.n;
-  const uint64_t m = static_cast<uint64_t>(c.m);
+  const uint64_t mi = e1 - e0;
   P.in_off.alloc(static_cast<size_t>(n) + 1, s);
-  if (m == 0 || n == 0) {
+  if (mi == 0 || n == 0) {
     if (n >= 0) TC_HIP(hipMemsetAsync(P.in_off.p, 0, (static_cast<size_t>(n) + 1) * sizeof(int64_t), s));
     P.hub_dhat = clamp_hub(o.hub_dhat);
     P.item_work = o.item_work;
@@ -853,29 +858,42 @@ void ensure_plan(Csr& c, hipStream_t s, const Options& o) {
     return;
   }
   const int b = bits_for(n > 1 ? static_cast<uint64_t>(n - 1) : 1);
-  // in-edge records of all m edges, sorted by pivot u (stable: by e within u)
-  const uint64_t mi = m;
-  DevBuf<uint64_t> ik(m, s), ik2(m, s);
-  DevBuf<uint32_t> il(m, s), il2(m, s);
-  k_inkeys<<<grid_for(m, kBlock, 65536), kBlock, 0, s>>>(c.off.p, c.adj.p, c.src.p, m, ik.get(), il.get());
+  // in-edge records sorted by pivot u (stable: by e within u)
+  DevBuf<uint64_t> ik(mi, s), ik2(mi, s);
+  DevBuf<uint32_t> il(mi, s), il2(mi, s);
+  k_inkeys<<<grid_for(mi, kBlock, 65536), kBlock, 0, s>>>(c.off.p, c.adj.p, c.src.p, e0, mi, ik.get(), il.get());
   TC_LAUNCH_CHECK();
   uint32_t* sl = il.get();
   uint64_t* sk = radix_sort_pairs<uint64_t, uint32_t>(ik.get(), ik2.get(), sl, il2.get(), mi, 32, 32 + b, s);
-  P.inrec.alloc(mi, s);
-  DevBuf<int64_t> fin(mi + 1, s);
-  k_inrec_fill<<<grid_for(mi, kBlock, 65536), kBlock, 0, s>>>(sk, sl, mi, P.inrec.p, fin.get());
-  TC_LAUNCH_CHECK();
-  offsets_from_key_rows(sk, mi, n, P.in_off.p, s);
-  exclusive_scan<int64_t>(fin.get(), fin.get(), mi, s, fin.get() + mi);
+  DevBuf<int64_t> fin;
+  plan_records(c, P, sk, sl, mi, fin, s);
   ik.release();
   ik2.release();
   il.release();
   il2.release();
+  plan_items(c, P, fin.get(), mi, s, o);
+}
 
+}  // namespace
+
+void plan_records(Csr& c, PivotPlan& P, const uint64_t* sk, const uint32_t* sl, uint64_t mi, DevBuf<int64_t>& fin,
+                  hipStream_t s) {
+  const int32_t n = c.n;
+  if (!P.in_off.p) P.in_off.alloc(static_cast<size_t>(n) + 1, s);
+  P.inrec.alloc(mi, s);
+  fin.alloc(mi + 1, s);
+  k_inrec_fill<<<grid_for(mi, kBlock, 65536), kBlock, 0, s>>>(sk, sl, c.off.p, c.src.p, mi, P.inrec.p, fin.get());
+  TC_LAUNCH_CHECK();
+  offsets_from_key_rows(sk, mi, n, P.in_off.p, s);
+  exclusive_scan<int64_t>(fin.get(), fin.get(), mi, s, fin.get() + mi);
+}
+
+void plan_items(Csr& c, PivotPlan& P, const int64_t* fin_p, uint64_t mi, hipStream_t s, const Options& o) {
+  const int32_t n = c.n;
   // classify pivots and count items; item_work 0: about 8 items per resident
   // wave, between 4096 and 65536 probe-equivalents
   int64_t total_cost = 0;
-  TC_HIP(hipMemcpyAsync(&total_cost, fin.get() + mi, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+  TC_HIP(hipMemcpyAsync(&total_cost, fin_p + mi, sizeof(int64_t), hipMemcpyDeviceToHost, s));
   TC_HIP(hipStreamSynchronize(s));
   int64_t iw_wave = o.item_work;
   if (iw_wave <= 0) {
@@ -891,7 +909,7 @@ void ensure_plan(Csr& c, hipStream_t s, const Options& o) {
   DevBuf<unsigned long long> d_probes(1, s);
   k_fill_words<unsigned long long><<<1, 64, 0, s>>>(d_probes.get(), 1, 0ull);
   TC_LAUNCH_CHECK();
-  k_pivot_classify<<<grid_for(n, kBlock, 65536), kBlock, 0, s>>>(n, c.off.p, P.in_off.p, fin.get(), clamp_hub(o.hub_dhat), cap,
+  k_pivot_classify<<<grid_for(n, kBlock, 65536), kBlock, 0, s>>>(n, c.off.p, P.in_off.p, fin_p, clamp_hub(o.hub_dhat), cap,
                                                                  iw_hub, iw_wave, nh.get(), ns.get(), grp.get(),
                                                                  d_probes.get());
   TC_LAUNCH_CHECK();
@@ -909,12 +927,12 @@ void ensure_plan(Csr& c, hipStream_t s, const Options& o) {
   P.items.alloc(P.n_hub_items + P.n_wave_items, s);
   if (P.n_hub_items) {
     k_items_fill<<<grid_for(P.n_hub_items, kBlock, 65536), kBlock, 0, s>>>(P.n_hub_items, nh.get(), n, c.off.p,
-                                                                          P.in_off.p, fin.get(), cap, iw_hub, P.items.p);
+                                                                          P.in_off.p, fin_p, cap, iw_hub, P.items.p);
     TC_LAUNCH_CHECK();
   }
   if (P.n_wave_items) {
     k_items_fill<<<grid_for(P.n_wave_items, kBlock, 65536), kBlock, 0, s>>>(
-        P.n_wave_items, ns.get(), n, c.off.p, P.in_off.p, fin.get(), 1ll << 40, iw_wave, P.items.p + P.n_hub_items);
+        P.n_wave_items, ns.get(), n, c.off.p, P.in_off.p, fin_p, 1ll << 40, iw_wave, P.items.p + P.n_hub_items);
     TC_LAUNCH_CHECK();
   }
   // grouped pivot list
@@ -931,6 +949,40 @@ void ensure_plan(Csr& c, hipStream_t s, const Options& o) {
   P.hub_dhat = clamp_hub(o.hub_dhat);
   P.item_work = o.item_work;
   P.ready = true;
+}
+
+namespace {
+
+bool plan_matches(const PivotPlan& P, int32_t lo, int32_t hi, const Options& o) {
+  return P.ready && P.src_lo == lo && P.src_hi == hi && P.hub_dhat == clamp_hub(o.hub_dhat) &&
+         P.item_work == o.item_work;
+}
+
+}  // namespace
+
+void ensure_plan(Csr& c, hipStream_t s, const Options& o) {
+  PivotPlan& P = c.plan;
+  if (plan_matches(P, 0, c.n, o)) return;
+  if (P.ready) TC_HIP(hipDeviceSynchronize());  // launches on other streams may still read the old plan
+  build_plan(c, P, 0, static_cast<uint64_t>(c.m), s, o);
+  P.src_lo = 0;
+  P.src_hi = c.n;
+}
+
+void ensure_shard_plan(Csr& c, int32_t lo, int32_t hi, hipStream_t s, const Options& o) {
+  if (lo < 0 || hi > c.n || lo > hi) fail(TC_E_RANGE, "shard rank range outside [0, n]");
+  PivotPlan& P = c.shard;
+  if (plan_matches(P, lo, hi, o)) return;
+  if (P.ready) TC_HIP(hipDeviceSynchronize());
+  int64_t e[2] = {0, 0};
+  if (c.n > 0) {
+    TC_HIP(hipMemcpyAsync(&e[0], c.off.p + lo, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    TC_HIP(hipMemcpyAsync(&e[1], c.off.p + hi, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    TC_HIP(hipStreamSynchronize(s));
+  }
+  build_plan(c, P, static_cast<uint64_t>(e[0]), static_cast<uint64_t>(e[1]), s, o);
+  P.src_lo = lo;
+  P.src_hi = hi;
 }
 
 namespace {
@@ -1187,11 +1239,8 @@ void fill_u64(unsigned long long* p, size_t n, unsigned long long v, hipStream_t
   TC_LAUNCH_CHECK();
 }
 
-void count_pivot(Csr& c, const CountArgs& ca, hipStream_t s, const Options& o, bool allow_rebuild) {
-  if (c.m == 0) return;
-  if (allow_rebuild) ensure_plan(c, s, o);
-  else if (!c.plan.ready) fail(TC_E_INVAL, "no work plan on this graph");
-  const PivotPlan& P = c.plan;
+// One persistent launch of k_pivot over the records and items of plan P of c.
+void launch_pivot(const Csr& c, const PivotPlan& P, const CountArgs& ca, hipStream_t s, const Options& o) {
   KernelArgs a{static_cast<int>(o.hub_bucket_load), c.off.p,     c.adj.p,          c.src.p,   P.inrec.p, P.in_off.p, ca.mode,  ca.total,
                ca.per_graph, ca.graph_of_rank, ca.t_rank, ca.order,  ca.tri,     ca.cursor, ca.cap};
   DevBuf<unsigned long long> qbuf;
@@ -1229,6 +1278,52 @@ void count_pivot(Csr& c, const CountArgs& ca, hipStream_t s, const Options& o, b
     k_pivot<kCountTotal, false><<<grid, kPivotBlock, lds, s>>>(a, hub, P.n_hub_items, split, P.n_wave_items,
                                                                P.grouped.p, P.n_grouped, q, hub_log2b, none);
   TC_LAUNCH_CHECK();
+}
+
+namespace {
+
+// f(v) = sum_{u in N_v} (dhat_v + dhat_u) by rank: the merge cost of v's
+// oriented edges (Theorem 2), the per-node cost of the DPD row of the
+// load-balancing table of Section 5.
+__global__ void k_rank_merge_costs(const int64_t* __restrict__ off, const int32_t* __restrict__ adj, int32_t n,
+                                   unsigned long long* __restrict__ f) {
+  for (int32_t r = blockIdx.x * blockDim.x + threadIdx.x; r < n; r += gridDim.x * blockDim.x) {
+    const unsigned long long dh = static_cast<unsigned long long>(off[r + 1] - off[r]);
+    unsigned long long x = 0;
+    for (int64_t j = off[r]; j < off[r + 1]; j++) x += dh + static_cast<unsigned long long>(off[adj[j] + 1] - off[adj[j]]);
+    f[r] = x;
+  }
+}
+
+}  // namespace
+
+void count_pivot(Csr& c, const CountArgs& ca, hipStream_t s, const Options& o, bool allow_rebuild) {
+  if (c.m == 0) return;
+  if (allow_rebuild) ensure_plan(c, s, o);
+  else if (!c.plan.ready) fail(TC_E_INVAL, "no work plan on this graph");
+  launch_pivot(c, c.plan, ca, s, o);
+}
+
+void shard_bounds(const Csr& c, int32_t k, int64_t* bounds, hipStream_t s) {
+  const int32_t n = c.n;
+  DevBuf<unsigned long long> f(static_cast<size_t>(n) + 1, s), Fx(static_cast<size_t>(n) + 1, s);
+  if (n > 0) {
+    k_rank_merge_costs<<<grid_for(n, kBlock, 65536), kBlock, 0, s>>>(c.off.p, c.adj.p, n, f.get());
+    TC_LAUNCH_CHECK();
+  }
+  exclusive_scan<unsigned long long>(f.get(), Fx.get(), static_cast<size_t>(n), s, Fx.get() + n);
+  k_part_bounds<<<grid_for(static_cast<uint64_t>(k) + 1, kBlock, 4096), kBlock, 0, s>>>(Fx.get(), f.get(), n,
+                                                                                          Fx.get() + n, k, bounds);
+  TC_LAUNCH_CHECK();
+}
+
+void count_shard(Csr& c, int32_t lo, int32_t hi, unsigned long long* total, hipStream_t s, const Options& o) {
+  ensure_shard_plan(c, lo, hi, s, o);
+  if (c.m == 0 || lo == hi) return;
+  CountArgs ca;
+  ca.mode = kCountTotal;
+  ca.total = total;
+  launch_pivot(c, c.shard, ca, s, o);
 }
 
 // One launch over the work of several graphs (plans must be ready). mode is
@@ -1302,7 +1397,9 @@ struct KeepPred {
   uint64_t key;  // mix(seed ^ domain)
   uint64_t tau;
   bool all;
+  uint64_t first;  // entries before this index are dropped
   __device__ bool operator()(size_t e) const {
+    if (e < first) return false;
     if (all) return true;
     const uint32_t a = static_cast<uint32_t>(order[src[e]]), b = static_cast<uint32_t>(order[adj[e]]);
     const uint64_t lo = a < b ? a : b, hi = a < b ? b : a;
@@ -1329,12 +1426,18 @@ __global__ void k_unpack_entries(const uint64_t* __restrict__ k, uint64_t n, int
 
 }  // namespace
 
-void build_sampled_csr(const tc_graph* g, double q, uint64_t seed, Csr& out, hipStream_t s) {
+void build_sampled_csr(const tc_graph* g, double q, uint64_t seed, Csr& out, hipStream_t s, int32_t first_rank) {
   const Csr& c = g->csr;
   const uint64_t m = static_cast<uint64_t>(c.m);
   const bool all = q >= 1.0;
   const uint64_t tau = all ? ~0ull : static_cast<uint64_t>(std::ldexp(q, 64));
-  KeepPred pred{c.adj.p, c.src.p, g->order.p, 0, tau, all};
+  int64_t first = 0;
+  if (first_rank > 0 && c.n > 0) {
+    if (first_rank > c.n) fail(TC_E_RANGE, "first rank outside [0, n]");
+    TC_HIP(hipMemcpyAsync(&first, c.off.p + first_rank, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    TC_HIP(hipStreamSynchronize(s));
+  }
+  KeepPred pred{c.adj.p, c.src.p, g->order.p, 0, tau, all, static_cast<uint64_t>(first)};
   {
     uint64_t z = seed ^ 0x5350415253494659ull;  // domain separation constant ("SPARSIFY")
     z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ull;

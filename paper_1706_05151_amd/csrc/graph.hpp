@@ -59,9 +59,13 @@ struct InRec {
   uint32_t a_len;    // entries of N_v after u
 };
 
-// The pivot work plan of one oriented CSR (built lazily, cached on the graph).
+// The pivot work plan of one oriented CSR (built lazily, cached on the graph):
+// the in-edge records of the oriented edges whose source rank lies in
+// [src_lo, src_hi) (all edges for the graph's own plan), grouped by pivot, and
+// the work items over them.
 struct PivotPlan {
   bool ready = false;
+  int32_t src_lo = 0, src_hi = 0;
   Owned<InRec> inrec;        // in-edge records grouped by pivot
   Owned<int64_t> in_off;     // [n+1]
   Owned<PivotItem> items;    // hub items first, then wave items
@@ -80,6 +84,7 @@ struct PivotPlan {
     grouped.reset();
     n_hub_items = n_wave_items = n_grouped = probes = 0;
     hub_dhat = item_work = 0;
+    src_lo = src_hi = 0;
   }
 };
 
@@ -92,7 +97,8 @@ struct Csr {
   Owned<int64_t> off;  // [n+1]
   Owned<int32_t> adj;  // [m]
   Owned<int32_t> src;  // [m] row of each entry
-  PivotPlan plan;
+  PivotPlan plan;      // all oriented edges
+  PivotPlan shard;     // the edges of one range of source ranks (tc_count_shard)
 };
 
 }  // namespace tc
@@ -155,6 +161,21 @@ struct CountArgs {
   unsigned long long* queues = nullptr;    // device [3] work-queue counters (optional)
 };
 void ensure_plan(Csr& c, hipStream_t s, const Options& o);
+// Plan steps from in-edge keys (pivot << 32 | e) sorted by pivot (stable in e):
+// the records and their cost prefix fin (lens: suffix lengths in key order, or
+// null to take them from c.off / c.src), then the classification and items.
+void plan_records(Csr& c, PivotPlan& P, const uint64_t* sk, const uint32_t* sl, uint64_t mi, DevBuf<int64_t>& fin,
+                  hipStream_t s);
+void plan_items(Csr& c, PivotPlan& P, const int64_t* fin, uint64_t mi, hipStream_t s, const Options& o);
+// the plan of the oriented edges whose source rank lies in [lo, hi), into c.shard
+void ensure_shard_plan(Csr& c, int32_t lo, int32_t hi, hipStream_t s, const Options& o);
+// triangles whose lowest vertex (in the orientation order) has rank in [lo, hi), added to *total
+void count_shard(Csr& c, int32_t lo, int32_t hi, unsigned long long* total, hipStream_t s, const Options& o);
+// ranks [bounds[j], bounds[j+1]) of shard j: the boundary rule over
+// f(v) = sum_{u in N_v} (dhat_v + dhat_u); bounds int64[k+1] (device)
+void shard_bounds(const Csr& c, int32_t k, int64_t* bounds, hipStream_t s);
+// one persistent launch of the pivot kernel over the records and items of P (a plan of c)
+void launch_pivot(const Csr& c, const PivotPlan& P, const CountArgs& a, hipStream_t s, const Options& o);
 // allow_rebuild = false: use the cached plan as is (capturable; fails if absent)
 void count_pivot(Csr& c, const CountArgs& a, hipStream_t s, const Options& o, bool allow_rebuild = true);
 void fill_u64(unsigned long long* p, size_t n, unsigned long long v, hipStream_t s);
@@ -171,7 +192,12 @@ void count_partitioned(const Csr& c, const int32_t* order, const int32_t* rank, 
                        hipStream_t s);
 // coreness of every rank of the CSR (neighbours: out-entries and in-edge records; needs the plan)
 void coreness_rank(const Csr& c, hipStream_t s, int32_t* core);
-void build_sampled_csr(const tc_graph* g, double q, uint64_t seed, Csr& out, hipStream_t s);
+// keeps each edge with probability q (Section 7); rows of ranks below first_rank are left empty
+// stream.hip: exact T of a rank-space oriented CSR held in host memory, streamed
+// through the device under a memory budget; info: {partitions, chunks, pairs, bytes copied in}
+uint64_t count_streamed(const int64_t* off, const int32_t* adj, int32_t n, int64_t m, uint64_t budget,
+                        hipStream_t s, const Options& o, uint64_t info[4]);
+void build_sampled_csr(const tc_graph* g, double q, uint64_t seed, Csr& out, hipStream_t s, int32_t first_rank = 0);
 void sort_triangles(int32_t* tri, int64_t count, int bits, hipStream_t s);
 // off[r] = first index whose row is >= r, for rows sorted ascending (length m); off has n+1 entries
 void offsets_from_rows(const int32_t* row, uint64_t m, int32_t n, int64_t* off, hipStream_t s);

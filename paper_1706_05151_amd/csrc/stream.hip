@@ -1,0 +1,285 @@
+// Exact triangle count of an oriented CSR that stays in host memory: the
+// non-overlapping partitions of Section 6 streamed through one GPU.
+//
+// The oriented CSR in rank space (row r holds later ranks, ascending) stays
+// on the host. The rows are split into pivot partitions V_j, each sized to
+// half of the device budget, and into source chunks sized to the other half.
+// For each j, the rows of V_j are loaded once. Every chunk of rows that start
+// before the end of V_j is then shipped to it: the surrogate pairing of
+// Section 6, where N_v travels to the partition owning u once per
+// (chunk, partition), and not once per edge. Triangle (v,u,w), v < u < w, is
+// counted where u lives: |N_v after u ∩ N_u| from the in-edge record (v,u),
+// by the pivot kernel of the in-memory path. Each (chunk, partition) pair is
+// visited once, and each triangle is counted once.
+//
+// Device layout of one (partition, chunk) pair, one CSR with local rows:
+//   rows [0, np)            the rows of V_j (adj entries [0, ep))
+//   row  np                 an empty gap spanning [ep, cap_p)
+//   rows (np, np + 1 + nc]  the chunk's rows (adj entries from cap_p)
+// Entries keep their global ranks, and the pivot kernel only compares them.
+// Records (v,u) are keyed by u's local row. The next chunk is copied into a
+// staging buffer on a second stream while the current pair is counted.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <vector>
+
+#include "graph.hpp"
+#include "primitives.hpp"
+
+namespace tc {
+namespace {
+
+constexpr int kBlock = 256;
+
+// Device bytes per entry and per row: a pivot partition holds adj, src, off,
+// the in-edge offsets and the classification arrays; a chunk adds its staged
+// copy, the two key buffers of the record sort, the records and their costs.
+constexpr uint64_t kPivotEntryBytes = 8;
+constexpr uint64_t kPivotRowBytes = 48;
+constexpr uint64_t kChunkEntryBytes = 56;
+constexpr uint64_t kChunkRowBytes = 56;
+constexpr int64_t kMaxRegionEntries = int64_t(1) << 31;  // record keys hold 32-bit entry indices
+
+// dst[r] = base + off[r] - off[0] for r in [0, rows]; flags offsets that decrease.
+__global__ void k_rebase(const int64_t* __restrict__ off, int32_t rows, int64_t base, int64_t* __restrict__ dst,
+                         uint32_t* __restrict__ bad) {
+  const int64_t o0 = off[0];
+  for (int32_t r = blockIdx.x * blockDim.x + threadIdx.x; r <= rows; r += gridDim.x * blockDim.x) {
+    dst[r] = base + off[r] - o0;
+    if (r < rows && off[r + 1] < off[r]) atomicOr(bad, 1u);
+  }
+}
+
+// Checks the rows [0, rows) of a region (global row of local row r: g0 + r):
+// entries strictly ascending, above their own row, below n. With src, writes
+// the local row (row_base + r) of every entry.
+__global__ void k_check_rows(const int64_t* __restrict__ off, const int32_t* __restrict__ adj, int32_t rows,
+                             int32_t row_base, int32_t g0, int32_t n, int32_t* __restrict__ src,
+                             uint32_t* __restrict__ bad) {
+  for (int32_t r = blockIdx.x * blockDim.x + threadIdx.x; r < rows; r += gridDim.x * blockDim.x) {
+    const int64_t b = off[row_base + r], e = off[row_base + r + 1];
+    int32_t prev = g0 + r;
+    bool ok = true;
+    for (int64_t k = b; k < e; k++) {
+      const int32_t x = adj[k];
+      ok = ok && x > prev && x < n;
+      prev = x;
+      if (src) src[k] = row_base + r;
+    }
+    if (!ok) atomicOr(bad, 2u);
+  }
+}
+
+// Record keys of the chunk entries that point into V_j = [lo, hi):
+// (u - lo) << 32 | e, e the entry's index in the combined adj.
+struct IntoPivots {
+  const int32_t* adj;
+  int64_t e0;
+  int32_t lo, hi;
+  __device__ bool operator()(size_t i) const {
+    const int32_t x = adj[e0 + static_cast<int64_t>(i)];
+    return x >= lo && x < hi;
+  }
+};
+struct PivotKey {
+  const int32_t* adj;
+  int64_t e0;
+  int32_t lo;
+  __device__ uint64_t operator()(size_t i) const {
+    const int64_t e = e0 + static_cast<int64_t>(i);
+    return (static_cast<uint64_t>(static_cast<uint32_t>(adj[e] - lo)) << 32) | static_cast<uint64_t>(e);
+  }
+};
+
+struct Range {
+  int32_t lo, hi;
+  int64_t e0, e1;  // entries [off[lo], off[hi])
+};
+
+// Splits rows [0, n) into consecutive ranges of cost eb * entries + rb * rows
+// <= cap (greedy, each range as long as fits); fails if one row alone exceeds it.
+std::vector<Range> split_rows(const int64_t* off, int32_t n, uint64_t cap, uint64_t eb, uint64_t rb) {
+  std::vector<Range> out;
+  int32_t lo = 0;
+  auto cost = [&](int32_t a, int32_t b) {
+    return eb * static_cast<uint64_t>(off[b] - off[a]) + rb * static_cast<uint64_t>(b - a);
+  };
+  while (lo < n) {
+    if (cost(lo, lo + 1) > cap || off[lo + 1] - off[lo] >= kMaxRegionEntries)
+      fail(TC_E_NOMEM, "device budget too small for one adjacency row");
+    int32_t a = lo + 1, b = n;  // the largest hi in [lo+1, n] that fits
+    while (a < b) {
+      const int32_t mid = a + (b - a + 1) / 2;
+      if (cost(lo, mid) <= cap && off[mid] - off[lo] < kMaxRegionEntries) a = mid;
+      else b = mid - 1;
+    }
+    out.push_back(Range{lo, a, off[lo], off[a]});
+    lo = a;
+  }
+  return out;
+}
+
+// A CSR whose arrays belong to someone else (cleared before destruction).
+struct CsrView {
+  Csr c;
+  CsrView(int64_t* off, int32_t* adj, int32_t* src) {
+    c.off.p = off;
+    c.adj.p = adj;
+    c.src.p = src;
+  }
+  ~CsrView() {
+    c.off.p = nullptr;
+    c.adj.p = nullptr;
+    c.src.p = nullptr;
+  }
+};
+
+uint32_t read_flags(const uint32_t* d, hipStream_t s) {
+  uint32_t h = 0;
+  TC_HIP(hipMemcpyAsync(&h, d, sizeof(h), hipMemcpyDeviceToHost, s));
+  TC_HIP(hipStreamSynchronize(s));
+  return h;
+}
+
+}  // namespace
+
+uint64_t count_streamed(const int64_t* off, const int32_t* adj, int32_t n, int64_t m, uint64_t budget,
+                        hipStream_t s, const Options& o, uint64_t info[4]) {
+  info[0] = info[1] = info[2] = info[3] = 0;
+  if (n <= 0 || m == 0) return 0;
+  const std::vector<Range> parts = split_rows(off, n, budget / 2, kPivotEntryBytes, kPivotRowBytes);
+  const std::vector<Range> chunks = split_rows(off, n, budget / 2, kChunkEntryBytes, kChunkRowBytes);
+  int64_t cap_p = 0, cap_c = 0;
+  int32_t rows_p = 0, rows_c = 0;
+  for (const Range& r : parts) {
+    cap_p = std::max(cap_p, r.e1 - r.e0);
+    rows_p = std::max(rows_p, r.hi - r.lo);
+  }
+  for (const Range& r : chunks) {
+    cap_c = std::max(cap_c, r.e1 - r.e0);
+    rows_c = std::max(rows_c, r.hi - r.lo);
+  }
+  info[0] = parts.size();
+  info[1] = chunks.size();
+
+  DevBuf<int32_t> adj_d(static_cast<size_t>(cap_p + cap_c), s), src_d(static_cast<size_t>(cap_p + cap_c), s);
+  DevBuf<int64_t> off_d(static_cast<size_t>(rows_p) + rows_c + 3, s);
+  DevBuf<int32_t> stage_adj(static_cast<size_t>(cap_c), s);
+  DevBuf<int64_t> stage_off(static_cast<size_t>(rows_c) + 1, s), pin_off(static_cast<size_t>(rows_p) + 1, s);
+  DevBuf<unsigned long long> total(1, s);
+  DevBuf<uint32_t> bad(1, s);
+  fill_u64(total.get(), 1, 0ull, s);
+  k_fill_words<uint32_t><<<1, 64, 0, s>>>(bad.get(), 1, 0u);
+  TC_LAUNCH_CHECK();
+
+  // the (partition, chunk) pairs in visiting order: chunks that start before the partition ends
+  std::vector<std::pair<int, int>> pairs;
+  for (int j = 0; j < static_cast<int>(parts.size()); j++)
+    for (int k = 0; k < static_cast<int>(chunks.size()) && chunks[k].lo < parts[j].hi; k++) pairs.emplace_back(j, k);
+  info[2] = pairs.size();
+
+  hipStream_t cs = nullptr;
+  TC_HIP(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+  hipEvent_t loaded = nullptr, freed = nullptr;
+  auto cleanup = [&] {
+    (void)hipStreamSynchronize(cs);
+    (void)hipStreamSynchronize(s);
+    if (loaded) (void)hipEventDestroy(loaded);
+    if (freed) (void)hipEventDestroy(freed);
+    (void)hipStreamDestroy(cs);
+  };
+  try {
+    TC_HIP(hipEventCreateWithFlags(&loaded, hipEventDisableTiming));
+    TC_HIP(hipEventCreateWithFlags(&freed, hipEventDisableTiming));
+    uint64_t h2d = 0;
+    auto prefetch = [&](int k) {  // chunk k into the staging buffers, on the copy stream
+      const Range& r = chunks[k];
+      TC_HIP(hipStreamWaitEvent(cs, freed, 0));
+      if (r.e1 > r.e0)
+        TC_HIP(hipMemcpyAsync(stage_adj.get(), adj + r.e0, static_cast<size_t>(r.e1 - r.e0) * sizeof(int32_t),
+                              hipMemcpyDefault, cs));
+      TC_HIP(hipMemcpyAsync(stage_off.get(), off + r.lo, (static_cast<size_t>(r.hi - r.lo) + 1) * sizeof(int64_t),
+                            hipMemcpyDefault, cs));
+      TC_HIP(hipEventRecord(loaded, cs));
+      h2d += static_cast<uint64_t>(r.e1 - r.e0) * sizeof(int32_t) + (static_cast<uint64_t>(r.hi - r.lo) + 1) * 8;
+    };
+    TC_HIP(hipEventRecord(freed, s));
+    prefetch(pairs[0].second);
+    int cur_part = -1;
+    int32_t dhat_p = 0;
+    CountArgs ca;
+    ca.mode = kCountTotal;
+    ca.total = total.get();
+    for (size_t q = 0; q < pairs.size(); q++) {
+      const Range& P = parts[pairs[q].first];
+      const Range& C = chunks[pairs[q].second];
+      const int32_t np = P.hi - P.lo, nc = C.hi - C.lo;
+      if (pairs[q].first != cur_part) {  // load the rows of V_j (on the counting stream)
+        cur_part = pairs[q].first;
+        if (P.e1 > P.e0)
+          TC_HIP(hipMemcpyAsync(adj_d.get(), adj + P.e0, static_cast<size_t>(P.e1 - P.e0) * sizeof(int32_t),
+                                hipMemcpyDefault, s));
+        TC_HIP(hipMemcpyAsync(pin_off.get(), off + P.lo, (static_cast<size_t>(np) + 1) * sizeof(int64_t),
+                              hipMemcpyDefault, s));
+        h2d += static_cast<uint64_t>(P.e1 - P.e0) * sizeof(int32_t) + (static_cast<uint64_t>(np) + 1) * 8;
+        k_rebase<<<grid_for(static_cast<uint64_t>(np) + 1, kBlock, 65536), kBlock, 0, s>>>(pin_off.get(), np, 0,
+                                                                                         off_d.get(), bad.get());
+        TC_LAUNCH_CHECK();
+        k_check_rows<<<grid_for(np, kBlock, 65536), kBlock, 0, s>>>(off_d.get(), adj_d.get(), np, 0, P.lo, n, nullptr,
+                                                                    bad.get());
+        TC_LAUNCH_CHECK();
+        dhat_p = max_row_length(off_d.get(), np, s);
+      }
+      // the chunk: staged copy into the combined arrays, rows after the gap row np
+      TC_HIP(hipStreamWaitEvent(s, loaded, 0));
+      if (C.e1 > C.e0)
+        TC_HIP(hipMemcpyAsync(adj_d.get() + cap_p, stage_adj.get(), static_cast<size_t>(C.e1 - C.e0) * sizeof(int32_t),
+                              hipMemcpyDeviceToDevice, s));
+      k_rebase<<<grid_for(static_cast<uint64_t>(nc) + 1, kBlock, 65536), kBlock, 0, s>>>(
+          stage_off.get(), nc, cap_p, off_d.get() + np + 1, bad.get());
+      TC_LAUNCH_CHECK();
+      TC_HIP(hipEventRecord(freed, s));
+      if (q + 1 < pairs.size()) prefetch(pairs[q + 1].second);
+      k_check_rows<<<grid_for(nc, kBlock, 65536), kBlock, 0, s>>>(off_d.get(), adj_d.get(), nc, np + 1, C.lo, n,
+                                                                  src_d.get(), bad.get());
+      TC_LAUNCH_CHECK();
+      if (read_flags(bad.get(), s)) fail(TC_E_INVAL, "rows must hold ascending ranks above their own row, below n");
+      // records (v,u) with u in V_j, sorted by u's local row
+      CsrView w(off_d.get(), adj_d.get(), src_d.get());
+      w.c.n = np + 1 + nc;
+      w.c.m = cap_p + (C.e1 - C.e0);
+      w.c.dhat_max = dhat_p;
+      const uint64_t ec = static_cast<uint64_t>(C.e1 - C.e0);
+      DevBuf<uint64_t> keys(ec, s), keys2(ec, s), cnt(1, s);
+      compact_if<uint64_t>(ec, IntoPivots{adj_d.get(), cap_p, P.lo, P.hi}, PivotKey{adj_d.get(), cap_p, P.lo},
+                           keys.get(), cnt.get(), s);
+      uint64_t mi = 0;
+      TC_HIP(hipMemcpyAsync(&mi, cnt.get(), sizeof(mi), hipMemcpyDeviceToHost, s));
+      TC_HIP(hipStreamSynchronize(s));
+      if (mi == 0) continue;
+      const int b = bits_for(np > 1 ? static_cast<uint64_t>(np - 1) : 1);
+      uint64_t* sk = radix_sort<uint64_t>(keys.get(), keys2.get(), mi, 32, 32 + b, s);
+      PivotPlan plan;
+      DevBuf<int64_t> fin;
+      plan_records(w.c, plan, sk, nullptr, mi, fin, s);
+      keys.release();
+      keys2.release();
+      plan_items(w.c, plan, fin.get(), mi, s, o);
+      fin.release();
+      launch_pivot(w.c, plan, ca, s, o);
+      TC_HIP(hipStreamSynchronize(s));  // the plan's arrays are freed on leaving this scope
+    }
+    info[3] = h2d;
+    unsigned long long T = 0;
+    TC_HIP(hipMemcpyAsync(&T, total.get(), sizeof(T), hipMemcpyDeviceToHost, s));
+    TC_HIP(hipStreamSynchronize(s));
+    cleanup();
+    return T;
+  } catch (...) {
+    cleanup();
+    throw;
+  }
+}
+
+}  // namespace tc

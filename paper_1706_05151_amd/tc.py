@@ -8,7 +8,7 @@ from __future__ import annotations
 
 import ctypes
 import os
-from typing import Optional, Tuple
+from typing import List, Optional, Tuple
 
 import numpy as np
 
@@ -41,6 +41,12 @@ SIGNATURES = {
     "tc_graph_coreness": ([_vp, _vp, _vp], ctypes.c_int),
     "tc_count_partitioned": ([_vp, _vp, _i32, _i32, _P(_u64), _vp, _vp], ctypes.c_int),
     "tc_graph_oriented": ([_vp, _vp, _vp, _vp], ctypes.c_int),
+    "tc_graph_order": ([_vp, _vp, _vp], ctypes.c_int),
+    "tc_graph_export_csr": ([_vp, _vp, _vp, _vp], ctypes.c_int),
+    "tc_count_streamed": ([_vp, _vp, _i32, _i64, _u64, _vp, _P(_u64), _vp], ctypes.c_int),
+    "tc_shard_bounds": ([_vp, _vp, _i32, _vp], ctypes.c_int),
+    "tc_count_shard": ([_vp, _vp, _i32, _i32, _P(_u64)], ctypes.c_int),
+    "tc_sparsify_count_partitioned": ([_vp, _dbl, _u64, _i32, _vp, _vp, _vp, _P(_u64), _P(_dbl)], ctypes.c_int),
     "tc_set_option": ([ctypes.c_int, _i64], ctypes.c_int),
     "tc_get_option": ([ctypes.c_int], _i64),
     "tc_batch_build": ([_vp, _vp, _vp, _vp, _i32, _u32, _vp, _P(_vp)], ctypes.c_int),
@@ -103,6 +109,15 @@ def _stream(stream) -> ctypes.c_void_p:
 
 def _dptr(t) -> ctypes.c_void_p:
     return ctypes.c_void_p(t.data_ptr())
+
+
+def _hptr(a) -> ctypes.c_void_p:
+    """Address of a torch tensor or a contiguous numpy array."""
+    if isinstance(a, np.ndarray):
+        if not a.flags["C_CONTIGUOUS"]:
+            raise ValueError("array must be contiguous")
+        return ctypes.c_void_p(a.ctypes.data)
+    return ctypes.c_void_p(a.data_ptr())
 
 
 def set_option(key: int, value: int):
@@ -243,6 +258,47 @@ class Graph:
         _check(lib().tc_graph_coreness(self._h, _stream(stream), _dptr(core)), "tc_graph_coreness")
         return core[: self.n]
 
+    def order(self, stream=None):
+        """Caller id of the vertex at each position of the orientation order: int32[n] on the device."""
+        torch = _torch()
+        order = torch.empty(max(self.n, 1), dtype=torch.int32, device="cuda")
+        _check(lib().tc_graph_order(self._h, _stream(stream), _dptr(order)), "tc_graph_order")
+        return order[: self.n]
+
+    def shard_bounds(self, k: int, stream=None) -> List[int]:
+        """Positions [b[j], b[j+1]) of the core nodes of shard j (boundary rule over the merge cost)."""
+        b = (ctypes.c_int32 * (k + 1))()
+        _check(lib().tc_shard_bounds(self._h, _stream(stream), int(k), b), "tc_shard_bounds")
+        return list(b)
+
+    def count_shard(self, lo: int, hi: int, stream=None) -> int:
+        """Triangles whose lowest vertex has its position in [lo, hi) of the orientation order."""
+        T = _u64()
+        _check(lib().tc_count_shard(self._h, _stream(stream), int(lo), int(hi), ctypes.byref(T)), "tc_count_shard")
+        return T.value
+
+    def sparsify_count_partitioned(self, q: float, seed: int, parts: int, stream=None):
+        """Per-shard independent samples (Section 7 with overlapping partitions):
+        (per-shard T_s list, bounds list, sum of T_s, estimate)."""
+        tp = (ctypes.c_uint64 * parts)()
+        b = (ctypes.c_int32 * (parts + 1))()
+        Ts, est = _u64(), _dbl()
+        _check(lib().tc_sparsify_count_partitioned(self._h, float(q), int(seed) & (2 ** 64 - 1), int(parts),
+                                                   _stream(stream), tp, b, ctypes.byref(Ts), ctypes.byref(est)),
+               "tc_sparsify_count_partitioned")
+        return list(tp), list(b), Ts.value, est.value
+
+    def export_csr(self, off=None, adj=None, stream=None):
+        """Copy the rank-space oriented CSR into off (int64[n+1]) and adj (int32[m]): torch tensors on
+        the host (pinned for speed) or the device; allocated as pinned host tensors when omitted."""
+        torch = _torch()
+        if off is None:
+            off = torch.empty(self.n + 1, dtype=torch.int64, pin_memory=True)
+        if adj is None:
+            adj = torch.empty(max(self.m, 1), dtype=torch.int32, pin_memory=True)
+        _check(lib().tc_graph_export_csr(self._h, _stream(stream), _dptr(off), _dptr(adj)), "tc_graph_export_csr")
+        return off, adj[: self.m]
+
     def degrees(self, stream=None):
         torch = _torch()
         k = max(self.n, 1)
@@ -308,3 +364,15 @@ def multi_count(graphs, T_out, t_outs=None, stream=None):
 
 def sparsify_estimate(Ts: int, q: float) -> float:
     return float(lib().tc_sparsify_estimate(int(Ts), float(q)))
+
+
+def count_streamed(off, adj, n: int, budget_bytes: int, stream=None):
+    """Exact T of a rank-space oriented CSR held in host memory (off: int64[n+1] host tensor or array,
+    adj: int32[m] host or device), streamed through the GPU within budget_bytes of device memory.
+    Returns (T, {"partitions", "chunks", "pairs", "bytes_in"})."""
+    m = int(off[n])
+    T = _u64()
+    info = (ctypes.c_uint64 * 4)()
+    _check(lib().tc_count_streamed(_hptr(off), _hptr(adj), int(n), m, int(budget_bytes), _stream(stream),
+                                   ctypes.byref(T), info), "tc_count_streamed")
+    return T.value, {"partitions": info[0], "chunks": info[1], "pairs": info[2], "bytes_in": info[3]}

@@ -295,6 +295,179 @@ def run_schemes(args):
             "table": table}
 
 
+def _best_ms(fn, reps=3):
+    import torch
+
+    best, out = float("inf"), None
+    for _ in range(reps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        out = fn()
+        torch.cuda.synchronize()
+        best = min(best, time.perf_counter() - t0)
+    return 1e3 * best, out
+
+
+def run_shards(args):
+    """One GPU's share of a sharded count: the R-MAT graph's core nodes split
+    into k shards by the boundary rule over the merge cost (Section 5), each
+    shard counted with its own work plan (in-edge records of its core nodes'
+    edges). Reports per-shard count time, the spread max/mean (the balance a
+    k-GPU run would see, each GPU holding the whole oriented graph) and the
+    time of building each shard's plan; checks that the shards add up to T."""
+    import torch
+
+    import synth
+
+    torch.cuda.set_device(0)
+    k = int(getattr(args, "shards", 8) or 8)
+    el = synth.config_rmat(args.scale)
+    s = torch.from_numpy(el.src).cuda()
+    d = torch.from_numpy(el.dst).cuda()
+    n = el.n
+    del el
+    g = tc.Graph.build(s, d, n)
+    del s, d
+    torch.cuda.empty_cache()
+    T = g.count()
+    full_ms, _ = _best_ms(g.count)
+    b = g.shard_bounds(k)
+    rows = []
+    for j in range(k):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        Tj = g.count_shard(b[j], b[j + 1])  # builds the shard's plan
+        torch.cuda.synchronize()
+        first_ms = 1e3 * (time.perf_counter() - t0)
+        ms, Tr = _best_ms(lambda: g.count_shard(b[j], b[j + 1]))
+        assert Tr == Tj
+        rows.append({"shard": j, "lo": b[j], "hi": b[j + 1], "T": Tj, "count_ms": ms,
+                     "plan_ms": max(first_ms - ms, 0.0)})
+        _log(f"[shards] {rows[-1]}")
+    assert sum(r["T"] for r in rows) == T, "shards do not add up to T"
+    times = [r["count_ms"] for r in rows]
+    total = sum(times)
+    m = g.m
+    g.close()
+    return {"metric": METRIC, "value": m / (total / 1e3), "unit": "oriented edges/s", "n_gpus": 1, "steps": 3,
+            "warmup": 1, "ms_per_step": total, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+            "dtype": "int32", "data": "synthetic",
+            "config": {"workload": f"rmat{args.scale}-shards{k}", "n": n, "m": m, "T": T, "shards": k,
+                       "step": "tc_count_shard over every shard in turn (plans built beforehand)",
+                       "parallelism": "single GPU"},
+            "full_count_ms": full_ms, "sum_shard_ms": total, "max_shard_ms": max(times),
+            "shard_max_over_mean": max(times) / (total / k), "per_shard": rows}
+
+
+def run_sampling(args):
+    """Sparsification with one sample (Section 7) against independent per-shard
+    samples (overlapping partitions, Eq. var2): time and estimate of each on the
+    R-MAT graph at q = 0.1 with 8 shards, and the spread of both estimators over
+    seeds on a smaller R-MAT graph (scale 18) at q = 0.1 and 0.2."""
+    import torch
+
+    import synth
+
+    torch.cuda.set_device(0)
+    k = int(getattr(args, "shards", 8) or 8)
+    out = {}
+    el = synth.config_rmat(args.scale)
+    s = torch.from_numpy(el.src).cuda()
+    d = torch.from_numpy(el.dst).cuda()
+    n = el.n
+    del el
+    g = tc.Graph.build(s, d, n)
+    del s, d
+    torch.cuda.empty_cache()
+    T = g.count()
+    q = 0.1
+    g.sparsify_count(q, 3)
+    plain_ms, (Ts, _, est) = _best_ms(lambda: g.sparsify_count(q, 3))
+    g.sparsify_count_partitioned(q, 3, k)
+    part_ms, (_, _, pTs, pest) = _best_ms(lambda: g.sparsify_count_partitioned(q, 3, k))
+    out["large"] = {"graph": f"rmat{args.scale}", "T": T, "q": q, "shards": k,
+                    "plain": {"ms": plain_ms, "T_s": Ts, "rel_err": est / T - 1},
+                    "partitioned": {"ms": part_ms, "T_s": pTs, "rel_err": pest / T - 1}}
+    _log(f"[sampling] {out['large']}")
+    m = g.m
+    g.close()
+    torch.cuda.empty_cache()
+    el = synth.rmat(18, 16, 3)
+    s = torch.from_numpy(el.src).cuda()
+    d = torch.from_numpy(el.dst).cuda()
+    gs = tc.Graph.build(s, d, el.n)
+    Tsmall = gs.count()
+    seeds = 64
+    spread = []
+    for qq in (0.1, 0.2):
+        pe = np.array([gs.sparsify_count(qq, 1000 + i)[2] for i in range(seeds)])
+        ae = np.array([gs.sparsify_count_partitioned(qq, 1000 + i, k)[3] for i in range(seeds)])
+        row = {"q": qq, "seeds": seeds, "plain_mean_rel": float(pe.mean() / Tsmall - 1),
+               "plain_rel_std": float(pe.std(ddof=1) / Tsmall),
+               "partitioned_mean_rel": float(ae.mean() / Tsmall - 1),
+               "partitioned_rel_std": float(ae.std(ddof=1) / Tsmall)}
+        _log(f"[sampling] rmat18 {row}")
+        spread.append(row)
+    gs.close()
+    out["spread_rmat18"] = {"T": Tsmall, "shards": k, "rows": spread}
+    return {"metric": METRIC, "value": m / (part_ms / 1e3), "unit": "oriented edges/s", "n_gpus": 1, "steps": 3,
+            "warmup": 1, "ms_per_step": part_ms, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+            "dtype": "int32", "data": "synthetic",
+            "config": {"workload": f"rmat{args.scale}-partitioned-sample-q0.1-shards{k}",
+                       "step": "tc_sparsify_count_partitioned (sample, plan and count of every shard)",
+                       "parallelism": "single GPU"},
+            **out}
+
+
+def run_streamed(args):
+    """Graphs larger than HBM (Section 6's non-overlapping partitions streamed
+    through one GPU): the R-MAT graph's rank-space oriented CSR is exported to
+    pinned host memory and counted by tc_count_streamed under device budgets
+    that split it into several pivot partitions and chunks. Reports the time,
+    the pairs visited, the bytes copied in and their rate, against the count of
+    the same graph resident in HBM; checks T."""
+    import torch
+
+    import synth
+
+    torch.cuda.set_device(0)
+    el = synth.config_rmat(args.scale)
+    s = torch.from_numpy(el.src).cuda()
+    d = torch.from_numpy(el.dst).cuda()
+    n = el.n
+    del el
+    g = tc.Graph.build(s, d, n)
+    del s, d
+    torch.cuda.empty_cache()
+    T = g.count()
+    resident_ms, _ = _best_ms(g.count)
+    m = g.m
+    off, adj = g.export_csr()
+    g.close()
+    torch.cuda.empty_cache()
+    csr_bytes = 8 * (n + 1) + 4 * m
+    rows = []
+    for budget in (int(x) << 30 for x in getattr(args, "budgets", None) or (4, 16, 64)):
+        got, info = tc.count_streamed(off, adj, n, budget)  # warm-up (allocations)
+        assert got == T, "streamed count disagrees"
+        ms, (got, info) = _best_ms(lambda: tc.count_streamed(off, adj, n, budget), reps=2)
+        assert got == T
+        row = {"budget_gib": budget >> 30, "ms": ms, **info, "copy_gbs": info["bytes_in"] / (ms / 1e3) / 1e9,
+               "edges_per_s": m / (ms / 1e3)}
+        _log(f"[streamed] {row}")
+        rows.append(row)
+    best = min(rows, key=lambda r: r["ms"])
+    small = rows[0]
+    return {"metric": METRIC, "value": m / (small["ms"] / 1e3), "unit": "oriented edges/s", "n_gpus": 1,
+            "steps": 2, "warmup": 1, "ms_per_step": small["ms"], "higher_is_better": True, "scaling": "weak",
+            "vs_baseline": None, "dtype": "int32", "data": "synthetic",
+            "config": {"workload": f"rmat{args.scale}-streamed-budget{small['budget_gib']}GiB", "n": n, "m": m,
+                       "T": T, "csr_bytes_host": csr_bytes,
+                       "step": "tc_count_streamed of the rank-space CSR in pinned host memory",
+                       "parallelism": "single GPU"},
+            "resident_count_ms": resident_ms, "best_streamed_ms": best["ms"], "budgets": rows}
+
+
 def run(args):
     if args.workload == "batch":
         return run_batch(args)
@@ -302,4 +475,10 @@ def run(args):
         return run_orders(args)
     if args.workload == "schemes":
         return run_schemes(args)
+    if args.workload == "shards":
+        return run_shards(args)
+    if args.workload == "sampling":
+        return run_sampling(args)
+    if args.workload == "streamed":
+        return run_streamed(args)
     return run_serve(args)

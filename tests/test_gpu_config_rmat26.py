@@ -2,7 +2,11 @@
 launch configuration bench.py times: totals, work, degrees and the sparsified
 counts against the oracle's stored results (tests/golden/rmat26.json, written
 by tests/golden/make_rmat26.py), per-node counts at 64 sampled vertices
-computed by the oracle from the definition, and sum_v t_v = 3T."""
+computed by the oracle from the definition, and sum_v t_v = 3T; the 8 core-node
+shards (boundaries from tests/golden/rmat26_shards.json, written by
+tests/golden/make_rmat26_shards.py) adding up to T, the per-shard sampled
+counts of the overlapping-partition sparsification, and the streamed count of
+the CSR held in host memory."""
 import json
 import os
 
@@ -15,6 +19,7 @@ import synth
 pytestmark = pytest.mark.gpu
 
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "rmat26.json")
+SHARDS = os.path.join(os.path.dirname(__file__), "golden", "rmat26_shards.json")
 
 
 @pytest.fixture(scope="module")
@@ -68,3 +73,37 @@ def test_sparsified(rmat26, q):
     Ts, mk, est = g.sparsify_count(float(q), ref["seed"])
     assert (Ts, mk) == (ref["T_s"], ref["m_kept"])
     assert est == oracle.estimate(Ts, float(q))
+
+
+def test_shards_add_up(rmat26):
+    g, gold = rmat26
+    with open(SHARDS) as f:
+        sh = json.load(f)
+    b = g.shard_bounds(sh["shards"])
+    assert b == sh["bounds"]
+    assert sum(g.count_shard(b[j], b[j + 1]) for j in range(sh["shards"])) == gold["T"]
+
+
+def test_partitioned_sample(rmat26):
+    g, _ = rmat26
+    with open(SHARDS) as f:
+        sh = json.load(f)
+    ps = sh["partitioned_sample"]
+    T_parts, b, Ts, est = g.sparsify_count_partitioned(ps["q"], ps["seed"], sh["shards"])
+    assert b == sh["bounds"]
+    assert T_parts == ps["T_parts"] and Ts == ps["T_s"]
+    assert est == oracle.estimate(Ts, ps["q"])
+
+
+def test_streamed_from_host(rmat26):
+    """The rank-space CSR in pinned host memory, counted under a 16 GiB device budget (several
+    pivot partitions and chunks), gives T."""
+    g, gold = rmat26
+    from paper_1706_05151_amd import tc
+
+    off, adj = g.export_csr()
+    assert int(off[-1]) == gold["m"]
+    T, info = tc.count_streamed(off, adj, g.n, 16 << 30)
+    print(f"[rmat26] streamed {info}", flush=True)
+    assert info["partitions"] > 1 and info["chunks"] > 1
+    assert T == gold["T"]

@@ -411,3 +411,205 @@ def test_partitioned_count_errors(tc):
             g.count_partitioned(0, 0)
         T, b, w = g.count_partitioned(5, 1)  # one range: the whole graph
         assert T == g.count() and b.cpu().tolist() == [0, el.n]
+
+
+# ----------------------------------------------------------------- shards ---
+
+def _shard_ref(el, k):
+    """Oracle positions, shard boundaries and per-shard counts (triangles by lowest vertex)."""
+    lo, hi = oracle.simple(el.src, el.dst, el.n)
+    deg = oracle.degrees(lo, hi, el.n)
+    off, adj = oracle.orient(lo, hi, deg, el.n)
+    pos = oracle.order_positions(deg, el.n)
+    b = oracle.shard_bounds(off, adj, el.n, pos, k)
+    T = [oracle.count_nin_pos_range(off, adj, el.n, pos, int(b[j]), int(b[j + 1])) for j in range(k)]
+    return pos, b, T, (lo, hi, deg, off, adj)
+
+
+SHARD_GRAPHS = [synth.rmat(12, 16, 61), synth.ba(20000, 5, 62), synth.er(3000, 0.01, 63), synth.wheel(300),
+                synth.complete(40)]
+
+
+@pytest.mark.parametrize("k", [1, 3, 8])
+def test_shards_match_oracle(tc, k):
+    """Shard boundaries, each shard's count and the order export equal the oracle's; shards add up to T."""
+    for el in SHARD_GRAPHS:
+        pos, b, T, _ = _shard_ref(el, k)
+        s, d = to_dev(el)
+        with tc.Graph.build(s, d, el.n) as g:
+            say(f"[parity] shards k={k} {el.name}")
+            order = g.order().cpu().numpy()
+            np.testing.assert_array_equal(pos[order], np.arange(el.n))
+            gb = g.shard_bounds(k)
+            assert gb == b.tolist()
+            gT = [g.count_shard(gb[j], gb[j + 1]) for j in range(k)]
+            assert gT == T
+            assert sum(gT) == g.count()
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_shard_ranges_messy(tc, seed):
+    """Arbitrary position ranges (empty, single vertex, whole graph) on raw edge lists."""
+    rng = np.random.default_rng(700 + seed)
+    n = int(rng.integers(5, 400))
+    el = _messy_el(n, int(rng.integers(0, 12 * n)), seed)
+    lo, hi = oracle.simple(el.src, el.dst, n)
+    deg = oracle.degrees(lo, hi, n)
+    off, adj = oracle.orient(lo, hi, deg, n)
+    pos = oracle.order_positions(deg, n)
+    ranges = [(0, 0), (0, n), (n, n), (n - 1, n)] + [tuple(sorted(rng.integers(0, n + 1, 2).tolist())) for _ in range(8)]
+    s, d = to_dev(el)
+    with tc.Graph.build(s, d, n) as g:
+        say(f"[parity] shard ranges seed {seed} n={n}")
+        for a, b in ranges:
+            assert g.count_shard(a, b) == oracle.count_nin_pos_range(off, adj, n, pos, a, b), (a, b)
+
+
+@pytest.mark.parametrize("hub,iw", [(0, 64), (16, 4096), (256, 0)])
+def test_shard_partitioner_settings(tc, hub, iw):
+    """A shard's own work plan follows the partitioner options and still counts exactly."""
+    el = synth.rmat(13, 16, 64)
+    pos, b, T, _ = _shard_ref(el, 5)
+    s, d = to_dev(el)
+    tc.set_option(tc.OPT_HUB_DHAT, hub)
+    tc.set_option(tc.OPT_ITEM_WORK, iw)
+    try:
+        with tc.Graph.build(s, d, el.n) as g:
+            say(f"[parity] shard settings hub={hub} iw={iw}")
+            assert [g.count_shard(int(b[j]), int(b[j + 1])) for j in range(5)] == T
+    finally:
+        tc.set_option(tc.OPT_HUB_DHAT, 256)
+        tc.set_option(tc.OPT_ITEM_WORK, 0)
+
+
+def test_shard_of_sampled_graph(tc):
+    """Shards of a sampled graph: triangles of the sample by lowest vertex, positions of the full graph."""
+    el = synth.rmat(13, 16, 65)
+    pos, b, _, (lo, hi, deg, _, _) = _shard_ref(el, 4)
+    klo, khi = oracle.sparsify(lo, hi, 0.4, 7)
+    koff, kadj = oracle.orient(klo, khi, deg, el.n)
+    ref = [oracle.count_nin_pos_range(koff, kadj, el.n, pos, int(b[j]), int(b[j + 1])) for j in range(4)]
+    s, d = to_dev(el)
+    with tc.Graph.build(s, d, el.n) as g, g.sparsify_build(0.4, 7) as gs:
+        say("[parity] shards of a sampled graph")
+        assert [gs.count_shard(int(b[j]), int(b[j + 1])) for j in range(4)] == ref
+        assert sum(ref) == gs.count()
+
+
+def test_shard_errors(tc):
+    el = synth.rmat(9, 8, 66)
+    s, d = to_dev(el)
+    with tc.Graph.build(s, d, el.n) as g:
+        for a, b in ((-1, 3), (5, 4), (0, el.n + 1)):
+            with pytest.raises(tc.TCError):
+                g.count_shard(a, b)
+        with pytest.raises(tc.TCError):
+            g.shard_bounds(0)
+        with g.sparsify_build(0.5, 1) as gs:
+            with pytest.raises(tc.TCError):
+                gs.order()
+            with pytest.raises(tc.TCError):
+                gs.sparsify_count_partitioned(0.5, 1, 2)
+        for q, parts in ((0.0, 2), (1.5, 2), (0.5, 0)):
+            with pytest.raises(tc.TCError):
+                g.sparsify_count_partitioned(q, 1, parts)
+
+
+@pytest.mark.parametrize("q,seed,parts", [(0.1, 3, 8), (0.5, 11, 4), (0.3, 2 ** 63 + 5, 1), (1.0, 4, 6),
+                                          (0.25, 8, 64)])
+def test_partitioned_sample_matches_oracle(tc, q, seed, parts):
+    """Per-shard independent samples (Section 7 with overlapping partitions): every shard's T_s,
+    the boundaries and the estimate equal the oracle's."""
+    for el in (synth.rmat(13, 16, 67), synth.ba(10000, 8, 68)):
+        lo, hi = oracle.simple(el.src, el.dst, el.n)
+        deg = oracle.degrees(lo, hi, el.n)
+        T_parts, b, Ts, est = oracle.sparsified_count_partitioned(lo, hi, deg, el.n, q, seed, parts)
+        s, d = to_dev(el)
+        with tc.Graph.build(s, d, el.n) as g:
+            say(f"[parity] partitioned sample q={q} seed={seed} parts={parts} {el.name}")
+            gT, gb, gTs, gest = g.sparsify_count_partitioned(q, seed, parts)
+            assert gb == b.tolist()
+            assert gT == T_parts
+            assert gTs == Ts and gest == est
+            if parts == 1:
+                assert g.sparsify_count(q, oracle.partition_seed(seed, 0))[0] == Ts
+
+
+# ------------------------------------------------------ streamed (host CSR) ---
+
+def _rank_csr(el):
+    """The rank-space oriented CSR built on the CPU from the oracle's orientation and positions:
+    row pos[v] holds pos[u] for u in N_v, ascending. Returns (off int64[n+1], adj int32[m], T)."""
+    lo, hi = oracle.simple(el.src, el.dst, el.n)
+    deg = oracle.degrees(lo, hi, el.n)
+    off, adj = oracle.orient(lo, hi, deg, el.n)
+    T = oracle.count_nin(off, adj, el.n)[0]
+    pos = oracle.order_positions(deg, el.n).astype(np.int64)
+    rows = pos[np.repeat(np.arange(el.n), np.diff(off))]
+    cols = pos[adj]
+    o = np.lexsort((cols, rows))
+    roff = np.zeros(el.n + 1, np.int64)
+    np.cumsum(np.bincount(rows, minlength=el.n), out=roff[1:])
+    return roff, np.ascontiguousarray(cols[o], dtype=np.int32), T
+
+
+STREAM_GRAPHS = [synth.rmat(12, 16, 71), synth.ba(5000, 6, 72), synth.er(2000, 0.01, 73), synth.wheel(500),
+                 synth.complete(60)]
+
+
+def test_export_csr_matches_positions(tc):
+    """The exported rank-space CSR equals the one built from the oracle's order and orientation."""
+    for el in STREAM_GRAPHS:
+        roff, radj, _ = _rank_csr(el)
+        s, d = to_dev(el)
+        with tc.Graph.build(s, d, el.n) as g:
+            say(f"[parity] export csr {el.name}")
+            off, adj = g.export_csr()
+            np.testing.assert_array_equal(off.numpy(), roff)
+            np.testing.assert_array_equal(adj.numpy(), radj)
+
+
+@pytest.mark.parametrize("budget", [24 << 10, 256 << 10, 64 << 20])
+def test_streamed_matches_oracle(tc, budget):
+    """The streamed count of a host-resident CSR equals the oracle's T for budgets that split the
+    graph into many pivot partitions and chunks and for one that holds it whole."""
+    import torch
+
+    for el in STREAM_GRAPHS:
+        roff, radj, T = _rank_csr(el)
+        say(f"[parity] streamed {el.name} budget {budget}")
+        got, info = tc.count_streamed(roff, radj, el.n, budget)
+        assert got == T, info
+        if budget == 24 << 10 and el.n >= 2000:
+            assert info["partitions"] > 1 and info["chunks"] > 1
+        # pinned host tensors and a device-resident adj give the same count
+        poff = torch.from_numpy(roff).pin_memory()
+        padj = torch.from_numpy(radj).pin_memory()
+        assert tc.count_streamed(poff, padj, el.n, budget)[0] == T
+        assert tc.count_streamed(poff, padj.cuda(), el.n, budget)[0] == T
+
+
+def test_streamed_edge_cases(tc):
+    """Empty graphs, isolated vertices, one edge, one triangle."""
+    for n, off, adj, T in ((0, [0], [], 0), (5, [0] * 6, [], 0), (2, [0, 1, 1], [1], 0),
+                           (3, [0, 2, 3, 3], [1, 2, 2], 1)):
+        got, _ = tc.count_streamed(np.array(off, np.int64), np.array(adj, np.int32), n, 4096)
+        assert got == T
+
+
+def test_streamed_errors(tc):
+    n = 4
+    good_off = np.array([0, 2, 3, 3, 3], np.int64)
+    for adj in ([2, 1, 2], [0, 2, 3], [1, 4, 3], [1, 2, 1]):  # descending, not above its row, >= n, not above row 1
+        with pytest.raises(tc.TCError):
+            tc.count_streamed(good_off, np.array(adj, np.int32), n, 1 << 20)
+    with pytest.raises(tc.TCError):  # offsets that do not start at 0
+        tc.count_streamed(np.array([1, 2, 3, 3, 3], np.int64), np.array([1, 2, 3], np.int32), n, 1 << 20)
+    with pytest.raises(tc.TCError):  # decreasing offsets
+        tc.count_streamed(np.array([0, 2, 1, 3, 3], np.int64), np.array([1, 2, 3], np.int32), n, 1 << 20)
+    with pytest.raises(tc.TCError):  # budget below the minimum
+        tc.count_streamed(good_off, np.array([1, 2, 2], np.int32), n, 1000)
+    el = synth.complete(400)  # rows of up to 399 entries: one row needs more than half of 16 KiB
+    roff, radj, _ = _rank_csr(el)
+    with pytest.raises(tc.TCError):
+        tc.count_streamed(roff, radj, el.n, 16 << 10)

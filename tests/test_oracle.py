@@ -506,3 +506,149 @@ def test_partition_boundary_rule_by_search(scheme):
         assert F[x] * p >= j * F[-1]
         assert x == 0 or F[x - 1] * p < j * F[-1]
     np.testing.assert_array_equal(work, [int(merge[bounds[j]:bounds[j + 1]].sum()) for j in range(p)])
+
+
+# ------------------------------------------------- shard and per-shard sample pins
+
+def test_partition_seed_is_splitmix64():
+    """Shard i's seed is output i+1 of SplitMix64: the published test vector for seed 1234567."""
+    with open(os.path.join(GOLDEN, "splitmix64_1234567.json")) as f:
+        ref = json.load(f)
+    got = [oracle.partition_seed(ref["seed"], i) for i in range(len(ref["outputs"]))]
+    assert got == [int(x) for x in ref["outputs"]]
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_order_positions_follow_eq1(seed):
+    """pos is a permutation and pos[u] < pos[v] exactly when u precedes v in Eq. (1)."""
+    rng = np.random.default_rng(500 + seed)
+    n = int(rng.integers(1, 60))
+    key = rng.integers(0, 6, n)
+    pos = oracle.order_positions(key, n)
+    assert sorted(pos.tolist()) == list(range(n))
+    for u in range(n):
+        for v in range(n):
+            if u != v:
+                assert (pos[u] < pos[v]) == (key[u] < key[v] or (key[u] == key[v] and u < v))
+
+
+def _triangles_by_lowest_position(n, src, dst, pos):
+    """Brute force over vertex triples: the number of triangles whose lowest-positioned vertex is at p."""
+    T, _, tris, _ = brute(n, src, dst)
+    per = np.zeros(max(n, 1), np.int64)
+    for tr in tris.tolist():
+        per[min(pos[x] for x in tr)] += 1
+    return T, per
+
+
+@pytest.mark.parametrize("seed", range(8))
+def test_count_by_position_range_brute_force(seed):
+    """NodeIteratorN over core nodes [p0, p1) counts exactly the triangles whose lowest vertex lies there."""
+    rng = np.random.default_rng(600 + seed)
+    n = int(rng.integers(1, 40))
+    src, dst = messy_random_graph(n, int(rng.integers(0, 5 * n + 1)), seed)
+    lo, hi = oracle.simple(src, dst, n)
+    deg = oracle.degrees(lo, hi, n)
+    off, adj = oracle.orient(lo, hi, deg, n)
+    pos = oracle.order_positions(deg, n)
+    T, per = _triangles_by_lowest_position(n, src, dst, pos)
+    for p in range(n):
+        assert oracle.count_nin_pos_range(off, adj, n, pos, p, p + 1) == per[p]
+    for _ in range(6):
+        a, b = sorted(rng.integers(0, n + 1, 2).tolist())
+        assert oracle.count_nin_pos_range(off, adj, n, pos, a, b) == int(per[a:b].sum())
+    assert oracle.count_nin_pos_range(off, adj, n, pos, 0, n) == T
+
+
+def test_shard_bounds_matching_closed_form():
+    """A perfect matching of M edges: every vertex has degree 1, so positions are ids; the even end
+    of each edge has f = 1 and the odd end f = 0, hence F(p) = floor(p/2) + 1 and the j-th boundary
+    is 2 (ceil(j M / k) - 1)."""
+    M, k = 501, 7
+    n = 2 * M
+    src = np.arange(0, n, 2, dtype=np.int32)
+    dst = src + 1
+    lo, hi = oracle.simple(src, dst, n)
+    deg = oracle.degrees(lo, hi, n)
+    off, adj = oracle.orient(lo, hi, deg, n)
+    pos = oracle.order_positions(deg, n)
+    b = oracle.shard_bounds(off, adj, n, pos, k)
+    assert b.tolist() == [0] + [2 * (-(-j * M // k) - 1) for j in range(1, k)] + [n]
+
+
+@pytest.mark.parametrize("k", [1, 2, 9, 64])
+def test_shard_bounds_by_search(k):
+    """Boundaries agree with a search on the cumulative merge cost by position (cost recomputed
+    from the oriented lists here), and the costs add up to W (Theorem 2)."""
+    g = synth.ba(2500, 6, 3)
+    lo, hi = oracle.simple(g.src, g.dst, g.n)
+    deg = oracle.degrees(lo, hi, g.n)
+    off, adj = oracle.orient(lo, hi, deg, g.n)
+    pos = oracle.order_positions(deg, g.n)
+    dh = np.diff(off).astype(np.int64)
+    src = np.repeat(np.arange(g.n), np.diff(off))
+    merge = np.bincount(src, weights=(dh[src] + dh[adj]).astype(np.float64), minlength=g.n).astype(np.int64)
+    assert int(merge.sum()) == oracle.work(off, adj, g.n)
+    f = np.zeros(g.n, np.int64)
+    f[pos] = merge
+    F = np.cumsum(f)
+    b = oracle.shard_bounds(off, adj, g.n, pos, k)
+    assert b[0] == 0 and b[-1] == g.n and (np.diff(b) >= 0).all()
+    for j in range(1, k):
+        x = int(b[j])
+        assert F[x] * k >= j * F[-1]
+        assert x == 0 or F[x - 1] * k < j * F[-1]
+
+
+def test_partitioned_sample_with_one_shard_is_the_plain_sample():
+    """One shard: the partitioned estimator is the sample of Section 7 under seed_0."""
+    g = synth.rmat(10, 8, 21)
+    lo, hi = oracle.simple(g.src, g.dst, g.n)
+    deg = oracle.degrees(lo, hi, g.n)
+    for q in (0.2, 0.7):
+        parts, b, Ts, est = oracle.sparsified_count_partitioned(lo, hi, deg, g.n, q, 99, 1)
+        ref = oracle.sparsified_count(lo, hi, deg, g.n, q, oracle.partition_seed(99, 0))
+        assert parts == [ref[0]] and Ts == ref[0] and est == ref[2]
+
+
+def _book(t):
+    """Book graph: spine edge (0,1) and t pages p >= 2 joined to both spine ends."""
+    pages = np.arange(2, t + 2, dtype=np.int32)
+    src = np.concatenate([[0], pages, pages]).astype(np.int32)
+    dst = np.concatenate([[1], np.zeros(t, np.int32), np.ones(t, np.int32)]).astype(np.int32)
+    return t + 2, src, dst
+
+
+def _edge_sharing_pairs(n, src, dst, pos, bounds):
+    """k = pairs of triangles sharing an edge; k' = those whose lowest vertices lie in one shard."""
+    _, _, tris, _ = brute(n, src, dst)
+    shard = np.searchsorted(np.asarray(bounds), np.arange(n), side="right") - 1  # by position
+    by_edge = {}
+    for tr in tris.tolist():
+        owner = int(shard[min(pos[x] for x in tr)])
+        for a, b in itertools.combinations(sorted(tr), 2):
+            by_edge.setdefault((a, b), []).append(owner)
+    k = sum(len(v) * (len(v) - 1) // 2 for v in by_edge.values())
+    kp = sum(sum(c * (c - 1) // 2 for c in np.bincount(v).tolist()) for v in by_edge.values())
+    return len(tris), k, kp
+
+
+def test_partitioned_sample_unbiased_with_var2():
+    """Monte Carlo over seeds on a book graph (every triangle shares the spine): both estimators are
+    unbiased; the plain sample has the variance (1/q^3 - 1) T + 2 k (1/q - 1) and the per-shard sample
+    (1/q^3 - 1) T + 2 k' (1/q - 1) (Section 7, Eq. var2), with k, k' counted by brute force."""
+    n, src, dst = _book(48)
+    lo, hi = oracle.simple(src, dst, n)
+    deg = oracle.degrees(lo, hi, n)
+    pos = oracle.order_positions(deg, n)
+    q, parts, S = 0.5, 8, 3000
+    _, bounds, _, _ = oracle.sparsified_count_partitioned(lo, hi, deg, n, q, 0, parts)
+    T, k, kp = _edge_sharing_pairs(n, src, dst, pos, bounds)
+    assert T == 48 and k == 48 * 47 // 2 and kp < k // 4
+    var1 = (1 / q ** 3 - 1) * T + 2 * k * (1 / q - 1)
+    var2 = (1 / q ** 3 - 1) * T + 2 * kp * (1 / q - 1)
+    plain = np.array([oracle.sparsified_count(lo, hi, deg, n, q, 1000 + s)[2] for s in range(S)])
+    part = np.array([oracle.sparsified_count_partitioned(lo, hi, deg, n, q, 1000 + s, parts)[3] for s in range(S)])
+    for est, var in ((plain, var1), (part, var2)):
+        assert abs(est.mean() - T) < 5 * math.sqrt(var / S)
+        assert 0.8 * var < est.var(ddof=1) < 1.25 * var
