@@ -36,7 +36,7 @@ sys.path.insert(0, ROOT)
 METRIC = "exact-count oriented edges/s vs plain kernel; served graphs/s + p50/p99 latency"
 HBM_PEAK_GBS = 8000.0
 PROFILE_SUMMARY = os.path.join(ROOT, "profiles", "k_pivot_rmat26_traffic.json")
-KERNEL_SOURCE = os.path.join(ROOT, "paper_1706_05151_amd", "csrc", "count.hip")
+KERNEL_SOURCE = os.path.join(ROOT, "paper_1706_05151_amd", "csrc", "pivot_kernel.hpp")
 
 
 def log(*a):

@@ -229,14 +229,14 @@ tc_status tc_graph_export_csr(tc_graph* g, void* stream, int64_t* off, int32_t* 
 /*
  * Exact T of an oriented CSR kept in host memory, streamed through the GPU
  * under a device-memory budget (the non-overlapping partitions of Section 6,
- * with the surrogate pairing). The rows are split into pivot partitions V_j
- * and source chunks, each sized to about half of budget_bytes. The rows of
- * each V_j are loaded once. Every chunk of rows that start before the end of
- * V_j is then shipped to it once (N_v goes to the owner of u once per chunk,
- * not once per edge). There the in-edge records (v,u), u in V_j, count
- * |N_v after u ∩ N_u| with the pivot kernel. Each triangle is counted once,
- * at the partition of its middle vertex. The next chunk is copied in while
- * the current one is counted.
+ * with the surrogate pairing). The rows are split into pivot partitions V_j,
+ * each sized to about half of budget_bytes. The rows of each V_j are loaded
+ * once and serve as their own sources. The rows before V_j are shipped to it
+ * in chunks sized to the other half (N_v goes to the owner of u once per
+ * chunk, not once per edge). For each source range, the in-edge records
+ * (v,u), u in V_j, count |N_v after u ∩ N_u| with the pivot kernel. Each
+ * triangle is counted once, at the partition of its middle vertex. The next
+ * chunk is copied in while the current one is counted.
  *
  * Input: off host int64[n+1] with off[0] = 0 and off[n] = m; adj int32[m]
  * (host, pinned for full copy speed, or device memory). Row r must hold
@@ -247,8 +247,9 @@ tc_status tc_graph_export_csr(tc_graph* g, void* stream, int64_t* off, int32_t* 
  * arguments and budget_bytes < 4096. TC_E_NOMEM if one row alone does not fit
  * half the budget. The budget covers the copies, records and plans; the
  * kernel's counters come on top. Output: *T. info (may be NULL) gets uint64[4]:
- * pivot partitions, chunks, (partition, chunk) pairs visited, bytes copied to
- * the device. Runs on the current device. Synchronises `stream`.
+ * pivot partitions, chunks shipped, (partition, source range) pairs visited,
+ * bytes copied to the device. Runs on the current device. Synchronises
+ * `stream`.
  */
 tc_status tc_count_streamed(const int64_t* off, const int32_t* adj, int32_t n, int64_t m, uint64_t budget_bytes,
                             void* stream, uint64_t* T, uint64_t* info);

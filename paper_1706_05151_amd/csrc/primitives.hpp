@@ -103,39 +103,64 @@ void exclusive_scan(const T* in, T* out, size_t N, hipStream_t s, T* total_dev =
 // ============================================================ compaction ===
 
 // Pred: __device__ bool operator()(size_t i) const; Gen: __device__ T operator()(size_t i) const.
+//
+// Two passes over wave-strided chunks: wave w of a block takes elements
+// [c, c + 64 * kFlagWords) of its block's range, word j covering
+// c + 64 j + lane. The first pass evaluates pred once per element, keeps the
+// ballot of every word and counts the block; the second reads the ballots back,
+// so pred runs once and loads are coalesced.
+
+constexpr int kFlagWords = 16;                               // 64-element words per wave
+constexpr int kFlagWaves = kScanBlock / kWave;
+constexpr size_t kFlagChunk = static_cast<size_t>(kScanBlock) * kFlagWords;  // elements per block
+
 template <typename Pred>
-__global__ __launch_bounds__(kScanBlock) void k_count_if(size_t N, Pred pred, uint64_t* __restrict__ counts) {
-  __shared__ uint64_t sm[kScanBlock / kWave];
-  const size_t base = static_cast<size_t>(blockIdx.x) * kScanChunk + static_cast<size_t>(threadIdx.x) * kScanItems;
+__global__ __launch_bounds__(kScanBlock) void k_flag_count(size_t N, Pred pred, uint64_t* __restrict__ flags,
+                                                           uint64_t* __restrict__ counts) {
+  __shared__ uint64_t sm[kFlagWaves];
+  const int w = threadIdx.x / kWave, lane = lane_id();
+  const size_t word0 = (static_cast<size_t>(blockIdx.x) * kFlagWaves + w) * kFlagWords;
   uint64_t c = 0;
 #pragma unroll
-  for (int j = 0; j < kScanItems; j++) {
-    size_t i = base + j;
-    if (i < N && pred(i)) c++;
+  for (int j = 0; j < kFlagWords; j++) {
+    const size_t i = (word0 + j) * kWave + lane;
+    const uint64_t b = __ballot(i < N && pred(i));
+    if (lane == 0) flags[word0 + j] = b;
+    c += static_cast<uint64_t>(__popcll(b));
   }
-  uint64_t tot;
-  (void)block_excl_scan<uint64_t, kScanBlock>(c, sm, tot);
-  if (threadIdx.x == 0) counts[blockIdx.x] = tot;
+  if (lane == 0) sm[w] = c;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    uint64_t t = 0;
+    for (int x = 0; x < kFlagWaves; x++) t += sm[x];
+    counts[blockIdx.x] = t;
+  }
 }
 
-template <typename T, typename Pred, typename Gen>
-__global__ __launch_bounds__(kScanBlock) void k_compact(size_t N, Pred pred, Gen gen, T* __restrict__ out,
-                                                         const uint64_t* __restrict__ offs) {
-  __shared__ uint64_t sm[kScanBlock / kWave];
-  const size_t base = static_cast<size_t>(blockIdx.x) * kScanChunk + static_cast<size_t>(threadIdx.x) * kScanItems;
-  bool f[kScanItems];
+template <typename T, typename Gen>
+__global__ __launch_bounds__(kScanBlock) void k_flag_compact(size_t N, const uint64_t* __restrict__ flags, Gen gen,
+                                                             T* __restrict__ out, const uint64_t* __restrict__ offs) {
+  __shared__ uint64_t sm[kFlagWaves];
+  const int w = threadIdx.x / kWave, lane = lane_id();
+  const size_t word0 = (static_cast<size_t>(blockIdx.x) * kFlagWaves + w) * kFlagWords;
+  const size_t nwords = (N + kWave - 1) / kWave;
+  uint64_t b[kFlagWords];
   uint64_t c = 0;
 #pragma unroll
-  for (int j = 0; j < kScanItems; j++) {
-    size_t i = base + j;
-    f[j] = i < N && pred(i);
-    c += f[j];
+  for (int j = 0; j < kFlagWords; j++) {
+    b[j] = word0 + j < nwords ? flags[word0 + j] : 0ull;
+    c += static_cast<uint64_t>(__popcll(b[j]));
   }
-  uint64_t tot;
-  uint64_t pos = offs[blockIdx.x] + block_excl_scan<uint64_t, kScanBlock>(c, sm, tot);
+  if (lane == 0) sm[w] = c;
+  __syncthreads();
+  uint64_t pos = offs[blockIdx.x];
+  for (int x = 0; x < w; x++) pos += sm[x];
+  const uint64_t lt = lanemask_lt();
 #pragma unroll
-  for (int j = 0; j < kScanItems; j++)
-    if (f[j]) out[pos++] = gen(base + j);
+  for (int j = 0; j < kFlagWords; j++) {
+    if ((b[j] >> lane) & 1ull) out[pos + static_cast<uint64_t>(__popcll(b[j] & lt))] = gen((word0 + j) * kWave + lane);
+    pos += static_cast<uint64_t>(__popcll(b[j]));
+  }
 }
 
 // Writes gen(i) for every i in [0,N) with pred(i), in index order, to out.
@@ -147,12 +172,12 @@ void compact_if(size_t N, Pred pred, Gen gen, T* out, uint64_t* count_dev, hipSt
     TC_LAUNCH_CHECK();
     return;
   }
-  const size_t nb = (N + kScanChunk - 1) / kScanChunk;
-  DevBuf<uint64_t> cnt(nb, s);
-  k_count_if<Pred><<<static_cast<unsigned>(nb), kScanBlock, 0, s>>>(N, pred, cnt.get());
+  const size_t nb = (N + kFlagChunk - 1) / kFlagChunk;
+  DevBuf<uint64_t> cnt(nb, s), flags(nb * kFlagWaves * kFlagWords, s);
+  k_flag_count<Pred><<<static_cast<unsigned>(nb), kScanBlock, 0, s>>>(N, pred, flags.get(), cnt.get());
   TC_LAUNCH_CHECK();
   exclusive_scan<uint64_t>(cnt.get(), cnt.get(), nb, s, count_dev);
-  k_compact<T, Pred, Gen><<<static_cast<unsigned>(nb), kScanBlock, 0, s>>>(N, pred, gen, out, cnt.get());
+  k_flag_compact<T, Gen><<<static_cast<unsigned>(nb), kScanBlock, 0, s>>>(N, flags.get(), gen, out, cnt.get());
   TC_LAUNCH_CHECK();
 }
 

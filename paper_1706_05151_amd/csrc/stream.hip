@@ -3,19 +3,20 @@
 //
 // The oriented CSR in rank space (row r holds later ranks, ascending) stays
 // on the host. The rows are split into pivot partitions V_j, each sized to
-// half of the device budget, and into source chunks sized to the other half.
-// For each j, the rows of V_j are loaded once. Every chunk of rows that start
-// before the end of V_j is then shipped to it: the surrogate pairing of
-// Section 6, where N_v travels to the partition owning u once per
-// (chunk, partition), and not once per edge. Triangle (v,u,w), v < u < w, is
-// counted where u lives: |N_v after u ∩ N_u| from the in-edge record (v,u),
-// by the pivot kernel of the in-memory path. Each (chunk, partition) pair is
-// visited once, and each triangle is counted once.
+// half of the device budget. For each j, the rows of V_j are loaded once and
+// serve as their own sources. The rows before V_j are then shipped to it in
+// chunks sized to the other half: the surrogate pairing of Section 6, where
+// N_v travels to the partition owning u once per (chunk, partition), and not
+// once per edge. Triangle (v,u,w), v < u < w, is counted where u lives:
+// |N_v after u ∩ N_u| from the in-edge record (v,u), by the pivot kernel of
+// the in-memory path. Each (source rows, partition) pair is visited once, and
+// each triangle is counted once.
 //
 // Device layout of one (partition, chunk) pair, one CSR with local rows:
 //   rows [0, np)            the rows of V_j (adj entries [0, ep))
 //   row  np                 an empty gap spanning [ep, cap_p)
-//   rows (np, np + 1 + nc]  the chunk's rows (adj entries from cap_p)
+//   rows (np, np + 1 + nc]  a shipped chunk's rows (adj entries from cap_p)
+// Resident sources use rows [0, np) alone.
 // Entries keep their global ranks, and the pivot kernel only compares them.
 // Records (v,u) are keyed by u's local row. The next chunk is copied into a
 // staging buffer on a second stream while the current pair is counted.
@@ -97,18 +98,17 @@ struct Range {
   int64_t e0, e1;  // entries [off[lo], off[hi])
 };
 
-// Splits rows [0, n) into consecutive ranges of cost eb * entries + rb * rows
+// Splits rows [lo, hi) into consecutive ranges of cost eb * entries + rb * rows
 // <= cap (greedy, each range as long as fits); fails if one row alone exceeds it.
-std::vector<Range> split_rows(const int64_t* off, int32_t n, uint64_t cap, uint64_t eb, uint64_t rb) {
+std::vector<Range> split_rows(const int64_t* off, int32_t lo, int32_t hi, uint64_t cap, uint64_t eb, uint64_t rb) {
   std::vector<Range> out;
-  int32_t lo = 0;
   auto cost = [&](int32_t a, int32_t b) {
     return eb * static_cast<uint64_t>(off[b] - off[a]) + rb * static_cast<uint64_t>(b - a);
   };
-  while (lo < n) {
+  while (lo < hi) {
     if (cost(lo, lo + 1) > cap || off[lo + 1] - off[lo] >= kMaxRegionEntries)
       fail(TC_E_NOMEM, "device budget too small for one adjacency row");
-    int32_t a = lo + 1, b = n;  // the largest hi in [lo+1, n] that fits
+    int32_t a = lo + 1, b = hi;  // the largest end in [lo+1, hi] that fits
     while (a < b) {
       const int32_t mid = a + (b - a + 1) / 2;
       if (cost(lo, mid) <= cap && off[mid] - off[lo] < kMaxRegionEntries) a = mid;
@@ -119,6 +119,15 @@ std::vector<Range> split_rows(const int64_t* off, int32_t n, uint64_t cap, uint6
   }
   return out;
 }
+
+// One visit: the records (v,u) with v in rows `src` and u in pivot partition
+// `part`; shipped sources come through the staging buffer, resident ones are
+// rows of the partition itself.
+struct Task {
+  int part;
+  bool shipped;
+  Range src;
+};
 
 // A CSR whose arrays belong to someone else (cleared before destruction).
 struct CsrView {
@@ -148,20 +157,30 @@ uint64_t count_streamed(const int64_t* off, const int32_t* adj, int32_t n, int64
                         hipStream_t s, const Options& o, uint64_t info[4]) {
   info[0] = info[1] = info[2] = info[3] = 0;
   if (n <= 0 || m == 0) return 0;
-  const std::vector<Range> parts = split_rows(off, n, budget / 2, kPivotEntryBytes, kPivotRowBytes);
-  const std::vector<Range> chunks = split_rows(off, n, budget / 2, kChunkEntryBytes, kChunkRowBytes);
+  const std::vector<Range> parts = split_rows(off, 0, n, budget / 2, kPivotEntryBytes, kPivotRowBytes);
+  // visiting order: for each partition, its own rows (resident) and then the
+  // rows before it, shipped in chunks
+  std::vector<Task> tasks;
+  for (int j = 0; j < static_cast<int>(parts.size()); j++) {
+    for (const Range& r : split_rows(off, parts[j].lo, parts[j].hi, budget / 2, kChunkEntryBytes, kChunkRowBytes))
+      tasks.push_back(Task{j, false, r});
+    for (const Range& r : split_rows(off, 0, parts[j].lo, budget / 2, kChunkEntryBytes, kChunkRowBytes))
+      tasks.push_back(Task{j, true, r});
+  }
   int64_t cap_p = 0, cap_c = 0;
   int32_t rows_p = 0, rows_c = 0;
   for (const Range& r : parts) {
     cap_p = std::max(cap_p, r.e1 - r.e0);
     rows_p = std::max(rows_p, r.hi - r.lo);
   }
-  for (const Range& r : chunks) {
-    cap_c = std::max(cap_c, r.e1 - r.e0);
-    rows_c = std::max(rows_c, r.hi - r.lo);
+  for (const Task& t : tasks) {
+    if (!t.shipped) continue;
+    cap_c = std::max(cap_c, t.src.e1 - t.src.e0);
+    rows_c = std::max(rows_c, t.src.hi - t.src.lo);
+    info[1]++;
   }
   info[0] = parts.size();
-  info[1] = chunks.size();
+  info[2] = tasks.size();
 
   DevBuf<int32_t> adj_d(static_cast<size_t>(cap_p + cap_c), s), src_d(static_cast<size_t>(cap_p + cap_c), s);
   DevBuf<int64_t> off_d(static_cast<size_t>(rows_p) + rows_c + 3, s);
@@ -172,12 +191,6 @@ uint64_t count_streamed(const int64_t* off, const int32_t* adj, int32_t n, int64
   fill_u64(total.get(), 1, 0ull, s);
   k_fill_words<uint32_t><<<1, 64, 0, s>>>(bad.get(), 1, 0u);
   TC_LAUNCH_CHECK();
-
-  // the (partition, chunk) pairs in visiting order: chunks that start before the partition ends
-  std::vector<std::pair<int, int>> pairs;
-  for (int j = 0; j < static_cast<int>(parts.size()); j++)
-    for (int k = 0; k < static_cast<int>(chunks.size()) && chunks[k].lo < parts[j].hi; k++) pairs.emplace_back(j, k);
-  info[2] = pairs.size();
 
   hipStream_t cs = nullptr;
   TC_HIP(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
@@ -193,8 +206,13 @@ uint64_t count_streamed(const int64_t* off, const int32_t* adj, int32_t n, int64
     TC_HIP(hipEventCreateWithFlags(&loaded, hipEventDisableTiming));
     TC_HIP(hipEventCreateWithFlags(&freed, hipEventDisableTiming));
     uint64_t h2d = 0;
-    auto prefetch = [&](int k) {  // chunk k into the staging buffers, on the copy stream
-      const Range& r = chunks[k];
+    auto next_shipped = [&](size_t from) {
+      while (from < tasks.size() && !tasks[from].shipped) from++;
+      return from;
+    };
+    auto prefetch = [&](size_t q) {  // task q's rows into the staging buffers, on the copy stream
+      if (q >= tasks.size()) return;
+      const Range& r = tasks[q].src;
       TC_HIP(hipStreamWaitEvent(cs, freed, 0));
       if (r.e1 > r.e0)
         TC_HIP(hipMemcpyAsync(stage_adj.get(), adj + r.e0, static_cast<size_t>(r.e1 - r.e0) * sizeof(int32_t),
@@ -205,18 +223,19 @@ uint64_t count_streamed(const int64_t* off, const int32_t* adj, int32_t n, int64
       h2d += static_cast<uint64_t>(r.e1 - r.e0) * sizeof(int32_t) + (static_cast<uint64_t>(r.hi - r.lo) + 1) * 8;
     };
     TC_HIP(hipEventRecord(freed, s));
-    prefetch(pairs[0].second);
+    prefetch(next_shipped(0));
     int cur_part = -1;
     int32_t dhat_p = 0;
     CountArgs ca;
     ca.mode = kCountTotal;
     ca.total = total.get();
-    for (size_t q = 0; q < pairs.size(); q++) {
-      const Range& P = parts[pairs[q].first];
-      const Range& C = chunks[pairs[q].second];
+    for (size_t q = 0; q < tasks.size(); q++) {
+      const Task& t = tasks[q];
+      const Range& P = parts[t.part];
+      const Range& C = t.src;
       const int32_t np = P.hi - P.lo, nc = C.hi - C.lo;
-      if (pairs[q].first != cur_part) {  // load the rows of V_j (on the counting stream)
-        cur_part = pairs[q].first;
+      if (t.part != cur_part) {  // load the rows of V_j (on the counting stream)
+        cur_part = t.part;
         if (P.e1 > P.e0)
           TC_HIP(hipMemcpyAsync(adj_d.get(), adj + P.e0, static_cast<size_t>(P.e1 - P.e0) * sizeof(int32_t),
                                 hipMemcpyDefault, s));
@@ -226,33 +245,40 @@ uint64_t count_streamed(const int64_t* off, const int32_t* adj, int32_t n, int64
         k_rebase<<<grid_for(static_cast<uint64_t>(np) + 1, kBlock, 65536), kBlock, 0, s>>>(pin_off.get(), np, 0,
                                                                                          off_d.get(), bad.get());
         TC_LAUNCH_CHECK();
-        k_check_rows<<<grid_for(np, kBlock, 65536), kBlock, 0, s>>>(off_d.get(), adj_d.get(), np, 0, P.lo, n, nullptr,
-                                                                    bad.get());
+        k_check_rows<<<grid_for(np, kBlock, 65536), kBlock, 0, s>>>(off_d.get(), adj_d.get(), np, 0, P.lo, n,
+                                                                    src_d.get(), bad.get());
         TC_LAUNCH_CHECK();
         dhat_p = max_row_length(off_d.get(), np, s);
       }
-      // the chunk: staged copy into the combined arrays, rows after the gap row np
-      TC_HIP(hipStreamWaitEvent(s, loaded, 0));
-      if (C.e1 > C.e0)
-        TC_HIP(hipMemcpyAsync(adj_d.get() + cap_p, stage_adj.get(), static_cast<size_t>(C.e1 - C.e0) * sizeof(int32_t),
-                              hipMemcpyDeviceToDevice, s));
-      k_rebase<<<grid_for(static_cast<uint64_t>(nc) + 1, kBlock, 65536), kBlock, 0, s>>>(
-          stage_off.get(), nc, cap_p, off_d.get() + np + 1, bad.get());
-      TC_LAUNCH_CHECK();
-      TC_HIP(hipEventRecord(freed, s));
-      if (q + 1 < pairs.size()) prefetch(pairs[q + 1].second);
-      k_check_rows<<<grid_for(nc, kBlock, 65536), kBlock, 0, s>>>(off_d.get(), adj_d.get(), nc, np + 1, C.lo, n,
-                                                                  src_d.get(), bad.get());
-      TC_LAUNCH_CHECK();
+      CsrView w(off_d.get(), adj_d.get(), src_d.get());
+      w.c.dhat_max = dhat_p;
+      int64_t e_begin = 0;  // the source entries in the combined adj
+      uint64_t ec = static_cast<uint64_t>(C.e1 - C.e0);
+      if (t.shipped) {  // the staged rows after the gap row np
+        TC_HIP(hipStreamWaitEvent(s, loaded, 0));
+        if (ec)
+          TC_HIP(hipMemcpyAsync(adj_d.get() + cap_p, stage_adj.get(), ec * sizeof(int32_t), hipMemcpyDeviceToDevice,
+                                s));
+        k_rebase<<<grid_for(static_cast<uint64_t>(nc) + 1, kBlock, 65536), kBlock, 0, s>>>(
+            stage_off.get(), nc, cap_p, off_d.get() + np + 1, bad.get());
+        TC_LAUNCH_CHECK();
+        TC_HIP(hipEventRecord(freed, s));
+        prefetch(next_shipped(q + 1));
+        k_check_rows<<<grid_for(nc, kBlock, 65536), kBlock, 0, s>>>(off_d.get(), adj_d.get(), nc, np + 1, C.lo, n,
+                                                                    src_d.get(), bad.get());
+        TC_LAUNCH_CHECK();
+        w.c.n = np + 1 + nc;
+        w.c.m = cap_p + static_cast<int64_t>(ec);
+        e_begin = cap_p;
+      } else {  // rows of the partition itself
+        w.c.n = np;
+        w.c.m = P.e1 - P.e0;
+        e_begin = C.e0 - P.e0;
+      }
       if (read_flags(bad.get(), s)) fail(TC_E_INVAL, "rows must hold ascending ranks above their own row, below n");
       // records (v,u) with u in V_j, sorted by u's local row
-      CsrView w(off_d.get(), adj_d.get(), src_d.get());
-      w.c.n = np + 1 + nc;
-      w.c.m = cap_p + (C.e1 - C.e0);
-      w.c.dhat_max = dhat_p;
-      const uint64_t ec = static_cast<uint64_t>(C.e1 - C.e0);
       DevBuf<uint64_t> keys(ec, s), keys2(ec, s), cnt(1, s);
-      compact_if<uint64_t>(ec, IntoPivots{adj_d.get(), cap_p, P.lo, P.hi}, PivotKey{adj_d.get(), cap_p, P.lo},
+      compact_if<uint64_t>(ec, IntoPivots{adj_d.get(), e_begin, P.lo, P.hi}, PivotKey{adj_d.get(), e_begin, P.lo},
                            keys.get(), cnt.get(), s);
       uint64_t mi = 0;
       TC_HIP(hipMemcpyAsync(&mi, cnt.get(), sizeof(mi), hipMemcpyDeviceToHost, s));

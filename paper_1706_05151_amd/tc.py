@@ -369,7 +369,7 @@ def sparsify_estimate(Ts: int, q: float) -> float:
 def count_streamed(off, adj, n: int, budget_bytes: int, stream=None):
     """Exact T of a rank-space oriented CSR held in host memory (off: int64[n+1] host tensor or array,
     adj: int32[m] host or device), streamed through the GPU within budget_bytes of device memory.
-    Returns (T, {"partitions", "chunks", "pairs", "bytes_in"})."""
+    Returns (T, {"partitions", "chunks" (shipped), "pairs" (partition, source range), "bytes_in"})."""
     m = int(off[n])
     T = _u64()
     info = (ctypes.c_uint64 * 4)()
