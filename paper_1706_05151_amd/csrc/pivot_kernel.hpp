@@ -225,7 +225,7 @@ __device__ __forceinline__ void emit_triangle(const KernelArgs& a, int32_t v, in
 //     kPerLane consecutive ones, finding the owner by binary search.
 
 constexpr int kPerLane = 4;
-constexpr uint32_t kLongMin = 64;
+constexpr uint32_t kLongMin = 128;
 constexpr uint32_t kSeg = kWave * kPerLane;
 
 // Record arrays of one batch of NR records (NR = 256 for a block, 64 for a wave).
@@ -252,6 +252,125 @@ __device__ __forceinline__ uint32_t probe_one(const KernelArgs& a, int32_t u, in
   return 1u;
 }
 
+// Totals only: kPerLane probes of one lane against one table form at once,
+// with no branch between them, so their LDS reads are in flight together.
+// Bitmap form: an element outside the staged range (the kEmpty filler lies
+// below every rank) reads word 0 and is masked off. Hash form: every filter
+// word is read, then every bucket (lanes without a filter hit read bucket 0,
+// their result masked off); only elements whose full home bucket did not
+// hold them search the buckets they spill into.
+template <bool kBitmap, bool kAllValid>
+__device__ __forceinline__ uint32_t count_probes(const Table& t, const int32_t (&x)[kPerLane]) {
+  uint32_t c = 0;
+  if constexpr (kBitmap) {
+    const uint32_t* W = reinterpret_cast<const uint32_t*>(t.T);
+    uint32_t d[kPerLane], w[kPerLane];
+    bool in[kPerLane];
+#pragma unroll
+    for (int i = 0; i < kPerLane; i++) {
+      d[i] = static_cast<uint32_t>(x[i] - t.lo);
+      in[i] = d[i] < t.span;
+    }
+#pragma unroll
+    for (int i = 0; i < kPerLane; i++) w[i] = W[in[i] ? d[i] >> 5 : 0u];
+#pragma unroll
+    for (int i = 0; i < kPerLane; i++) c += in[i] ? (w[i] >> (d[i] & 31u)) & 1u : 0u;
+  } else {
+#pragma unroll
+    for (int h0 = 0; h0 < kPerLane; h0 += 2) {
+      uint32_t b[2], fs[2], f[2];
+      bool hit[2];
+#pragma unroll
+      for (int i = 0; i < 2; i++) {
+        const uint32_t h = hash_of(x[h0 + i]);
+        b[i] = home_bucket(h, t.log2b);
+        fs[i] = filter_shift(h, t.log2b);
+      }
+#pragma unroll
+      for (int i = 0; i < 2; i++) f[i] = t.F[b[i]];
+#pragma unroll
+      for (int i = 0; i < 2; i++) hit[i] = (kAllValid || x[h0 + i] != kEmpty) && ((f[i] >> fs[i]) & 1u);
+      int4 q[2];
+#pragma unroll
+      for (int i = 0; i < 2; i++) q[i] = reinterpret_cast<const int4*>(t.T)[hit[i] ? b[i] : 0u];
+      bool spill = false;
+#pragma unroll
+      for (int i = 0; i < 2; i++) {
+        const bool found = hit[i] && bucket_miss(q[i], x[h0 + i]) == 0;
+        c += found ? 1u : 0u;
+        spill = spill || (hit[i] && !found && q[i].w != kEmpty);
+      }
+      if (spill) {
+#pragma unroll
+        for (int i = 0; i < 2; i++)
+          if (hit[i] && bucket_miss(q[i], x[h0 + i]) != 0 && q[i].w != kEmpty)
+            c += bt_find_spilled(t.T, t.log2b, b[i], x[h0 + i]) >= 0 ? 1u : 0u;
+      }
+    }
+  }
+  return c;
+}
+
+// Totals only: the long records of probe_long with one table form.
+template <bool kBitmap, int NR>
+__device__ __forceinline__ uint32_t count_long(const KernelArgs& a, const BatchLds<NR>& B, uint32_t nrec, uint32_t w0,
+                                               uint32_t stride, const Table& tab) {
+  const int lane = lane_id();
+  uint32_t cnt = 0;
+  for (uint32_t j = w0; j < nrec; j += stride) {
+    const uint32_t len = __builtin_amdgcn_readfirstlane(B.len[j]);
+    if (len < kLongMin) continue;
+    const uint32_t beg = __builtin_amdgcn_readfirstlane(B.beg[j]);
+    uint32_t k0 = 0;
+    for (; k0 + kSeg <= len; k0 += kSeg) {
+      const int32_t* wbase = a.adj + beg + k0;
+      int32_t x[kPerLane];
+#pragma unroll
+      for (int i = 0; i < kPerLane; i++) x[i] = wbase[lane + kWave * i];
+      cnt += count_probes<kBitmap, true>(tab, x);
+    }
+    if (k0 < len) {
+      const uint32_t rem = len - k0;
+      int32_t x[kPerLane];
+#pragma unroll
+      for (int i = 0; i < kPerLane; i++) {
+        const uint32_t k = static_cast<uint32_t>(lane + kWave * i);
+        x[i] = k < rem ? a.adj[beg + k0 + k] : kEmpty;
+      }
+      cnt += count_probes<kBitmap, false>(tab, x);
+    }
+  }
+  return cnt;
+}
+
+// Totals only: the concatenated short-record elements of probe_short with one table form.
+template <bool kBitmap, int NR>
+__device__ __forceinline__ uint32_t count_short(const KernelArgs& a, const BatchLds<NR>& B, uint32_t tot, int slot,
+                                                int width, const Table& tab) {
+  uint32_t cnt = 0;
+  for (uint32_t k0 = 0; k0 < tot; k0 += static_cast<uint32_t>(width) * kPerLane) {
+    const uint32_t kb = k0 + static_cast<uint32_t>(slot) * kPerLane;
+    int j = 0;
+    if (kb < tot) {
+#pragma unroll
+      for (int step = NR / 2; step > 0; step >>= 1)
+        if (B.spre[j + step] <= kb) j += step;  // j + step <= NR - 1
+    }
+    int32_t x[kPerLane];
+#pragma unroll
+    for (int i = 0; i < kPerLane; i++) {
+      const uint32_t k = kb + i;
+      x[i] = kEmpty;
+      if (k < tot) {
+        while (B.spre[j + 1] <= k) j++;  // stops at j = NR - 1 because spre[NR] = tot > k
+        x[i] = a.adj[B.beg[j] + (k - B.spre[j])];
+      }
+    }
+    cnt += count_probes<kBitmap, false>(tab, x);
+  }
+  return cnt;
+}
+
 // Long records of the batch, wave `w0` of `stride` taking records w0,
 // w0+stride, ...: the wave walks a record's suffix in windows of kSeg
 // elements, lane L reading elements L, L+64, L+128, L+192 of the window.
@@ -259,6 +378,8 @@ template <int MODE, int NR>
 __device__ __forceinline__ uint32_t probe_long(const KernelArgs& a, int32_t u, const BatchLds<NR>& B, uint32_t nrec,
                                                uint32_t w0, uint32_t stride, const Table& tab,
                                                uint32_t* hits) {
+  if constexpr (MODE == kCountTotal)
+    return tab.span ? count_long<true, NR>(a, B, nrec, w0, stride, tab) : count_long<false, NR>(a, B, nrec, w0, stride, tab);
   const int lane = lane_id();
   uint32_t cnt = 0;
   for (uint32_t j = w0; j < nrec; j += stride) {
@@ -300,6 +421,8 @@ __device__ __forceinline__ uint32_t probe_long(const KernelArgs& a, int32_t u, c
 template <int MODE, int NR>
 __device__ __forceinline__ uint32_t probe_short(const KernelArgs& a, int32_t u, const BatchLds<NR>& B, uint32_t tot,
                                                 int slot, int width, const Table& tab, uint32_t* hits) {
+  if constexpr (MODE == kCountTotal)
+    return tab.span ? count_short<true, NR>(a, B, tot, slot, width, tab) : count_short<false, NR>(a, B, tot, slot, width, tab);
   uint32_t cnt = 0;
   for (uint32_t k0 = 0; k0 < tot; k0 += static_cast<uint32_t>(width) * kPerLane) {
     const uint32_t kb = k0 + static_cast<uint32_t>(slot) * kPerLane;
