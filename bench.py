@@ -8,8 +8,9 @@ in HBM (the whole exact-count job: simple graph, degree order, oriented CSR,
 work plan, intersection). value = oriented edges (m) / seconds per step.
 
 Also reported: the count kernel alone, the plain per-edge merge kernel on the
-same graph, the sparsified estimates at q = 0.1 and 0.5, the roofline of the
-dominant kernel and the CPU oracle on a bounded sample.
+same graph, the sparsified estimates at q = 0.1 and 0.5, the per-node counts
+and clustering coefficients, the roofline of the dominant kernel and the CPU
+oracle on a bounded sample.
 
 Other workloads (--workload): er10k (G(10^4, 0.0016) seed 1), ba22 (PA n=2^22,
 k=8, seed 2; count + per-node + clustering + list), batch (4096 mixed small
@@ -221,6 +222,24 @@ def run_graph_bench(args):
             log(f"[bench] sparsified q={q}: {dt:.1f} ms (first call {times[0]:.1f} ms), estimate {est:.4e} "
                 f"({est / T - 1:+.4%})")
         out["sparsified"] = sp
+        # per-node counts (Section 9) and clustering coefficients on the same graph
+        times = []
+        for _ in range(3):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            Tn, t = g.count_per_node(stream=stream)
+            torch.cuda.synchronize()
+            times.append(1e3 * (time.perf_counter() - t0))
+            assert Tn == T, "per-node count disagrees"
+            del t
+        out["per_node_ms"] = min(times[1:])
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        num, den, c = g.clustering(stream)
+        torch.cuda.synchronize()
+        out["clustering_ms"] = 1e3 * (time.perf_counter() - t0)
+        del num, den, c
+        log(f"[bench] per-node counts {out['per_node_ms']:.1f} ms, clustering {out['clustering_ms']:.1f} ms")
     if args.workload in ("ba22", "er10k"):
         torch.cuda.synchronize()
         t0 = time.perf_counter()

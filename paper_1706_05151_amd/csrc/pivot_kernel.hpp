@@ -371,6 +371,119 @@ __device__ __forceinline__ uint32_t count_short(const KernelArgs& a, const Batch
   return cnt;
 }
 
+// Per-node counts: kPerLane probes of one lane against a hash table at once
+// (two in flight, as in count_probes), adding one to the tally of every slot
+// found. Returns the found elements as bits 0..kPerLane-1.
+template <bool kAllValid>
+__device__ __forceinline__ uint32_t tally_probes(const Table& t, const int32_t (&x)[kPerLane]) {
+  uint32_t found_bits = 0;
+#pragma unroll
+  for (int h0 = 0; h0 < kPerLane; h0 += 2) {
+    uint32_t b[2], fs[2], f[2];
+    bool hit[2];
+#pragma unroll
+    for (int i = 0; i < 2; i++) {
+      const uint32_t h = hash_of(x[h0 + i]);
+      b[i] = home_bucket(h, t.log2b);
+      fs[i] = filter_shift(h, t.log2b);
+    }
+#pragma unroll
+    for (int i = 0; i < 2; i++) f[i] = t.F[b[i]];
+#pragma unroll
+    for (int i = 0; i < 2; i++) hit[i] = (kAllValid || x[h0 + i] != kEmpty) && ((f[i] >> fs[i]) & 1u);
+    int4 q[2];
+#pragma unroll
+    for (int i = 0; i < 2; i++) q[i] = reinterpret_cast<const int4*>(t.T)[hit[i] ? b[i] : 0u];
+#pragma unroll
+    for (int i = 0; i < 2; i++) {
+      if (!hit[i]) continue;
+      const int32_t v = x[h0 + i];
+      int slot = -1;
+      if (bucket_miss(q[i], v) == 0)
+        slot = static_cast<int>(4 * b[i]) + (q[i].x == v ? 0 : q[i].y == v ? 1 : q[i].z == v ? 2 : 3);
+      else if (q[i].w != kEmpty)
+        slot = bt_find_spilled(t.T, t.log2b, b[i], v);
+      if (slot >= 0) {
+        atomicAdd(&t.C[slot], 1u);
+        found_bits |= 1u << (h0 + i);
+      }
+    }
+  }
+  return found_bits;
+}
+
+// Per-node counts: the long records of probe_long. A window belongs to one
+// record, so the record's hits are added once per window.
+template <int NR>
+__device__ __forceinline__ uint32_t tally_long(const KernelArgs& a, const BatchLds<NR>& B, uint32_t nrec, uint32_t w0,
+                                               uint32_t stride, const Table& tab, uint32_t* hits) {
+  const int lane = lane_id();
+  uint32_t cnt = 0;
+  for (uint32_t j = w0; j < nrec; j += stride) {
+    const uint32_t len = __builtin_amdgcn_readfirstlane(B.len[j]);
+    if (len < kLongMin) continue;
+    const uint32_t beg = __builtin_amdgcn_readfirstlane(B.beg[j]);
+    uint32_t rec = 0;
+    uint32_t k0 = 0;
+    for (; k0 + kSeg <= len; k0 += kSeg) {
+      const int32_t* wbase = a.adj + beg + k0;
+      int32_t x[kPerLane];
+#pragma unroll
+      for (int i = 0; i < kPerLane; i++) x[i] = wbase[lane + kWave * i];
+      rec += static_cast<uint32_t>(__popc(tally_probes<true>(tab, x)));
+    }
+    if (k0 < len) {
+      const uint32_t rem = len - k0;
+      int32_t x[kPerLane];
+#pragma unroll
+      for (int i = 0; i < kPerLane; i++) {
+        const uint32_t k = static_cast<uint32_t>(lane + kWave * i);
+        x[i] = k < rem ? a.adj[beg + k0 + k] : kEmpty;
+      }
+      rec += static_cast<uint32_t>(__popc(tally_probes<false>(tab, x)));
+    }
+    const uint32_t wrec = wave_sum(rec);
+    if (lane == 0 && wrec) atomicAdd(&hits[j], wrec);
+    cnt += rec;
+  }
+  return cnt;
+}
+
+// Per-node counts: the concatenated short-record elements of probe_short.
+template <int NR>
+__device__ __forceinline__ uint32_t tally_short(const KernelArgs& a, const BatchLds<NR>& B, uint32_t tot, int slot,
+                                                int width, const Table& tab, uint32_t* hits) {
+  uint32_t cnt = 0;
+  for (uint32_t k0 = 0; k0 < tot; k0 += static_cast<uint32_t>(width) * kPerLane) {
+    const uint32_t kb = k0 + static_cast<uint32_t>(slot) * kPerLane;
+    int j = 0;
+    if (kb < tot) {
+#pragma unroll
+      for (int step = NR / 2; step > 0; step >>= 1)
+        if (B.spre[j + step] <= kb) j += step;  // j + step <= NR - 1
+    }
+    int32_t x[kPerLane];
+    int jj[kPerLane];
+#pragma unroll
+    for (int i = 0; i < kPerLane; i++) {
+      const uint32_t k = kb + i;
+      jj[i] = 0;
+      x[i] = kEmpty;
+      if (k < tot) {
+        while (B.spre[j + 1] <= k) j++;  // stops at j = NR - 1 because spre[NR] = tot > k
+        jj[i] = j;
+        x[i] = a.adj[B.beg[j] + (k - B.spre[j])];
+      }
+    }
+    const uint32_t fb = tally_probes<false>(tab, x);
+#pragma unroll
+    for (int i = 0; i < kPerLane; i++)
+      if ((fb >> i) & 1u) atomicAdd(&hits[jj[i]], 1u);
+    cnt += static_cast<uint32_t>(__popc(fb));
+  }
+  return cnt;
+}
+
 // Long records of the batch, wave `w0` of `stride` taking records w0,
 // w0+stride, ...: the wave walks a record's suffix in windows of kSeg
 // elements, lane L reading elements L, L+64, L+128, L+192 of the window.
@@ -380,6 +493,7 @@ __device__ __forceinline__ uint32_t probe_long(const KernelArgs& a, int32_t u, c
                                                uint32_t* hits) {
   if constexpr (MODE == kCountTotal)
     return tab.span ? count_long<true, NR>(a, B, nrec, w0, stride, tab) : count_long<false, NR>(a, B, nrec, w0, stride, tab);
+  if constexpr (MODE == kCountPerNode) return tally_long<NR>(a, B, nrec, w0, stride, tab, hits);
   const int lane = lane_id();
   uint32_t cnt = 0;
   for (uint32_t j = w0; j < nrec; j += stride) {
@@ -423,6 +537,7 @@ __device__ __forceinline__ uint32_t probe_short(const KernelArgs& a, int32_t u, 
                                                 int slot, int width, const Table& tab, uint32_t* hits) {
   if constexpr (MODE == kCountTotal)
     return tab.span ? count_short<true, NR>(a, B, tot, slot, width, tab) : count_short<false, NR>(a, B, tot, slot, width, tab);
+  if constexpr (MODE == kCountPerNode) return tally_short<NR>(a, B, tot, slot, width, tab, hits);
   uint32_t cnt = 0;
   for (uint32_t k0 = 0; k0 < tot; k0 += static_cast<uint32_t>(width) * kPerLane) {
     const uint32_t kb = k0 + static_cast<uint32_t>(slot) * kPerLane;
