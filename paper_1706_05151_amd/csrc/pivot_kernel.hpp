@@ -95,9 +95,11 @@ __device__ __forceinline__ int log2_buckets(int64_t len, int load = 1) {
 // probe reads one 4-byte filter word; only filter hits (true hits and ~6%
 // false positives) read the 16-byte bucket.
 //
-// Bitmap form (counts and listing): when the staged entries lie in a short
-// range [lo, lo + span), the region holds one bit per value of the range
-// instead; a probe is a range check and one 4-byte LDS read, exact.
+// Bitmap form: when the staged entries lie in a short range [lo, lo + span),
+// the region holds one bit per value of the range instead; a probe is a range
+// check and one 4-byte LDS read, exact. For per-node counts each bit word is
+// followed by the number of set bits before it, so a hit's entry index (its
+// tally slot in C, one per staged entry) is that count plus a popcount.
 struct Table {
   int32_t* T;
   uint32_t* F;
@@ -105,6 +107,7 @@ struct Table {
   int log2b;
   int32_t lo;     // bitmap form: smallest staged entry
   uint32_t span;  // bitmap form: entries lie in [lo, lo + span); 0 for the hash form
+  uint32_t len;   // per-node bitmap form: staged entries (tallies C[0..len))
 };
 
 // Words of a table region of 2^log2b buckets: T, then F, then C (per-node).
@@ -120,31 +123,43 @@ __device__ __forceinline__ Table table_at(int32_t* base, int log2b, bool per_nod
   t.C = per_node ? reinterpret_cast<uint32_t*>(base + (4 << log2b) + (1 << log2b)) : nullptr;
   t.lo = 0;
   t.span = 0;
+  t.len = 0;
   return t;
 }
 
 // The table for the sorted entries list[0..len) in a region of `words`
-// 32-bit words: the bitmap form if the mode needs no slot tallies and the
-// entries' range fits the region, else the hash form with 2^log2b buckets.
+// 32-bit words: the bitmap form if the entries' range fits the region (with
+// room for the prefix words and one tally per entry in per-node mode), else
+// the hash form with 2^log2b buckets.
 template <int MODE>
 __device__ __forceinline__ Table table_for(int32_t* base, const int32_t* list, uint32_t len, int log2b, uint32_t words) {
-  if (MODE != kCountPerNode && len > 0) {
+  if (len > 0) {
     const int32_t lo = __builtin_amdgcn_readfirstlane(list[0]);
     const uint32_t span = static_cast<uint32_t>(__builtin_amdgcn_readfirstlane(list[len - 1]) - lo) + 1u;
     if (span <= 32u * words) {
-      Table t = table_at(base, log2b, false);
-      t.lo = lo;
-      t.span = span;
-      return t;
+      const uint32_t W = (span + 31u) >> 5;
+      if (MODE != kCountPerNode || 2u * W + len <= words) {
+        Table t = table_at(base, log2b, false);
+        t.lo = lo;
+        t.span = span;
+        if (MODE == kCountPerNode) {
+          t.len = len;
+          t.C = reinterpret_cast<uint32_t*>(base + 2u * W);
+        }
+        return t;
+      }
     }
   }
   return table_at(base, log2b, MODE == kCountPerNode);
 }
 
+template <int MODE>
 __device__ __forceinline__ void tb_clear(const Table& t, int i0, int step) {
   if (t.span) {
-    const int words = static_cast<int>((t.span + 31u) >> 5);
+    const int words = static_cast<int>((t.span + 31u) >> 5) * (MODE == kCountPerNode ? 2 : 1);
     for (int w = i0; w < words; w += step) t.T[w] = 0;
+    if (MODE == kCountPerNode)
+      for (int i = i0; i < static_cast<int>(t.len); i += step) t.C[i] = 0;
     return;
   }
   const int S = 4 << t.log2b;
@@ -155,10 +170,11 @@ __device__ __forceinline__ void tb_clear(const Table& t, int i0, int step) {
   for (int w = i0; w < (1 << t.log2b); w += step) t.F[w] = 0u;
 }
 
+template <int MODE>
 __device__ __forceinline__ void tb_insert(const Table& t, int32_t x) {
   if (t.span) {
     const uint32_t d = static_cast<uint32_t>(x - t.lo);
-    atomicOr(reinterpret_cast<uint32_t*>(t.T) + (d >> 5), 1u << (d & 31u));
+    atomicOr(reinterpret_cast<uint32_t*>(t.T) + ((d >> 5) << (MODE == kCountPerNode ? 1 : 0)), 1u << (d & 31u));
     return;
   }
   const uint32_t h = hash_of(x);
@@ -170,10 +186,17 @@ __device__ __forceinline__ void tb_insert(const Table& t, int32_t x) {
 // Slot of x or -1 (MODE == kCountTotal: kAnySlot for found).
 template <int MODE>
 __device__ __forceinline__ int tb_find(const Table& t, int32_t x) {
-  if (MODE != kCountPerNode && t.span) {
-    // branch-free: out-of-range values read word 0 and are masked off
+  if (t.span) {
     const uint32_t d = static_cast<uint32_t>(x - t.lo);
     const bool in = d < t.span;
+    if (MODE == kCountPerNode) {  // the entry's index: prefix word plus the bits below it
+      if (!in) return -1;
+      const uint2 v = reinterpret_cast<const uint2*>(t.T)[d >> 5];
+      const uint32_t sh = d & 31u;
+      if (!((v.x >> sh) & 1u)) return -1;
+      return static_cast<int>(v.y + static_cast<uint32_t>(__popc(v.x & ((1u << sh) - 1u))));
+    }
+    // branch-free: out-of-range values read word 0 and are masked off
     const uint32_t w = reinterpret_cast<const uint32_t*>(t.T)[in ? d >> 5 : 0u];
     return (in && ((w >> (d & 31u)) & 1u)) ? kAnySlot : -1;
   }
@@ -181,6 +204,37 @@ __device__ __forceinline__ int tb_find(const Table& t, int32_t x) {
   const uint32_t b = home_bucket(h, t.log2b);
   if (!((t.F[b] >> filter_shift(h, t.log2b)) & 1u)) return -1;
   return bt_find<MODE != kCountTotal>(t.T, t.log2b, b, x);
+}
+
+// Per-node bitmap form: writes after each bit word the number of set bits in
+// the words before it. Wave form: the calling wave's lanes take consecutive
+// runs of words.
+__device__ __forceinline__ void tb_prefix_wave(const Table& t) {
+  const uint32_t W = (t.span + 31u) >> 5, per = (W + kWave - 1) / kWave;
+  const uint32_t w0 = static_cast<uint32_t>(lane_id()) * per;
+  uint32_t* R = reinterpret_cast<uint32_t*>(t.T);
+  uint32_t c = 0;
+  for (uint32_t w = w0; w < w0 + per && w < W; w++) c += static_cast<uint32_t>(__popc(R[2 * w]));
+  uint32_t run = wave_incl_scan(c) - c;
+  for (uint32_t w = w0; w < w0 + per && w < W; w++) {
+    R[2 * w + 1] = run;
+    run += static_cast<uint32_t>(__popc(R[2 * w]));
+  }
+}
+
+// Block form of tb_prefix_wave (all threads of the block call it).
+__device__ __forceinline__ void tb_prefix_block(const Table& t, uint32_t* scan_tmp) {
+  const uint32_t W = (t.span + 31u) >> 5, per = (W + kPivotBlock - 1) / kPivotBlock;
+  const uint32_t w0 = static_cast<uint32_t>(threadIdx.x) * per;
+  uint32_t* R = reinterpret_cast<uint32_t*>(t.T);
+  uint32_t c = 0;
+  for (uint32_t w = w0; w < w0 + per && w < W; w++) c += static_cast<uint32_t>(__popc(R[2 * w]));
+  uint32_t all;
+  uint32_t run = block_excl_scan<uint32_t, kPivotBlock>(c, scan_tmp, all);
+  for (uint32_t w = w0; w < w0 + per && w < W; w++) {
+    R[2 * w + 1] = run;
+    run += static_cast<uint32_t>(__popc(R[2 * w]));
+  }
 }
 
 struct KernelArgs {
@@ -412,9 +466,41 @@ __device__ __forceinline__ uint32_t tally_probes(const Table& t, const int32_t (
   return found_bits;
 }
 
+// Per-node counts against the bitmap form: kPerLane probes with their LDS
+// reads in flight together; a hit adds one to its entry's tally.
+__device__ __forceinline__ uint32_t tally_probes_bitmap(const Table& t, const int32_t (&x)[kPerLane]) {
+  const uint2* R = reinterpret_cast<const uint2*>(t.T);
+  uint32_t d[kPerLane];
+  bool in[kPerLane];
+  uint2 v[kPerLane];
+#pragma unroll
+  for (int i = 0; i < kPerLane; i++) {
+    d[i] = static_cast<uint32_t>(x[i] - t.lo);
+    in[i] = d[i] < t.span;
+  }
+#pragma unroll
+  for (int i = 0; i < kPerLane; i++) v[i] = R[in[i] ? d[i] >> 5 : 0u];
+  uint32_t found_bits = 0;
+#pragma unroll
+  for (int i = 0; i < kPerLane; i++) {
+    const uint32_t sh = d[i] & 31u;
+    if (in[i] && ((v[i].x >> sh) & 1u)) {
+      atomicAdd(&t.C[v[i].y + static_cast<uint32_t>(__popc(v[i].x & ((1u << sh) - 1u)))], 1u);
+      found_bits |= 1u << i;
+    }
+  }
+  return found_bits;
+}
+
+template <bool kBitmap, bool kAllValid>
+__device__ __forceinline__ uint32_t tally4(const Table& t, const int32_t (&x)[kPerLane]) {
+  if constexpr (kBitmap) return tally_probes_bitmap(t, x);
+  else return tally_probes<kAllValid>(t, x);
+}
+
 // Per-node counts: the long records of probe_long. A window belongs to one
 // record, so the record's hits are added once per window.
-template <int NR>
+template <bool kBitmap, int NR>
 __device__ __forceinline__ uint32_t tally_long(const KernelArgs& a, const BatchLds<NR>& B, uint32_t nrec, uint32_t w0,
                                                uint32_t stride, const Table& tab, uint32_t* hits) {
   const int lane = lane_id();
@@ -430,7 +516,7 @@ __device__ __forceinline__ uint32_t tally_long(const KernelArgs& a, const BatchL
       int32_t x[kPerLane];
 #pragma unroll
       for (int i = 0; i < kPerLane; i++) x[i] = wbase[lane + kWave * i];
-      rec += static_cast<uint32_t>(__popc(tally_probes<true>(tab, x)));
+      rec += static_cast<uint32_t>(__popc(tally4<kBitmap, true>(tab, x)));
     }
     if (k0 < len) {
       const uint32_t rem = len - k0;
@@ -440,7 +526,7 @@ __device__ __forceinline__ uint32_t tally_long(const KernelArgs& a, const BatchL
         const uint32_t k = static_cast<uint32_t>(lane + kWave * i);
         x[i] = k < rem ? a.adj[beg + k0 + k] : kEmpty;
       }
-      rec += static_cast<uint32_t>(__popc(tally_probes<false>(tab, x)));
+      rec += static_cast<uint32_t>(__popc(tally4<kBitmap, false>(tab, x)));
     }
     const uint32_t wrec = wave_sum(rec);
     if (lane == 0 && wrec) atomicAdd(&hits[j], wrec);
@@ -450,7 +536,7 @@ __device__ __forceinline__ uint32_t tally_long(const KernelArgs& a, const BatchL
 }
 
 // Per-node counts: the concatenated short-record elements of probe_short.
-template <int NR>
+template <bool kBitmap, int NR>
 __device__ __forceinline__ uint32_t tally_short(const KernelArgs& a, const BatchLds<NR>& B, uint32_t tot, int slot,
                                                 int width, const Table& tab, uint32_t* hits) {
   uint32_t cnt = 0;
@@ -475,7 +561,7 @@ __device__ __forceinline__ uint32_t tally_short(const KernelArgs& a, const Batch
         x[i] = a.adj[B.beg[j] + (k - B.spre[j])];
       }
     }
-    const uint32_t fb = tally_probes<false>(tab, x);
+    const uint32_t fb = tally4<kBitmap, false>(tab, x);
 #pragma unroll
     for (int i = 0; i < kPerLane; i++)
       if ((fb >> i) & 1u) atomicAdd(&hits[jj[i]], 1u);
@@ -493,7 +579,9 @@ __device__ __forceinline__ uint32_t probe_long(const KernelArgs& a, int32_t u, c
                                                uint32_t* hits) {
   if constexpr (MODE == kCountTotal)
     return tab.span ? count_long<true, NR>(a, B, nrec, w0, stride, tab) : count_long<false, NR>(a, B, nrec, w0, stride, tab);
-  if constexpr (MODE == kCountPerNode) return tally_long<NR>(a, B, nrec, w0, stride, tab, hits);
+  if constexpr (MODE == kCountPerNode)
+    return tab.span ? tally_long<true, NR>(a, B, nrec, w0, stride, tab, hits)
+                    : tally_long<false, NR>(a, B, nrec, w0, stride, tab, hits);
   const int lane = lane_id();
   uint32_t cnt = 0;
   for (uint32_t j = w0; j < nrec; j += stride) {
@@ -537,7 +625,9 @@ __device__ __forceinline__ uint32_t probe_short(const KernelArgs& a, int32_t u, 
                                                 int slot, int width, const Table& tab, uint32_t* hits) {
   if constexpr (MODE == kCountTotal)
     return tab.span ? count_short<true, NR>(a, B, tot, slot, width, tab) : count_short<false, NR>(a, B, tot, slot, width, tab);
-  if constexpr (MODE == kCountPerNode) return tally_short<NR>(a, B, tot, slot, width, tab, hits);
+  if constexpr (MODE == kCountPerNode)
+    return tab.span ? tally_short<true, NR>(a, B, tot, slot, width, tab, hits)
+                    : tally_short<false, NR>(a, B, tot, slot, width, tab, hits);
   uint32_t cnt = 0;
   for (uint32_t k0 = 0; k0 < tot; k0 += static_cast<uint32_t>(width) * kPerLane) {
     const uint32_t kb = k0 + static_cast<uint32_t>(slot) * kPerLane;
@@ -649,17 +739,26 @@ __device__ __forceinline__ unsigned long long wave_pivot(const KernelArgs& a, in
   int log2b = log2_buckets(nlen);
   if (log2b > kWaveLog2b) log2b = kWaveLog2b;  // >= 2 slots per entry
   const Table tab = table_for<MODE>(region, a.adj + nb, nlen, log2b, region_words);
-  tb_clear(tab, lane, kWave);
+  tb_clear<MODE>(tab, lane, kWave);
   wave_sync();
-  for (uint32_t k = lane; k < nlen; k += kWave) tb_insert(tab, a.adj[nb + k]);
+  for (uint32_t k = lane; k < nlen; k += kWave) tb_insert<MODE>(tab, a.adj[nb + k]);
   wave_sync();
+  if (MODE == kCountPerNode && tab.span) {
+    tb_prefix_wave(tab);
+    wave_sync();
+  }
   uint32_t cnt = 0;
   for (uint32_t r0 = ibeg; r0 < iend; r0 += kWave)
     cnt += probe_batch_wave<MODE>(a, u, r0, iend < r0 + kWave ? iend : r0 + kWave, tab, B);
   const unsigned long long tot = wave_sum(static_cast<unsigned long long>(cnt));
   if (MODE == kCountPerNode) {
-    for (int s = lane; s < (4 << log2b); s += kWave)
-      if (tab.C[s]) atomicAdd(&a.t_rank[tab.T[s]], static_cast<unsigned long long>(tab.C[s]));
+    if (tab.span) {
+      for (uint32_t i = lane; i < nlen; i += kWave)
+        if (tab.C[i]) atomicAdd(&a.t_rank[a.adj[nb + i]], static_cast<unsigned long long>(tab.C[i]));
+    } else {
+      for (int s = lane; s < (4 << log2b); s += kWave)
+        if (tab.C[s]) atomicAdd(&a.t_rank[tab.T[s]], static_cast<unsigned long long>(tab.C[s]));
+    }
   }
   if (lane == 0 && tot) {
     if (a.per_graph) atomicAdd(&a.per_graph[a.graph_of_rank ? a.graph_of_rank[u] : 0], tot);
@@ -681,10 +780,14 @@ __device__ __forceinline__ unsigned long long hub_item(const KernelArgs& a, cons
   const int log2b = log2_buckets(item.nlen, a.bucket_load);
   const int64_t nb = a.off[item.u] + item.nbeg_rel;
   const Table tab = table_for<MODE>(region, a.adj + nb, item.nlen, log2b, region_words);
-  tb_clear(tab, tid, kPivotBlock);
+  tb_clear<MODE>(tab, tid, kPivotBlock);
   __syncthreads();
-  for (uint32_t k = tid; k < item.nlen; k += kPivotBlock) tb_insert(tab, a.adj[nb + k]);
+  for (uint32_t k = tid; k < item.nlen; k += kPivotBlock) tb_insert<MODE>(tab, a.adj[nb + k]);
   __syncthreads();
+  if (per_node && tab.span) {
+    tb_prefix_block(tab, scan_tmp);
+    __syncthreads();
+  }
   uint32_t cnt = 0;
   for (uint32_t r0 = item.ibeg; r0 < item.iend; r0 += kPivotBlock)
     cnt += probe_batch_block<MODE>(a, item.u, r0, item.iend < r0 + kPivotBlock ? item.iend : r0 + kPivotBlock, tab, bl,
@@ -693,8 +796,13 @@ __device__ __forceinline__ unsigned long long hub_item(const KernelArgs& a, cons
   if (lane == 0) red[w] = ws;
   __syncthreads();
   if (per_node) {
-    for (int s = tid; s < (4 << log2b); s += kPivotBlock)
-      if (tab.C[s]) atomicAdd(&a.t_rank[tab.T[s]], static_cast<unsigned long long>(tab.C[s]));
+    if (tab.span) {
+      for (uint32_t i = tid; i < item.nlen; i += kPivotBlock)
+        if (tab.C[i]) atomicAdd(&a.t_rank[a.adj[nb + i]], static_cast<unsigned long long>(tab.C[i]));
+    } else {
+      for (int s = tid; s < (4 << log2b); s += kPivotBlock)
+        if (tab.C[s]) atomicAdd(&a.t_rank[tab.T[s]], static_cast<unsigned long long>(tab.C[s]));
+    }
   }
   unsigned long long tot = 0;
   if (tid == 0) {
