@@ -178,13 +178,18 @@ tc_status tc_graph_order(tc_graph* g, void* stream, int32_t* order_dev);
  * with the whole oriented graph resident): shard j holds the core nodes with
  * positions [bounds[j], bounds[j+1]) in the orientation order. The boundaries
  * follow the rule x_j = argmin_v F(v) >= j*alpha, alpha = F(n-1)/k (compared
- * exactly as F(v)*k >= j*F(n-1)), over positions, with F the prefix sum of
- * f(v) = sum_{u in N_v} (dhat_v + dhat_u) (the cost-function table of
- * Section 5, the merge cost of Theorem 2). bounds is host int32[k+1], with
- * bounds[0] = 0 and bounds[k] = n. TC_E_INVAL for k < 1 or NULL arguments.
- * Synchronises `stream`.
+ * exactly as F(v)*k >= j*F(n-1)), over positions, with F the prefix sum of a
+ * per-node cost f:
+ *   cost 0: f(v) = sum_{u in N_v} (dhat_v + dhat_u), the DPD row of the
+ *           cost-function table of Section 5 (the merge cost of Theorem 2);
+ *   cost 1: f(v) = 2 dhat_v (dhat_v - 1) + 16 dhat_v + sum_{u in N_v} dhat_u,
+ *           the pivot kernel's own work model: four times C(dhat_v, 2)
+ *           probes plus 4 per in-edge record, and a quarter of the lengths of
+ *           the lists those records meet.
+ * bounds is host int32[k+1], with bounds[0] = 0 and bounds[k] = n. TC_E_INVAL
+ * for k < 1, an unknown cost or NULL arguments. Synchronises `stream`.
  */
-tc_status tc_shard_bounds(tc_graph* g, void* stream, int32_t k, int32_t* bounds);
+tc_status tc_shard_bounds(tc_graph* g, void* stream, int32_t k, int32_t cost, int32_t* bounds);
 
 /*
  * The triangles counted by the shard whose core nodes have positions [lo, hi)
@@ -201,7 +206,7 @@ tc_status tc_count_shard(tc_graph* g, void* stream, int32_t lo, int32_t hi, uint
 /*
  * Sparsification with overlapping partitions (Section 7, parallel
  * sparsification; Eq. var2): the core nodes are split into `parts` shards as
- * in tc_shard_bounds, and shard i keeps each edge it uses independently of the
+ * in tc_shard_bounds with cost 0, and shard i keeps each edge it uses independently of the
  * other shards, with the keep rule of tc_sparsify_count under the seed
  * seed_i = output i+1 of SplitMix64 started at `seed` (seed + (i+1)*
  * 0x9E3779B97F4A7C15, then the SplitMix64 finaliser). Shard i counts the

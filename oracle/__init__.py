@@ -77,7 +77,7 @@ def _load():
         "orc_coreness": ([vp, vp, i32, vp], None),
         "orc_partition_work": ([vp, vp, vp, i32, ctypes.c_int, i32, vp, vp], None),
         "orc_order_positions": ([vp, i32, vp], None),
-        "orc_shard_bounds": ([vp, vp, i32, vp, i32, vp], None),
+        "orc_shard_bounds": ([vp, vp, i32, vp, i32, ctypes.c_int, vp], None),
         "orc_count_nin_pos_range": ([vp, vp, i32, vp, i32, i32], u64),
         "orc_partition_seed": ([u64, i32], u64),
     }
@@ -214,12 +214,13 @@ def order_positions(key, n: int) -> np.ndarray:
     return pos[:n]
 
 
-def shard_bounds(off, adj, n: int, pos, k: int) -> np.ndarray:
+def shard_bounds(off, adj, n: int, pos, k: int, cost: int = 0) -> np.ndarray:
     """Boundary positions of k core-node shards: the rule x_j = argmin F >= j*alpha over positions,
-    f(v) = sum_{u in N_v} (dhat_v + dhat_u) (Section 5 cost-function table); int64[k+1]."""
+    with f(v) = sum_{u in N_v} (dhat_v + dhat_u) (cost 0, Section 5 cost-function table) or
+    2 dhat_v (dhat_v - 1) + 16 dhat_v + sum_{u in N_v} dhat_u (cost 1); int64[k+1]."""
     pos = _i32(pos)
     bounds = np.zeros(k + 1, np.int64)
-    _load().orc_shard_bounds(_p(off), _p(adj), n, _p(pos), k, _p(bounds))
+    _load().orc_shard_bounds(_p(off), _p(adj), n, _p(pos), k, int(cost), _p(bounds))
     return bounds
 
 

@@ -379,21 +379,25 @@ void orc_order_positions(const int64_t* key, int32_t n, int32_t* pos) {
 
 /*
  * Core-node shards over positions (the overlapping partitions of Section 5
- * with the partitioning done on the orientation order): f at position pos[v]
- * is sum_{u in N_v} (dhat_v + dhat_u) (cost-function table), F its inclusive
- * prefix over positions, and bounds[j] (0 < j < k) the first position p with
- * F(p)*k >= j*F(n-1) (the boundary rule x_j = argmin F >= j*alpha, exactly);
- * bounds[0] = 0, bounds[k] = n.
+ * with the partitioning done on the orientation order). The cost at position
+ * pos[v] is, for cost 0, sum_{u in N_v} (dhat_v + dhat_u) (the DPD row of the
+ * cost-function table) and, for cost 1, 2 dhat_v (dhat_v - 1) + 16 dhat_v +
+ * sum_{u in N_v} dhat_u (four times the C(dhat_v,2) wedges of v plus 4 per
+ * oriented edge, and a quarter of the lengths of the lists N_u). F is its
+ * inclusive prefix over positions, and bounds[j] (0 < j < k) the first
+ * position p with F(p)*k >= j*F(n-1) (the boundary rule x_j = argmin F >=
+ * j*alpha, exactly); bounds[0] = 0, bounds[k] = n.
  */
-void orc_shard_bounds(const int64_t* off, const int32_t* adj, int32_t n, const int32_t* pos, int32_t k,
+void orc_shard_bounds(const int64_t* off, const int32_t* adj, int32_t n, const int32_t* pos, int32_t k, int cost,
                       int64_t* bounds) {
   uint64_t* f = (uint64_t*)calloc((size_t)(n > 0 ? n : 1), sizeof(uint64_t));
   for (int32_t v = 0; v < n; v++) {
     uint64_t dv = (uint64_t)(off[v + 1] - off[v]), x = 0;
     for (int64_t j = off[v]; j < off[v + 1]; j++) {
       int32_t u = adj[j];
-      x += dv + (uint64_t)(off[u + 1] - off[u]);
+      x += (cost == 0 ? dv : 0) + (uint64_t)(off[u + 1] - off[u]);
     }
+    if (cost == 1) x += 2 * dv * (dv > 0 ? dv - 1 : 0) + 16 * dv;
     f[pos[v]] = x;
   }
   uint64_t total = 0;

@@ -404,14 +404,15 @@ tc_status tc_graph_coreness(tc_graph* g, void* stream, int32_t* core_dev) {
   });
 }
 
-tc_status tc_shard_bounds(tc_graph* g, void* stream, int32_t k, int32_t* bounds) {
+tc_status tc_shard_bounds(tc_graph* g, void* stream, int32_t k, int32_t cost, int32_t* bounds) {
   return guarded([&] {
     require(g != nullptr && bounds != nullptr, TC_E_INVAL, "NULL argument");
     require(k >= 1, TC_E_INVAL, "k < 1");
+    require(cost == 0 || cost == 1, TC_E_INVAL, "cost must be 0 or 1");
     DeviceScope ds(g->device);
     const hipStream_t s = as_stream(stream);
     DevBuf<int64_t> b(static_cast<size_t>(k) + 1, s);
-    shard_bounds(g->csr, k, b.get(), s);
+    shard_bounds(g->csr, k, cost, b.get(), s);
     std::vector<int64_t> h(static_cast<size_t>(k) + 1);
     TC_HIP(hipMemcpyAsync(h.data(), b.get(), h.size() * sizeof(int64_t), hipMemcpyDeviceToHost, s));
     TC_HIP(hipStreamSynchronize(s));
@@ -460,7 +461,7 @@ tc_status tc_sparsify_count_partitioned(tc_graph* g, double q, uint64_t seed, in
     std::vector<int64_t> hb(static_cast<size_t>(parts) + 1);
     {
       DevBuf<int64_t> b(hb.size(), s);
-      shard_bounds(g->csr, parts, b.get(), s);
+      shard_bounds(g->csr, parts, 0, b.get(), s);
       TC_HIP(hipMemcpyAsync(hb.data(), b.get(), hb.size() * sizeof(int64_t), hipMemcpyDeviceToHost, s));
       TC_HIP(hipStreamSynchronize(s));
     }

@@ -683,16 +683,18 @@ void launch_pivot(const Csr& c, const PivotPlan& P, const CountArgs& ca, hipStre
 
 namespace {
 
-// f(v) = sum_{u in N_v} (dhat_v + dhat_u) by rank: the merge cost of v's
-// oriented edges (Theorem 2), the per-node cost of the DPD row of the
-// load-balancing table of Section 5.
-__global__ void k_rank_merge_costs(const int64_t* __restrict__ off, const int32_t* __restrict__ adj, int32_t n,
-                                   unsigned long long* __restrict__ f) {
+// Per-rank shard cost. cost 0: f(v) = sum_{u in N_v} (dhat_v + dhat_u), the
+// merge cost of v's oriented edges (Theorem 2) and the DPD row of the
+// load-balancing table of Section 5. cost 1: the pivot kernel's own model,
+// four times C(dhat_v, 2) + 4 dhat_v (probes and per-record work of v's
+// in-edge records) + sum_{u in N_v} dhat_u / 4 (staging the lists they meet).
+__global__ void k_rank_shard_costs(const int64_t* __restrict__ off, const int32_t* __restrict__ adj, int32_t n,
+                                   int cost, unsigned long long* __restrict__ f) {
   for (int32_t r = blockIdx.x * blockDim.x + threadIdx.x; r < n; r += gridDim.x * blockDim.x) {
     const unsigned long long dh = static_cast<unsigned long long>(off[r + 1] - off[r]);
-    unsigned long long x = 0;
-    for (int64_t j = off[r]; j < off[r + 1]; j++) x += dh + static_cast<unsigned long long>(off[adj[j] + 1] - off[adj[j]]);
-    f[r] = x;
+    unsigned long long nb = 0;
+    for (int64_t j = off[r]; j < off[r + 1]; j++) nb += static_cast<unsigned long long>(off[adj[j] + 1] - off[adj[j]]);
+    f[r] = cost == 0 ? dh * dh + nb : 2 * dh * (dh > 0 ? dh - 1 : 0) + 16 * dh + nb;
   }
 }
 
@@ -705,11 +707,11 @@ void count_pivot(Csr& c, const CountArgs& ca, hipStream_t s, const Options& o, b
   launch_pivot(c, c.plan, ca, s, o);
 }
 
-void shard_bounds(const Csr& c, int32_t k, int64_t* bounds, hipStream_t s) {
+void shard_bounds(const Csr& c, int32_t k, int cost, int64_t* bounds, hipStream_t s) {
   const int32_t n = c.n;
   DevBuf<unsigned long long> f(static_cast<size_t>(n) + 1, s), Fx(static_cast<size_t>(n) + 1, s);
   if (n > 0) {
-    k_rank_merge_costs<<<grid_for(n, kBlock, 65536), kBlock, 0, s>>>(c.off.p, c.adj.p, n, f.get());
+    k_rank_shard_costs<<<grid_for(n, kBlock, 65536), kBlock, 0, s>>>(c.off.p, c.adj.p, n, cost, f.get());
     TC_LAUNCH_CHECK();
   }
   exclusive_scan<unsigned long long>(f.get(), Fx.get(), static_cast<size_t>(n), s, Fx.get() + n);

@@ -171,9 +171,10 @@ void plan_items(Csr& c, PivotPlan& P, const int64_t* fin, uint64_t mi, hipStream
 void ensure_shard_plan(Csr& c, int32_t lo, int32_t hi, hipStream_t s, const Options& o);
 // triangles whose lowest vertex (in the orientation order) has rank in [lo, hi), added to *total
 void count_shard(Csr& c, int32_t lo, int32_t hi, unsigned long long* total, hipStream_t s, const Options& o);
-// ranks [bounds[j], bounds[j+1]) of shard j: the boundary rule over
-// f(v) = sum_{u in N_v} (dhat_v + dhat_u); bounds int64[k+1] (device)
-void shard_bounds(const Csr& c, int32_t k, int64_t* bounds, hipStream_t s);
+// ranks [bounds[j], bounds[j+1]) of shard j: the boundary rule over the cost
+// (0: sum_{u in N_v} (dhat_v + dhat_u); 1: 2 dhat_v (dhat_v - 1) + 16 dhat_v +
+// sum_{u in N_v} dhat_u); bounds int64[k+1] (device)
+void shard_bounds(const Csr& c, int32_t k, int cost, int64_t* bounds, hipStream_t s);
 // one persistent launch of the pivot kernel over the records and items of P (a plan of c)
 void launch_pivot(const Csr& c, const PivotPlan& P, const CountArgs& a, hipStream_t s, const Options& o);
 // allow_rebuild = false: use the cached plan as is (capturable; fails if absent)

@@ -44,7 +44,7 @@ SIGNATURES = {
     "tc_graph_order": ([_vp, _vp, _vp], ctypes.c_int),
     "tc_graph_export_csr": ([_vp, _vp, _vp, _vp], ctypes.c_int),
     "tc_count_streamed": ([_vp, _vp, _i32, _i64, _u64, _vp, _P(_u64), _vp], ctypes.c_int),
-    "tc_shard_bounds": ([_vp, _vp, _i32, _vp], ctypes.c_int),
+    "tc_shard_bounds": ([_vp, _vp, _i32, _i32, _vp], ctypes.c_int),
     "tc_count_shard": ([_vp, _vp, _i32, _i32, _P(_u64)], ctypes.c_int),
     "tc_sparsify_count_partitioned": ([_vp, _dbl, _u64, _i32, _vp, _vp, _vp, _P(_u64), _P(_dbl)], ctypes.c_int),
     "tc_set_option": ([ctypes.c_int, _i64], ctypes.c_int),
@@ -265,10 +265,11 @@ class Graph:
         _check(lib().tc_graph_order(self._h, _stream(stream), _dptr(order)), "tc_graph_order")
         return order[: self.n]
 
-    def shard_bounds(self, k: int, stream=None) -> List[int]:
-        """Positions [b[j], b[j+1]) of the core nodes of shard j (boundary rule over the merge cost)."""
+    def shard_bounds(self, k: int, cost: int = 0, stream=None) -> List[int]:
+        """Positions [b[j], b[j+1]) of the core nodes of shard j: the boundary rule over the merge cost
+        (cost 0, Section 5) or the pivot kernel's work model (cost 1)."""
         b = (ctypes.c_int32 * (k + 1))()
-        _check(lib().tc_shard_bounds(self._h, _stream(stream), int(k), b), "tc_shard_bounds")
+        _check(lib().tc_shard_bounds(self._h, _stream(stream), int(k), int(cost), b), "tc_shard_bounds")
         return list(b)
 
     def count_shard(self, lo: int, hi: int, stream=None) -> int:

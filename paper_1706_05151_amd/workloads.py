@@ -310,11 +310,13 @@ def _best_ms(fn, reps=3):
 
 def run_shards(args):
     """One GPU's share of a sharded count: the R-MAT graph's core nodes split
-    into k shards by the boundary rule over the merge cost (Section 5), each
-    shard counted with its own work plan (in-edge records of its core nodes'
-    edges). Reports per-shard count time, the spread max/mean (the balance a
-    k-GPU run would see, each GPU holding the whole oriented graph) and the
-    time of building each shard's plan; checks that the shards add up to T."""
+    into k shards by the boundary rule (Section 5) over two per-node costs
+    (0: the merge cost of the paper's cost table; 1: the pivot kernel's own
+    work model), each shard counted with its own work plan (in-edge records of
+    its core nodes' edges). Reports per-shard count time, the spread max/mean
+    (the balance a k-GPU run would see, each GPU holding the whole oriented
+    graph) and the time of building each shard's plan; checks that the shards
+    add up to T."""
     import torch
 
     import synth
@@ -331,32 +333,38 @@ def run_shards(args):
     torch.cuda.empty_cache()
     T = g.count()
     full_ms, _ = _best_ms(g.count)
-    b = g.shard_bounds(k)
-    rows = []
-    for j in range(k):
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        Tj = g.count_shard(b[j], b[j + 1])  # builds the shard's plan
-        torch.cuda.synchronize()
-        first_ms = 1e3 * (time.perf_counter() - t0)
-        ms, Tr = _best_ms(lambda: g.count_shard(b[j], b[j + 1]))
-        assert Tr == Tj
-        rows.append({"shard": j, "lo": b[j], "hi": b[j + 1], "T": Tj, "count_ms": ms,
-                     "plan_ms": max(first_ms - ms, 0.0)})
-        _log(f"[shards] {rows[-1]}")
-    assert sum(r["T"] for r in rows) == T, "shards do not add up to T"
-    times = [r["count_ms"] for r in rows]
-    total = sum(times)
+    by_cost = {}
+    for cost in (0, 1):
+        b = g.shard_bounds(k, cost)
+        rows = []
+        for j in range(k):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            Tj = g.count_shard(b[j], b[j + 1])  # builds the shard's plan
+            torch.cuda.synchronize()
+            first_ms = 1e3 * (time.perf_counter() - t0)
+            ms, Tr = _best_ms(lambda: g.count_shard(b[j], b[j + 1]))
+            assert Tr == Tj
+            rows.append({"shard": j, "lo": b[j], "hi": b[j + 1], "T": Tj, "count_ms": ms,
+                         "plan_ms": max(first_ms - ms, 0.0)})
+            _log(f"[shards] cost {cost} {rows[-1]}")
+        assert sum(r["T"] for r in rows) == T, "shards do not add up to T"
+        times = [r["count_ms"] for r in rows]
+        by_cost[cost] = {"sum_shard_ms": sum(times), "max_shard_ms": max(times),
+                         "shard_max_over_mean": max(times) / (sum(times) / k), "per_shard": rows}
+        _log(f"[shards] cost {cost}: sum {sum(times):.1f} ms, max {max(times):.1f} ms, "
+             f"max/mean {by_cost[cost]['shard_max_over_mean']:.3f}")
     m = g.m
     g.close()
+    total = by_cost[1]["sum_shard_ms"]
     return {"metric": METRIC, "value": m / (total / 1e3), "unit": "oriented edges/s", "n_gpus": 1, "steps": 3,
             "warmup": 1, "ms_per_step": total, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
             "dtype": "int32", "data": "synthetic",
             "config": {"workload": f"rmat{args.scale}-shards{k}", "n": n, "m": m, "T": T, "shards": k,
-                       "step": "tc_count_shard over every shard in turn (plans built beforehand)",
+                       "step": "tc_count_shard over every shard in turn (plans built beforehand), shards by cost 1",
                        "parallelism": "single GPU"},
-            "full_count_ms": full_ms, "sum_shard_ms": total, "max_shard_ms": max(times),
-            "shard_max_over_mean": max(times) / (total / k), "per_shard": rows}
+            "full_count_ms": full_ms,
+            "cost_merge": by_cost[0], "cost_kernel_model": by_cost[1]}
 
 
 def run_sampling(args):

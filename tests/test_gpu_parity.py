@@ -415,13 +415,13 @@ def test_partitioned_count_errors(tc):
 
 # ----------------------------------------------------------------- shards ---
 
-def _shard_ref(el, k):
+def _shard_ref(el, k, cost=0):
     """Oracle positions, shard boundaries and per-shard counts (triangles by lowest vertex)."""
     lo, hi = oracle.simple(el.src, el.dst, el.n)
     deg = oracle.degrees(lo, hi, el.n)
     off, adj = oracle.orient(lo, hi, deg, el.n)
     pos = oracle.order_positions(deg, el.n)
-    b = oracle.shard_bounds(off, adj, el.n, pos, k)
+    b = oracle.shard_bounds(off, adj, el.n, pos, k, cost)
     T = [oracle.count_nin_pos_range(off, adj, el.n, pos, int(b[j]), int(b[j + 1])) for j in range(k)]
     return pos, b, T, (lo, hi, deg, off, adj)
 
@@ -430,17 +430,18 @@ SHARD_GRAPHS = [synth.rmat(12, 16, 61), synth.ba(20000, 5, 62), synth.er(3000, 0
                 synth.complete(40)]
 
 
-@pytest.mark.parametrize("k", [1, 3, 8])
-def test_shards_match_oracle(tc, k):
-    """Shard boundaries, each shard's count and the order export equal the oracle's; shards add up to T."""
+@pytest.mark.parametrize("k,cost", [(1, 0), (3, 0), (8, 0), (3, 1), (8, 1)])
+def test_shards_match_oracle(tc, k, cost):
+    """Shard boundaries (both costs), each shard's count and the order export equal the oracle's;
+    shards add up to T."""
     for el in SHARD_GRAPHS:
-        pos, b, T, _ = _shard_ref(el, k)
+        pos, b, T, _ = _shard_ref(el, k, cost)
         s, d = to_dev(el)
         with tc.Graph.build(s, d, el.n) as g:
-            say(f"[parity] shards k={k} {el.name}")
+            say(f"[parity] shards k={k} cost={cost} {el.name}")
             order = g.order().cpu().numpy()
             np.testing.assert_array_equal(pos[order], np.arange(el.n))
-            gb = g.shard_bounds(k)
+            gb = g.shard_bounds(k, cost)
             assert gb == b.tolist()
             gT = [g.count_shard(gb[j], gb[j + 1]) for j in range(k)]
             assert gT == T
@@ -505,6 +506,8 @@ def test_shard_errors(tc):
                 g.count_shard(a, b)
         with pytest.raises(tc.TCError):
             g.shard_bounds(0)
+        with pytest.raises(tc.TCError):
+            g.shard_bounds(4, 2)
         with g.sparsify_build(0.5, 1) as gs:
             with pytest.raises(tc.TCError):
                 gs.order()

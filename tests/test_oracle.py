@@ -572,14 +572,15 @@ def test_shard_bounds_matching_closed_form():
     deg = oracle.degrees(lo, hi, n)
     off, adj = oracle.orient(lo, hi, deg, n)
     pos = oracle.order_positions(deg, n)
-    b = oracle.shard_bounds(off, adj, n, pos, k)
-    assert b.tolist() == [0] + [2 * (-(-j * M // k) - 1) for j in range(1, k)] + [n]
+    for cost in (0, 1):  # cost 1 is 16 times cost 0 here: the same boundaries
+        b = oracle.shard_bounds(off, adj, n, pos, k, cost)
+        assert b.tolist() == [0] + [2 * (-(-j * M // k) - 1) for j in range(1, k)] + [n]
 
 
-@pytest.mark.parametrize("k", [1, 2, 9, 64])
-def test_shard_bounds_by_search(k):
-    """Boundaries agree with a search on the cumulative merge cost by position (cost recomputed
-    from the oriented lists here), and the costs add up to W (Theorem 2)."""
+@pytest.mark.parametrize("k,cost", [(1, 0), (2, 0), (9, 0), (64, 0), (2, 1), (9, 1), (64, 1)])
+def test_shard_bounds_by_search(k, cost):
+    """Boundaries agree with a search on the cumulative cost by position (cost recomputed from the
+    oriented lists here), and the merge costs add up to W (Theorem 2)."""
     g = synth.ba(2500, 6, 3)
     lo, hi = oracle.simple(g.src, g.dst, g.n)
     deg = oracle.degrees(lo, hi, g.n)
@@ -589,10 +590,11 @@ def test_shard_bounds_by_search(k):
     src = np.repeat(np.arange(g.n), np.diff(off))
     merge = np.bincount(src, weights=(dh[src] + dh[adj]).astype(np.float64), minlength=g.n).astype(np.int64)
     assert int(merge.sum()) == oracle.work(off, adj, g.n)
+    nb = np.bincount(src, weights=dh[adj].astype(np.float64), minlength=g.n).astype(np.int64)
     f = np.zeros(g.n, np.int64)
-    f[pos] = merge
+    f[pos] = merge if cost == 0 else 2 * dh * np.maximum(dh - 1, 0) + 16 * dh + nb
     F = np.cumsum(f)
-    b = oracle.shard_bounds(off, adj, g.n, pos, k)
+    b = oracle.shard_bounds(off, adj, g.n, pos, k, cost)
     assert b[0] == 0 and b[-1] == g.n and (np.diff(b) >= 0).all()
     for j in range(1, k):
         x = int(b[j])
