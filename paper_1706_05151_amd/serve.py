@@ -22,7 +22,7 @@ from __future__ import annotations
 import collections
 import time
 from dataclasses import dataclass, field
-from typing import Dict, List, Optional
+from typing import Dict, List, Optional, Tuple
 
 import numpy as np
 
@@ -331,6 +331,31 @@ def serve_fifo(registry: Registry, trace: List[Request], t0: Optional[float] = N
         torch.cuda.synchronize()
         answers[r.rid] = Answer(r.rid, r.kind, val, time.perf_counter() - start)
     return answers
+
+
+def serve_plain(edges_dev, trace: List[Request]) -> Tuple[Dict[int, Answer], float]:
+    """The plain per-graph launch: for each request in arrival order, as fast as
+    possible, build its graph from the edge list already in HBM, answer it with
+    the single-graph calls and free the graph (no registry, no batching).
+    edges_dev[g] = (src, dst, n) device tensors. Returns (answers, wall seconds)."""
+    import torch
+
+    answers = {}
+    torch.cuda.synchronize()
+    start = time.perf_counter()
+    for r in sorted(trace, key=lambda r: r.arrival):
+        src, dst, n = edges_dev[r.graph]
+        with tc.Graph.build(src, dst, n) as g:
+            if r.kind == COUNT:
+                val = g.count()
+            elif r.kind == SPARSE:
+                val = g.sparsify_count(r.q, r.seed)[2]
+            else:
+                num, den, c = g.clustering()
+                val = cc_digest(num.cpu().numpy(), den.cpu().numpy(), c.cpu().numpy())
+        answers[r.rid] = Answer(r.rid, r.kind, val, time.perf_counter() - start)
+    torch.cuda.synchronize()
+    return answers, time.perf_counter() - start
 
 
 def make_trace(num_graphs: int, rate: float, duration: float, seed: int, mix=(0.6, 0.25, 0.15), q: float = 0.2):

@@ -160,6 +160,13 @@ def test_served_results_equal_standalone(tcm):
             assert ans[r.rid].value == ref.T
         elif r.kind == serve.CLUSTER:
             assert ans[r.rid].value == serve.cc_digest(ref.num, ref.den, ref.cc)
+    # the plain per-graph launch (build, answer, free per request) gives the same answers
+    import torch
+
+    edges = [(torch.from_numpy(e.src).cuda(), torch.from_numpy(e.dst).cuda(), e.n) for e in els]
+    plain, _ = serve.serve_plain(edges, trace)
+    for r in trace:
+        assert serve.same_answer(plain[r.rid], fifo[r.rid]), r
     reg.close()
     reg2.close()
 
