@@ -293,14 +293,16 @@ void build_graph(const int32_t* src, const int32_t* dst, int64_t E, int32_t n, c
   DevBuf<uint64_t> keys(E, s), tmp(E, s);
   DevBuf<int> err(1, s);
   DevBuf<uint64_t> d_m(1, s);
+  DevBuf<uint32_t> sort_fail(1, s);  // set by any sort whose look-back gave up; checked at the syncs below
   TC_HIP(hipMemsetAsync(err.get(), 0, sizeof(int), s));
+  TC_HIP(hipMemsetAsync(sort_fail.get(), 0, sizeof(uint32_t), s));
   uint64_t* uniq = nullptr;
   uint64_t* spare = nullptr;
   if (E > 0) {
     k_canon<<<grid_for(E, kBlock, 65536), kBlock, 0, s>>>(dsrc, ddst, static_cast<uint32_t>(E), n, b, d_eoff.get(),
                                                           d_vbase.get(), G, keys.get(), err.get());
     TC_LAUNCH_CHECK();
-    uint64_t* sorted = radix_sort<uint64_t>(keys.get(), tmp.get(), E, 0, 2 * b, s);
+    uint64_t* sorted = radix_sort<uint64_t>(keys.get(), tmp.get(), E, 0, 2 * b, s, sort_fail.get());
     spare = sorted == keys.get() ? tmp.get() : keys.get();
     compact_if<uint64_t>(E, UniquePred{sorted}, GatherU64{sorted}, spare, d_m.get(), s);
     uniq = spare;
@@ -312,9 +314,12 @@ void build_graph(const int32_t* src, const int32_t* dst, int64_t E, int32_t n, c
   hdst.release();
   int h_err = 0;
   uint64_t m = 0;
+  uint32_t h_fail = 0;
   TC_HIP(hipMemcpyAsync(&h_err, err.get(), sizeof(int), hipMemcpyDeviceToHost, s));
   TC_HIP(hipMemcpyAsync(&m, d_m.get(), sizeof(uint64_t), hipMemcpyDeviceToHost, s));
+  TC_HIP(hipMemcpyAsync(&h_fail, sort_fail.get(), sizeof(uint32_t), hipMemcpyDeviceToHost, s));
   TC_HIP(hipStreamSynchronize(s));
+  if (h_fail) fail(TC_E_DEVICE, "radix_sort: a tile's look-back did not complete");
   if (h_err) fail(TC_E_RANGE, "vertex id outside [0, n)");
   g->m = static_cast<int64_t>(m);
 
@@ -330,7 +335,7 @@ void build_graph(const int32_t* src, const int32_t* dst, int64_t E, int32_t n, c
     uint32_t* ends = reinterpret_cast<uint32_t*>(spare);
     k_larger_ends<<<grid_for(m, kBlock, 65536), kBlock, 0, s>>>(uniq, m, b, ends);
     TC_LAUNCH_CHECK();
-    const uint32_t* sorted_ends = radix_sort<uint32_t>(ends, ends + m, m, 0, b, s);
+    const uint32_t* sorted_ends = radix_sort<uint32_t>(ends, ends + m, m, 0, b, s, sort_fail.get());
     k_run_counts<<<grid_for(m, kBlock, 65536), kBlock, 0, s>>>(HiEnd{sorted_ends}, m, g->deg.p);
     TC_LAUNCH_CHECK();
   }
@@ -345,9 +350,9 @@ void build_graph(const int32_t* src, const int32_t* dst, int64_t E, int32_t n, c
     k_rank_keys<<<grid_for(n, kBlock, 65536), kBlock, 0, s>>>(n, b, key_by_id ? key_by_id : g->deg.p, d_vbase.get(),
                                                                G, key_by_id ? 0 : order, rk.get());
     TC_LAUNCH_CHECK();
-    u128* r1 = radix_sort<u128>(rk.get(), rk2.get(), n, 0, 2 * b, s);
+    u128* r1 = radix_sort<u128>(rk.get(), rk2.get(), n, 0, 2 * b, s, sort_fail.get());
     u128* r2 = r1;
-    if (G > 1) r2 = radix_sort<u128>(r1, r1 == rk.get() ? rk2.get() : rk.get(), n, 64, 64 + gbits, s);
+    if (G > 1) r2 = radix_sort<u128>(r1, r1 == rk.get() ? rk2.get() : rk.get(), n, 64, 64 + gbits, s, sort_fail.get());
     k_rank_from_sorted<<<grid_for(n, kBlock, 65536), kBlock, 0, s>>>(r2, n, b, g->order.p, g->rank.p,
                                                                       G > 1 ? g->graph_of_rank.p : nullptr);
     TC_LAUNCH_CHECK();
@@ -363,7 +368,7 @@ void build_graph(const int32_t* src, const int32_t* dst, int64_t E, int32_t n, c
   if (m > 0) {
     k_relabel<<<grid_for(m, kBlock, 65536), kBlock, 0, s>>>(uniq, m, b, g->rank.p, spare);
     TC_LAUNCH_CHECK();
-    uint64_t* ok = radix_sort<uint64_t>(spare, uniq, m, 0, 2 * b, s);
+    uint64_t* ok = radix_sort<uint64_t>(spare, uniq, m, 0, 2 * b, s, sort_fail.get());
     k_csr_fill<<<grid_for(m, kBlock, 65536), kBlock, 0, s>>>(ok, m, b, c.adj.p, c.src.p);
     TC_LAUNCH_CHECK();
   }
@@ -381,7 +386,9 @@ void build_graph(const int32_t* src, const int32_t* dst, int64_t E, int32_t n, c
   }
   int h_mx[2] = {0, 0};
   TC_HIP(hipMemcpyAsync(h_mx, mx.get(), 2 * sizeof(int), hipMemcpyDeviceToHost, s));
+  TC_HIP(hipMemcpyAsync(&h_fail, sort_fail.get(), sizeof(uint32_t), hipMemcpyDeviceToHost, s));
   TC_HIP(hipStreamSynchronize(s));
+  if (h_fail) fail(TC_E_DEVICE, "radix_sort: a tile's look-back did not complete");
   c.dhat_max = h_mx[0];
   g->d_max = h_mx[1];
 }

@@ -265,14 +265,17 @@ void build_plan(Csr& c, PivotPlan& P, uint64_t e0, uint64_t e1, hipStream_t s, c
   k_inkeys<<<grid_for(mi, kBlock, 65536), kBlock, 0, s>>>(c.off.p, c.adj.p, c.src.p, e0, mi, ik.get(), il.get());
   TC_LAUNCH_CHECK();
   uint32_t* sl = il.get();
-  uint64_t* sk = radix_sort_pairs<uint64_t, uint32_t>(ik.get(), ik2.get(), sl, il2.get(), mi, 32, 32 + b, s);
+  DevBuf<uint32_t> sort_fail(1, s);
+  TC_HIP(hipMemsetAsync(sort_fail.get(), 0, sizeof(uint32_t), s));
+  uint64_t* sk = radix_sort_pairs<uint64_t, uint32_t>(ik.get(), ik2.get(), sl, il2.get(), mi, 32, 32 + b, s,
+                                                      sort_fail.get());
   DevBuf<int64_t> fin;
   plan_records(c, P, sk, sl, mi, fin, s);
   ik.release();
   ik2.release();
   il.release();
   il2.release();
-  plan_items(c, P, fin.get(), mi, s, o);
+  plan_items(c, P, fin.get(), mi, s, o, sort_fail.get());
 }
 
 }  // namespace
@@ -289,13 +292,17 @@ void plan_records(Csr& c, PivotPlan& P, const uint64_t* sk, const uint32_t* sl, 
   exclusive_scan<int64_t>(fin.get(), fin.get(), mi, s, fin.get() + mi);
 }
 
-void plan_items(Csr& c, PivotPlan& P, const int64_t* fin_p, uint64_t mi, hipStream_t s, const Options& o) {
+void plan_items(Csr& c, PivotPlan& P, const int64_t* fin_p, uint64_t mi, hipStream_t s, const Options& o,
+                const uint32_t* sort_fail) {
   const int32_t n = c.n;
   // classify pivots and count items; item_work 0: about 8 items per resident
   // wave, between 4096 and 65536 probe-equivalents
   int64_t total_cost = 0;
+  uint32_t h_fail = 0;
   TC_HIP(hipMemcpyAsync(&total_cost, fin_p + mi, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+  if (sort_fail) TC_HIP(hipMemcpyAsync(&h_fail, sort_fail, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
   TC_HIP(hipStreamSynchronize(s));
+  if (h_fail) fail(TC_E_DEVICE, "radix_sort: a tile's look-back did not complete");
   int64_t iw_wave = o.item_work;
   if (iw_wave <= 0) {
     const int64_t waves = static_cast<int64_t>(device_cus()) * 4 * kPivotWaves;

@@ -166,7 +166,9 @@ void ensure_plan(Csr& c, hipStream_t s, const Options& o);
 // null to take them from c.off / c.src), then the classification and items.
 void plan_records(Csr& c, PivotPlan& P, const uint64_t* sk, const uint32_t* sl, uint64_t mi, DevBuf<int64_t>& fin,
                   hipStream_t s);
-void plan_items(Csr& c, PivotPlan& P, const int64_t* fin, uint64_t mi, hipStream_t s, const Options& o);
+// sort_fail (device, optional): a sort failure flag checked at plan_items' first synchronisation
+void plan_items(Csr& c, PivotPlan& P, const int64_t* fin, uint64_t mi, hipStream_t s, const Options& o,
+                const uint32_t* sort_fail = nullptr);
 // the plan of the oriented edges whose source rank lies in [lo, hi), into c.shard
 void ensure_shard_plan(Csr& c, int32_t lo, int32_t hi, hipStream_t s, const Options& o);
 // triangles whose lowest vertex (in the orientation order) has rank in [lo, hi), added to *total

@@ -337,7 +337,7 @@ struct NoVal {};
 // One pass. Wave w ranks the contiguous chunk [w*ITEMS*64, (w+1)*ITEMS*64)
 // of the tile among equal digits with wave-private 16-bit counters (ballot
 // match, the lowest lane of each group updating the counter), so tile order is
-// index order and the pass is stable. ctr[0] hands out tile indices; ctr[1]
+// index order and the pass is stable. ctr[0] hands out tile indices; *fail
 // is set if a look-back gave up. With a value type V, each key's value moves
 // with it (staged through the same LDS tile after the keys are written).
 template <typename K, typename V>
@@ -346,7 +346,8 @@ __global__ __launch_bounds__(kScatterBlock) void k_sweep_scatter(const K* __rest
                                                                  uint32_t N, int shift, uint32_t dmask, uint64_t tag,
                                                                  const uint32_t* __restrict__ starts,
                                                                  uint64_t* __restrict__ status,
-                                                                 uint32_t* __restrict__ ctr) {
+                                                                 uint32_t* __restrict__ ctr,
+                                                                 uint32_t* __restrict__ fail) {
   constexpr bool kHasVal = !std::is_same<V, NoVal>::value;
   constexpr int ITEMS = ScatterItems<K>::value;
   constexpr int TILE = kScatterBlock * ITEMS;
@@ -429,7 +430,7 @@ __global__ __launch_bounds__(kScatterBlock) void k_sweep_scatter(const K* __rest
       const uint64_t kind = v & kKindMask;
       if (kind == 0 || (v & ~kKindMask & ~kValMask) != tag) {
         if (++polls > kSpinLimit) {
-          atomicOr(&ctr[1], 1u);
+          atomicOr(fail, 1u);
           break;
         }
         __builtin_amdgcn_s_sleep(1);
@@ -494,18 +495,21 @@ __global__ void k_fill_words(T* __restrict__ p, size_t n, T v) {
 // Sorts N keys ascending by bits [bit_lo, bit_hi) (9-bit digits, stable),
 // each value in `vals` moving with its key. Uses `keys`/`tmp` and
 // `vals`/`vtmp` as ping-pong buffers; returns the key buffer holding the
-// result and points `vals` at the value buffer holding the result.
-// Synchronises the stream before returning (it checks the look-back flags).
+// result and points `vals` at the value buffer holding the result. A pass
+// whose look-back gave up sets *fail_dev (device word, never cleared here);
+// the caller checks it at its next synchronisation. Without fail_dev the
+// sort synchronises the stream and checks its own flag before returning.
 template <typename K, typename V>
-K* radix_sort_pairs(K* keys, K* tmp, V*& vals, V* vtmp, size_t N, int bit_lo, int bit_hi, hipStream_t s) {
+K* radix_sort_pairs(K* keys, K* tmp, V*& vals, V* vtmp, size_t N, int bit_lo, int bit_hi, hipStream_t s,
+                    uint32_t* fail_dev = nullptr) {
   if (N <= 1 || bit_hi <= bit_lo) return keys;
   if (N >= (1ull << 32)) fail(TC_E_INVAL, "radix_sort: more than 2^32 - 1 keys");
   constexpr int TILE = kScatterBlock * ScatterItems<K>::value;
   const int passes = (bit_hi - bit_lo + kRadixBits - 1) / kRadixBits;
   if (passes > kMaxPasses) fail(TC_E_INVAL, "radix_sort: bit range too wide");
   const uint32_t tiles = static_cast<uint32_t>((N + TILE - 1) / TILE);
-  // words: passes*kBins histogram/starts, then per pass {tile counter, look-back failure flag}
-  const size_t nwords = static_cast<size_t>(passes) * kBins + 2 * passes;
+  // words: passes*kBins histogram/starts, per pass a tile counter, then a local failure flag
+  const size_t nwords = static_cast<size_t>(passes) * kBins + passes + 1;
   DevBuf<uint32_t> words(nwords, s);
   DevBuf<uint64_t> status(static_cast<size_t>(tiles) * kBins, s);
   k_fill_words<uint32_t><<<grid_for(nwords, 256, 64), 256, 0, s>>>(words.get(), nwords, 0u);
@@ -515,6 +519,7 @@ K* radix_sort_pairs(K* keys, K* tmp, V*& vals, V* vtmp, size_t N, int bit_lo, in
   TC_LAUNCH_CHECK();
   uint32_t* hist = words.get();
   uint32_t* ctrs = hist + static_cast<size_t>(passes) * kBins;
+  uint32_t* fail_flag = fail_dev ? fail_dev : ctrs + passes;
   const int copies = passes <= 8 ? 4 : 2;  // LDS: passes * kBins * copies words <= 64 KiB
   k_sweep_hist<K><<<tiles < 2048u ? tiles : 2048u, kSortBlock, static_cast<size_t>(passes) * kBins * copies * 4, s>>>(
       keys, static_cast<uint32_t>(N), bit_lo, bit_hi, passes, copies, hist);
@@ -531,25 +536,26 @@ K* radix_sort_pairs(K* keys, K* tmp, V*& vals, V* vtmp, size_t N, int bit_lo, in
                                                           radix_digit_mask(shift, bit_hi),
                                                           static_cast<uint64_t>(p + 1) << kTagShift,
                                                           hist + static_cast<size_t>(p) * kBins, status.get(),
-                                                          ctrs + 2 * p);
+                                                          ctrs + p, fail_flag);
     TC_LAUNCH_CHECK();
     std::swap(a, b);
     std::swap(va, vb);
   }
-  uint32_t h_ctr[2 * kMaxPasses] = {};
-  TC_HIP(hipMemcpyAsync(h_ctr, ctrs, 2 * passes * sizeof(uint32_t), hipMemcpyDeviceToHost, s));
-  TC_HIP(hipStreamSynchronize(s));
-  for (int p = 0; p < passes; p++)
-    if (h_ctr[2 * p + 1]) fail(TC_E_DEVICE, "radix_sort: a tile's look-back did not complete");
   vals = va;
+  if (!fail_dev) {
+    uint32_t h_fail = 0;
+    TC_HIP(hipMemcpyAsync(&h_fail, fail_flag, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+    TC_HIP(hipStreamSynchronize(s));
+    if (h_fail) fail(TC_E_DEVICE, "radix_sort: a tile's look-back did not complete");
+  }
   return a;
 }
 
 // Keys-only form of radix_sort_pairs.
 template <typename K>
-K* radix_sort(K* keys, K* tmp, size_t N, int bit_lo, int bit_hi, hipStream_t s) {
+K* radix_sort(K* keys, K* tmp, size_t N, int bit_lo, int bit_hi, hipStream_t s, uint32_t* fail_dev = nullptr) {
   NoVal* none = nullptr;
-  return radix_sort_pairs<K, NoVal>(keys, tmp, none, nullptr, N, bit_lo, bit_hi, s);
+  return radix_sort_pairs<K, NoVal>(keys, tmp, none, nullptr, N, bit_lo, bit_hi, s, fail_dev);
 }
 
 }  // namespace tc
