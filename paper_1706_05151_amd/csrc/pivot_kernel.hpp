@@ -138,7 +138,8 @@ __device__ __forceinline__ Table table_for(int32_t* base, const int32_t* list, u
     const uint32_t span = static_cast<uint32_t>(__builtin_amdgcn_readfirstlane(list[len - 1]) - lo) + 1u;
     if (span <= 32u * words) {
       const uint32_t W = (span + 31u) >> 5;
-      if (MODE != kCountPerNode || 2u * W + len <= words) {
+      // counts and listing keep one zero word after the bitmap (read by values out of range)
+      if (MODE != kCountPerNode ? W + 1u <= words : 2u * W + len <= words) {
         Table t = table_at(base, log2b, false);
         t.lo = lo;
         t.span = span;
@@ -156,7 +157,8 @@ __device__ __forceinline__ Table table_for(int32_t* base, const int32_t* list, u
 template <int MODE>
 __device__ __forceinline__ void tb_clear(const Table& t, int i0, int step) {
   if (t.span) {
-    const int words = static_cast<int>((t.span + 31u) >> 5) * (MODE == kCountPerNode ? 2 : 1);
+    const int words = MODE == kCountPerNode ? static_cast<int>((t.span + 31u) >> 5) * 2
+                                            : static_cast<int>((t.span + 31u) >> 5) + 1;  // and the zero word
     for (int w = i0; w < words; w += step) t.T[w] = 0;
     if (MODE == kCountPerNode)
       for (int i = i0; i < static_cast<int>(t.len); i += step) t.C[i] = 0;
@@ -196,9 +198,9 @@ __device__ __forceinline__ int tb_find(const Table& t, int32_t x) {
       if (!((v.x >> sh) & 1u)) return -1;
       return static_cast<int>(v.y + static_cast<uint32_t>(__popc(v.x & ((1u << sh) - 1u))));
     }
-    // branch-free: out-of-range values read word 0 and are masked off
-    const uint32_t w = reinterpret_cast<const uint32_t*>(t.T)[in ? d >> 5 : 0u];
-    return (in && ((w >> (d & 31u)) & 1u)) ? kAnySlot : -1;
+    // branch-free: out-of-range values read the zero word after the bitmap
+    const uint32_t w = reinterpret_cast<const uint32_t*>(t.T)[in ? d >> 5 : (t.span + 31u) >> 5];
+    return ((w >> (d & 31u)) & 1u) ? kAnySlot : -1;
   }
   const uint32_t h = hash_of(x);
   const uint32_t b = home_bucket(h, t.log2b);
@@ -308,8 +310,9 @@ __device__ __forceinline__ uint32_t probe_one(const KernelArgs& a, int32_t u, in
 
 // Totals only: kPerLane probes of one lane against one table form at once,
 // with no branch between them, so their LDS reads are in flight together.
-// Bitmap form: an element outside the staged range (the kEmpty filler lies
-// below every rank) reads word 0 and is masked off. Hash form: every filter
+// Bitmap form: an element past the staged range (the kEmpty filler lies
+// below every rank, so it wraps to a large offset) reads zeros: its word
+// index is clamped to the zero word kept after the bitmap. Hash form: every filter
 // word is read, then every bucket (lanes without a filter hit read bucket 0,
 // their result masked off); only elements whose full home bucket did not
 // hold them search the buckets they spill into.
@@ -318,17 +321,17 @@ __device__ __forceinline__ uint32_t count_probes(const Table& t, const int32_t (
   uint32_t c = 0;
   if constexpr (kBitmap) {
     const uint32_t* W = reinterpret_cast<const uint32_t*>(t.T);
+    const uint32_t zero = (t.span + 31u) >> 5;
     uint32_t d[kPerLane], w[kPerLane];
-    bool in[kPerLane];
 #pragma unroll
-    for (int i = 0; i < kPerLane; i++) {
-      d[i] = static_cast<uint32_t>(x[i] - t.lo);
-      in[i] = d[i] < t.span;
-    }
+    for (int i = 0; i < kPerLane; i++) d[i] = static_cast<uint32_t>(x[i] - t.lo);
+    // word d / 32, clamped to the zero word: bits of the last word at or past
+    // span are never set, so values in [span, 32 * zero) read zeros as well
 #pragma unroll
-    for (int i = 0; i < kPerLane; i++) w[i] = W[in[i] ? d[i] >> 5 : 0u];
+    for (int i = 0; i < kPerLane; i++) w[i] = W[min(d[i] >> 5, zero)];
+    // bit d mod 32 of w (the hardware bit-field extract reads the low 5 bits of the offset)
 #pragma unroll
-    for (int i = 0; i < kPerLane; i++) c += in[i] ? (w[i] >> (d[i] & 31u)) & 1u : 0u;
+    for (int i = 0; i < kPerLane; i++) c += __builtin_amdgcn_ubfe(w[i], d[i], 1u);
   } else {
 #pragma unroll
     for (int h0 = 0; h0 < kPerLane; h0 += 2) {
