@@ -244,16 +244,20 @@ struct ScatterItems {
 };
 
 // Mask of the lanes whose BITS-bit value equals this lane's (all 64 lanes active).
+// Per bit: the bit as 0 / all-ones, its ballot, and the lanes whose bit differs
+// (ballot xor own bit) OR-ed into a mismatch mask; the peers are the rest.
 template <int BITS>
 __device__ __forceinline__ uint64_t match_any(uint32_t d) {
-  uint64_t peers = ~0ull;
+  uint32_t mis_lo = 0, mis_hi = 0;
 #pragma unroll
   for (int b = 0; b < BITS; b++) {
-    const bool bit = (d >> b) & 1u;
-    const uint64_t bb = __ballot(bit);
-    peers &= bit ? bb : ~bb;
+    const uint32_t m = static_cast<uint32_t>(__builtin_amdgcn_sbfe(static_cast<int32_t>(d), b, 1));
+    const uint64_t bb = __ballot(m != 0u);
+    // mis |= bb ^ m in one op per half (truth table of S0 | (S1 ^ S2))
+    mis_lo = __builtin_amdgcn_bitop3_b32(mis_lo, static_cast<uint32_t>(bb), m, 0xF6);
+    mis_hi = __builtin_amdgcn_bitop3_b32(mis_hi, static_cast<uint32_t>(bb >> 32), m, 0xF6);
   }
-  return peers;
+  return ~((static_cast<uint64_t>(mis_hi) << 32) | mis_lo);
 }
 
 // Single-sweep LSD radix sort. One read of the keys counts the digits of
@@ -371,15 +375,13 @@ __global__ __launch_bounds__(kScatterBlock) void k_sweep_scatter(const K* __rest
   uint32_t rk[ITEMS];
   uint32_t dg[ITEMS];
   uint16_t* cnt = wc[w];
+  // All peers read the digit's count (one broadcast read), then the lowest
+  // peer adds the group; LDS operations of one wave complete in order.
   auto rank_item = [&](int i, uint32_t d, uint64_t peers, bool valid) {
     const uint32_t lr = static_cast<uint32_t>(__popcll(peers & lanemask_lt()));
-    const int leader = __ffsll(static_cast<long long>(peers)) - 1;
-    uint32_t old = 0;
-    if (valid && lr == 0) {
-      old = cnt[d];
-      cnt[d] = static_cast<uint16_t>(old + static_cast<uint32_t>(__popcll(peers)));
-    }
-    old = __shfl(old, leader, kWave);
+    const uint32_t old = valid ? static_cast<uint32_t>(cnt[d]) : 0u;
+    __builtin_amdgcn_wave_barrier();
+    if (valid && lr == 0) cnt[d] = static_cast<uint16_t>(old + static_cast<uint32_t>(__popcll(peers)));
     dg[i] = d;
     rk[i] = old + lr;
     __builtin_amdgcn_wave_barrier();
