@@ -274,7 +274,7 @@ def main():
     args = ap.parse_args()
     ws = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or ws != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}), flush=True)
+        print(json.dumps({"error": "the benchmark measures one GPU (one process, no collectives); --gpus must be 1"}), flush=True)
         sys.exit(2)
     if args.calibrate_copy_gib > 0:
         import torch
