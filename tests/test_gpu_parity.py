@@ -281,6 +281,47 @@ def test_config_ba22(tc):
     check_all(tc, synth.config_ba22(), listing=True, label="BA n=2^22 k=8 seed 2")
 
 
+def test_sparse_graph_on_a_large_id_range(tc):
+    """A small R-MAT graph spread over ids 0 .. n-1 with n = 2^28 + 3 (29-bit ids, 58-bit sort keys). By
+    relabelling invariance (pinned in the oracle tests) every output is the compact graph's, mapped through
+    the increasing id map; the map keeps the degree-order ties, so W and P are unchanged too. Unused ids are
+    isolated: per-node counts and clustering numerators 0."""
+    import torch
+
+    small = synth.rmat(11, 8, 77)
+    k = small.n
+    n = (1 << 28) + 3
+    ids = np.arange(k, dtype=np.int64) * ((n - 1) // (k - 1))
+    ids[-1] = n - 1
+    assert np.all(np.diff(ids) > 0)
+    ref = oracle.solve(small.src, small.dst, k, per_node=True, listing=True)
+    say(f"[parity] large id range: n={n} k={k} m={ref.m} T={ref.T}")
+    s = torch.from_numpy(ids[small.src].astype(np.int32)).cuda()
+    d = torch.from_numpy(ids[small.dst].astype(np.int32)).cuda()
+    with tc.Graph.build(s, d, n) as g:
+        assert g.n == n and g.m == ref.m
+        assert g.count() == ref.T
+        T, t = g.count_per_node()
+        assert T == ref.T
+        t = t.cpu().numpy().astype(np.uint64)
+        np.testing.assert_array_equal(t[ids], ref.t)
+        assert int(t.sum()) == 3 * ref.T
+        del t
+        num, den, c = g.clustering()
+        num = num.cpu().numpy().astype(np.uint64)
+        np.testing.assert_array_equal(num[ids], ref.num)
+        assert int(num.sum()) == 3 * ref.T
+        del num, den
+        c = c.cpu().numpy()
+        np.testing.assert_array_equal(c[ids].view(np.uint64), ref.cc.view(np.uint64))
+        del c
+        np.testing.assert_array_equal(g.list().cpu().numpy(), ids[ref.tri].astype(np.int32))
+        W, P = g.work()
+        assert W == oracle.work(ref.off, ref.adj, k)
+        dh = np.diff(ref.off).astype(np.int64)
+        assert P == int((dh * (dh - 1) // 2).sum())
+
+
 # ----------------------------------------------------------------- orders ---
 
 @pytest.mark.parametrize("order", [0, 1, 2, 3, 4])
