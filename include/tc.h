@@ -57,7 +57,8 @@ typedef enum tc_status {
  *   src, dst   : int32[num_edges] endpoint ids (host, or device with TC_IN_DEVICE).
  *                May be freed as soon as the call returns.
  *   num_edges  : >= 0 raw records (loops and duplicates allowed).
- *   n          : >= 0 vertices; ids must lie in [0,n) else TC_E_RANGE.
+ *   n          : 0 .. 2^31 - 2^25 vertices (else TC_E_RANGE); ids must lie in
+ *                [0,n) else TC_E_RANGE.
  *   out        : receives the new graph; owned by the caller until tc_graph_free.
  * Internally vertices are numbered by their position in the degree order, so
  * that every oriented list holds only later vertices in ascending order.
@@ -249,7 +250,8 @@ tc_status tc_graph_export_csr(tc_graph* g, void* stream, int64_t* off, int32_t* 
  * tc_graph_export_csr writes. The offsets are checked on the host and the
  * rows on the device before they are counted. A violation gives TC_E_INVAL,
  * as do off in device memory, NULL
- * arguments and budget_bytes < 4096. TC_E_NOMEM if one row alone does not fit
+ * arguments and budget_bytes < 4096; n above 2^31 - 2^25 gives TC_E_RANGE.
+ * TC_E_NOMEM if one row alone does not fit
  * half the budget. The budget covers the copies, records and plans; the
  * kernel's counters come on top. Output: *T. info (may be NULL) gets uint64[4]:
  * pivot partitions, chunks shipped, (partition, source range) pairs visited,
@@ -315,7 +317,8 @@ int64_t tc_get_option(tc_option key);
  * All arrays are host memory unless TC_IN_DEVICE (src/dst only; edge_off and
  * n_per_graph are always host). Counting on the result gives per-graph totals
  * with tc_batch_count; per-node arrays are indexed by base[g] + local id with
- * base[g] = n_per_graph[0] + ... + n_per_graph[g-1].
+ * base[g] = n_per_graph[0] + ... + n_per_graph[g-1]. More than 2^31 - 2^25
+ * vertices in all gives TC_E_RANGE.
  */
 tc_status tc_batch_build(const int32_t* src, const int32_t* dst, const int64_t* edge_off,
                          const int32_t* n_per_graph, int32_t num_graphs, uint32_t flags, void* stream,

@@ -207,7 +207,7 @@ tc_status tc_batch_build(const int32_t* src, const int32_t* dst, const int64_t* 
     *out = nullptr;
     int64_t ntot = 0;
     for (int32_t i = 0; i < num_graphs; i++) ntot += n_per_graph[i] > 0 ? n_per_graph[i] : 0;
-    require(ntot <= INT32_MAX, TC_E_RANGE, "batch has more than 2^31 - 1 vertices");
+    require(ntot <= kMaxVertices, TC_E_RANGE, "batch has more than 2^31 - 2^25 vertices");
     const hipStream_t s = as_stream(stream);
     auto* g = new tc_graph();
     try {
@@ -497,6 +497,7 @@ tc_status tc_count_streamed(const int64_t* off, const int32_t* adj, int32_t n, i
   return guarded([&] {
     require(off != nullptr && T != nullptr && (adj != nullptr || m == 0), TC_E_INVAL, "NULL argument");
     require(n >= 0 && m >= 0, TC_E_INVAL, "negative size");
+    require(n <= kMaxVertices, TC_E_RANGE, "more than 2^31 - 2^25 vertices");
     require(budget_bytes >= 4096, TC_E_INVAL, "budget below 4096 bytes");
     hipPointerAttribute_t at{};
     if (hipPointerGetAttributes(&at, off) == hipSuccess && at.type == hipMemoryTypeDevice)

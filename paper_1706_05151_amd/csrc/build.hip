@@ -242,6 +242,7 @@ void build_graph(const int32_t* src, const int32_t* dst, int64_t E, int32_t n, c
                  const int32_t* n_per_graph_host, int32_t G, bool on_device, hipStream_t s, tc_graph* g, int order,
                  const int32_t* key_by_id) {
   if (E < 0 || n < 0) fail(TC_E_RANGE, "negative edge or vertex count");
+  if (n > kMaxVertices) fail(TC_E_RANGE, "more than 2^31 - 2^25 vertices");
   if (E >= (1ll << 32) - 1) fail(TC_E_INVAL, "more than 2^32 - 2 edge records");
   if (E > 0 && (!src || !dst)) fail(TC_E_INVAL, "NULL edge array");
   TC_HIP(hipGetDevice(&g->device));

@@ -13,6 +13,9 @@
 namespace tc {
 
 constexpr int kWave = 64;
+// Most vertices a graph may have: grid-stride loops over vertices count in
+// int32 with strides of at most 2^24, so n + 2^24 must stay below 2^31.
+constexpr int32_t kMaxVertices = (1 << 30) + ((1 << 30) - (1 << 25));
 
 // ------------------------------------------------------------ host errors --
 

@@ -3,6 +3,7 @@
 Integer results (T, t_v, m', T_s, lists, orientation) must be bit-exact; the
 clustering doubles are compared bit for bit as well, beside the exact rationals.
 """
+import ctypes
 import math
 import sys
 
@@ -222,6 +223,17 @@ def test_errors(tc):
         assert g.list(cap=20).shape == (20, 3)
     with pytest.raises(tc.TCError):
         tc.set_option(tc.OPT_KERNEL, 7)
+    # more vertices than the int32 vertex loops allow: refused before anything is allocated
+    big = 2 ** 31 - 2 ** 25 + 1
+    s = torch.tensor([0], dtype=torch.int32, device="cuda")
+    d = torch.tensor([1], dtype=torch.int32, device="cuda")
+    with pytest.raises(tc.TCError) as e:
+        tc.Graph.build(s, d, big)
+    assert e.value.status == tc.TC_E_RANGE
+    off = np.zeros(2, np.int64)  # n is checked before the offsets are read
+    T = ctypes.c_uint64()
+    st = tc.lib().tc_count_streamed(tc._hptr(off), None, big, 0, 1 << 20, tc._stream(None), ctypes.byref(T), None)
+    assert st == tc.TC_E_RANGE
 
 
 # ---------------------------------------------------------------- batches ---
