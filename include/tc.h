@@ -23,7 +23,9 @@
  *     for the calling thread.
  *   - A tc_graph is read-only after it is built. Queries on one graph may run
  *     concurrently on different streams; each call takes its own scratch memory.
- *   - Limits: n <= 2^31 - 1, and the number of input edge records < 2^32.
+ *   - Limits: n <= 2^31 - 2^25 vertices and at most 2^32 - 2^25 input edge
+ *     records (32-bit counters with grid strides of up to 2^24), else TC_E_RANGE
+ *     and TC_E_INVAL.
  */
 #ifndef TC_H_
 #define TC_H_
@@ -56,7 +58,8 @@ typedef enum tc_status {
  * the oriented lists N_v sorted ascending as a CSR.
  *   src, dst   : int32[num_edges] endpoint ids (host, or device with TC_IN_DEVICE).
  *                May be freed as soon as the call returns.
- *   num_edges  : >= 0 raw records (loops and duplicates allowed).
+ *   num_edges  : 0 .. 2^32 - 2^25 raw records (loops and duplicates allowed;
+ *                more gives TC_E_INVAL).
  *   n          : 0 .. 2^31 - 2^25 vertices (else TC_E_RANGE); ids must lie in
  *                [0,n) else TC_E_RANGE.
  *   out        : receives the new graph; owned by the caller until tc_graph_free.

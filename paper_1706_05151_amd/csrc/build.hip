@@ -243,7 +243,8 @@ void build_graph(const int32_t* src, const int32_t* dst, int64_t E, int32_t n, c
                  const int32_t* key_by_id) {
   if (E < 0 || n < 0) fail(TC_E_RANGE, "negative edge or vertex count");
   if (n > kMaxVertices) fail(TC_E_RANGE, "more than 2^31 - 2^25 vertices");
-  if (E >= (1ll << 32) - 1) fail(TC_E_INVAL, "more than 2^32 - 2 edge records");
+  // k_canon counts records in uint32 with strides of up to 2^24
+  if (E > (1ll << 32) - (1ll << 25)) fail(TC_E_INVAL, "more than 2^32 - 2^25 edge records");
   if (E > 0 && (!src || !dst)) fail(TC_E_INVAL, "NULL edge array");
   TC_HIP(hipGetDevice(&g->device));
   g->n = n;
