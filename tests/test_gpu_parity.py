@@ -293,6 +293,37 @@ def test_config_ba22(tc):
     check_all(tc, synth.config_ba22(), listing=True, label="BA n=2^22 k=8 seed 2")
 
 
+@pytest.mark.parametrize("hub", [256, 0])
+def test_complete_graph_with_lists_past_the_slice_caps(tc, hub):
+    """K_5000 by its closed forms: in the degree order (all degrees equal, ties by id) N_v holds the 4999 - v
+    later vertices, so the first pivots' lists exceed the 2048- and 4096-entry slices that hub items stage
+    and are cut into several slices. T = C(n,3); t_v = C(n-1,2); every clustering coefficient is 1;
+    P = sum C(dhat,2) = C(n,3); W = sum over edges of dhat_v + dhat_u = (n-1) m."""
+    import torch
+
+    n = 5000
+    el = synth.complete(n)
+    old = tc.get_option(tc.OPT_HUB_DHAT)
+    tc.set_option(tc.OPT_HUB_DHAT, hub)
+    try:
+        with tc.Graph.build(*to_dev(el), n) as g:
+            say(f"[parity] K_{n} hub={hub}")
+            m = n * (n - 1) // 2
+            assert g.m == m and g.dhat_max == n - 1
+            T3 = math.comb(n, 3)
+            assert g.count() == T3
+            T, t = g.count_per_node()
+            assert T == T3
+            assert np.all(u64(t) == math.comb(n - 1, 2))
+            num, den, c = g.clustering()
+            assert np.all(u64(num) == math.comb(n - 1, 2)) and np.all(u64(den) == math.comb(n - 1, 2))
+            assert np.all(c.cpu().numpy() == 1.0)
+            W, P = g.work()
+            assert P == T3 and W == (n - 1) * m
+    finally:
+        tc.set_option(tc.OPT_HUB_DHAT, old)
+
+
 def test_sparse_graph_on_a_large_id_range(tc):
     """A small R-MAT graph spread over ids 0 .. n-1 with n = 2^28 + 3 (29-bit ids, 58-bit sort keys). By
     relabelling invariance (pinned in the oracle tests) every output is the compact graph's, mapped through
