@@ -293,6 +293,37 @@ def test_config_ba22(tc):
     check_all(tc, synth.config_ba22(), listing=True, label="BA n=2^22 k=8 seed 2")
 
 
+@pytest.fixture(scope="module")
+def rmat19():
+    el = synth.rmat(19, 16, 21)
+    return el, oracle.solve(el.src, el.dst, el.n, per_node=True, listing=False)
+
+
+@pytest.mark.parametrize("hub,load", [(16, 2), (16, 1), (256, 2)])
+def test_block_hash_tables(tc, rmat19, hub, load):
+    """R-MAT 19 (n = 2^19): with pivots of more than 16 entries on the block path, 93,679 of them span more
+    ranks than a block's bitmap holds and take the block hash table (either bucket load); per-node counts
+    and clustering in full against the oracle."""
+    el, ref = rmat19
+    old = (tc.get_option(tc.OPT_HUB_DHAT), tc.get_option(tc.OPT_HUB_BUCKET_LOAD))
+    tc.set_option(tc.OPT_HUB_DHAT, hub)
+    tc.set_option(tc.OPT_HUB_BUCKET_LOAD, load)
+    try:
+        with tc.Graph.build(*to_dev(el), el.n) as g:
+            say(f"[parity] R-MAT 19 block hash hub={hub} load={load}")
+            assert g.m == ref.m
+            assert g.count() == ref.T
+            T, t = g.count_per_node()
+            assert T == ref.T
+            np.testing.assert_array_equal(u64(t), ref.t)
+            num, den, c = g.clustering()
+            np.testing.assert_array_equal(u64(num), ref.num)
+            np.testing.assert_array_equal(c.cpu().numpy().view(np.uint64), ref.cc.view(np.uint64))
+    finally:
+        tc.set_option(tc.OPT_HUB_DHAT, old[0])
+        tc.set_option(tc.OPT_HUB_BUCKET_LOAD, old[1])
+
+
 @pytest.mark.parametrize("hub", [256, 0])
 def test_complete_graph_with_lists_past_the_slice_caps(tc, hub):
     """K_5000 by its closed forms: in the degree order (all degrees equal, ties by id) N_v holds the 4999 - v
