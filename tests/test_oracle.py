@@ -216,6 +216,24 @@ def test_theorem1_any_order_counts_once():
         assert T == r.T
 
 
+def test_work_equals_sum_of_degree_products():
+    """Theorem 2: the merge work W, the sum over oriented edges (v,u) of dhat_v + dhat_u, equals
+    sum_v d_v dhat_v, since v is the source of dhat_v oriented edges and the target of the other d_v - dhat_v;
+    this holds under any order. For K_n every vertex has d = n - 1, so W = (n - 1) m."""
+    src, dst = messy_random_graph(300, 2000, 4)
+    graphs = [(g.src, g.dst, g.n) for g in (synth.ba(3000, 4, 7), synth.rmat(11, 8, 8), synth.er(2000, 0.01, 9))]
+    for s, d, n in graphs + [(src, dst, 300)]:
+        r = oracle.solve(s, d, n)
+        lo, hi = r.extra["lo"], r.extra["hi"]
+        rng = np.random.default_rng(11)
+        for off, adj in [(r.off, r.adj), oracle.orient_by_key(lo, hi, rng.permutation(n).astype(np.int64), n)]:
+            assert oracle.work(off, adj, n) == int((r.deg.astype(np.int64) * np.diff(off)).sum())
+    for n in (2, 3, 30, 101):
+        g = synth.complete(n)
+        r = oracle.solve(g.src, g.dst, n)
+        assert oracle.work(r.off, r.adj, n) == (n - 1) * (n * (n - 1) // 2)
+
+
 def test_theorem3_degree_order_minimises_cost():
     """Theorem 3: sum_v d_v * dhat_v is smallest under the degree order."""
     for g in (synth.ba(3000, 4, 7), synth.rmat(11, 8, 8), synth.er(2000, 0.01, 9)):
