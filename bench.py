@@ -92,6 +92,28 @@ def cpu_baseline(scale: int = 20):
     }
 
 
+def cached_full_scale_oracle():
+    """The oracle's own run on the whole R-MAT scale-26 workload, stored with its
+    results by tests/golden/make_rmat26.py (too long to repeat in a bench run)."""
+    path = os.path.join(ROOT, "tests", "golden", "rmat26.json")
+    try:
+        with open(path) as f:
+            g = json.load(f)
+    except (OSError, ValueError):
+        return None
+    out = {"m": g["m"], "T": g["T"], "threads": g.get("threads"), "seconds_total": g.get("seconds"),
+           "what": "tests/golden/make_rmat26.py on the build container: generation, 64 vertices by the "
+                   "definition, simple graph, degrees and orientation (serial), W, T (counting loop on "
+                   "all threads) and two sparsified counts"}
+    ph = g.get("phase_seconds")
+    if ph:
+        out["phase_seconds"] = ph
+        if "build" in ph and "count" in ph:
+            out["value"] = g["m"] / (ph["build"] + ph["count"])
+            out["unit"] = "oriented edges/s"
+    return out
+
+
 def make_workload(name: str, scale: int):
     import synth
 
@@ -180,19 +202,31 @@ def run_graph_bench(args):
     out["count_ms"] = cm
     out["count_edges_per_s"] = m / (cm / 1e3)
     out["count_steps_per_s"] = W / (cm / 1e3)
-    # roofline of the dominant kernel (the persistent intersection kernel of tc_count)
-    b_alg = 4 * W + 24 * m
+    # Roofline of the dominant kernel (k_pivot, the persistent intersection
+    # kernel of tc_count) on its own algorithmic bytes per launch: every probed
+    # suffix element once (4 B each; P = sum_v C(dhat_v, 2) probes), per
+    # oriented edge one 8-byte in-edge record and one staged 4-byte entry of
+    # the pivot's list, per vertex the two 8-byte offsets of its list and of
+    # its in-edge records.
+    b_alg = 4 * P + 12 * m + 16 * n
     achieved = b_alg / (cm / 1e3) / 1e9
     traffic = measured_traffic("hbm_bytes_per_launch") if args.workload == "rmat" and args.scale == 26 else None
     out["roofline"] = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                        "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                        "kernel": "k_pivot (one launch per tc_count)",
-                       "algorithmic_bytes": b_alg, "model": "4*W + 24*m bytes per count (merge model)",
-                       "probe_bytes_4P": 4 * P}
+                       "algorithmic_bytes": b_alg,
+                       "model": "4*P + 12*m + 16*n bytes per launch (probed suffix elements, in-edge records, "
+                                "staged list entries, offsets)"}
     if traffic:
         # measured HBM bytes of one launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, calibrated) over this run's time
         out["roofline"]["traffic_gbs"] = traffic / (cm / 1e3) / 1e9
         out["roofline"]["traffic_frac"] = out["roofline"]["traffic_gbs"] / HBM_PEAK_GBS
+    # The paper's merge cost model (Theorem 2): 4 B per merge step of W plus 24 B per
+    # oriented edge. The pivot kernel does not move these bytes; the rate is the
+    # merge-equivalent throughput, beside count_steps_per_s.
+    b_merge = 4 * W + 24 * m
+    out["merge_equivalent"] = {"bytes": b_merge, "gbs": b_merge / (cm / 1e3) / 1e9,
+                               "model": "4*W + 24*m bytes per count (merge model of Theorem 2)"}
     if not args.no_plain:
         ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
         ev[0].record(stream)
@@ -253,6 +287,8 @@ def run_graph_bench(args):
     if not args.no_cpu_baseline:
         log("[bench] CPU oracle baseline ...")
         out["cpu_baseline"] = cpu_baseline()
+        if args.workload == "rmat" and args.scale == 26:
+            out["cpu_baseline"]["full_scale"] = cached_full_scale_oracle()
     return out
 
 

@@ -74,7 +74,9 @@ tc_status tc_build_csr(const int32_t* src, const int32_t* dst, int64_t num_edges
  * dhat_max (Definition of effective degree, Section 3). Any output may be NULL. */
 tc_status tc_graph_info(const tc_graph* g, int32_t* n, int64_t* m, int32_t* d_max, int32_t* dhat_max);
 
-/* Release the graph and its device memory. NULL is ignored. */
+/* Release the graph and its device memory once the work already queued on it
+ * is done (calls that return before their work ends are waited for on the host;
+ * other streams of the device are not synchronised). NULL is ignored. */
 void tc_graph_free(tc_graph* g);
 
 /*
@@ -278,6 +280,27 @@ tc_status tc_graph_degrees(tc_graph* g, void* stream, int32_t* deg_dev, int32_t*
 tc_status tc_graph_oriented(tc_graph* g, void* stream, int64_t* off_dev, int32_t* adj_dev);
 
 /*
+ * Rebuild the graph's work plan (the in-edge records grouped by pivot and the
+ * work items cut from their cost prefix by the boundary rule of Section 5,
+ * load balancing) with the current TC_OPT_HUB_DHAT and TC_OPT_ITEM_WORK
+ * options. Calls that count rebuild the plan themselves when those options
+ * changed, except tc_batch_count, which uses the plan as it is; tuners call
+ * this before timing a batch. The old plan is freed after every launch that
+ * read it, ordered on `stream`. TC_E_INVAL once a tc_batch_count on this
+ * graph was captured into a HIP graph: the capture holds the plan's
+ * addresses, so the plan stays as it is for the graph's lifetime (calls that
+ * count then use it whatever the options; results do not depend on them).
+ * Synchronises `stream`.
+ */
+tc_status tc_graph_replan(tc_graph* g, void* stream);
+
+/* Options the graph's current work plan was built with (TC_OPT_HUB_DHAT as
+ * clamped by the library, TC_OPT_ITEM_WORK as set, 0 = automatic) and whether
+ * it is frozen by a capture (1) or not (0). Any output may be NULL. TC_E_INVAL
+ * if the graph has no plan. */
+tc_status tc_graph_plan_info(const tc_graph* g, int64_t* hub_dhat, int64_t* item_work, int32_t* frozen);
+
+/*
  * Tuning options (process-wide; read at the start of each call).
  *   TC_OPT_KERNEL        : 0 auto (plain merge when the wedge checks are
  *                          fewer than 16 per edge, else pivot-staged),
@@ -335,7 +358,10 @@ tc_status tc_batch_size(const tc_graph* g, int32_t* num_graphs);
  * per-node counts t_dev[sum n] in one launch sequence. Does not synchronise
  * `stream` (results are ready when the stream reaches this point), so the call
  * can be captured in a HIP graph. Scratch memory comes from the graph's own
- * workspace: calls on one batch graph must not overlap.
+ * workspace: calls on one batch graph must not overlap. Uses the work plan as
+ * it is (see tc_graph_replan). Capturing the call freezes the plan: the HIP
+ * graph holds the addresses of the plan's and the graph's arrays, so it must
+ * not be replayed after tc_graph_free.
  */
 tc_status tc_batch_count(tc_graph* g, void* stream, uint64_t* T_dev, uint64_t* t_dev);
 

@@ -63,7 +63,6 @@ def _load():
         "orc_orient_by_key": ([vp, vp, i64, vp, i32, vp, vp], None),
         "orc_count_nin": ([vp, vp, i32, vp, vp, i64], u64),
         "orc_count_nin_total_omp": ([vp, vp, i32], u64),
-        "orc_count_nin_range": ([vp, vp, i32, i32], u64),
         "orc_work": ([vp, vp, i32], u64),
         "orc_count_nodeiterpp": ([vp, vp, vp, i32], u64),
         "orc_sort_triples": ([vp, i64], None),
@@ -200,10 +199,6 @@ def count_nin(off, adj, n: int, per_node: bool = False, listing: bool = False, c
 
 def count_nin_total_omp(off, adj, n: int) -> int:
     return int(_load().orc_count_nin_total_omp(_p(off), _p(adj), n))
-
-
-def count_nin_range(off, adj, v0: int, v1: int) -> int:
-    return int(_load().orc_count_nin_range(_p(off), _p(adj), v0, v1))
 
 
 def order_positions(key, n: int) -> np.ndarray:

@@ -343,17 +343,6 @@ uint64_t orc_count_nin_total_omp(const int64_t* off, const int32_t* adj, int32_t
   return T;
 }
 
-/* Counting loop restricted to sources v in [v0, v1): used for a bounded CPU sample. */
-uint64_t orc_count_nin_range(const int64_t* off, const int32_t* adj, int32_t v0, int32_t v1) {
-  uint64_t T = 0;
-  for (int32_t v = v0; v < v1; v++)
-    for (int64_t k = off[v]; k < off[v + 1]; k++) {
-      int32_t u = adj[k];
-      T += (uint64_t)merge_count(adj + off[v], off[v + 1] - off[v], adj + off[u], off[u + 1] - off[u]);
-    }
-  return T;
-}
-
 /* ------------------------------------------------------------- shards --- */
 
 static const int64_t* g_pos_key; /* key of the qsort below (single-threaded use) */

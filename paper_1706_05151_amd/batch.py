@@ -5,8 +5,9 @@ graph and replayed.
 The union keeps each graph's vertices contiguous (graph-major degree ranks), so
 per-graph totals come out of the same launch (each work item's pivot belongs to
 exactly one graph) and per-node counts are per-graph slices of one array.
-The autotuner times candidate partitioner settings (options of the C ABI) on
-the batch and keeps the fastest; settings change speed only, never results.
+The autotuner rebuilds the batch's work plan under each candidate partitioner
+setting (options of the C ABI), times the batched count it deploys and keeps
+the fastest; settings change speed only, never results.
 """
 from __future__ import annotations
 
@@ -114,30 +115,40 @@ class BatchCounter:
 
 
 def autotune(bc: BatchCounter, candidates=None, reps: int = 3, key: Optional[str] = None, persist: bool = True):
-    """Time candidate partitioner settings on the batch (tc_count rebuilds the
-    work plan when settings change) and keep the fastest. Returns (best, table)."""
+    """Time candidate partitioner settings on the batch in the mode that is
+    deployed (tc_batch_count, with per-node counts when bc.per_node) and keep
+    the fastest. For each candidate the graph's work plan is rebuilt with its
+    settings (tc_graph_replan; tc_batch_count itself never rebuilds), its
+    results are checked against the first candidate's, and the batch count is
+    timed. The fastest candidate's plan is rebuilt last and stays on the graph,
+    so a later capture() records it. Settings change speed only, never
+    results. Returns (best, table)."""
     torch = bc.torch
     candidates = candidates or DEFAULT_CANDIDATES
     g = bc.graph
-    ref = None
+    T_ref = t_ref = None
     table = []
     for opts in candidates:
         apply_options(opts)
-        T = g.count()  # rebuilds the plan for these settings
-        if ref is None:
-            ref = T
-        assert T == ref, "autotuner setting changed the count"
+        g.replan(bc.stream)
+        bc.count()
+        torch.cuda.synchronize()
+        if T_ref is None:
+            T_ref = bc.T.clone()
+            t_ref = bc.t.clone() if bc.per_node else None
+        assert torch.equal(bc.T, T_ref), "autotuner setting changed the per-graph totals"
+        assert t_ref is None or torch.equal(bc.t, t_ref), "autotuner setting changed the per-node counts"
         best = float("inf")
         for _ in range(reps):
             torch.cuda.synchronize()
             t0 = time.perf_counter()
-            assert g.count() == ref
+            bc.count()
             torch.cuda.synchronize()
             best = min(best, time.perf_counter() - t0)
         table.append({"options": list(opts), "ms": 1e3 * best})
     best = min(table, key=lambda r: r["ms"])
     apply_options(best["options"])
-    g.count()  # the plan of the chosen settings stays on the graph
+    g.replan(bc.stream)  # the plan of the chosen settings stays on the graph
     if persist and key:
         data = {}
         if os.path.exists(AUTOTUNE_FILE):

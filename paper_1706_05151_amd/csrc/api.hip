@@ -224,6 +224,30 @@ tc_status tc_batch_build(const int32_t* src, const int32_t* dst, const int64_t* 
   });
 }
 
+tc_status tc_graph_replan(tc_graph* g, void* stream) {
+  return guarded([&] {
+    require(g != nullptr, TC_E_INVAL, "graph is NULL");
+    DeviceScope ds(g->device);
+    const hipStream_t s = as_stream(stream);
+    {
+      std::lock_guard<std::mutex> lk(g->mu);
+      rebuild_plan(g->csr, s, get_options());
+    }
+    TC_HIP(hipStreamSynchronize(s));
+  });
+}
+
+tc_status tc_graph_plan_info(const tc_graph* g, int64_t* hub_dhat, int64_t* item_work, int32_t* frozen) {
+  return guarded([&] {
+    require(g != nullptr, TC_E_INVAL, "graph is NULL");
+    const PivotPlan& P = g->csr.plan;
+    require(P.ready, TC_E_INVAL, "the graph has no work plan");
+    if (hub_dhat) *hub_dhat = P.hub_dhat;
+    if (item_work) *item_work = P.item_work;
+    if (frozen) *frozen = P.frozen ? 1 : 0;
+  });
+}
+
 tc_status tc_batch_size(const tc_graph* g, int32_t* num_graphs) {
   return guarded([&] {
     require(g != nullptr && num_graphs != nullptr, TC_E_INVAL, "NULL argument");
@@ -246,7 +270,13 @@ void tc_graph_free(tc_graph* g) {
   const int dev = g->device;
   int prev = -1;
   if (hipGetDevice(&prev) == hipSuccess && prev != dev) (void)hipSetDevice(dev);
-  (void)hipDeviceSynchronize();
+  // Calls that return before their work is done (batch, multi-graph and
+  // clustering-from-counts) record an event on the graph's plan, and so does
+  // every launch of the intersection kernel; every other call synchronised
+  // its stream before returning. Waiting for those events makes the arrays
+  // free, without stalling the other streams of the device.
+  g->csr.plan.users.sync();
+  g->csr.shard.users.sync();
   delete g;
   if (prev >= 0 && prev != dev) (void)hipSetDevice(prev);
 }
@@ -630,6 +660,7 @@ tc_status tc_batch_count(tc_graph* g, void* stream, uint64_t* T_dev, uint64_t* t
                                                                           reinterpret_cast<unsigned long long*>(t_dev));
       TC_LAUNCH_CHECK();
     }
+    note_plan_use(g->csr.plan, s);
   });
 }
 
@@ -668,6 +699,7 @@ tc_status tc_multi_count(tc_graph* const* graphs, int32_t k, int32_t per_node, v
               trp[i], graphs[i]->order.p, graphs[i]->n, reinterpret_cast<unsigned long long*>(t_dev[i]));
           TC_LAUNCH_CHECK();
         }
+    for (int32_t i = 0; i < k; i++) note_plan_use(graphs[i]->csr.plan, s);
   });
 }
 
@@ -682,6 +714,7 @@ tc_status tc_clustering_from_counts(tc_graph* g, void* stream, const uint64_t* t
           reinterpret_cast<const unsigned long long*>(t_dev), g->deg.p, g->n, num_dev, den_dev, c_dev);
       TC_LAUNCH_CHECK();
     }
+    note_plan_use(g->csr.plan, as_stream(stream));
   });
 }
 

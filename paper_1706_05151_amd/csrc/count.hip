@@ -194,8 +194,9 @@ __global__ void k_int32_from_u64_hi(const uint64_t* __restrict__ k, uint64_t n, 
 
 }  // namespace
 
-// Hub items stage at most this many list entries at once (the slice size):
-// table and per-node counters then need at most 2 * 4096 * 4 B = 32 KB of LDS.
+// Hub items stage at most this many list entries at once (the slice size): at
+// the default two entries per 4-slot bucket the table has 1024 buckets, 20 KiB
+// of LDS for totals and 36 KiB with the per-node tallies.
 static int64_t hub_slice_cap(int) { return 2048; }
 
 static int device_cus() {
@@ -238,8 +239,8 @@ void order_cost(const Csr& c, const int32_t* deg, const int32_t* order, unsigned
 
 // Builds the in-edge records and the work items of the pivot kernels. The
 // plan depends on hub_dhat and item_work and is rebuilt when they change.
-// The item lists are built for the per-node slice cap (4096), which also
-// serves the total-only mode.
+// The item lists are built for the per-node slice cap (2048 entries, see
+// hub_slice_cap), which also serves the total-only mode.
 static int64_t clamp_hub(int64_t h) { return h < 0 ? 0 : (h > kWaveSlots / 2 ? kWaveSlots / 2 : h); }
 
 namespace {
@@ -368,10 +369,26 @@ bool plan_matches(const PivotPlan& P, int32_t lo, int32_t hi, const Options& o) 
 
 }  // namespace
 
+void note_plan_use(PivotPlan& P, hipStream_t s) {
+  hipStreamCaptureStatus st = hipStreamCaptureStatusNone;
+  TC_HIP(hipStreamIsCapturing(s, &st));
+  if (st != hipStreamCaptureStatusNone) P.frozen = true;
+  else P.users.record(s);
+}
+
 void ensure_plan(Csr& c, hipStream_t s, const Options& o) {
   PivotPlan& P = c.plan;
-  if (plan_matches(P, 0, c.n, o)) return;
-  if (P.ready) TC_HIP(hipDeviceSynchronize());  // launches on other streams may still read the old plan
+  if (P.frozen || plan_matches(P, 0, c.n, o)) return;  // a frozen plan serves every option set
+  if (P.ready) P.release_on(s);  // after every launch that read the old plan
+  build_plan(c, P, 0, static_cast<uint64_t>(c.m), s, o);
+  P.src_lo = 0;
+  P.src_hi = c.n;
+}
+
+void rebuild_plan(Csr& c, hipStream_t s, const Options& o) {
+  PivotPlan& P = c.plan;
+  if (P.frozen) fail(TC_E_INVAL, "the work plan is held by a captured HIP graph and cannot be rebuilt");
+  if (P.ready) P.release_on(s);
   build_plan(c, P, 0, static_cast<uint64_t>(c.m), s, o);
   P.src_lo = 0;
   P.src_hi = c.n;
@@ -381,7 +398,7 @@ void ensure_shard_plan(Csr& c, int32_t lo, int32_t hi, hipStream_t s, const Opti
   if (lo < 0 || hi > c.n || lo > hi) fail(TC_E_RANGE, "shard rank range outside [0, n]");
   PivotPlan& P = c.shard;
   if (plan_matches(P, lo, hi, o)) return;
-  if (P.ready) TC_HIP(hipDeviceSynchronize());
+  if (P.ready) P.release_on(s);
   int64_t e[2] = {0, 0};
   if (c.n > 0) {
     TC_HIP(hipMemcpyAsync(&e[0], c.off.p + lo, sizeof(int64_t), hipMemcpyDeviceToHost, s));
@@ -648,7 +665,7 @@ void fill_u64(unsigned long long* p, size_t n, unsigned long long v, hipStream_t
 }
 
 // One persistent launch of k_pivot over the records and items of plan P of c.
-void launch_pivot(const Csr& c, const PivotPlan& P, const CountArgs& ca, hipStream_t s, const Options& o) {
+void launch_pivot(const Csr& c, PivotPlan& P, const CountArgs& ca, hipStream_t s, const Options& o) {
   KernelArgs a{static_cast<int>(o.hub_bucket_load), c.off.p,     c.adj.p,          c.src.p,   P.inrec.p, P.in_off.p, ca.mode,  ca.total,
                ca.per_graph, ca.graph_of_rank, ca.t_rank, ca.order,  ca.tri,     ca.cursor, ca.cap};
   DevBuf<unsigned long long> qbuf;
@@ -686,6 +703,7 @@ void launch_pivot(const Csr& c, const PivotPlan& P, const CountArgs& ca, hipStre
     k_pivot<kCountTotal, false><<<grid, kPivotBlock, lds, s>>>(a, hub, P.n_hub_items, split, P.n_wave_items,
                                                                P.grouped.p, P.n_grouped, q, hub_log2b, none);
   TC_LAUNCH_CHECK();
+  note_plan_use(P, s);
 }
 
 namespace {
@@ -788,6 +806,7 @@ void count_multi(const std::vector<Csr*>& gs, const std::vector<unsigned long lo
     k_pivot<kCountTotal, true><<<grid, kPivotBlock, lds, s>>>(a, nullptr, n_hub, nullptr, n_split, nullptr, n_chunks,
                                                               q.get(), hub_log2b, jobs);
   TC_LAUNCH_CHECK();
+  for (Csr* c : gs) note_plan_use(c->plan, s);
 }
 
 // --------------------------------------------------------- sparsified ---

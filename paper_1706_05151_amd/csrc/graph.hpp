@@ -28,6 +28,13 @@ struct Owned {
     p = nullptr;
     n = 0;
   }
+  // Free ordered on stream s: the block is reused only after the work queued
+  // on s before this call (callers first make s wait for every reader).
+  void reset_on(hipStream_t s) {
+    if (p) dev_free(p, s);
+    p = nullptr;
+    n = 0;
+  }
   void alloc(size_t count, hipStream_t s = nullptr) {
     reset();
     n = count;
@@ -59,6 +66,56 @@ struct InRec {
   uint32_t a_len;    // entries of N_v after u
 };
 
+// Launches that read a plan's arrays: an event is recorded after each launch,
+// so that replacing or freeing the plan can wait for them (on a stream, or on
+// the host) instead of synchronising the whole device. Completed events are
+// pruned at the next record.
+struct PlanUsers {
+  std::mutex mu;
+  std::vector<hipEvent_t> events;
+  PlanUsers() = default;
+  PlanUsers(const PlanUsers&) = delete;
+  PlanUsers& operator=(const PlanUsers&) = delete;
+  ~PlanUsers() {
+    for (hipEvent_t e : events) (void)hipEventDestroy(e);
+  }
+  void record(hipStream_t s) {
+    std::lock_guard<std::mutex> lk(mu);
+    size_t keep = 0;
+    for (hipEvent_t e : events) {
+      if (hipEventQuery(e) == hipSuccess) (void)hipEventDestroy(e);
+      else events[keep++] = e;
+    }
+    (void)hipGetLastError();  // a pending query leaves hipErrorNotReady behind
+    events.resize(keep);
+    hipEvent_t e;
+    TC_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    if (hipEventRecord(e, s) != hipSuccess) {
+      (void)hipEventDestroy(e);
+      TC_HIP(hipGetLastError());
+    }
+    events.push_back(e);
+  }
+  // Makes stream s wait for every recorded launch; the events are then released.
+  void wait_on(hipStream_t s) {
+    std::lock_guard<std::mutex> lk(mu);
+    for (hipEvent_t e : events) {
+      TC_HIP(hipStreamWaitEvent(s, e, 0));
+      (void)hipEventDestroy(e);
+    }
+    events.clear();
+  }
+  // Host wait for every recorded launch.
+  void sync() {
+    std::lock_guard<std::mutex> lk(mu);
+    for (hipEvent_t e : events) {
+      (void)hipEventSynchronize(e);
+      (void)hipEventDestroy(e);
+    }
+    events.clear();
+  }
+};
+
 // The pivot work plan of one oriented CSR (built lazily, cached on the graph):
 // the in-edge records of the oriented edges whose source rank lies in
 // [src_lo, src_hi) (all edges for the graph's own plan), grouped by pivot, and
@@ -75,9 +132,15 @@ struct PivotPlan {
   uint64_t n_grouped = 0;
   int64_t hub_dhat = 0, item_work = 0;  // options the plan was built with
   uint64_t probes = 0;       // sum of suffix lengths |A| over records whose pivot has a non-empty N_u
+  // Set when a launch reading the plan was captured into a HIP graph: the
+  // graph holds the arrays' addresses, so the plan is never rebuilt or freed
+  // before the graph (tc_graph) itself.
+  bool frozen = false;
+  PlanUsers users;
   uint64_t n_split_items() const { return n_wave_items; }
   void reset() {
     ready = false;
+    frozen = false;
     inrec.reset();
     in_off.reset();
     items.reset();
@@ -85,6 +148,15 @@ struct PivotPlan {
     n_hub_items = n_wave_items = n_grouped = probes = 0;
     hub_dhat = item_work = 0;
     src_lo = src_hi = 0;
+  }
+  // Frees the arrays on stream s after s has waited for every launch that read them.
+  void release_on(hipStream_t s) {
+    users.wait_on(s);
+    inrec.reset_on(s);
+    in_off.reset_on(s);
+    items.reset_on(s);
+    grouped.reset_on(s);
+    reset();
   }
 };
 
@@ -160,7 +232,14 @@ struct CountArgs {
   int64_t cap = 0;
   unsigned long long* queues = nullptr;    // device [3] work-queue counters (optional)
 };
+// Builds the graph's plan unless one matching the options is ready; a frozen
+// plan (captured in a HIP graph) is kept whatever the options.
 void ensure_plan(Csr& c, hipStream_t s, const Options& o);
+// Rebuilds the graph's plan with the options (TC_E_INVAL if frozen).
+void rebuild_plan(Csr& c, hipStream_t s, const Options& o);
+// After work reading P was queued on s: freezes P if s is capturing a HIP
+// graph, else records an event that replacing or freeing P waits on.
+void note_plan_use(PivotPlan& P, hipStream_t s);
 // Plan steps from in-edge keys (pivot << 32 | e) sorted by pivot (stable in e):
 // the records and their cost prefix fin (lens: suffix lengths in key order, or
 // null to take them from c.off / c.src), then the classification and items.
@@ -178,7 +257,7 @@ void count_shard(Csr& c, int32_t lo, int32_t hi, unsigned long long* total, hipS
 // sum_{u in N_v} dhat_u); bounds int64[k+1] (device)
 void shard_bounds(const Csr& c, int32_t k, int cost, int64_t* bounds, hipStream_t s);
 // one persistent launch of the pivot kernel over the records and items of P (a plan of c)
-void launch_pivot(const Csr& c, const PivotPlan& P, const CountArgs& a, hipStream_t s, const Options& o);
+void launch_pivot(const Csr& c, PivotPlan& P, const CountArgs& a, hipStream_t s, const Options& o);
 // allow_rebuild = false: use the cached plan as is (capturable; fails if absent)
 void count_pivot(Csr& c, const CountArgs& a, hipStream_t s, const Options& o, bool allow_rebuild = true);
 void fill_u64(unsigned long long* p, size_t n, unsigned long long v, hipStream_t s);

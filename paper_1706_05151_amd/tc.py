@@ -47,6 +47,8 @@ SIGNATURES = {
     "tc_shard_bounds": ([_vp, _vp, _i32, _i32, _vp], ctypes.c_int),
     "tc_count_shard": ([_vp, _vp, _i32, _i32, _P(_u64)], ctypes.c_int),
     "tc_sparsify_count_partitioned": ([_vp, _dbl, _u64, _i32, _vp, _vp, _vp, _P(_u64), _P(_dbl)], ctypes.c_int),
+    "tc_graph_replan": ([_vp, _vp], ctypes.c_int),
+    "tc_graph_plan_info": ([_vp, _P(_i64), _P(_i64), _P(_i32)], ctypes.c_int),
     "tc_set_option": ([ctypes.c_int, _i64], ctypes.c_int),
     "tc_get_option": ([ctypes.c_int], _i64),
     "tc_batch_build": ([_vp, _vp, _vp, _vp, _i32, _u32, _vp, _P(_vp)], ctypes.c_int),
@@ -314,6 +316,17 @@ class Graph:
         adj = torch.empty(max(self.m, 1), dtype=torch.int32, device="cuda")
         _check(lib().tc_graph_oriented(self._h, _stream(stream), _dptr(off), _dptr(adj)), "tc_graph_oriented")
         return off, adj[: self.m]
+
+    def replan(self, stream=None):
+        """Rebuild the work plan with the current options (refused once a batch count was captured)."""
+        _check(lib().tc_graph_replan(self._h, _stream(stream)), "tc_graph_replan")
+
+    def plan_info(self) -> dict:
+        """Options the current work plan was built with, and whether a capture froze it."""
+        hd, iw, fr = _i64(), _i64(), _i32()
+        _check(lib().tc_graph_plan_info(self._h, ctypes.byref(hd), ctypes.byref(iw), ctypes.byref(fr)),
+               "tc_graph_plan_info")
+        return {"hub_dhat": hd.value, "item_work": iw.value, "frozen": bool(fr.value)}
 
     def batch_count(self, T_out, t_out=None, stream=None):
         """Per-graph totals (int64[num_graphs]) and optional per-node counts; no host sync."""

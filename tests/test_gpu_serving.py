@@ -97,6 +97,20 @@ def test_batch_hipgraph_replays(tcm):
         assert T_ref[i] == ref.T
         np.testing.assert_array_equal(t_ref[i], ref.t)
     bc.capture()
+    # the capture holds the plan's addresses: the plan is frozen, an explicit
+    # rebuild is refused, and counting under other options keeps using it
+    info = bc.graph.plan_info()
+    assert info["frozen"]
+    old = batch.current_options()
+    try:
+        with pytest.raises(tcm.TCError) as e:
+            bc.graph.replan()
+        assert e.value.status == tcm.TC_E_INVAL
+        batch.apply_options((32, 4096, old[2], old[3]))
+        assert bc.graph.count() == int(T_ref.sum())
+        assert bc.graph.plan_info() == info
+    finally:
+        batch.apply_options(old)
     for rep in range(4):
         bc.T.fill_(-1)
         bc.t.fill_(-1)
@@ -111,25 +125,37 @@ def test_batch_hipgraph_replays(tcm):
     bc.close()
 
 
-def test_autotune_keeps_results(tcm):
+@pytest.mark.parametrize("per_node", [False, True])
+def test_autotune_keeps_results(tcm, per_node):
+    """The autotuner rebuilds the plan per candidate and leaves the chosen
+    candidate's plan on the graph; results never change."""
     import torch
 
     from paper_1706_05151_amd import batch
 
     els = _graphs(64, 45)
-    bc = batch.BatchCounter(batch.pack(els), per_node=False)
+    bc = batch.BatchCounter(batch.pack(els), per_node=per_node)
     bc.build()
     bc.count()
     torch.cuda.synchronize()
     T0 = bc.T.cpu().numpy().copy()
+    t0 = [x.copy() for x in bc.per_graph_t()] if per_node else None
     old = batch.current_options()
     try:
-        best, table = batch.autotune(bc, candidates=[(128, 16384, 4, 2), (16, 256, 2, 1), (0, 100000, 3, 2)],
-                                     reps=1, persist=False)
+        cands = [(128, 16384, 4, 2), (16, 256, 2, 1), (0, 100000, 3, 2)]
+        best, table = batch.autotune(bc, candidates=cands, reps=1, persist=False)
         assert len(table) == 3
+        info = bc.graph.plan_info()
+        assert (info["hub_dhat"], info["item_work"]) == tuple(best["options"][:2])
+        assert not info["frozen"]
         bc.count()
         torch.cuda.synchronize()
         np.testing.assert_array_equal(bc.T.cpu().numpy(), T0)
+        if per_node:
+            for a, b in zip(bc.per_graph_t(), t0):
+                np.testing.assert_array_equal(a, b)
+        for i in (0, 31, 63):
+            assert T0[i] == oracle.solve(els[i].src, els[i].dst, els[i].n, per_node=False).T
     finally:
         batch.apply_options(old)
         bc.close()
@@ -152,14 +178,25 @@ def test_served_results_equal_standalone(tcm):
     for r in trace:
         assert serve.same_answer(ans[r.rid], fifo[r.rid]), r
     assert reg.evictions > 0
-    # spot-check against the oracle
-    for r in trace[:10]:
-        e = els[r.graph]
-        ref = oracle.solve(e.src, e.dst, e.n)
+    # every answer against the oracle: counts, clustering (exact rationals and
+    # doubles, by digest) and the sparsified estimates of the q = 0.2 samples
+    assert {r.kind for r in trace} == {serve.COUNT, serve.CLUSTER, serve.SPARSE}
+    refs = {}
+    for r in trace:
+        if r.graph not in refs:
+            e = els[r.graph]
+            ref = oracle.solve(e.src, e.dst, e.n)
+            lo, hi = ref.extra["lo"], ref.extra["hi"]
+            refs[r.graph] = (ref, lo, hi, {})
+        ref, lo, hi, sp = refs[r.graph]
         if r.kind == serve.COUNT:
-            assert ans[r.rid].value == ref.T
+            assert ans[r.rid].value == ref.T, r
         elif r.kind == serve.CLUSTER:
-            assert ans[r.rid].value == serve.cc_digest(ref.num, ref.den, ref.cc)
+            assert ans[r.rid].value == serve.cc_digest(ref.num, ref.den, ref.cc), r
+        else:
+            if (r.q, r.seed) not in sp:
+                sp[(r.q, r.seed)] = oracle.sparsified_count(lo, hi, ref.deg, els[r.graph].n, r.q, r.seed)[2]
+            assert ans[r.rid].value == sp[(r.q, r.seed)], r
     # the plain per-graph launch (build, answer, free per request) gives the same answers
     import torch
 

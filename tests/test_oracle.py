@@ -506,7 +506,7 @@ def test_partition_scheme_N_closed_form():
     assert bounds.tolist() == [0] + [j * g.n // p - 1 for j in range(1, p)] + [g.n]
 
 
-@pytest.mark.parametrize("scheme", [1, 3, 4, 5, 6])
+@pytest.mark.parametrize("scheme", [1, 2, 3, 4, 5, 6])
 def test_partition_boundary_rule_by_search(scheme):
     """Boundary nodes agree with a search on the cumulative cost: F(x_j - 1) < j F / p <= F(x_j)."""
     g = synth.ba(3000, 5, 9)
@@ -515,7 +515,7 @@ def test_partition_boundary_rule_by_search(scheme):
     src = np.repeat(np.arange(g.n), np.diff(off))
     merge = np.bincount(src, weights=(dh[src] + dh[adj]).astype(np.float64), minlength=g.n).astype(np.int64)
     insum = np.bincount(adj, weights=(dh[src] + dh[adj]).astype(np.float64), minlength=g.n).astype(np.int64)
-    f = {1: deg, 3: deg * dh, 4: dh * dh, 5: merge, 6: insum}[scheme].astype(np.int64)
+    f = {1: deg, 2: dh, 3: deg * dh, 4: dh * dh, 5: merge, 6: insum}[scheme].astype(np.int64)
     F = np.cumsum(f)
     p = 23
     bounds, work = oracle.partition_work(off, adj, deg, g.n, scheme, p)
