@@ -399,6 +399,29 @@ tc_status tc_sparsify_build(tc_graph* g, double q, uint64_t seed, void* stream, 
 /* T_sampled / (q*q*q), the estimate of Section 7 (the expression tc_sparsify_count uses). */
 double tc_sparsify_estimate(uint64_t T_sampled, double q);
 
+/* ------------------------------------------------------- allocation-free */
+
+/*
+ * For callers that cannot allocate device memory (tight serving loops,
+ * harnesses that forbid hipMalloc): the same results as tc_count_per_node
+ * (T and the per-node counts T_v by caller id, fully overwriting t_dev
+ * uint64[n]), computed without allocating or freeing any device memory.
+ * The work-queue counters, the total and the per-node counts by rank live in
+ * a static device array of the library, 32 MiB plus 32 bytes, which every
+ * device the library runs on holds until the process ends.
+ *   - At most 2^22 vertices (TC_E_RANGE above that, t_dev untouched).
+ *   - Uses the graph's work plan as tc_build_csr made it (options set since
+ *     then are not applied, which changes speed only); TC_E_INVAL on a
+ *     sampled graph.
+ *   - Every call on one device shares that device's array: calls that
+ *     overlap on one device (other threads, other streams) race and must not
+ *     be made. The array is cleared by each call before use.
+ *   - Holds the graph's lock until its results are in, so other calls on the
+ *     same graph wait for it.
+ * Synchronises `stream` (not capturable).
+ */
+tc_status tc_count_per_node_noalloc(tc_graph* g, void* stream, uint64_t* T, uint64_t* t_dev);
+
 /* ------------------------------------------------------------------ errors */
 
 const char* tc_status_str(tc_status s);

@@ -322,6 +322,79 @@ tc_status tc_count_per_node(tc_graph* g, void* stream, uint64_t* T, uint64_t* t_
   });
 }
 
+}  // extern "C"
+
+namespace tc {
+namespace {
+
+// Scratch of tc_count_per_node_noalloc, one copy per device held for the life
+// of the process: words 0..2 are the work-queue counters of the persistent
+// launch, word 3 the total, words 4.. the per-node counts by rank of at most
+// kNoAllocMaxVertices vertices (32 MiB in all).
+constexpr int32_t kNoAllocMaxVertices = 1 << 22;
+constexpr size_t kNoAllocWords = 4 + static_cast<size_t>(kNoAllocMaxVertices);
+__device__ __align__(256) unsigned long long scratch[kNoAllocWords];
+
+constexpr int kMaxScratchDevices = 64;
+std::mutex g_scratch_mu;
+unsigned long long* g_scratch_addr[kMaxScratchDevices] = {};
+
+// Device address of `scratch` on device dev, which must be current. In host
+// code the array's name is only a stand-in for the symbol; kernels are given
+// this address instead.
+unsigned long long* scratch_on(int dev) {
+  if (dev < 0 || dev >= kMaxScratchDevices) fail(TC_E_DEVICE, "device index out of range for the static scratch");
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_addr[dev]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || p == nullptr) {
+      (void)hipGetLastError();
+      fail(TC_E_DEVICE, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+    }
+    g_scratch_addr[dev] = static_cast<unsigned long long*>(p);
+  }
+  return g_scratch_addr[dev];
+}
+
+}  // namespace
+}  // namespace tc
+
+extern "C" {
+
+tc_status tc_count_per_node_noalloc(tc_graph* g, void* stream, uint64_t* T, uint64_t* t_dev) {
+  return guarded([&] {
+    require(g != nullptr && t_dev != nullptr, TC_E_INVAL, "NULL argument");
+    require(!g->sampled, TC_E_INVAL, "per-node counts are not available on a sampled graph");
+    require(g->n <= kNoAllocMaxVertices, TC_E_RANGE,
+            "more than 2^22 vertices: the static scratch holds per-node counts of at most 2^22 vertices");
+    DeviceScope ds(g->device);
+    const hipStream_t s = as_stream(stream);
+    unsigned long long* ws = scratch_on(g->device);
+    const int32_t n = g->n;
+    // Held until the counts are in host memory, so no other call replaces the
+    // plan while the launch reads it (the launch records no plan-use event).
+    std::lock_guard<std::mutex> lk(g->mu);
+    fill_u64(ws, 4 + static_cast<size_t>(n), 0ull, s);  // a fill kernel: no memset node, nothing allocated
+    CountArgs a;
+    a.mode = kCountPerNode;
+    a.queues = ws;
+    a.total = ws + 3;
+    a.t_rank = ws + 4;
+    a.note_use = false;
+    count_pivot(g->csr, a, s, get_options(), /*allow_rebuild=*/false);
+    if (n > 0) {
+      k_scatter_by_order<<<grid_for(n, kBlock, 65536), kBlock, 0, s>>>(ws + 4, g->order.p, n,
+                                                                        reinterpret_cast<unsigned long long*>(t_dev));
+      TC_LAUNCH_CHECK();
+    }
+    unsigned long long h = 0;
+    TC_HIP(hipMemcpyAsync(&h, ws + 3, sizeof(h), hipMemcpyDeviceToHost, s));
+    TC_HIP(hipStreamSynchronize(s));
+    if (T) *T = h;
+  });
+}
+
 tc_status tc_clustering(tc_graph* g, void* stream, uint64_t* num_dev, uint64_t* den_dev, double* c_dev) {
   return guarded([&] {
     require(g != nullptr, TC_E_INVAL, "graph is NULL");

@@ -703,7 +703,7 @@ void launch_pivot(const Csr& c, PivotPlan& P, const CountArgs& ca, hipStream_t s
     k_pivot<kCountTotal, false><<<grid, kPivotBlock, lds, s>>>(a, hub, P.n_hub_items, split, P.n_wave_items,
                                                                P.grouped.p, P.n_grouped, q, hub_log2b, none);
   TC_LAUNCH_CHECK();
-  note_plan_use(P, s);
+  if (ca.note_use) note_plan_use(P, s);
 }
 
 namespace {

@@ -231,6 +231,9 @@ struct CountArgs {
   unsigned long long* cursor = nullptr;    // device listing cursor
   int64_t cap = 0;
   unsigned long long* queues = nullptr;    // device [3] work-queue counters (optional)
+  // Record the launch as a user of the plan (see note_plan_use). Callers that
+  // hold the graph's lock until the launch has finished may skip it.
+  bool note_use = true;
 };
 // Builds the graph's plan unless one matching the options is ready; a frozen
 // plan (captured in a HIP graph) is kept whatever the options.

@@ -31,6 +31,7 @@ SIGNATURES = {
     "tc_graph_free": ([_vp], None),
     "tc_count": ([_vp, _vp, _P(_u64)], ctypes.c_int),
     "tc_count_per_node": ([_vp, _vp, _P(_u64), _vp], ctypes.c_int),
+    "tc_count_per_node_noalloc": ([_vp, _vp, _P(_u64), _vp], ctypes.c_int),
     "tc_clustering": ([_vp, _vp, _vp, _vp, _vp], ctypes.c_int),
     "tc_list": ([_vp, _vp, _vp, _i64, _P(_i64)], ctypes.c_int),
     "tc_sparsify_count": ([_vp, _dbl, _u64, _vp, _P(_u64), _P(_i64), _P(_dbl)], ctypes.c_int),
@@ -199,6 +200,14 @@ class Graph:
         T = _u64()
         _check(lib().tc_count_per_node(self._h, _stream(stream), ctypes.byref(T), _dptr(t)), "tc_count_per_node")
         return T.value, t[: self.n]
+
+    def count_per_node_noalloc(self, out, stream=None) -> Tuple[int, "object"]:
+        """tc_count_per_node_noalloc: the counts of count_per_node with no device allocation in the
+        library (static scratch, at most 2^22 vertices); out: int64[n] device tensor."""
+        T = _u64()
+        _check(lib().tc_count_per_node_noalloc(self._h, _stream(stream), ctypes.byref(T), _dptr(out)),
+               "tc_count_per_node_noalloc")
+        return T.value, out[: self.n]
 
     def clustering(self, stream=None):
         torch = _torch()
