@@ -74,6 +74,11 @@ tc_status tc_build_csr(const int32_t* src, const int32_t* dst, int64_t num_edges
  * dhat_max (Definition of effective degree, Section 3). Any output may be NULL. */
 tc_status tc_graph_info(const tc_graph* g, int32_t* n, int64_t* m, int32_t* d_max, int32_t* dhat_max);
 
+/* Device bytes the graph holds now (its CSR, work plans, vertex arrays and
+ * workspace, as the library's allocator reserved them), for callers that keep
+ * many graphs resident under a memory budget. */
+tc_status tc_graph_bytes(const tc_graph* g, uint64_t* bytes);
+
 /* Release the graph and its device memory once the work already queued on it
  * is done (calls that return before their work ends are waited for on the host;
  * other streams of the device are not synchronised). NULL is ignored. */
@@ -238,6 +243,33 @@ tc_status tc_sparsify_count_partitioned(tc_graph* g, double q, uint64_t seed, in
 tc_status tc_graph_export_csr(tc_graph* g, void* stream, int64_t* off, int32_t* adj);
 
 /*
+ * The same rank-space CSR as tc_build_csr + tc_graph_export_csr, for a graph
+ * whose edge list stays in host memory and need not fit the device: the
+ * simple graph, degrees, the order of Eq. (1) and the sorted oriented lists
+ * N_v (Section 3) are computed with the records streamed through the GPU in
+ * pieces that fit budget_bytes (the graphs larger than one machine's memory
+ * of Section 6, here larger than one device). The records are split by a hash
+ * of their smaller endpoint into parts sorted and deduplicated one at a time
+ * (degrees accumulate on the device); after the ranks, the unique edges
+ * stream through again to count the rows, and once per range of rows that
+ * fits the budget to sort that range and copy its entries out.
+ *   src, dst : host int32[num_edges] ids in [0,n) (pinned memory copies fastest).
+ *   off      : host int64[n+1], written: row r holds adj[off[r] .. off[r+1]).
+ *   adj      : host int32 with room for the unique edges (num_edges suffices).
+ *   m        : receives the number of unique undirected edges.
+ *   info     : host uint64[4] or NULL: parts, row ranges, bytes copied to the
+ *              device, bytes copied to the host.
+ * The budget covers the library's device buffers of this call (edge pieces,
+ * sort buffers, per-vertex arrays of 64 bytes per vertex); it must be at least
+ * 64 n + 32 MiB, else TC_E_NOMEM, as when one part or one row does not fit.
+ * TC_E_RANGE for ids outside [0,n). The result feeds tc_count_streamed.
+ * Synchronises `stream`.
+ */
+tc_status tc_build_csr_host(const int32_t* src, const int32_t* dst, int64_t num_edges, int32_t n,
+                            uint64_t budget_bytes, void* stream, int64_t* off, int32_t* adj, int64_t* m,
+                            uint64_t* info);
+
+/*
  * Exact T of an oriented CSR kept in host memory, streamed through the GPU
  * under a device-memory budget (the non-overlapping partitions of Section 6,
  * with the surrogate pairing). The rows are split into pivot partitions V_j,
@@ -386,6 +418,17 @@ tc_status tc_multi_count(tc_graph* const* graphs, int32_t k, int32_t per_node, v
  */
 tc_status tc_clustering_from_counts(tc_graph* g, void* stream, const uint64_t* t_dev, uint64_t* num_dev,
                                     uint64_t* den_dev, double* c_dev);
+
+/*
+ * 128-bit digest of a clustering answer (num, den, c as tc_clustering writes
+ * them, n entries), so that servers can record and compare answers without
+ * copying them to the host: with f the SplitMix64 output function and
+ * h_v = f(f(f(f(v ^ 0x434C555354455221) ^ num[v]) ^ den[v]) ^ bits(c[v])),
+ * digest_dev[0] = sum_v h_v and digest_dev[1] = sum_v f(h_v ^ 0x4449474553543132),
+ * both modulo 2^64. digest_dev: device uint64[2]. Does not synchronise `stream`.
+ */
+tc_status tc_clustering_digest(const uint64_t* num_dev, const uint64_t* den_dev, const double* c_dev, int32_t n,
+                               void* stream, uint64_t* digest_dev);
 
 /*
  * The edge sample of tc_sparsify_count (Section 7: same keep rule, q, seed)

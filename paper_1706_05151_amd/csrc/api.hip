@@ -68,6 +68,33 @@ __global__ void k_clustering(const unsigned long long* __restrict__ t, const int
   }
 }
 
+// Order-independent 128-bit digest of a clustering answer: per vertex v,
+// h = f(f(f(f(v ^ K) ^ num) ^ den) ^ bits(c)) with f the SplitMix64 output
+// function; digest = (sum of h, sum of f(h ^ K')) modulo 2^64. Sums commute,
+// so the atomics give the same bits in any order.
+__device__ __forceinline__ uint64_t mix64(uint64_t z) {
+  z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ull;
+  z = (z ^ (z >> 27)) * 0x94d049bb133111ebull;
+  return z ^ (z >> 31);
+}
+
+__global__ void k_cc_digest(const uint64_t* __restrict__ num, const uint64_t* __restrict__ den,
+                            const double* __restrict__ c, int32_t n, unsigned long long* __restrict__ out) {
+  unsigned long long a = 0, b = 0;
+  for (int32_t v = blockIdx.x * blockDim.x + threadIdx.x; v < n; v += gridDim.x * blockDim.x) {
+    const uint64_t cb = static_cast<uint64_t>(__double_as_longlong(c[v]));
+    const uint64_t h = mix64(mix64(mix64(mix64(static_cast<uint64_t>(v) ^ 0x434c555354455221ull) ^ num[v]) ^ den[v]) ^ cb);
+    a += h;
+    b += mix64(h ^ 0x4449474553543132ull);
+  }
+  a = wave_sum(a);
+  b = wave_sum(b);
+  if (lane_id() == 0) {
+    atomicAdd(&out[0], a);
+    atomicAdd(&out[1], b);
+  }
+}
+
 __global__ void k_dhat_by_id(const int64_t* __restrict__ off, const int32_t* __restrict__ order, int32_t n,
                              int32_t* __restrict__ dhat) {
   for (int32_t r = blockIdx.x * blockDim.x + threadIdx.x; r < n; r += gridDim.x * blockDim.x)
@@ -245,6 +272,24 @@ tc_status tc_graph_plan_info(const tc_graph* g, int64_t* hub_dhat, int64_t* item
     if (hub_dhat) *hub_dhat = P.hub_dhat;
     if (item_work) *item_work = P.item_work;
     if (frozen) *frozen = P.frozen ? 1 : 0;
+  });
+}
+
+static size_t plan_reserved(const PivotPlan& P) {
+  return dev_reserved_bytes(P.inrec.p) + dev_reserved_bytes(P.in_off.p) + dev_reserved_bytes(P.items.p) +
+         dev_reserved_bytes(P.grouped.p);
+}
+
+tc_status tc_graph_bytes(const tc_graph* g, uint64_t* bytes) {
+  return guarded([&] {
+    require(g != nullptr && bytes != nullptr, TC_E_INVAL, "NULL argument");
+    DeviceScope ds(g->device);
+    const Csr& c = g->csr;
+    size_t b = dev_reserved_bytes(c.off.p) + dev_reserved_bytes(c.adj.p) + dev_reserved_bytes(c.src.p) +
+               plan_reserved(c.plan) + plan_reserved(c.shard) + dev_reserved_bytes(g->order.p) +
+               dev_reserved_bytes(g->rank.p) + dev_reserved_bytes(g->deg.p) +
+               dev_reserved_bytes(g->graph_of_rank.p) + dev_reserved_bytes(g->workspace.p);
+    *bytes = static_cast<uint64_t>(b);
   });
 }
 
@@ -613,6 +658,17 @@ tc_status tc_count_streamed(const int64_t* off, const int32_t* adj, int32_t n, i
   });
 }
 
+tc_status tc_build_csr_host(const int32_t* src, const int32_t* dst, int64_t num_edges, int32_t n,
+                            uint64_t budget_bytes, void* stream, int64_t* off, int32_t* adj, int64_t* m,
+                            uint64_t* info) {
+  return guarded([&] {
+    uint64_t inf[4] = {0, 0, 0, 0};
+    build_host_csr(src, dst, num_edges, n, budget_bytes, as_stream(stream), off, adj, m, inf);
+    if (info)
+      for (int i = 0; i < 4; i++) info[i] = inf[i];
+  });
+}
+
 tc_status tc_graph_export_csr(tc_graph* g, void* stream, int64_t* off, int32_t* adj) {
   return guarded([&] {
     require(g != nullptr, TC_E_INVAL, "graph is NULL");
@@ -788,6 +844,21 @@ tc_status tc_clustering_from_counts(tc_graph* g, void* stream, const uint64_t* t
       TC_LAUNCH_CHECK();
     }
     note_plan_use(g->csr.plan, as_stream(stream));
+  });
+}
+
+tc_status tc_clustering_digest(const uint64_t* num_dev, const uint64_t* den_dev, const double* c_dev, int32_t n,
+                               void* stream, uint64_t* digest_dev) {
+  return guarded([&] {
+    require(digest_dev != nullptr && n >= 0, TC_E_INVAL, "bad argument");
+    require(n == 0 || (num_dev && den_dev && c_dev), TC_E_INVAL, "NULL array");
+    const hipStream_t s = as_stream(stream);
+    unsigned long long* d = reinterpret_cast<unsigned long long*>(digest_dev);
+    fill_u64(d, 2, 0ull, s);
+    if (n > 0) {
+      k_cc_digest<<<grid_for(n, kBlock, 2048), kBlock, 0, s>>>(num_dev, den_dev, c_dev, n, d);
+      TC_LAUNCH_CHECK();
+    }
   });
 }
 

@@ -47,6 +47,8 @@ void* dev_alloc(size_t bytes, hipStream_t s);
 void dev_free(void* p, hipStream_t s);
 void dev_release_cached();   // returns the current device's idle blocks to the driver
 size_t dev_cached_bytes();   // idle bytes held for the current device
+size_t dev_reserved_bytes(const void* p);  // bytes of the live block at p (current device), 0 if none
+size_t dev_block_bytes(size_t bytes);      // bytes a request of `bytes` reserves
 
 // Scratch buffer released on destruction, ordered after the work queued on its stream.
 template <typename T>

@@ -218,6 +218,12 @@ void build_graph(const int32_t* src, const int32_t* dst, int64_t E, int32_t n, c
                  const int32_t* n_per_graph_host, int32_t num_graphs, bool on_device, hipStream_t s, tc_graph* g,
                  int order, const int32_t* key_by_id);
 
+// The rank-space oriented CSR of a host edge list built under a device budget
+// into host memory: off_h[n+1], adj_h[>= m]; info = {parts, row ranges, bytes
+// copied to the device, bytes copied to the host}
+void build_host_csr(const int32_t* src, const int32_t* dst, int64_t E, int32_t n, uint64_t budget, hipStream_t s,
+                    int64_t* off_h, int32_t* adj_h, int64_t* m_out, uint64_t info[4]);
+
 // count.hip
 enum CountMode { kCountTotal = 0, kCountPerNode = 1, kCountList = 2 };
 struct CountArgs {

@@ -5,8 +5,12 @@
 // back at synchronisation points. Graph builds and queries allocate the same
 // large sizes again and again, so the library keeps freed blocks itself:
 //
-//  * sizes are rounded up to 2 MiB; a request takes the smallest cached block
-//    that is at least as large and at most 25 % larger;
+//  * requests of at most 1 MiB take a block of the next power of two (at least
+//    4 KiB) carved from 2 MiB slabs, kept per size class when freed (slabs
+//    stay with the library until the process ends), so a small graph does not
+//    hold a 2 MiB block per array;
+//  * larger sizes are rounded up to 2 MiB; a request takes the smallest cached
+//    block that is at least as large and at most 25 % larger;
 //  * a freed block gets an event recorded on the freeing stream; the stream
 //    that takes the block next waits on that event (stream-ordered reuse, no
 //    host synchronisation);
@@ -18,6 +22,7 @@
 #include <map>
 #include <mutex>
 #include <unordered_map>
+#include <vector>
 
 #include "common.hpp"
 
@@ -28,9 +33,13 @@ constexpr size_t kGranule = size_t(2) << 20;
 constexpr size_t kCacheLimit = size_t(96) << 30;
 constexpr int kMaxDevices = 64;
 
+constexpr size_t kSmallMin = size_t(4) << 10;  // smallest size class
+constexpr size_t kSmallMax = size_t(1) << 20;  // largest size class
+constexpr int kClasses = 9;                    // 4 KiB, 8 KiB, ..., 1 MiB
+
 struct Block {
   size_t bytes;
-  hipEvent_t ready;  // recorded when the block was freed
+  hipEvent_t ready;  // recorded when the block was freed (null: never used)
 };
 
 struct DeviceCache {
@@ -38,7 +47,14 @@ struct DeviceCache {
   std::multimap<size_t, std::pair<void*, Block>> idle;  // by size
   std::unordered_map<void*, Block> live;
   size_t idle_bytes = 0;
+  std::vector<std::pair<void*, hipEvent_t>> small_free[kClasses];  // freed blocks of each size class
 };
+
+int small_class(size_t bytes) {
+  int k = 0;
+  for (size_t c = kSmallMin; c < bytes; c <<= 1) k++;
+  return k;
+}
 
 // Never destroyed: the runtime may be gone when static destructors run.
 DeviceCache* cache_of(int dev) {
@@ -64,13 +80,41 @@ void drop_idle(DeviceCache& c, std::multimap<size_t, std::pair<void*, Block>>::i
   (void)hipFree(p);
 }
 
+// Caller holds c.mu. hipMalloc, returning every idle block first if the device is full.
+hipError_t malloc_or_drop(DeviceCache& c, void** p, size_t bytes) {
+  hipError_t e = hipMalloc(p, bytes);
+  if (e == hipErrorOutOfMemory || e == hipErrorMemoryAllocation) {
+    (void)hipGetLastError();
+    while (!c.idle.empty()) drop_idle(c, c.idle.begin());
+    e = hipMalloc(p, bytes);
+  }
+  return e;
+}
+
+// Caller holds c.mu. A block of size class k, waited for on s if it was used before.
+void* small_alloc(DeviceCache& c, int k, hipStream_t s) {
+  const size_t cb = kSmallMin << k;
+  auto& fl = c.small_free[k];
+  if (fl.empty()) {
+    void* slab = nullptr;
+    TC_HIP(malloc_or_drop(c, &slab, kGranule));
+    for (size_t off = kGranule; off >= cb; off -= cb) fl.emplace_back(static_cast<char*>(slab) + off - cb, nullptr);
+  }
+  const auto blk = fl.back();
+  fl.pop_back();
+  if (blk.second) TC_HIP(hipStreamWaitEvent(s, blk.second, 0));
+  c.live.emplace(blk.first, Block{cb, blk.second});
+  return blk.first;
+}
+
 }  // namespace
 
 void* dev_alloc(size_t bytes, hipStream_t s) {
   if (bytes == 0) return nullptr;
-  const size_t rb = (bytes + kGranule - 1) / kGranule * kGranule;
   DeviceCache& c = *cache_of(current_device());
   std::lock_guard<std::mutex> lk(c.mu);
+  if (bytes <= kSmallMax) return small_alloc(c, small_class(bytes), s);
+  const size_t rb = (bytes + kGranule - 1) / kGranule * kGranule;
   auto it = c.idle.lower_bound(rb);
   if (it != c.idle.end() && it->first <= rb + rb / 4) {
     void* p = it->second.first;
@@ -82,12 +126,7 @@ void* dev_alloc(size_t bytes, hipStream_t s) {
     return p;
   }
   void* p = nullptr;
-  hipError_t e = hipMalloc(&p, rb);
-  if (e == hipErrorOutOfMemory || e == hipErrorMemoryAllocation) {
-    (void)hipGetLastError();
-    while (!c.idle.empty()) drop_idle(c, c.idle.begin());
-    e = hipMalloc(&p, rb);
-  }
+  hipError_t e = malloc_or_drop(c, &p, rb);
   TC_HIP(e);
   hipEvent_t ev;
   e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
@@ -105,8 +144,21 @@ void dev_free(void* p, hipStream_t s) {
   std::lock_guard<std::mutex> lk(c.mu);
   auto it = c.live.find(p);
   if (it == c.live.end()) return;  // not ours
-  const Block b = it->second;
+  Block b = it->second;
   c.live.erase(it);
+  if (b.bytes <= kSmallMax) {  // back to its size class, ready once s passes this point
+    if (!b.ready && hipEventCreateWithFlags(&b.ready, hipEventDisableTiming) != hipSuccess) {
+      (void)hipGetLastError();
+      (void)hipStreamSynchronize(s);  // no event: the block is free once s has drained
+      b.ready = nullptr;
+    }
+    if (b.ready && hipEventRecord(b.ready, s) != hipSuccess) {
+      (void)hipGetLastError();
+      (void)hipDeviceSynchronize();
+    }
+    c.small_free[small_class(b.bytes)].emplace_back(p, b.ready);
+    return;
+  }
   if (hipEventRecord(b.ready, s) != hipSuccess) {
     // the stream is unusable: wait for the device instead and give the block back
     (void)hipGetLastError();
@@ -124,6 +176,20 @@ void dev_release_cached() {
   DeviceCache& c = *cache_of(current_device());
   std::lock_guard<std::mutex> lk(c.mu);
   while (!c.idle.empty()) drop_idle(c, c.idle.begin());
+}
+
+size_t dev_reserved_bytes(const void* p) {
+  if (!p) return 0;
+  DeviceCache& c = *cache_of(current_device());
+  std::lock_guard<std::mutex> lk(c.mu);
+  auto it = c.live.find(const_cast<void*>(p));
+  return it == c.live.end() ? 0 : it->second.bytes;
+}
+
+size_t dev_block_bytes(size_t bytes) {
+  if (bytes == 0) return 0;
+  if (bytes <= kSmallMax) return kSmallMin << small_class(bytes);
+  return (bytes + kGranule - 1) / kGranule * kGranule;
 }
 
 size_t dev_cached_bytes() {

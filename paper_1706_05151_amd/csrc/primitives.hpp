@@ -374,6 +374,9 @@ __global__ __launch_bounds__(kScatterBlock) void k_sweep_scatter(const K* __rest
   K key[ITEMS];
   uint32_t rk[ITEMS];
   uint32_t dg[ITEMS];
+  // values are loaded with the keys, so their latency overlaps the ranking
+  using VReg = typename std::conditional<kHasVal, V, uint8_t>::type;
+  VReg val[kHasVal ? ITEMS : 1];
   uint16_t* cnt = wc[w];
   // All peers read the digit's count (one broadcast read), then the lowest
   // peer adds the group; LDS operations of one wave complete in order.
@@ -390,6 +393,11 @@ __global__ __launch_bounds__(kScatterBlock) void k_sweep_scatter(const K* __rest
   if (base + TILE <= N) {  // full tile (wave-uniform): no bounds checks, one ballot per digit bit
 #pragma unroll
     for (int i = 0; i < ITEMS; i++) key[i] = chunk[i * kWave + lane];
+    if constexpr (kHasVal) {
+      const V* vchunk = vin + base + static_cast<size_t>(w) * CHUNK;
+#pragma unroll
+      for (int i = 0; i < ITEMS; i++) val[i] = vchunk[i * kWave + lane];
+    }
 #pragma unroll
     for (int i = 0; i < ITEMS; i++) {
       const uint32_t d = RadixKey<K>::bits(key[i], shift) & dmask;
@@ -401,6 +409,10 @@ __global__ __launch_bounds__(kScatterBlock) void k_sweep_scatter(const K* __rest
       const size_t idx = base + static_cast<size_t>(w) * CHUNK + static_cast<size_t>(i) * kWave + lane;
       key[i] = K{};
       if (idx < N) key[i] = chunk[i * kWave + lane];
+      if constexpr (kHasVal) {
+        val[i] = V{};
+        if (idx < N) val[i] = vin[idx];
+      }
     }
 #pragma unroll
     for (int i = 0; i < ITEMS; i++) {
@@ -475,8 +487,7 @@ __global__ __launch_bounds__(kScatterBlock) void k_sweep_scatter(const K* __rest
     V* vt = reinterpret_cast<V*>(tile);
 #pragma unroll
     for (int i = 0; i < ITEMS; i++) {
-      const size_t idx = base + static_cast<size_t>(w) * CHUNK + static_cast<size_t>(i) * kWave + lane;
-      if (dg[i] < kBins) vt[rk[i]] = vin[idx];
+      if (dg[i] < kBins) vt[rk[i]] = val[i];
     }
     __syncthreads();
 #pragma unroll
@@ -494,6 +505,13 @@ __global__ void k_fill_words(T* __restrict__ p, size_t n, T v) {
     p[i] = v;
 }
 
+// Called after each scatter pass with the pass index and the buffer that
+// holds the keys sorted by the bits of that pass and the ones before it.
+struct NoHook {
+  template <typename K>
+  void operator()(int, const K*) const {}
+};
+
 // Sorts N keys ascending by bits [bit_lo, bit_hi) (9-bit digits, stable),
 // each value in `vals` moving with its key. Uses `keys`/`tmp` and
 // `vals`/`vtmp` as ping-pong buffers; returns the key buffer holding the
@@ -501,9 +519,12 @@ __global__ void k_fill_words(T* __restrict__ p, size_t n, T v) {
 // whose look-back gave up sets *fail_dev (device word, never cleared here);
 // the caller checks it at its next synchronisation. Without fail_dev the
 // sort synchronises the stream and checks its own flag before returning.
-template <typename K, typename V>
+// hook(p, buf) runs on the host after pass p is queued (work it queues on s
+// sees the keys sorted by bits [bit_lo, bit_lo + 9 (p + 1))); no pass runs,
+// and the hook is not called, when N <= 1.
+template <typename K, typename V, typename Hook = NoHook>
 K* radix_sort_pairs(K* keys, K* tmp, V*& vals, V* vtmp, size_t N, int bit_lo, int bit_hi, hipStream_t s,
-                    uint32_t* fail_dev = nullptr) {
+                    uint32_t* fail_dev = nullptr, Hook hook = Hook()) {
   if (N <= 1 || bit_hi <= bit_lo) return keys;
   if (N >= (1ull << 32)) fail(TC_E_INVAL, "radix_sort: more than 2^32 - 1 keys");
   constexpr int TILE = kScatterBlock * ScatterItems<K>::value;
@@ -542,6 +563,7 @@ K* radix_sort_pairs(K* keys, K* tmp, V*& vals, V* vtmp, size_t N, int bit_lo, in
     TC_LAUNCH_CHECK();
     std::swap(a, b);
     std::swap(va, vb);
+    hook(p, static_cast<const K*>(a));
   }
   vals = va;
   if (!fail_dev) {
@@ -554,10 +576,11 @@ K* radix_sort_pairs(K* keys, K* tmp, V*& vals, V* vtmp, size_t N, int bit_lo, in
 }
 
 // Keys-only form of radix_sort_pairs.
-template <typename K>
-K* radix_sort(K* keys, K* tmp, size_t N, int bit_lo, int bit_hi, hipStream_t s, uint32_t* fail_dev = nullptr) {
+template <typename K, typename Hook = NoHook>
+K* radix_sort(K* keys, K* tmp, size_t N, int bit_lo, int bit_hi, hipStream_t s, uint32_t* fail_dev = nullptr,
+              Hook hook = Hook()) {
   NoVal* none = nullptr;
-  return radix_sort_pairs<K, NoVal>(keys, tmp, none, nullptr, N, bit_lo, bit_hi, s, fail_dev);
+  return radix_sort_pairs<K, NoVal, Hook>(keys, tmp, none, nullptr, N, bit_lo, bit_hi, s, fail_dev, hook);
 }
 
 }  // namespace tc

@@ -50,21 +50,46 @@ class Answer:
     error: str = ""
 
 
+_K_V, _K_B = np.uint64(0x434C555354455221), np.uint64(0x4449474553543132)
+
+
+def _mix64(z: np.ndarray) -> np.ndarray:
+    """SplitMix64 output function on uint64 arrays (wrapping arithmetic)."""
+    z = (z ^ (z >> np.uint64(30))) * np.uint64(0xBF58476D1CE4E5B9)
+    z = (z ^ (z >> np.uint64(27))) * np.uint64(0x94D049BB133111EB)
+    return z ^ (z >> np.uint64(31))
+
+
 def cc_digest(num, den, c) -> str:
     """128-bit digest of a clustering answer (numerators, denominators and the
-    doubles, bit for bit): answers are compared and stored by digest so the
-    host keeps no per-request arrays."""
-    import xxhash
+    doubles, bit for bit), computed on the host from its arrays: answers are
+    compared and stored by digest so the host keeps no per-request arrays. It
+    is the digest tc_clustering_digest computes on the device (see tc.h)."""
+    num = np.asarray(num).astype(np.uint64, copy=False)
+    den = np.asarray(den).astype(np.uint64, copy=False)
+    cb = np.ascontiguousarray(np.asarray(c, dtype=np.float64)).view(np.uint64)
+    v = np.arange(num.shape[0], dtype=np.uint64)
+    with np.errstate(over="ignore"):
+        h = _mix64(_mix64(_mix64(_mix64(v ^ _K_V) ^ num) ^ den) ^ cb)
+        a = int(h.sum(dtype=np.uint64)) if h.size else 0
+        b = int(_mix64(h ^ _K_B).sum(dtype=np.uint64)) if h.size else 0
+    return _digest_hex(a, b)
 
-    h = xxhash.xxh3_128()
-    for a, dt in ((num, np.uint64), (den, np.uint64), (c, np.float64)):
-        h.update(np.ascontiguousarray(np.asarray(a).astype(dt, copy=False)).tobytes())
-    return h.hexdigest()
+
+def _digest_hex(a: int, b: int) -> str:
+    return f"{a & 0xFFFFFFFFFFFFFFFF:016x}{b & 0xFFFFFFFFFFFFFFFF:016x}"
+
+
+def device_cc_digest(num, den, c, n: int, out, stream=None):
+    """Queue the device digest of a clustering answer into out (int64[2] device tensor)."""
+    tc.clustering_digest(num, den, c, n, out, stream)
 
 
 def footprint_bytes(n: int, m: int) -> int:
-    """Device bytes of a resident graph: CSR (adj, row ids), in-edge records,
-    offsets, ranks and degrees, with headroom for the work plan."""
+    """Estimate of a graph's device bytes before it is built (CSR, in-edge
+    records, offsets, ranks and degrees, with headroom for the work plan):
+    room is made for this much, and once built the graph is charged what
+    tc_graph_bytes reports."""
     return 24 * m + 48 * n + (1 << 16)
 
 
@@ -79,6 +104,8 @@ class Registry:
         self.pinned: Dict[object, int] = collections.Counter()
         self.builds = 0
         self.evictions = 0
+        self.peak = 0             # largest resident bytes right after a build
+        self.peak_after_evict = 0  # largest resident bytes once room was made (> budget only if pinned graphs hold it)
 
     def _evict_for(self, need: int):
         for key in list(self.graphs.keys()):
@@ -126,9 +153,18 @@ class Registry:
             g = self.graphs[gid].sparsify_build(sample[0], sample[1], self.stream)
             need = footprint_bytes(g.n, g.m)
         self.builds += 1
+        need = g.bytes()  # what the library really holds for it
         self.graphs[key] = g
         self.sizes[key] = need
         self.used += need
+        self.peak = max(self.peak, self.used)
+        if self.used > self.budget:  # the estimate was short: make room behind the new graph
+            self.pinned[key] += 1
+            try:
+                self._evict_for(0)
+            finally:
+                self.pinned[key] -= 1
+            self.peak_after_evict = max(self.peak_after_evict, self.used)
         return g
 
     def pin(self, keys):
@@ -213,25 +249,23 @@ class Server:
             if graphs_tot:
                 tc.multi_count(graphs_tot, T_dev, None, stream)
                 T_host.copy_(T_dev, non_blocking=True)
-            cc_host = []
+            cc_host = None
             if graphs_cc:
                 Tc = torch.empty(len(graphs_cc), dtype=torch.int64, device="cuda")
                 ts = [torch.empty(max(g.n, 1), dtype=torch.int64, device="cuda") for g in graphs_cc]
                 tc.multi_count(graphs_cc, Tc, ts, stream)
                 keep += [Tc] + ts
-                for g, t in zip(graphs_cc, ts):
+                dig = torch.empty((len(graphs_cc), 2), dtype=torch.int64, device="cuda")
+                for i, (g, t) in enumerate(zip(graphs_cc, ts)):
                     num = torch.empty(max(g.n, 1), dtype=torch.int64, device="cuda")
                     den = torch.empty(max(g.n, 1), dtype=torch.int64, device="cuda")
                     c = torch.empty(max(g.n, 1), dtype=torch.float64, device="cuda")
                     g.clustering_from_counts(t, num, den, c, stream)
-                    hn = torch.empty(g.n, dtype=torch.int64, pin_memory=True)
-                    hd = torch.empty(g.n, dtype=torch.int64, pin_memory=True)
-                    hc = torch.empty(g.n, dtype=torch.float64, pin_memory=True)
-                    hn.copy_(num[: g.n], non_blocking=True)
-                    hd.copy_(den[: g.n], non_blocking=True)
-                    hc.copy_(c[: g.n], non_blocking=True)
+                    device_cc_digest(num, den, c, g.n, dig[i], stream)
                     keep += [num, den, c]
-                    cc_host.append((hn, hd, hc))
+                cc_host = torch.empty((len(graphs_cc), 2), dtype=torch.int64, pin_memory=True)
+                cc_host.copy_(dig, non_blocking=True)
+                keep.append(dig)
             ev = torch.cuda.Event()
             ev.record(stream)
         b = _Batch(reqs, stream, ev, pins, T_host, cc_host, idx_tot, idx_cc, None)
@@ -246,8 +280,8 @@ class Server:
             elif r.kind == SPARSE:
                 val = tc.sparsify_estimate(int(T[b.tot_keys[(r.graph, r.q, r.seed)]]), r.q)
             else:
-                hn, hd, hc = b.cc_host[b.cc_reqs[r.graph]]
-                val = cc_digest(hn.numpy(), hd.numpy(), hc.numpy())
+                d = b.cc_host[b.cc_reqs[r.graph]]
+                val = _digest_hex(int(d[0]), int(d[1]))
             self.answers[r.rid] = Answer(r.rid, r.kind, val, now)
         self.reg.unpin(b.keys)
         b.keep = b.cc_host = b.T_host = None  # pinned and device buffers return to torch's caches
@@ -308,6 +342,17 @@ class Server:
         return self.answers
 
 
+def _answer_digest(g) -> str:
+    """tc_clustering on one graph and the device digest of its answer (16 bytes to the host)."""
+    import torch
+
+    num, den, c = g.clustering()
+    d = torch.empty(2, dtype=torch.int64, device="cuda")
+    device_cc_digest(num, den, c, g.n, d)
+    h = d.cpu()
+    return _digest_hex(int(h[0]), int(h[1]))
+
+
 def serve_fifo(registry: Registry, trace: List[Request], t0: Optional[float] = None) -> Dict[int, Answer]:
     """One request at a time, in arrival order, with the single-graph calls."""
     import torch
@@ -323,10 +368,8 @@ def serve_fifo(registry: Registry, trace: List[Request], t0: Optional[float] = N
         elif r.kind == SPARSE:
             val = tc.sparsify_estimate(registry.get(r.graph, (r.q, r.seed)).count(), r.q)
         else:
-            num, den, c = registry.get(r.graph).clustering()
-            host = (num.cpu().numpy(), den.cpu().numpy(), c.cpu().numpy())
-            done = time.perf_counter() - start
-            answers[r.rid] = Answer(r.rid, r.kind, cc_digest(*host), done)
+            g = registry.get(r.graph)
+            answers[r.rid] = Answer(r.rid, r.kind, _answer_digest(g), time.perf_counter() - start)
             continue
         torch.cuda.synchronize()
         answers[r.rid] = Answer(r.rid, r.kind, val, time.perf_counter() - start)
@@ -351,8 +394,7 @@ def serve_plain(edges_dev, trace: List[Request]) -> Tuple[Dict[int, Answer], flo
             elif r.kind == SPARSE:
                 val = g.sparsify_count(r.q, r.seed)[2]
             else:
-                num, den, c = g.clustering()
-                val = cc_digest(num.cpu().numpy(), den.cpu().numpy(), c.cpu().numpy())
+                val = _answer_digest(g)
         answers[r.rid] = Answer(r.rid, r.kind, val, time.perf_counter() - start)
     torch.cuda.synchronize()
     return answers, time.perf_counter() - start

@@ -29,6 +29,7 @@ SIGNATURES = {
     "tc_build_csr": ([_vp, _vp, _i64, _i32, _u32, _vp, _P(_vp)], ctypes.c_int),
     "tc_graph_info": ([_vp, _P(_i32), _P(_i64), _P(_i32), _P(_i32)], ctypes.c_int),
     "tc_graph_free": ([_vp], None),
+    "tc_graph_bytes": ([_vp, _P(_u64)], ctypes.c_int),
     "tc_count": ([_vp, _vp, _P(_u64)], ctypes.c_int),
     "tc_count_per_node": ([_vp, _vp, _P(_u64), _vp], ctypes.c_int),
     "tc_count_per_node_noalloc": ([_vp, _vp, _P(_u64), _vp], ctypes.c_int),
@@ -45,6 +46,7 @@ SIGNATURES = {
     "tc_graph_order": ([_vp, _vp, _vp], ctypes.c_int),
     "tc_graph_export_csr": ([_vp, _vp, _vp, _vp], ctypes.c_int),
     "tc_count_streamed": ([_vp, _vp, _i32, _i64, _u64, _vp, _P(_u64), _vp], ctypes.c_int),
+    "tc_build_csr_host": ([_vp, _vp, _i64, _i32, _u64, _vp, _vp, _vp, _P(_i64), _vp], ctypes.c_int),
     "tc_shard_bounds": ([_vp, _vp, _i32, _i32, _vp], ctypes.c_int),
     "tc_count_shard": ([_vp, _vp, _i32, _i32, _P(_u64)], ctypes.c_int),
     "tc_sparsify_count_partitioned": ([_vp, _dbl, _u64, _i32, _vp, _vp, _vp, _P(_u64), _P(_dbl)], ctypes.c_int),
@@ -57,6 +59,7 @@ SIGNATURES = {
     "tc_batch_count": ([_vp, _vp, _vp, _vp], ctypes.c_int),
     "tc_multi_count": ([_vp, _i32, _i32, _vp, _vp, _vp], ctypes.c_int),
     "tc_clustering_from_counts": ([_vp, _vp, _vp, _vp, _vp, _vp], ctypes.c_int),
+    "tc_clustering_digest": ([_vp, _vp, _vp, _i32, _vp, _vp], ctypes.c_int),
     "tc_sparsify_build": ([_vp, _dbl, _u64, _vp, _P(_vp)], ctypes.c_int),
     "tc_sparsify_estimate": ([_u64, _dbl], _dbl),
     "tc_status_str": ([ctypes.c_int], ctypes.c_char_p),
@@ -184,6 +187,12 @@ class Graph:
         return cls(h, torch.cuda.current_device())
 
     # ------------------------------------------------------------- queries
+    def bytes(self) -> int:
+        """Device bytes the graph holds (tc_graph_bytes)."""
+        b = _u64()
+        _check(lib().tc_graph_bytes(self._h, ctypes.byref(b)), "tc_graph_bytes")
+        return b.value
+
     def count(self, stream=None) -> int:
         T = _u64()
         _check(lib().tc_count(self._h, _stream(stream), ctypes.byref(T)), "tc_count")
@@ -385,8 +394,31 @@ def multi_count(graphs, T_out, t_outs=None, stream=None):
            "tc_multi_count")
 
 
+def clustering_digest(num, den, c, n: int, out, stream=None):
+    """Device digest of a clustering answer (tc_clustering_digest) into out: int64[2] device tensor."""
+    _check(lib().tc_clustering_digest(_dptr(num), _dptr(den), _dptr(c), int(n), _stream(stream), _dptr(out)),
+           "tc_clustering_digest")
+
+
 def sparsify_estimate(Ts: int, q: float) -> float:
     return float(lib().tc_sparsify_estimate(int(Ts), float(q)))
+
+
+def build_csr_host(src, dst, n: int, budget_bytes: int, off=None, adj=None, stream=None):
+    """Rank-space oriented CSR of a host edge list (int32 numpy arrays or host tensors) built under a
+    device budget (tc_build_csr_host). Returns (off int64[n+1], adj int32[m], info dict); off and adj
+    are pinned host tensors unless given (adj needs room for len(src) entries)."""
+    torch = _torch()
+    E = int(len(src))
+    if off is None:
+        off = torch.empty(n + 1, dtype=torch.int64, pin_memory=True)
+    if adj is None:
+        adj = torch.empty(max(E, 1), dtype=torch.int32, pin_memory=True)
+    m = _i64()
+    info = (ctypes.c_uint64 * 4)()
+    _check(lib().tc_build_csr_host(_hptr(src), _hptr(dst), E, int(n), int(budget_bytes), _stream(stream), _hptr(off),
+                                   _hptr(adj), ctypes.byref(m), info), "tc_build_csr_host")
+    return off, adj[: m.value], {"parts": info[0], "row_ranges": info[1], "bytes_in": info[2], "bytes_out": info[3]}
 
 
 def count_streamed(off, adj, n: int, budget_bytes: int, stream=None):

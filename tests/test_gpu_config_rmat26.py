@@ -20,6 +20,31 @@ pytestmark = pytest.mark.gpu
 
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "rmat26.json")
 SHARDS = os.path.join(os.path.dirname(__file__), "golden", "rmat26_shards.json")
+GOLDEN20 = os.path.join(os.path.dirname(__file__), "golden", "rmat20.json")
+
+
+def test_rmat20_stored_golden():
+    """The same checks at scale 20 against tests/golden/rmat20.json (written by
+    tests/golden/make_rmat26.py 20 with the oracle)."""
+    import torch
+
+    from paper_1706_05151_amd import tc
+
+    with open(GOLDEN20) as f:
+        gold = json.load(f)
+    el = synth.rmat(20, 16, 3)
+    with tc.Graph.build(torch.from_numpy(el.src).cuda(), torch.from_numpy(el.dst).cuda(), el.n) as g:
+        assert (g.n, g.m, g.d_max, g.dhat_max) == (gold["n"], gold["m"], gold["d_max"], gold["dhat_max"])
+        assert g.count() == gold["T"] and g.work()[0] == gold["W"]
+        T, t = g.count_per_node()
+        ids = np.array(gold["sample_ids"], dtype=np.int64)
+        np.testing.assert_array_equal(t.cpu().numpy().astype(np.uint64)[ids],
+                                      np.array(gold["sample_t"], dtype=np.uint64))
+        deg, _ = g.degrees()
+        np.testing.assert_array_equal(deg.cpu().numpy()[ids], np.array(gold["sample_deg"], dtype=np.int32))
+        for q, ref in gold["sparsified"].items():
+            Ts, mk, _ = g.sparsify_count(float(q), ref["seed"])
+            assert (Ts, mk) == (ref["T_s"], ref["m_kept"])
 
 
 @pytest.fixture(scope="module")
@@ -64,6 +89,21 @@ def test_per_node_samples(rmat26):
     deg, dhat = g.degrees()
     np.testing.assert_array_equal(deg.cpu().numpy()[ids], np.array(gold["sample_deg"], dtype=np.int32))
     assert int(dhat.sum().item()) == gold["m"]
+
+
+def test_clustering_samples(rmat26):
+    """C_v at the 64 sampled vertices: the exact rational T_v / C(d_v, 2) from the stored
+    definition-based counts, and its double bit for bit."""
+    g, gold = rmat26
+    num, den, c = g.clustering()
+    ids = np.array(gold["sample_ids"], dtype=np.int64)
+    t = np.array(gold["sample_t"], dtype=np.uint64)
+    d = np.array(gold["sample_deg"], dtype=np.uint64)
+    want_den = np.where(d >= 2, d * (d - np.uint64(1)) // np.uint64(2), np.uint64(0))
+    np.testing.assert_array_equal(num.cpu().numpy().astype(np.uint64)[ids], t)
+    np.testing.assert_array_equal(den.cpu().numpy().astype(np.uint64)[ids], want_den)
+    want_c = np.array([float(a) / float(b) if b else 0.0 for a, b in zip(t, want_den)], dtype=np.float64)
+    np.testing.assert_array_equal(c.cpu().numpy()[ids].view(np.uint64), want_c.view(np.uint64))
 
 
 @pytest.mark.parametrize("q", ["0.1", "0.5"])
