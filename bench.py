@@ -304,7 +304,8 @@ def main():
     ap.add_argument("--shards", type=int, default=8, help="core-node shards for --workload shards / sampling")
     ap.add_argument("--scale", type=int, default=26, help="R-MAT scale for --workload rmat")
     ap.add_argument("--serve-seconds", type=float, default=60.0, help="trace length for --workload serve")
-    ap.add_argument("--serve-budget-gib", type=float, default=16.0, help="device budget for --workload serve")
+    ap.add_argument("--serve-budget-frac", type=float, default=0.85,
+                    help="device budget for --workload serve, as a fraction of the pool's resident footprint")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--calibrate-copy-gib", type=float, default=0.0,

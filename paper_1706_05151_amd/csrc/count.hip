@@ -93,15 +93,24 @@ __global__ __launch_bounds__(kBlock) void k_inrec_fill(const uint64_t* __restric
                                                        const uint32_t* __restrict__ lens,
                                                        const int64_t* __restrict__ off,
                                                        const int32_t* __restrict__ src, uint64_t mi,
-                                                       InRec* __restrict__ rec, int64_t* __restrict__ cost) {
+                                                       InRec* __restrict__ rec) {
   for (uint64_t i = static_cast<uint64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < mi;
        i += static_cast<uint64_t>(gridDim.x) * blockDim.x) {
     const uint32_t e = static_cast<uint32_t>(ikeys[i] & 0xffffffffu);
     const uint32_t len = lens ? lens[i] : static_cast<uint32_t>(off[src[e] + 1] - static_cast<int64_t>(e) - 1);
     rec[i] = InRec{e + 1, len};
-    cost[i] = static_cast<int64_t>(len) + kCostPerRecord;
   }
 }
+
+// Cost of record i, |A| + kCostPerRecord, from the sorted suffix lengths or the records.
+struct LenCost {
+  const uint32_t* lens;
+  __device__ int64_t operator()(size_t i) const { return static_cast<int64_t>(lens[i]) + kCostPerRecord; }
+};
+struct RecCost {
+  const InRec* rec;
+  __device__ int64_t operator()(size_t i) const { return static_cast<int64_t>(rec[i].a_len) + kCostPerRecord; }
+};
 
 __device__ __forceinline__ int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
@@ -287,10 +296,12 @@ void plan_records(Csr& c, PivotPlan& P, const uint64_t* sk, const uint32_t* sl, 
   if (!P.in_off.p) P.in_off.alloc(static_cast<size_t>(n) + 1, s);
   P.inrec.alloc(mi, s);
   fin.alloc(mi + 1, s);
-  k_inrec_fill<<<grid_for(mi, kBlock, 65536), kBlock, 0, s>>>(sk, sl, c.off.p, c.src.p, mi, P.inrec.p, fin.get());
+  k_inrec_fill<<<grid_for(mi, kBlock, 65536), kBlock, 0, s>>>(sk, sl, c.off.p, c.src.p, mi, P.inrec.p);
   TC_LAUNCH_CHECK();
   offsets_from_key_rows(sk, mi, n, P.in_off.p, s);
-  exclusive_scan<int64_t>(fin.get(), fin.get(), mi, s, fin.get() + mi);
+  // the cost prefix F over the records (the boundary rule of Section 5 cuts items from it)
+  if (sl) exclusive_scan_of<int64_t>(LenCost{sl}, fin.get(), mi, s, fin.get() + mi);
+  else exclusive_scan_of<int64_t>(RecCost{P.inrec.p}, fin.get(), mi, s, fin.get() + mi);
 }
 
 void plan_items(Csr& c, PivotPlan& P, const int64_t* fin_p, uint64_t mi, hipStream_t s, const Options& o,

@@ -16,25 +16,33 @@ constexpr int kScanBlock = 256;
 constexpr int kScanItems = 8;
 constexpr int kScanChunk = kScanBlock * kScanItems;
 
+// Input of a scan: element i of an array, or any functor of i.
 template <typename T>
-__global__ __launch_bounds__(kScanBlock) void k_scan_reduce(const T* __restrict__ in, size_t N, T* __restrict__ partial) {
+struct ArrayAt {
+  const T* a;
+  __device__ T operator()(size_t i) const { return a[i]; }
+};
+
+template <typename T, typename Get>
+__global__ __launch_bounds__(kScanBlock) void k_scan_reduce(Get get, size_t N, T* __restrict__ partial) {
   __shared__ T sm[kScanBlock / kWave];
   const size_t base = static_cast<size_t>(blockIdx.x) * kScanChunk;
   T s = 0;
 #pragma unroll
   for (int i = 0; i < kScanItems; i++) {
     size_t idx = base + static_cast<size_t>(i) * kScanBlock + threadIdx.x;
-    if (idx < N) s += in[idx];
+    if (idx < N) s += get(idx);
   }
   T tot;
   (void)block_excl_scan<T, kScanBlock>(s, sm, tot);
   if (threadIdx.x == 0) partial[blockIdx.x] = tot;
 }
 
-// out[i] = carry(block) + sum of in[j] for j < i within the block's chunk.
-// `in` and `out` may alias. The last block stores the grand total.
-template <typename T>
-__global__ __launch_bounds__(kScanBlock) void k_scan_apply(const T* in, T* out, size_t N, const T* __restrict__ carry,
+// out[i] = carry(block) + sum of get(j) for j < i within the block's chunk.
+// The input may alias `out` (the chunk is read before it is written). The
+// last block stores the grand total.
+template <typename T, typename Get>
+__global__ __launch_bounds__(kScanBlock) void k_scan_apply(Get get, T* out, size_t N, const T* __restrict__ carry,
                                                             T* __restrict__ total_out) {
   __shared__ T sm[kScanBlock / kWave];
   __shared__ T tile[kScanChunk + kScanChunk / 32];
@@ -44,7 +52,7 @@ __global__ __launch_bounds__(kScanBlock) void k_scan_apply(const T* in, T* out, 
   for (int i = 0; i < kScanItems; i++) {
     int j = i * kScanBlock + threadIdx.x;
     size_t idx = base + j;
-    tile[pad(j)] = idx < N ? in[idx] : T(0);
+    tile[pad(j)] = idx < N ? get(idx) : T(0);
   }
   __syncthreads();
   T v[kScanItems];
@@ -75,10 +83,20 @@ __global__ __launch_bounds__(kScanBlock) void k_scan_apply(const T* in, T* out, 
 template <typename T>
 __global__ void k_store_zero(T* p) { *p = T(0); }
 
+// Exclusive prefix sum of get(0..N) into out; total_dev (optional) receives
+// the sum of all N inputs.
+template <typename T, typename Get>
+void exclusive_scan_of(Get get, T* out, size_t N, hipStream_t s, T* total_dev = nullptr);
+
 // Exclusive prefix sum of in[0..N) into out (may alias); total_dev (optional)
 // receives the sum of all N inputs.
 template <typename T>
 void exclusive_scan(const T* in, T* out, size_t N, hipStream_t s, T* total_dev = nullptr) {
+  exclusive_scan_of<T>(ArrayAt<T>{in}, out, N, s, total_dev);
+}
+
+template <typename T, typename Get>
+void exclusive_scan_of(Get get, T* out, size_t N, hipStream_t s, T* total_dev) {
   if (N == 0) {
     if (total_dev) {
       k_store_zero<T><<<1, 1, 0, s>>>(total_dev);
@@ -88,15 +106,15 @@ void exclusive_scan(const T* in, T* out, size_t N, hipStream_t s, T* total_dev =
   }
   const size_t nb = (N + kScanChunk - 1) / kScanChunk;
   if (nb == 1) {
-    k_scan_apply<T><<<1, kScanBlock, 0, s>>>(in, out, N, nullptr, total_dev);
+    k_scan_apply<T, Get><<<1, kScanBlock, 0, s>>>(get, out, N, nullptr, total_dev);
     TC_LAUNCH_CHECK();
     return;
   }
   DevBuf<T> part(nb, s);
-  k_scan_reduce<T><<<static_cast<unsigned>(nb), kScanBlock, 0, s>>>(in, N, part.get());
+  k_scan_reduce<T, Get><<<static_cast<unsigned>(nb), kScanBlock, 0, s>>>(get, N, part.get());
   TC_LAUNCH_CHECK();
   exclusive_scan<T>(part.get(), part.get(), nb, s, nullptr);
-  k_scan_apply<T><<<static_cast<unsigned>(nb), kScanBlock, 0, s>>>(in, out, N, part.get(), total_dev);
+  k_scan_apply<T, Get><<<static_cast<unsigned>(nb), kScanBlock, 0, s>>>(get, out, N, part.get(), total_dev);
   TC_LAUNCH_CHECK();
 }
 

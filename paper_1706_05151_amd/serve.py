@@ -94,18 +94,36 @@ def footprint_bytes(n: int, m: int) -> int:
 
 
 class Registry:
-    def __init__(self, edge_lists, budget_bytes: int, stream=None):
+    """Device-resident graphs and samples under a byte budget, least recently
+    used first out. A graph is charged the estimate of footprint_bytes while it
+    is being built and what tc_graph_bytes reports once it is in; pinned graphs
+    (used by a batch in flight, or the base of a sample being drawn) are never
+    evicted."""
+
+    def __init__(self, edge_lists, budget_bytes: int, stream=None, host_edges=None):
         self.edge_lists = edge_lists
+        self.host_edges = host_edges  # optional pinned (src, dst) tensors per graph, from pin_edge_lists
         self.budget = budget_bytes
         self.used = 0
         self.stream = stream
         self.graphs: "collections.OrderedDict[object, tc.Graph]" = collections.OrderedDict()
         self.sizes: Dict[object, int] = {}
+        self.reserved: Dict[object, int] = {}
         self.pinned: Dict[object, int] = collections.Counter()
         self.builds = 0
         self.evictions = 0
-        self.peak = 0             # largest resident bytes right after a build
-        self.peak_after_evict = 0  # largest resident bytes once room was made (> budget only if pinned graphs hold it)
+        self.peak = 0  # largest bytes held (resident and reserved) right after a build
+
+    @staticmethod
+    def key_of(gid: int, sample=None):
+        return gid if sample is None else (gid, sample[0], sample[1])
+
+    def estimate(self, key) -> int:
+        if isinstance(key, tuple):
+            el = self.edge_lists[key[0]]
+            return footprint_bytes(el.n, int(el.num_edges * key[1]) + 1)
+        el = self.edge_lists[key]
+        return footprint_bytes(el.n, el.num_edges)
 
     def _evict_for(self, need: int):
         for key in list(self.graphs.keys()):
@@ -119,52 +137,81 @@ class Registry:
             self.evictions += 1
         return self.used + need <= self.budget
 
-    def get(self, gid: int, sample=None) -> Optional[tc.Graph]:
-        """The resident graph (or its sample (q, seed)); builds it if there is room.
-        Returns None when the budget is held by graphs in flight."""
-        key = gid if sample is None else (gid, sample[0], sample[1])
-        if key in self.graphs:
-            self.graphs.move_to_end(key)
-            return self.graphs[key]
-        el = self.edge_lists[gid]
-        need = footprint_bytes(el.n, el.num_edges)
-        if sample is not None:
-            need = footprint_bytes(el.n, int(el.num_edges * sample[0]) + 1)
-            base = self.get(gid)
-            if base is None:
-                return None
-            self.pinned[gid] += 1  # the sample is drawn from the resident graph: keep it while making room
-            try:
-                ok = self._evict_for(need)
-            finally:
-                self.pinned[gid] -= 1
-            if not ok:
-                return None
-        elif not self._evict_for(need):
-            return None
-        if sample is None:
-            import torch
+    def peek(self, key) -> Optional[tc.Graph]:
+        """The resident graph of key, if any, without counting it as a use."""
+        return self.graphs.get(key)
 
+    def resident(self, key) -> Optional[tc.Graph]:
+        """The resident graph of key, if any, counted as a use (most recently used)."""
+        g = self.graphs.get(key)
+        if g is not None:
+            self.graphs.move_to_end(key)
+        return g
+
+    def reserve(self, key) -> bool:
+        """Make room for the estimate of key and charge it; False if the budget is held by pinned graphs."""
+        need = self.estimate(key)
+        if not self._evict_for(need):
+            return False
+        self.reserved[key] = need
+        self.used += need
+        return True
+
+    def cancel(self, key):
+        self.used -= self.reserved.pop(key, 0)
+
+    def build(self, key, stream=None, base: Optional[tc.Graph] = None) -> tc.Graph:
+        """Build key's graph (or draw its sample from the resident base graph); no accounting."""
+        if isinstance(key, tuple):
+            base = base if base is not None else self.graphs[key[0]]
+            return base.sparsify_build(key[1], key[2], stream if stream is not None else self.stream)
+        import torch
+
+        el = self.edge_lists[key]
+        if self.host_edges is not None:  # pinned: asynchronous copies on the building stream
+            hs, hd = self.host_edges[key]
+            src = hs.to("cuda", non_blocking=True)
+            dst = hd.to("cuda", non_blocking=True)
+        else:
             src = torch.from_numpy(el.src).cuda(non_blocking=False)
             dst = torch.from_numpy(el.dst).cuda(non_blocking=False)
-            g = tc.Graph.build(src, dst, el.n, self.stream)
-            need = footprint_bytes(g.n, g.m)
-        else:
-            g = self.graphs[gid].sparsify_build(sample[0], sample[1], self.stream)
-            need = footprint_bytes(g.n, g.m)
+        return tc.Graph.build(src, dst, el.n, stream if stream is not None else self.stream)
+
+    def install(self, key, g: tc.Graph):
+        """The built graph replaces its reservation and is charged its real bytes. Nothing
+        is evicted here (graphs whose requests are about to run would go): if the estimate
+        was short, the next reservation makes the room."""
+        self.cancel(key)
         self.builds += 1
-        need = g.bytes()  # what the library really holds for it
+        need = g.bytes()
         self.graphs[key] = g
         self.sizes[key] = need
         self.used += need
         self.peak = max(self.peak, self.used)
-        if self.used > self.budget:  # the estimate was short: make room behind the new graph
-            self.pinned[key] += 1
+
+    def get(self, gid: int, sample=None) -> Optional[tc.Graph]:
+        """The resident graph (or its sample (q, seed)), built here if there is room.
+        Returns None when the budget is held by pinned graphs."""
+        key = self.key_of(gid, sample)
+        g = self.resident(key)
+        if g is not None:
+            return g
+        if sample is not None:
+            if self.get(gid) is None:
+                return None
+            self.pinned[gid] += 1  # the sample is drawn from the resident graph: keep it while making room
+        try:
+            if not self.reserve(key):
+                return None
             try:
-                self._evict_for(0)
-            finally:
-                self.pinned[key] -= 1
-            self.peak_after_evict = max(self.peak_after_evict, self.used)
+                g = self.build(key)
+            except BaseException:
+                self.cancel(key)
+                raise
+            self.install(key, g)
+        finally:
+            if sample is not None:
+                self.pinned[gid] -= 1
         return g
 
     def pin(self, keys):
@@ -179,7 +226,28 @@ class Registry:
         for g in self.graphs.values():
             g.close()
         self.graphs.clear()
+        self.sizes.clear()
+        self.reserved.clear()
         self.used = 0
+
+
+def pin_edge_lists(edge_lists):
+    """Pinned host copies of the pool's edge lists, (src, dst) per graph, slices of
+    one pinned buffer per endpoint array, so graphs are built from them with
+    asynchronous copies."""
+    import torch
+
+    sizes = [int(el.num_edges) for el in edge_lists]
+    total = max(sum(sizes), 1)
+    src = torch.empty(total, dtype=torch.int32, pin_memory=True)
+    dst = torch.empty(total, dtype=torch.int32, pin_memory=True)
+    out, o = [], 0
+    for el, e in zip(edge_lists, sizes):
+        src[o:o + e].copy_(torch.from_numpy(np.ascontiguousarray(el.src, dtype=np.int32)))
+        dst[o:o + e].copy_(torch.from_numpy(np.ascontiguousarray(el.dst, dtype=np.int32)))
+        out.append((src[o:o + e], dst[o:o + e]))
+        o += e
+    return out
 
 
 class _Batch:
@@ -196,8 +264,73 @@ class _Batch:
         self.keep = []
 
 
+class _Builder:
+    """Builds graphs and samples on threads of its own, each with its own HIP
+    stream, so the serving loop keeps batching requests on resident graphs
+    meanwhile (the library releases the interpreter lock inside its calls and
+    is safe to call from several threads on different streams)."""
+
+    def __init__(self, registry: Registry, threads: int = 2):
+        import queue
+        import threading
+
+        import torch
+
+        self.reg = registry
+        self.todo: "queue.Queue" = queue.Queue()
+        self.done: "queue.Queue" = queue.Queue()
+        self.device = torch.cuda.current_device()
+        self.threads = [threading.Thread(target=self._run, daemon=True) for _ in range(threads)]
+        for t in self.threads:
+            t.start()
+
+    def _run(self):
+        import torch
+
+        torch.cuda.set_device(self.device)
+        stream = torch.cuda.Stream()
+        while True:
+            item = self.todo.get()
+            if item is None:
+                return
+            key, base = item
+            try:
+                with torch.cuda.stream(stream):
+                    g = self.reg.build(key, stream, base)
+                self.done.put((key, g, ""))
+            except Exception as e:  # reported with the requests that wait for it
+                self.done.put((key, None, getattr(e, "status", None) and tc.lib().tc_status_str(e.status).decode()
+                               or "TC_E_DEVICE"))
+
+    def close(self):
+        for _ in self.threads:
+            self.todo.put(None)
+        for t in self.threads:
+            t.join()
+
+
 class Server:
-    def __init__(self, registry: Registry, max_batch: int = 64, streams: int = 3):
+    """Continuous batching over per-graph queues.
+
+    Requests wait in one queue per registry key (a graph, or a graph's sample),
+    the queues ordered by their oldest request. Each turn of the loop
+
+    * takes arrivals into their queues, installs what the builders finished and
+      retires the batches whose event has fired;
+    * when a stream is free, launches one batch holding the queued requests on
+      resident keys, oldest queue first, up to max_batch requests;
+    * starts builds for the oldest queues whose key is not resident, at most
+      two per builder thread at a time (a sample's graph is built first, then
+      the sample is drawn from it). Room for a build is made by evicting, least
+      recently used first, graphs that no queued request needs; only the oldest
+      queue may also evict what younger queues need, and when even that finds
+      no room nothing younger starts a build, so no two queues can keep
+      evicting each other's graphs. When nothing is in flight, building or
+      launchable and the oldest queue's key still does not fit, its requests
+      are answered TC_E_NOMEM.
+    """
+
+    def __init__(self, registry: Registry, max_batch: int = 64, streams: int = 3, builders: int = 2):
         import torch
 
         self.torch = torch
@@ -208,6 +341,110 @@ class Server:
         self.answers: Dict[int, Answer] = {}
         self.batches = 0
         self.batch_sizes: List[int] = []
+        self.queued: "collections.OrderedDict[object, List[Request]]" = collections.OrderedDict()
+        self.building: Dict[object, object] = {}  # key being built -> graph pinned as its base (or None)
+        self.nbuilders = builders
+        self.max_building = 2 * builders
+        self.builder: Optional[_Builder] = None
+
+    # ------------------------------------------------------------ building
+    @staticmethod
+    def _key(r: Request):
+        return r.graph if r.kind != SPARSE else (r.graph, r.q, r.seed)
+
+    def _need(self, key):
+        """What must be built next for key (None if key is resident): the key, or
+        the graph a sample is drawn from while that graph is not resident."""
+        if self.reg.peek(key) is not None:
+            return None
+        if isinstance(key, tuple) and self.reg.peek(key[0]) is None:
+            return key[0]
+        return key
+
+    def _uses(self, key):
+        """The resident graphs a queue needs kept: its key, or the graph its sample is drawn from."""
+        if self.reg.peek(key) is not None:
+            return (key,)
+        if isinstance(key, tuple) and self.reg.peek(key[0]) is not None:
+            return (key[0],)
+        return ()
+
+    def _try_reserve(self, need, protect) -> bool:
+        self.reg.pin(protect)
+        try:
+            return self.reg.reserve(need)
+        finally:
+            self.reg.unpin(protect)
+
+    def _start_builds(self, clock) -> bool:
+        """Start builds for the oldest queues; True if the oldest queue's key can never fit."""
+        if len(self.building) >= self.max_building:
+            return False
+        uses_all = [k for key in self.queued for k in self._uses(key)]
+        older: List[object] = []
+        head = True  # still at the oldest queue that needs a build
+        for key in list(self.queued):
+            need = self._need(key)
+            if need is None or need in self.building:
+                older.extend(self._uses(key))
+                continue
+            base = need[0] if isinstance(need, tuple) else None
+            if base is not None:
+                self.reg.pinned[base] += 1  # the sample is drawn from it
+            ok = self._try_reserve(need, uses_all) or (head and self._try_reserve(need, older))
+            if not ok:
+                if base is not None:
+                    self.reg.pinned[base] -= 1
+                return head and not self.inflight and not self.building and \
+                    not any(self.reg.peek(k) is not None for k in self.queued)
+            self.building[need] = base
+            self.builder.todo.put((need, self.reg.peek(base) if base is not None else None))
+            head = False
+            older.extend(self._uses(key))
+            if len(self.building) >= self.max_building:
+                break
+        return False
+
+    def _collect_builds(self, clock) -> bool:
+        import queue
+
+        got = False
+        while True:
+            try:
+                key, g, err = self.builder.done.get_nowait()
+            except queue.Empty:
+                return got
+            got = True
+            base = self.building.pop(key)
+            if base is not None:
+                self.reg.pinned[base] -= 1
+            if g is not None:
+                self.reg.install(key, g)
+                continue
+            self.reg.cancel(key)
+            # the requests on key fail, and so do those on samples drawn from it
+            for k in [k for k in self.queued if k == key or (isinstance(k, tuple) and k[0] == key)]:
+                for r in self.queued.pop(k):
+                    self.answers[r.rid] = Answer(r.rid, r.kind, None, clock(), err)
+
+    def _take(self) -> List[Request]:
+        """The oldest queued requests on resident keys, at most max_batch."""
+        take: List[Request] = []
+        done: List[object] = []
+        for key, reqs in self.queued.items():
+            if self.reg.peek(key) is None:
+                continue
+            room = self.max_batch - len(take)
+            take.extend(reqs[:room])
+            if room >= len(reqs):
+                done.append(key)
+            else:
+                del reqs[:room]
+            if len(take) >= self.max_batch:
+                break
+        for key in done:
+            del self.queued[key]
+        return take
 
     # ------------------------------------------------------------ batching
     def _launch(self, reqs: List[Request], stream) -> Optional[_Batch]:
@@ -218,30 +455,25 @@ class Server:
         idx_cc: Dict[int, int] = {}
         graphs_tot, graphs_cc = [], []
         pins: List[object] = []  # graphs are pinned as they are fetched so later fetches cannot evict them
+        batch: List[Request] = []
         for r in reqs:
+            key = self._key(r)
+            g = self.reg.resident(key)
+            if g is None:
+                raise RuntimeError("a batch request whose graph is not resident")
+            if key not in pins:
+                self.reg.pin([key])
+                pins.append(key)
+            batch.append(r)
             if r.kind == CLUSTER:
                 if r.graph not in idx_cc:
-                    g = self.reg.get(r.graph)
-                    if g is None:
-                        self.reg.unpin(pins)
-                        return None
-                    self.reg.pin([r.graph])
-                    pins.append(r.graph)
                     idx_cc[r.graph] = len(cc_keys)
                     cc_keys.append(r.graph)
                     graphs_cc.append(g)
-            else:
-                key = r.graph if r.kind == COUNT else (r.graph, r.q, r.seed)
-                if key not in idx_tot:
-                    g = self.reg.get(r.graph, None if r.kind == COUNT else (r.q, r.seed))
-                    if g is None:
-                        self.reg.unpin(pins)
-                        return None
-                    self.reg.pin([key])
-                    pins.append(key)
-                    idx_tot[key] = len(keys_tot)
-                    keys_tot.append(key)
-                    graphs_tot.append(g)
+            elif key not in idx_tot:
+                idx_tot[key] = len(keys_tot)
+                keys_tot.append(key)
+                graphs_tot.append(g)
         with torch.cuda.stream(stream):
             T_dev = torch.empty(max(len(graphs_tot), 1), dtype=torch.int64, device="cuda")
             T_host = torch.empty(max(len(graphs_tot), 1), dtype=torch.int64, pin_memory=True)
@@ -268,7 +500,7 @@ class Server:
                 keep.append(dig)
             ev = torch.cuda.Event()
             ev.record(stream)
-        b = _Batch(reqs, stream, ev, pins, T_host, cc_host, idx_tot, idx_cc, None)
+        b = _Batch(batch, stream, ev, pins, T_host, cc_host, idx_tot, idx_cc, None)
         b.keep = keep
         return b
 
@@ -303,42 +535,50 @@ class Server:
         """Serve an open-loop trace (arrival times relative to the start)."""
         start = time.perf_counter() if t0 is None else t0
         clock = lambda: time.perf_counter() - start  # noqa: E731
-        pending = collections.deque(sorted(trace, key=lambda r: r.arrival))
-        ready: collections.deque = collections.deque()
+        pending = collections.deque(sorted(trace, key=lambda r: (r.arrival, r.rid)))
         free_streams = list(self.streams)
-        while pending or ready or self.inflight:
-            now = clock()
-            while pending and pending[0].arrival <= now:
-                ready.append(pending.popleft())
-            if self._poll(clock):
-                free_streams = [s for s in self.streams if all(b.stream is not s for b in self.inflight)]
-            if ready and free_streams:
-                reqs = [ready.popleft() for _ in range(min(self.max_batch, len(ready)))]
-                b = self._launch(reqs, free_streams[0])
-                if b is None:  # HBM budget held by batches in flight: wait for one to finish
-                    if self.inflight:
-                        for r in reversed(reqs):
-                            ready.appendleft(r)
-                        self.inflight[0].event.synchronize()
+        self.builder = _Builder(self.reg, self.nbuilders)
+        changed = True
+        try:
+            while pending or self.queued or self.inflight or self.building:
+                now = clock()
+                while pending and pending[0].arrival <= now:
+                    r = pending.popleft()
+                    self.queued.setdefault(self._key(r), []).append(r)
+                    changed = True
+                if self._collect_builds(clock):
+                    changed = True
+                if self._poll(clock):
+                    changed = True
+                    free_streams = [s for s in self.streams if all(b.stream is not s for b in self.inflight)]
+                more = False
+                if changed and free_streams:
+                    take = self._take()
+                    if take:
+                        self.inflight.append(self._launch(take, free_streams[0]))
+                        self.batches += 1
+                        free_streams = free_streams[1:]
+                        more = len(take) == self.max_batch  # launchable requests may remain
+                if changed:
+                    changed = False
+                    if self._start_builds(clock):
+                        key = next(iter(self.queued))
+                        for r in self.queued.pop(key):
+                            self.answers[r.rid] = Answer(r.rid, r.kind, None, clock(), "TC_E_NOMEM")
+                        changed = True
                         continue
-                    if len(reqs) > 1:  # retry the oldest request alone
-                        for r in reversed(reqs[1:]):
-                            ready.appendleft(r)
-                        b = self._launch(reqs[:1], free_streams[0])
-                        reqs = reqs[:1]
-                    if b is None:  # its graph alone exceeds the budget
-                        self.answers[reqs[0].rid] = Answer(reqs[0].rid, reqs[0].kind, None, clock(), "TC_E_NOMEM")
-                        continue
-                self.inflight.append(b)
-                self.batches += 1
-                free_streams = free_streams[1:]
-                continue
-            if not ready and not self.inflight and pending:
-                wait = pending[0].arrival - clock()
-                if wait > 0:
-                    time.sleep(min(wait, 0.002))
-            elif self.inflight and (not ready or not free_streams):
-                time.sleep(0.0001)
+                if more:
+                    changed = True
+                    continue
+                if self.inflight or self.building:
+                    time.sleep(0.0001)
+                elif pending:
+                    wait = pending[0].arrival - clock()
+                    if wait > 0:
+                        time.sleep(min(wait, 0.002))
+        finally:
+            self.builder.close()
+            self.builder = None
         return self.answers
 
 

@@ -169,7 +169,9 @@ def test_served_results_equal_standalone(tcm):
     els = [s.make() for s in synth.pool_specs(24, 9, n_lo=1e3, n_hi=3e4)]
     trace = serve.make_trace(len(els), rate=3000.0, duration=0.4, seed=9)
     say(f"[serving] trace of {len(trace)} requests on {len(els)} graphs")
-    reg = serve.Registry(els, budget_bytes=12 << 20)  # a few graphs at a time
+    # a few graphs at a time, built from pinned host copies (the one-at-a-time run below copies
+    # from pageable memory)
+    reg = serve.Registry(els, budget_bytes=12 << 20, host_edges=serve.pin_edge_lists(els))
     srv = serve.Server(reg, max_batch=16, streams=3)
     ans = srv.run(trace)
     reg2 = serve.Registry(els, budget_bytes=1 << 34)
