@@ -330,7 +330,7 @@ class Server:
       are answered TC_E_NOMEM.
     """
 
-    def __init__(self, registry: Registry, max_batch: int = 64, streams: int = 3, builders: int = 2):
+    def __init__(self, registry: Registry, max_batch: int = 64, streams: int = 3, builders: int = 4):
         import torch
 
         self.torch = torch
