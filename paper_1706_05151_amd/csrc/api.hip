@@ -201,10 +201,15 @@ static void build_in_order(const int32_t* src, const int32_t* dst, int64_t E, in
     coreness_by_id(g0.get(), s, core.get());
     build_graph(src, dst, E, n, edge_off, n_per_graph, G, on_device, s, g, 4, core.get());
     TC_HIP(hipStreamSynchronize(s));
-  } else {
-    build_graph(src, dst, E, n, edge_off, n_per_graph, G, on_device, s, g, static_cast<int>(o.order), nullptr);
+    ensure_plan(g->csr, s, o);
+    return;
   }
-  ensure_plan(g->csr, s, o);  // work plan of the intersection kernel
+  HostWords tail(s);
+  build_graph(src, dst, E, n, edge_off, n_per_graph, G, on_device, s, g, static_cast<int>(o.order), nullptr,
+              tail.get());
+  ensure_plan(g->csr, s, o);  // work plan of the intersection kernel (it needs no dhat_max)
+  TC_HIP(hipStreamSynchronize(s));
+  build_graph_finish(g, tail.get());
 }
 
 tc_status tc_build_csr(const int32_t* src, const int32_t* dst, int64_t num_edges, int32_t n, uint32_t flags,
@@ -215,7 +220,6 @@ tc_status tc_build_csr(const int32_t* src, const int32_t* dst, int64_t num_edges
     auto* g = new tc_graph();
     try {
       build_in_order(src, dst, num_edges, n, nullptr, nullptr, 1, (flags & TC_IN_DEVICE) != 0, as_stream(stream), g);
-      TC_HIP(hipStreamSynchronize(as_stream(stream)));
     } catch (...) {
       (void)hipStreamSynchronize(as_stream(stream));
       delete g;
@@ -877,10 +881,12 @@ tc_status tc_sparsify_build(tc_graph* g, double q, uint64_t seed, void* stream, 
       h->bits = g->bits;
       h->sampled = true;
       h->q = q;
-      build_sampled_csr(g, q, seed, h->csr, s);
+      HostWords dh(s);  // the sample's longest row, read after the synchronisation below
+      build_sampled_csr(g, q, seed, h->csr, s, 0, dh.get());
       h->m = h->csr.m;
       ensure_plan(h->csr, s, get_options());
       TC_HIP(hipStreamSynchronize(s));
+      h->csr.dhat_max = static_cast<int32_t>(dh[0]);
     } catch (...) {
       (void)hipStreamSynchronize(s);
       delete h;

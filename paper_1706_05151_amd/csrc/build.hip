@@ -285,20 +285,22 @@ __device__ __forceinline__ uint32_t wave_bitonic_sort(uint32_t x) {
   return x;
 }
 
-// Rows of at most 64 entries: each wave takes 64 consecutive rows; a row of
-// one entry is copied by its lane, a row of 2..64 entries is sorted by the
-// whole wave (one entry per lane). Longer rows are left to k_seg_rows_block.
+// Rows of at most 64 entries: each wave takes rpw consecutive rows (rpw a
+// power of two up to 64, smaller for small graphs so that their rows spread
+// over more waves); a row of one entry is copied by its lane, a row of 2..64
+// entries is sorted by the whole wave (one entry per lane). Longer rows are
+// left to k_seg_rows_wide and k_seg_rows_block.
 __global__ __launch_bounds__(kSegBlock) void k_seg_rows_wave(const uint64_t* __restrict__ keys,
-                                                           const int64_t* __restrict__ off, int32_t n, int b,
+                                                           const int64_t* __restrict__ off, int32_t n, int b, int rpw,
                                                            int32_t* __restrict__ adj, int32_t* __restrict__ src) {
   const uint32_t mask = static_cast<uint32_t>((1ull << b) - 1);
   const int lane = lane_id();
   const int64_t wave = static_cast<int64_t>(blockIdx.x) * (kSegBlock / kWave) + threadIdx.x / kWave;
-  const int64_t stride = static_cast<int64_t>(gridDim.x) * (kSegBlock / kWave) * kWave;
-  for (int64_t r0 = wave * kWave; r0 < n; r0 += stride) {
+  const int64_t stride = static_cast<int64_t>(gridDim.x) * (kSegBlock / kWave) * rpw;
+  for (int64_t r0 = wave * rpw; r0 < n; r0 += stride) {
     const int64_t r = r0 + lane;
     int64_t o = 0, len = 0;
-    if (r < n) {
+    if (lane < rpw && r < n) {
       o = off[r];
       len = off[r + 1] - o;
     }
@@ -509,22 +511,33 @@ void offsets_from_key_rows(const uint64_t* keys, uint64_t m, int32_t n, int64_t*
   TC_LAUNCH_CHECK();
 }
 
-int32_t max_row_length(const int64_t* off, int32_t n, hipStream_t s) {
-  DevBuf<int> mx(1, s);
-  TC_HIP(hipMemsetAsync(mx.get(), 0, sizeof(int), s));
+void row_max_to_host(const int64_t* off, int32_t n, hipStream_t s, uint64_t* host) {
+  DevBuf<uint64_t> mx(1, s);
+  k_fill_words<uint64_t><<<1, 64, 0, s>>>(mx.get(), 1, 0ull);
+  TC_LAUNCH_CHECK();
   if (n > 0) {
-    k_row_max<<<grid_for(n, kBlock, 4096), kBlock, 0, s>>>(off, n, mx.get());
+    k_row_max<<<grid_for(n, kBlock, 4096), kBlock, 0, s>>>(off, n, reinterpret_cast<int*>(mx.get()));
     TC_LAUNCH_CHECK();
   }
-  int h = 0;
-  TC_HIP(hipMemcpyAsync(&h, mx.get(), sizeof(int), hipMemcpyDeviceToHost, s));
+  TC_HIP(hipMemcpyAsync(host, mx.get(), sizeof(uint64_t), hipMemcpyDeviceToHost, s));
+}
+
+int32_t max_row_length(const int64_t* off, int32_t n, hipStream_t s) {
+  HostWords h(s);
+  row_max_to_host(off, n, s, h.get());
   TC_HIP(hipStreamSynchronize(s));
-  return h;
+  return static_cast<int32_t>(h[0]);
+}
+
+void build_graph_finish(tc_graph* g, const uint64_t* tail) {
+  if (tail[0]) fail(TC_E_DEVICE, "radix_sort: a tile's look-back did not complete");
+  g->csr.dhat_max = static_cast<int32_t>(tail[1]);
+  g->d_max = static_cast<int32_t>(tail[2]);
 }
 
 void build_graph(const int32_t* src, const int32_t* dst, int64_t E, int32_t n, const int64_t* edge_off_host,
                  const int32_t* n_per_graph_host, int32_t G, bool on_device, hipStream_t s, tc_graph* g, int order,
-                 const int32_t* key_by_id) {
+                 const int32_t* key_by_id, uint64_t* tail) {
   if (E < 0 || n < 0) fail(TC_E_RANGE, "negative edge or vertex count");
   if (n > kMaxVertices) fail(TC_E_RANGE, "more than 2^31 - 2^25 vertices");
   // k_canon counts records in uint32 with strides of up to 2^24
@@ -577,53 +590,50 @@ void build_graph(const int32_t* src, const int32_t* dst, int64_t E, int32_t n, c
 
   // ---- 1-3: canonical keys, sort, duplicates and degrees
   DevBuf<uint64_t> keys(E, s), tmp(E, s);
-  DevBuf<int> err(1, s);
-  DevBuf<uint64_t> d_m(1, s);
-  DevBuf<uint32_t> sort_fail(1, s);  // set by any sort whose look-back gave up; checked at the syncs below
-  TC_HIP(hipMemsetAsync(err.get(), 0, sizeof(int), s));
-  TC_HIP(hipMemsetAsync(sort_fail.get(), 0, sizeof(uint32_t), s));
+  // control words, read back in one copy per synchronisation: [0] kept keys m,
+  // [1] repeated keys, [2] vertex id out of range, [3] a sort's look-back gave
+  // up, [4] dhat_max, [5] d_max
+  DevBuf<uint64_t> ctl(8, s);
+  k_fill_words<uint64_t><<<1, 64, 0, s>>>(ctl.get(), 8, 0ull);
+  TC_LAUNCH_CHECK();
+  uint64_t* d_m = ctl.get();
+  unsigned long long* d_dup = reinterpret_cast<unsigned long long*>(ctl.get() + 1);
+  int* err = reinterpret_cast<int*>(ctl.get() + 2);
+  uint32_t* sort_fail = reinterpret_cast<uint32_t*>(ctl.get() + 3);
+  HostWords hw(s);
   g->deg.alloc(n, s);
   if (n > 0) TC_HIP(hipMemsetAsync(g->deg.p, 0, n * sizeof(int32_t), s));
   const uint64_t hmask = (1ull << b) - 1;
   // kept-key flags and per-block counts over the sorted keys (the compaction layout)
   const size_t nfb = (static_cast<size_t>(E) + kFlagChunk - 1) / kFlagChunk;
-  DevBuf<uint64_t> kflags(nfb * kFlagWaves * kFlagWords, s), kcnt(nfb, s), d_dup(1, s);
-  TC_HIP(hipMemsetAsync(d_dup.get(), 0, sizeof(uint64_t), s));
+  DevBuf<uint64_t> kflags(nfb * kFlagWaves * kFlagWords, s), kcnt(nfb, s);
   uint64_t* sorted = nullptr;
   uint64_t* spare = nullptr;
   if (E > 0) {
     k_canon<<<grid_for(E, kBlock, 65536), kBlock, 0, s>>>(dsrc, ddst, static_cast<uint32_t>(E), n, b, d_eoff.get(),
-                                                          d_vbase.get(), G, keys.get(), err.get());
+                                                          d_vbase.get(), G, keys.get(), err);
     TC_LAUNCH_CHECK();
     // d_v of the larger endpoints once the passes over their bits [0, b) are done
     const LargerEndHook larger{(b + kRadixBits - 1) / kRadixBits - 1, static_cast<uint64_t>(E), hmask, g->deg.p, s};
-    sorted = radix_sort<uint64_t>(keys.get(), tmp.get(), E, 0, 2 * b, s, sort_fail.get(), larger);
+    sorted = radix_sort<uint64_t>(keys.get(), tmp.get(), E, 0, 2 * b, s, sort_fail, larger);
     if (E == 1) larger(larger.last_pass, sorted);  // one key is sorted without a pass
     spare = sorted == keys.get() ? tmp.get() : keys.get();
     // repeats' larger endpoints go to the spare key buffer (room for 2E of them)
     k_dedup_degrees<<<static_cast<unsigned>(nfb), kScanBlock, 0, s>>>(
         sorted, static_cast<uint64_t>(E), b, g->deg.p, kflags.get(), kcnt.get(), reinterpret_cast<uint32_t*>(spare),
-        reinterpret_cast<unsigned long long*>(d_dup.get()));
+        d_dup);
     TC_LAUNCH_CHECK();
-    exclusive_scan<uint64_t>(kcnt.get(), kcnt.get(), nfb, s, d_m.get());
-  } else {
-    TC_HIP(hipMemsetAsync(d_m.get(), 0, sizeof(uint64_t), s));
+    exclusive_scan<uint64_t>(kcnt.get(), kcnt.get(), nfb, s, d_m);
   }
   hsrc.release();
   hdst.release();
-  int h_err = 0;
-  uint64_t m = 0;
-  uint32_t h_fail = 0;
-  TC_HIP(hipMemcpyAsync(&h_err, err.get(), sizeof(int), hipMemcpyDeviceToHost, s));
-  uint64_t ndup = 0;
-  TC_HIP(hipMemcpyAsync(&m, d_m.get(), sizeof(uint64_t), hipMemcpyDeviceToHost, s));
-  TC_HIP(hipMemcpyAsync(&ndup, d_dup.get(), sizeof(uint64_t), hipMemcpyDeviceToHost, s));
-  TC_HIP(hipMemcpyAsync(&h_fail, sort_fail.get(), sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+  TC_HIP(hipMemcpyAsync(hw.get(), ctl.get(), 4 * sizeof(uint64_t), hipMemcpyDeviceToHost, s));
   TC_HIP(hipStreamSynchronize(s));
-  if (h_fail) fail(TC_E_DEVICE, "radix_sort: a tile's look-back did not complete");
-  if (h_err) fail(TC_E_RANGE, "vertex id outside [0, n)");
+  if (hw[3]) fail(TC_E_DEVICE, "radix_sort: a tile's look-back did not complete");
+  if (hw[2]) fail(TC_E_RANGE, "vertex id outside [0, n)");
+  const uint64_t m = hw[0], ndup = hw[1];
   g->m = static_cast<int64_t>(m);
-  take_off_repeats(reinterpret_cast<uint32_t*>(spare), ndup, b, g->deg.p, s, sort_fail.get());
+  take_off_repeats(reinterpret_cast<uint32_t*>(spare), ndup, b, g->deg.p, s, sort_fail);
 
   // ---- 4: ranks in the degree order
   g->order.alloc(n, s);
@@ -637,9 +647,9 @@ void build_graph(const int32_t* src, const int32_t* dst, int64_t E, int32_t n, c
     TC_LAUNCH_CHECK();
     // the keys are made in id order, so a stable sort of the order-key bits
     // [b, 2b) alone leaves equal order keys in id order
-    u128* r1 = radix_sort<u128>(rk.get(), rk2.get(), n, b, 2 * b, s, sort_fail.get());
+    u128* r1 = radix_sort<u128>(rk.get(), rk2.get(), n, b, 2 * b, s, sort_fail);
     u128* r2 = r1;
-    if (G > 1) r2 = radix_sort<u128>(r1, r1 == rk.get() ? rk2.get() : rk.get(), n, 64, 64 + gbits, s, sort_fail.get());
+    if (G > 1) r2 = radix_sort<u128>(r1, r1 == rk.get() ? rk2.get() : rk.get(), n, 64, 64 + gbits, s, sort_fail);
     k_rank_from_sorted<<<grid_for(n, kBlock, 65536), kBlock, 0, s>>>(r2, n, b, g->order.p, g->rank.p,
                                                                       G > 1 ? g->graph_of_rank.p : nullptr);
     TC_LAUNCH_CHECK();
@@ -657,15 +667,24 @@ void build_graph(const int32_t* src, const int32_t* dst, int64_t E, int32_t n, c
         static_cast<size_t>(E), kflags.get(), RelabelKey{sorted, b, g->rank.p}, spare, kcnt.get());
     TC_LAUNCH_CHECK();
     // group the entries by row: a stable sort of the row bits [b, 2b)
-    uint64_t* rows = radix_sort<uint64_t>(spare, sorted, m, b, 2 * b, s, sort_fail.get());
+    uint64_t* rows = radix_sort<uint64_t>(spare, sorted, m, b, 2 * b, s, sort_fail);
     uint64_t* other = rows == spare ? sorted : spare;
     k_offsets_from_rows<<<grid_for(static_cast<uint64_t>(n) + 1, kBlock, 65536), kBlock, 0, s>>>(RowOfKey{rows, b}, m,
                                                                                                n, c.off.p);
     TC_LAUNCH_CHECK();
-    if (max_row_length(c.off.p, n, s) <= kSegBlockMax) {
+    // In the degree order of Eq. (1) every entry u of row v has d_u >= d_v >= dhat_v, and
+    // the degrees of a row's entries sum to at most 2m, so no row is longer than sqrt(2m):
+    // small enough graphs skip reading the longest row back.
+    const bool short_rows = order == 0 && key_by_id == nullptr &&
+                            2 * m <= static_cast<uint64_t>(kSegBlockMax) * static_cast<uint64_t>(kSegBlockMax);
+    if (short_rows || max_row_length(c.off.p, n, s) <= kSegBlockMax) {
       const unsigned cus = static_cast<unsigned>(device_cus());
-      k_seg_rows_wave<<<grid_for((static_cast<uint64_t>(n) + kWave - 1) / kWave * kWave, kSegBlock, cus * 16), kSegBlock,
-                        0, s>>>(rows, c.off.p, n, b, c.adj.p, c.src.p);
+      int rpw = kWave;  // rows per wave: fewer while the rows would fill fewer waves than the grid holds
+      while (rpw > 1 && (static_cast<uint64_t>(n) + rpw - 1) / rpw < static_cast<uint64_t>(cus) * 16 * (kSegBlock / kWave))
+        rpw >>= 1;
+      const uint64_t waves = (static_cast<uint64_t>(n) + rpw - 1) / rpw;
+      k_seg_rows_wave<<<grid_for(waves * kWave, kSegBlock, cus * 16), kSegBlock, 0, s>>>(rows, c.off.p, n, b, rpw,
+                                                                                        c.adj.p, c.src.p);
       TC_LAUNCH_CHECK();
       DevBuf<int32_t> longrows(n, s);
       DevBuf<uint64_t> nlong(2, s);
@@ -679,7 +698,7 @@ void build_graph(const int32_t* src, const int32_t* dst, int64_t E, int32_t n, c
                                                       c.src.p);
       TC_LAUNCH_CHECK();
     } else {  // some row is longer than a block sorts: sort every key by row and column instead
-      uint64_t* ok = radix_sort<uint64_t>(rows, other, m, 0, 2 * b, s, sort_fail.get());
+      uint64_t* ok = radix_sort<uint64_t>(rows, other, m, 0, 2 * b, s, sort_fail);
       k_csr_fill<<<grid_for(m, kBlock, 65536), kBlock, 0, s>>>(ok, m, b, c.adj.p, c.src.p);
       TC_LAUNCH_CHECK();
     }
@@ -691,21 +710,19 @@ void build_graph(const int32_t* src, const int32_t* dst, int64_t E, int32_t n, c
   keys.release();
   tmp.release();
 
-  DevBuf<int> mx(2, s);
-  TC_HIP(hipMemsetAsync(mx.get(), 0, 2 * sizeof(int), s));
   if (n > 0) {
-    k_row_max<<<grid_for(n, kBlock, 4096), kBlock, 0, s>>>(c.off.p, n, mx.get());
+    k_row_max<<<grid_for(n, kBlock, 4096), kBlock, 0, s>>>(c.off.p, n, reinterpret_cast<int*>(ctl.get() + 4));
     TC_LAUNCH_CHECK();
-    k_array_max<<<grid_for(n, kBlock, 4096), kBlock, 0, s>>>(g->deg.p, n, mx.get() + 1);
+    k_array_max<<<grid_for(n, kBlock, 4096), kBlock, 0, s>>>(g->deg.p, n, reinterpret_cast<int*>(ctl.get() + 5));
     TC_LAUNCH_CHECK();
   }
-  int h_mx[2] = {0, 0};
-  TC_HIP(hipMemcpyAsync(h_mx, mx.get(), 2 * sizeof(int), hipMemcpyDeviceToHost, s));
-  TC_HIP(hipMemcpyAsync(&h_fail, sort_fail.get(), sizeof(uint32_t), hipMemcpyDeviceToHost, s));
-  TC_HIP(hipStreamSynchronize(s));
-  if (h_fail) fail(TC_E_DEVICE, "radix_sort: a tile's look-back did not complete");
-  c.dhat_max = h_mx[0];
-  g->d_max = h_mx[1];
+  // the tail words [look-back failure, dhat_max, d_max]: the caller reads them after its next
+  // synchronisation (build_graph_finish), or they are read here
+  TC_HIP(hipMemcpyAsync(tail ? tail : hw.get(), ctl.get() + 3, 3 * sizeof(uint64_t), hipMemcpyDeviceToHost, s));
+  if (!tail) {
+    TC_HIP(hipStreamSynchronize(s));
+    build_graph_finish(g, hw.get());
+  }
 }
 
 // ============================================================ out of core

@@ -5,6 +5,7 @@
 
 #include <cstdint>
 #include <cstdio>
+#include <exception>
 #include <stdexcept>
 #include <string>
 
@@ -88,6 +89,35 @@ class DevBuf {
   T* p_ = nullptr;
   size_t n_ = 0;
   hipStream_t s_ = nullptr;
+};
+
+// Pinned host words for small device-to-host readbacks on stream s, taken
+// from a process-wide pool (memory.hip) and given back on destruction. A copy
+// into pinned memory is one asynchronous transfer; into pageable memory the
+// runtime stages every copy and waits for it. Values are read only after a
+// synchronisation of s that follows the copy; when an exception unwinds past
+// the words, s is synchronised first, so no copy still in flight lands in
+// words handed to another caller.
+constexpr int kHostWords = 16;
+uint64_t* host_words_take();
+void host_words_give(uint64_t* p);
+
+class HostWords {
+ public:
+  explicit HostWords(hipStream_t s) : p_(host_words_take()), s_(s), unwinding_(std::uncaught_exceptions()) {}
+  ~HostWords() {
+    if (std::uncaught_exceptions() > unwinding_) (void)hipStreamSynchronize(s_);
+    host_words_give(p_);
+  }
+  HostWords(const HostWords&) = delete;
+  HostWords& operator=(const HostWords&) = delete;
+  uint64_t* get() const { return p_; }
+  uint64_t operator[](int i) const { return p_[i]; }
+
+ private:
+  uint64_t* p_;
+  hipStream_t s_;
+  int unwinding_;
 };
 
 inline int bits_for(uint64_t max_value) {  // bits needed to hold values 0..max_value

@@ -114,12 +114,31 @@ struct RecCost {
 
 __device__ __forceinline__ int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
+// Target probe-equivalents of a wave item: the item_work option, else about 8
+// items per resident wave from the plan's total cost, within [4096, 65536];
+// never below 64. Block items take 8 times as much. Read on the device from
+// the cost total, so the plan needs no readback before it classifies.
+struct ItemWidth {
+  const int64_t* total;  // the cost prefix's total
+  int64_t option;        // TC_OPT_ITEM_WORK (0: from the total)
+  int64_t waves;         // resident waves of the persistent launch
+  __device__ int64_t wave() const {
+    int64_t w = option;
+    if (w <= 0) {
+      w = *total / (8 * waves);
+      w = w < 4096 ? 4096 : w > 65536 ? 65536 : w;
+    }
+    return w < 64 ? 64 : w;
+  }
+};
+
 // Per pivot: number of block items, number of split wave items, and whether it
 // is served from the grouped queue.
 __global__ void k_pivot_classify(int32_t n, const int64_t* __restrict__ off, const int64_t* __restrict__ in_off,
-                                 const int64_t* __restrict__ fin, int64_t hub_dhat, int64_t hub_cap, int64_t iw_hub,
-                                 int64_t iw_wave, int64_t* __restrict__ n_hub, int64_t* __restrict__ n_split,
+                                 const int64_t* __restrict__ fin, int64_t hub_dhat, int64_t hub_cap, ItemWidth width,
+                                 int64_t* __restrict__ n_hub, int64_t* __restrict__ n_split,
                                  int32_t* __restrict__ grouped, unsigned long long* __restrict__ probes) {
+  const int64_t iw_wave = width.wave(), iw_hub = 8 * iw_wave;
   unsigned long long pr = 0;
   for (int32_t u = blockIdx.x * blockDim.x + threadIdx.x; u < n; u += gridDim.x * blockDim.x) {
     const int64_t dh = off[u + 1] - off[u];
@@ -160,7 +179,9 @@ __device__ __forceinline__ int64_t boundary(const int64_t* fin, int64_t i0, int6
 
 __global__ void k_items_fill(uint64_t n_items, const int64_t* __restrict__ item_off, int32_t n,
                              const int64_t* __restrict__ off, const int64_t* __restrict__ in_off,
-                             const int64_t* __restrict__ fin, int64_t cap, int64_t iw, PivotItem* __restrict__ items) {
+                             const int64_t* __restrict__ fin, int64_t cap, ItemWidth width, int64_t scale,
+                             PivotItem* __restrict__ items) {
+  const int64_t iw = scale * width.wave();
   for (uint64_t t = static_cast<uint64_t>(blockIdx.x) * blockDim.x + threadIdx.x; t < n_items;
        t += static_cast<uint64_t>(gridDim.x) * blockDim.x) {
     // pivot: largest u with item_off[u] <= t (item_off holds n+1 exclusive offsets)
@@ -307,65 +328,48 @@ void plan_records(Csr& c, PivotPlan& P, const uint64_t* sk, const uint32_t* sl, 
 void plan_items(Csr& c, PivotPlan& P, const int64_t* fin_p, uint64_t mi, hipStream_t s, const Options& o,
                 const uint32_t* sort_fail) {
   const int32_t n = c.n;
-  // classify pivots and count items; item_work 0: about 8 items per resident
-  // wave, between 4096 and 65536 probe-equivalents
-  int64_t total_cost = 0;
-  uint32_t h_fail = 0;
-  TC_HIP(hipMemcpyAsync(&total_cost, fin_p + mi, sizeof(int64_t), hipMemcpyDeviceToHost, s));
-  if (sort_fail) TC_HIP(hipMemcpyAsync(&h_fail, sort_fail, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
-  TC_HIP(hipStreamSynchronize(s));
-  if (h_fail) fail(TC_E_DEVICE, "radix_sort: a tile's look-back did not complete");
-  int64_t iw_wave = o.item_work;
-  if (iw_wave <= 0) {
-    const int64_t waves = static_cast<int64_t>(device_cus()) * 4 * kPivotWaves;
-    iw_wave = total_cost / (8 * waves);
-    iw_wave = iw_wave < 4096 ? 4096 : iw_wave > 65536 ? 65536 : iw_wave;
-  }
-  if (iw_wave < 64) iw_wave = 64;
-  const int64_t iw_hub = 8 * iw_wave;
   const int64_t cap = hub_slice_cap(kCountPerNode);
-  DevBuf<int64_t> nh(static_cast<size_t>(n) + 1, s), ns(static_cast<size_t>(n) + 1, s);
-  DevBuf<int32_t> grp(n, s);
-  DevBuf<unsigned long long> d_probes(1, s);
-  k_fill_words<unsigned long long><<<1, 64, 0, s>>>(d_probes.get(), 1, 0ull);
+  const ItemWidth width{fin_p + mi, o.item_work, static_cast<int64_t>(device_cus()) * 4 * kPivotWaves};
+  // control words, read back in one copy: [0] block items, [1] wave items, [2] probes,
+  // [3] grouped pivots, [4] a sort's look-back gave up
+  DevBuf<uint64_t> ctl(5, s);
+  k_fill_words<uint64_t><<<1, 64, 0, s>>>(ctl.get(), 5, 0ull);
   TC_LAUNCH_CHECK();
-  k_pivot_classify<<<grid_for(n, kBlock, 65536), kBlock, 0, s>>>(n, c.off.p, P.in_off.p, fin_p, clamp_hub(o.hub_dhat), cap,
-                                                                 iw_hub, iw_wave, nh.get(), ns.get(), grp.get(),
-                                                                 d_probes.get());
+  DevBuf<int64_t> nh(n, s), ns(n, s);
+  DevBuf<int32_t> grp(n, s), glist(n, s);
+  k_pivot_classify<<<grid_for(n, kBlock, 65536), kBlock, 0, s>>>(
+      n, c.off.p, P.in_off.p, fin_p, clamp_hub(o.hub_dhat), cap, width, nh.get(), ns.get(), grp.get(),
+      reinterpret_cast<unsigned long long*>(ctl.get() + 2));
   TC_LAUNCH_CHECK();
-  exclusive_scan<int64_t>(nh.get(), nh.get(), n, s, nh.get() + n);
-  exclusive_scan<int64_t>(ns.get(), ns.get(), n, s, ns.get() + n);
-  int64_t counts[3] = {0, 0, 0};
-  TC_HIP(hipMemcpyAsync(&counts[0], nh.get() + n, sizeof(int64_t), hipMemcpyDeviceToHost, s));
-  TC_HIP(hipMemcpyAsync(&counts[1], ns.get() + n, sizeof(int64_t), hipMemcpyDeviceToHost, s));
-  TC_HIP(hipMemcpyAsync(&counts[2], d_probes.get(), sizeof(int64_t), hipMemcpyDeviceToHost, s));
+  exclusive_scan<int64_t>(nh.get(), nh.get(), n, s, reinterpret_cast<int64_t*>(ctl.get()));
+  exclusive_scan<int64_t>(ns.get(), ns.get(), n, s, reinterpret_cast<int64_t*>(ctl.get() + 1));
+  compact_if<int32_t>(n, GroupedPred{grp.get()}, IdentityI32{}, glist.get(), ctl.get() + 3, s);
+  if (sort_fail) {
+    TC_HIP(hipMemcpyAsync(ctl.get() + 4, sort_fail, sizeof(uint32_t), hipMemcpyDeviceToDevice, s));
+  }
+  HostWords hw(s);
+  TC_HIP(hipMemcpyAsync(hw.get(), ctl.get(), 5 * sizeof(uint64_t), hipMemcpyDeviceToHost, s));
   TC_HIP(hipStreamSynchronize(s));
-  P.probes = static_cast<uint64_t>(counts[2]);
-  P.n_hub_items = static_cast<uint64_t>(counts[0]);
-  P.n_wave_items = static_cast<uint64_t>(counts[1]);
-  // items: [hub items | split wave items | grouped pivots as int32 at the end]
+  if (hw[4]) fail(TC_E_DEVICE, "radix_sort: a tile's look-back did not complete");
+  P.n_hub_items = hw[0];
+  P.n_wave_items = hw[1];
+  P.probes = hw[2];
+  const uint64_t ng = hw[3];
+  // items: [hub items | split wave items]; the grouped pivots as int32 in a list of their own
   P.items.alloc(P.n_hub_items + P.n_wave_items, s);
   if (P.n_hub_items) {
     k_items_fill<<<grid_for(P.n_hub_items, kBlock, 65536), kBlock, 0, s>>>(P.n_hub_items, nh.get(), n, c.off.p,
-                                                                          P.in_off.p, fin_p, cap, iw_hub, P.items.p);
+                                                                          P.in_off.p, fin_p, cap, width, 8, P.items.p);
     TC_LAUNCH_CHECK();
   }
   if (P.n_wave_items) {
     k_items_fill<<<grid_for(P.n_wave_items, kBlock, 65536), kBlock, 0, s>>>(
-        P.n_wave_items, ns.get(), n, c.off.p, P.in_off.p, fin_p, 1ll << 40, iw_wave, P.items.p + P.n_hub_items);
+        P.n_wave_items, ns.get(), n, c.off.p, P.in_off.p, fin_p, 1ll << 40, width, 1, P.items.p + P.n_hub_items);
     TC_LAUNCH_CHECK();
   }
-  // grouped pivot list
-  DevBuf<uint64_t> d_g(1, s);
-  DevBuf<int32_t> glist(n, s);
-  compact_if<int32_t>(n, GroupedPred{grp.get()}, IdentityI32{}, glist.get(), d_g.get(), s);
-  uint64_t ng = 0;
-  TC_HIP(hipMemcpyAsync(&ng, d_g.get(), sizeof(uint64_t), hipMemcpyDeviceToHost, s));
-  TC_HIP(hipStreamSynchronize(s));
   P.grouped.alloc(ng, s);
   if (ng) TC_HIP(hipMemcpyAsync(P.grouped.p, glist.get(), ng * sizeof(int32_t), hipMemcpyDeviceToDevice, s));
   P.n_grouped = ng;
-  TC_HIP(hipStreamSynchronize(s));
   P.hub_dhat = clamp_hub(o.hub_dhat);
   P.item_work = o.item_work;
   P.ready = true;
@@ -866,16 +870,19 @@ __global__ void k_unpack_entries(const uint64_t* __restrict__ k, uint64_t n, int
 
 }  // namespace
 
-void build_sampled_csr(const tc_graph* g, double q, uint64_t seed, Csr& out, hipStream_t s, int32_t first_rank) {
+void build_sampled_csr(const tc_graph* g, double q, uint64_t seed, Csr& out, hipStream_t s, int32_t first_rank,
+                       uint64_t* dhat_host) {
   const Csr& c = g->csr;
   const uint64_t m = static_cast<uint64_t>(c.m);
   const bool all = q >= 1.0;
   const uint64_t tau = all ? ~0ull : static_cast<uint64_t>(std::ldexp(q, 64));
+  HostWords hw(s);
   int64_t first = 0;
   if (first_rank > 0 && c.n > 0) {
     if (first_rank > c.n) fail(TC_E_RANGE, "first rank outside [0, n]");
-    TC_HIP(hipMemcpyAsync(&first, c.off.p + first_rank, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    TC_HIP(hipMemcpyAsync(hw.get(), c.off.p + first_rank, sizeof(int64_t), hipMemcpyDeviceToHost, s));
     TC_HIP(hipStreamSynchronize(s));
+    first = static_cast<int64_t>(hw[0]);
   }
   KeepPred pred{c.adj.p, c.src.p, g->order.p, 0, tau, all, static_cast<uint64_t>(first)};
   {
@@ -887,9 +894,9 @@ void build_sampled_csr(const tc_graph* g, double q, uint64_t seed, Csr& out, hip
   DevBuf<uint64_t> packed(m, s);
   DevBuf<uint64_t> d_cnt(1, s);
   compact_if<uint64_t>(m, pred, PackEntry{c.adj.p, c.src.p}, packed.get(), d_cnt.get(), s);
-  uint64_t mk = 0;
-  TC_HIP(hipMemcpyAsync(&mk, d_cnt.get(), sizeof(uint64_t), hipMemcpyDeviceToHost, s));
+  TC_HIP(hipMemcpyAsync(hw.get(), d_cnt.get(), sizeof(uint64_t), hipMemcpyDeviceToHost, s));
   TC_HIP(hipStreamSynchronize(s));
+  const uint64_t mk = hw[0];
   out.n = c.n;
   out.m = static_cast<int64_t>(mk);
   out.off.alloc(static_cast<size_t>(c.n) + 1, s);
@@ -900,7 +907,8 @@ void build_sampled_csr(const tc_graph* g, double q, uint64_t seed, Csr& out, hip
     TC_LAUNCH_CHECK();
   }
   offsets_from_rows(out.src.p, mk, c.n, out.off.p, s);
-  out.dhat_max = max_row_length(out.off.p, c.n, s);
+  if (dhat_host) row_max_to_host(out.off.p, c.n, s, dhat_host);
+  else out.dhat_max = max_row_length(out.off.p, c.n, s);
 }
 
 // ------------------------------------------------------------ listing ---

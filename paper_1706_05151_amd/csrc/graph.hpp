@@ -213,10 +213,17 @@ Options get_options();
 
 // build.hip
 // order: TC_OPT_ORDER value recorded on the graph; key_by_id (device, optional)
-// replaces the degree as the ascending order key (ties by id)
+// replaces the degree as the ascending order key (ties by id). tail (pinned
+// host words, optional): the last readback [look-back failure, dhat_max,
+// d_max] is copied there and left for the caller to read with
+// build_graph_finish after its next synchronisation of s; without it
+// build_graph synchronises and finishes itself.
 void build_graph(const int32_t* src, const int32_t* dst, int64_t E, int32_t n, const int64_t* edge_off_host,
                  const int32_t* n_per_graph_host, int32_t num_graphs, bool on_device, hipStream_t s, tc_graph* g,
-                 int order, const int32_t* key_by_id);
+                 int order, const int32_t* key_by_id, uint64_t* tail = nullptr);
+void build_graph_finish(tc_graph* g, const uint64_t* tail);
+// the longest row of a CSR, copied (as a 64-bit word) into pinned host memory without synchronising
+void row_max_to_host(const int64_t* off, int32_t n, hipStream_t s, uint64_t* host);
 
 // The rank-space oriented CSR of a host edge list built under a device budget
 // into host memory: off_h[n+1], adj_h[>= m]; info = {parts, row ranges, bytes
@@ -288,7 +295,10 @@ void coreness_rank(const Csr& c, hipStream_t s, int32_t* core);
 // through the device under a memory budget; info: {partitions, chunks, pairs, bytes copied in}
 uint64_t count_streamed(const int64_t* off, const int32_t* adj, int32_t n, int64_t m, uint64_t budget,
                         hipStream_t s, const Options& o, uint64_t info[4]);
-void build_sampled_csr(const tc_graph* g, double q, uint64_t seed, Csr& out, hipStream_t s, int32_t first_rank = 0);
+// dhat_host (pinned host word, optional): the sample's dhat_max is copied there for the
+// caller to read after its next synchronisation, instead of being read here
+void build_sampled_csr(const tc_graph* g, double q, uint64_t seed, Csr& out, hipStream_t s, int32_t first_rank = 0,
+                       uint64_t* dhat_host = nullptr);
 void sort_triangles(int32_t* tri, int64_t count, int bits, hipStream_t s);
 // off[r] = first index whose row is >= r, for rows sorted ascending (length m); off has n+1 entries
 void offsets_from_rows(const int32_t* row, uint64_t m, int32_t n, int64_t* off, hipStream_t s);

@@ -198,4 +198,35 @@ size_t dev_cached_bytes() {
   return c.idle_bytes;
 }
 
+// ---- pinned host words: slabs of 64 slots, never returned (a few KiB per
+// readback in flight at once); pageable slabs if pinned memory is refused
+
+namespace {
+std::mutex g_words_mu;
+std::vector<uint64_t*> g_words_free;
+}  // namespace
+
+uint64_t* host_words_take() {
+  std::lock_guard<std::mutex> lk(g_words_mu);
+  if (g_words_free.empty()) {
+    constexpr int kSlots = 64;
+    const size_t bytes = sizeof(uint64_t) * kHostWords * kSlots;
+    void* p = nullptr;
+    if (hipHostMalloc(&p, bytes, hipHostMallocDefault) != hipSuccess || p == nullptr) {
+      (void)hipGetLastError();
+      p = new uint64_t[static_cast<size_t>(kHostWords) * kSlots];
+    }
+    for (int i = 0; i < kSlots; i++) g_words_free.push_back(static_cast<uint64_t*>(p) + static_cast<size_t>(i) * kHostWords);
+  }
+  uint64_t* w = g_words_free.back();
+  g_words_free.pop_back();
+  return w;
+}
+
+void host_words_give(uint64_t* p) {
+  if (!p) return;
+  std::lock_guard<std::mutex> lk(g_words_mu);
+  g_words_free.push_back(p);
+}
+
 }  // namespace tc
