@@ -285,11 +285,23 @@ __device__ __forceinline__ uint32_t wave_bitonic_sort(uint32_t x) {
   return x;
 }
 
+// Sorting network of 8 inputs (Batcher's odd-even merge sort, 19 comparators), ascending.
+__device__ __forceinline__ void sort8(uint32_t (&x)[8]) {
+  constexpr int kPairs[19][2] = {{0, 1}, {2, 3}, {4, 5}, {6, 7}, {0, 2}, {1, 3}, {4, 6}, {5, 7}, {1, 2}, {5, 6},
+                                 {0, 4}, {1, 5}, {2, 6}, {3, 7}, {2, 4}, {3, 5}, {1, 2}, {3, 4}, {5, 6}};
+#pragma unroll
+  for (int c = 0; c < 19; c++) {
+    const uint32_t a = x[kPairs[c][0]], b = x[kPairs[c][1]];
+    x[kPairs[c][0]] = a < b ? a : b;
+    x[kPairs[c][1]] = a < b ? b : a;
+  }
+}
+
 // Rows of at most 64 entries: each wave takes rpw consecutive rows (rpw a
 // power of two up to 64, smaller for small graphs so that their rows spread
-// over more waves); a row of one entry is copied by its lane, a row of 2..64
-// entries is sorted by the whole wave (one entry per lane). Longer rows are
-// left to k_seg_rows_wide and k_seg_rows_block.
+// over more waves); a row of 1..8 entries is sorted by its own lane in
+// registers, a row of 9..64 entries by the whole wave (one entry per lane).
+// Longer rows are left to k_seg_rows_wide and k_seg_rows_block.
 __global__ __launch_bounds__(kSegBlock) void k_seg_rows_wave(const uint64_t* __restrict__ keys,
                                                            const int64_t* __restrict__ off, int32_t n, int b, int rpw,
                                                            int32_t* __restrict__ adj, int32_t* __restrict__ src) {
@@ -304,11 +316,20 @@ __global__ __launch_bounds__(kSegBlock) void k_seg_rows_wave(const uint64_t* __r
       o = off[r];
       len = off[r + 1] - o;
     }
-    if (len == 1) {
-      adj[o] = static_cast<int32_t>(static_cast<uint32_t>(keys[o]) & mask);
-      src[o] = static_cast<int32_t>(r);
+    if (len >= 1 && len <= 8) {
+      uint32_t x[8];
+#pragma unroll
+      for (int e = 0; e < 8; e++) x[e] = e < len ? (static_cast<uint32_t>(keys[o + e]) & mask) : 0xFFFFFFFFu;
+      sort8(x);
+#pragma unroll
+      for (int e = 0; e < 8; e++) {
+        if (e < len) {
+          adj[o + e] = static_cast<int32_t>(x[e]);
+          src[o + e] = static_cast<int32_t>(r);
+        }
+      }
     }
-    uint64_t todo = __ballot(len >= 2 && len <= kWave);
+    uint64_t todo = __ballot(len > 8 && len <= kWave);
     while (todo) {
       const int l = __ffsll(static_cast<long long>(todo)) - 1;
       todo &= todo - 1;

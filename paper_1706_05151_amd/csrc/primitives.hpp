@@ -298,25 +298,37 @@ __host__ __device__ __forceinline__ uint32_t radix_digit_mask(int shift, int bit
 }
 
 // hist[p * kBins + d] += number of keys whose pass-p digit is d. The block's
-// LDS counts are kept in `copies` interleaved copies (lane L adds to copy
-// L % copies), so lanes with equal digits hit different banks.
+// LDS counts are kept in `copies` copies (lane L adds to copy L % copies),
+// each one word further along the banks than the last, so lanes with equal
+// digits in different copies hit different banks, and so do lanes of one copy
+// with digits that differ below 32.
 template <typename K>
 __global__ __launch_bounds__(kSortBlock) void k_sweep_hist(const K* __restrict__ keys, uint32_t N, int bit_lo,
                                                             int bit_hi, int passes, int copies,
                                                             uint32_t* __restrict__ hist) {
   constexpr int ITEMS = RadixItems<K>::value;
   constexpr int TILE = kSortBlock * ITEMS;
-  extern __shared__ uint32_t h[];  // passes * kBins * copies
-  const int nh = passes * static_cast<int>(kBins) * copies;
+  extern __shared__ uint32_t h[];  // copies * (passes * kBins + 1)
+  const int cstride = passes * static_cast<int>(kBins) + 1;
+  const int nh = cstride * copies;
   for (int i = threadIdx.x; i < nh; i += kSortBlock) h[i] = 0;
   __syncthreads();
   const uint32_t c = static_cast<uint32_t>(lane_id()) & static_cast<uint32_t>(copies - 1);
-  for (size_t base = static_cast<size_t>(blockIdx.x) * TILE; base < N; base += static_cast<size_t>(gridDim.x) * TILE) {
-    K k[ITEMS];
+  const size_t stride = static_cast<size_t>(gridDim.x) * TILE;
+  // the next tile's keys are loaded while this tile's digits are counted
+  K k[ITEMS], nk[ITEMS];
+  size_t base = static_cast<size_t>(blockIdx.x) * TILE;
+#pragma unroll
+  for (int i = 0; i < ITEMS; i++) {
+    const size_t idx = base + static_cast<size_t>(i) * kSortBlock + threadIdx.x;
+    if (idx < N) k[i] = keys[idx];
+  }
+  for (; base < N; base += stride) {
+    const size_t next = base + stride;
 #pragma unroll
     for (int i = 0; i < ITEMS; i++) {
-      const size_t idx = base + static_cast<size_t>(i) * kSortBlock + threadIdx.x;
-      if (idx < N) k[i] = keys[idx];
+      const size_t idx = next + static_cast<size_t>(i) * kSortBlock + threadIdx.x;
+      if (idx < N) nk[i] = keys[idx];
     }
     for (int p = 0; p < passes; p++) {
       const int shift = bit_lo + kRadixBits * p;
@@ -324,14 +336,16 @@ __global__ __launch_bounds__(kSortBlock) void k_sweep_hist(const K* __restrict__
 #pragma unroll
       for (int i = 0; i < ITEMS; i++) {
         const size_t idx = base + static_cast<size_t>(i) * kSortBlock + threadIdx.x;
-        if (idx < N) atomicAdd(&h[(p * kBins + (RadixKey<K>::bits(k[i], shift) & dm)) * copies + c], 1u);
+        if (idx < N) atomicAdd(&h[c * cstride + p * kBins + (RadixKey<K>::bits(k[i], shift) & dm)], 1u);
       }
     }
+#pragma unroll
+    for (int i = 0; i < ITEMS; i++) k[i] = nk[i];
   }
   __syncthreads();
   for (int i = threadIdx.x; i < passes * static_cast<int>(kBins); i += kSortBlock) {
     uint32_t t = 0;
-    for (int x = 0; x < copies; x++) t += h[i * copies + x];
+    for (int x = 0; x < copies; x++) t += h[x * cstride + i];
     if (t) atomicAdd(&hist[i], t);
   }
 }
@@ -561,8 +575,10 @@ K* radix_sort_pairs(K* keys, K* tmp, V*& vals, V* vtmp, size_t N, int bit_lo, in
   uint32_t* hist = words.get();
   uint32_t* ctrs = hist + static_cast<size_t>(passes) * kBins;
   uint32_t* fail_flag = fail_dev ? fail_dev : ctrs + passes;
-  const int copies = passes <= 8 ? 4 : 2;  // LDS: passes * kBins * copies words <= 64 KiB
-  k_sweep_hist<K><<<tiles < 2048u ? tiles : 2048u, kSortBlock, static_cast<size_t>(passes) * kBins * copies * 4, s>>>(
+  int copies = 4;  // LDS: copies * (passes * kBins + 1) words <= 64 KiB
+  while (copies > 1 && static_cast<size_t>(copies) * (static_cast<size_t>(passes) * kBins + 1) * 4 > 65536) copies >>= 1;
+  k_sweep_hist<K><<<tiles < 2048u ? tiles : 2048u, kSortBlock,
+                    static_cast<size_t>(copies) * (static_cast<size_t>(passes) * kBins + 1) * 4, s>>>(
       keys, static_cast<uint32_t>(N), bit_lo, bit_hi, passes, copies, hist);
   TC_LAUNCH_CHECK();
   k_sweep_starts<<<passes, kBins, 0, s>>>(hist);
