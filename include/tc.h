@@ -284,8 +284,9 @@ tc_status tc_build_csr_host(const int32_t* src, const int32_t* dst, int64_t num_
  * Input: off host int64[n+1] with off[0] = 0 and off[n] = m; adj int32[m]
  * (host, pinned for full copy speed, or device memory). Row r must hold
  * strictly ascending values in (r, n): a rank-space CSR such as
- * tc_graph_export_csr writes. The offsets are checked on the host and the
- * rows on the device before they are counted. A violation gives TC_E_INVAL,
+ * tc_graph_export_csr writes. The offsets at the ends of every partition and
+ * chunk are checked on the host, the offsets between them and the rows on the
+ * device, before anything is counted. A violation gives TC_E_INVAL,
  * as do off in device memory, NULL
  * arguments and budget_bytes < 4096; n above 2^31 - 2^25 gives TC_E_RANGE.
  * TC_E_NOMEM if one row alone does not fit

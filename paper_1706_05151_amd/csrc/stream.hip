@@ -35,41 +35,66 @@ constexpr int kBlock = 256;
 
 // Device bytes per entry and per row: a pivot partition holds adj, src, off,
 // the in-edge offsets and the classification arrays; a chunk adds its staged
-// copy, the two key buffers of the record sort, the records and their costs.
+// copy, the two key and two suffix-length buffers of the record sort, the
+// records and their costs.
 constexpr uint64_t kPivotEntryBytes = 8;
 constexpr uint64_t kPivotRowBytes = 48;
-constexpr uint64_t kChunkEntryBytes = 56;
+constexpr uint64_t kChunkEntryBytes = 64;
 constexpr uint64_t kChunkRowBytes = 56;
 constexpr int64_t kMaxRegionEntries = int64_t(1) << 31;  // record keys hold 32-bit entry indices
 
 // dst[r] = base + off[r] - off[0] for r in [0, rows]; flags offsets that decrease.
+// The host has checked only the region's end offsets (off[0] <= off[rows]);
+// an offset between them that breaks the order is clamped into the region, so
+// nothing reads outside it before the flag is seen.
 __global__ void k_rebase(const int64_t* __restrict__ off, int32_t rows, int64_t base, int64_t* __restrict__ dst,
                          uint32_t* __restrict__ bad) {
-  const int64_t o0 = off[0];
+  const int64_t o0 = off[0], span = off[rows] - o0;
   for (int32_t r = blockIdx.x * blockDim.x + threadIdx.x; r <= rows; r += gridDim.x * blockDim.x) {
-    dst[r] = base + off[r] - o0;
+    const int64_t x = off[r] - o0;
+    dst[r] = base + (x < 0 ? 0 : x > span ? span : x);
     if (r < rows && off[r + 1] < off[r]) atomicOr(bad, 1u);
   }
 }
 
 // Checks the rows [0, rows) of a region (global row of local row r: g0 + r):
 // entries strictly ascending, above their own row, below n. With src, writes
-// the local row (row_base + r) of every entry.
+// the local row (row_base + r) of every entry. Each wave takes groups of 32
+// consecutive rows and walks their entries 64 at a time, so a long row is
+// shared by the whole wave; an entry finds its row among the group's 33
+// offsets (lane i holds the start of row i) by a 5-step search over shuffles.
+// The offsets are non-decreasing (the caller checks them on the host).
 __global__ void k_check_rows(const int64_t* __restrict__ off, const int32_t* __restrict__ adj, int32_t rows,
                              int32_t row_base, int32_t g0, int32_t n, int32_t* __restrict__ src,
                              uint32_t* __restrict__ bad) {
-  for (int32_t r = blockIdx.x * blockDim.x + threadIdx.x; r < rows; r += gridDim.x * blockDim.x) {
-    const int64_t b = off[row_base + r], e = off[row_base + r + 1];
-    int32_t prev = g0 + r;
-    bool ok = true;
-    for (int64_t k = b; k < e; k++) {
-      const int32_t x = adj[k];
-      ok = ok && x > prev && x < n;
-      prev = x;
-      if (src) src[k] = row_base + r;
+  constexpr int kGroup = 32;
+  const int lane = lane_id();
+  const int64_t wave = (static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x) / kWave;
+  const int64_t nwaves = static_cast<int64_t>(gridDim.x) * blockDim.x / kWave;
+  bool ok = true;
+  for (int64_t r0 = wave * kGroup; r0 < rows; r0 += nwaves * kGroup) {
+    const int rl = static_cast<int>(rows - r0 < kGroup ? rows - r0 : kGroup);
+    const int64_t mine = lane <= rl ? off[row_base + r0 + lane] : 0;
+    const int64_t b = __shfl(mine, 0, kWave), e = __shfl(mine, rl, kWave);
+    for (int64_t base = b; base < e; base += kWave) {  // uniform: every lane takes part in the shuffles
+      const int64_t k = base + lane;
+      int row = 0;
+#pragma unroll
+      for (int step = kGroup / 2; step > 0; step >>= 1) {
+        const int cand = row + step;
+        const int64_t start = __shfl(mine, cand < rl ? cand : 0, kWave);
+        if (cand < rl && start <= k) row = cand;
+      }
+      const int64_t start = __shfl(mine, row, kWave);
+      if (k < e) {
+        const int32_t x = adj[k];
+        const int32_t prev = k == start ? g0 + static_cast<int32_t>(r0) + row : adj[k - 1];
+        ok = ok && x > prev && x < n;
+        if (src) src[k] = row_base + static_cast<int32_t>(r0) + row;
+      }
     }
-    if (!ok) atomicOr(bad, 2u);
   }
+  if (!ok) atomicOr(bad, 2u);
 }
 
 // Record keys of the chunk entries that point into V_j = [lo, hi):
@@ -93,6 +118,18 @@ struct PivotKey {
   }
 };
 
+// |N_v after u| of the record of entry e = e0 + i: the rest of e's row, read
+// in entry order (the records are then sorted with it as their value).
+struct SuffixLen {
+  const int64_t* off;
+  const int32_t* src;
+  int64_t e0;
+  __device__ uint32_t operator()(size_t i) const {
+    const int64_t e = e0 + static_cast<int64_t>(i);
+    return static_cast<uint32_t>(off[src[e] + 1] - e - 1);
+  }
+};
+
 struct Range {
   int32_t lo, hi;
   int64_t e0, e1;  // entries [off[lo], off[hi])
@@ -106,6 +143,7 @@ std::vector<Range> split_rows(const int64_t* off, int32_t lo, int32_t hi, uint64
     return eb * static_cast<uint64_t>(off[b] - off[a]) + rb * static_cast<uint64_t>(b - a);
   };
   while (lo < hi) {
+    if (off[lo + 1] < off[lo]) fail(TC_E_INVAL, "row offsets must not decrease");
     if (cost(lo, lo + 1) > cap || off[lo + 1] - off[lo] >= kMaxRegionEntries)
       fail(TC_E_NOMEM, "device budget too small for one adjacency row");
     int32_t a = lo + 1, b = hi;  // the largest end in [lo+1, hi] that fits
@@ -114,6 +152,9 @@ std::vector<Range> split_rows(const int64_t* off, int32_t lo, int32_t hi, uint64
       if (cost(lo, mid) <= cap && off[mid] - off[lo] < kMaxRegionEntries) a = mid;
       else b = mid - 1;
     }
+    // the ends of every range run from 0 to m without decreasing (the offsets inside a
+    // range are checked on the device)
+    if (off[a] < off[lo]) fail(TC_E_INVAL, "row offsets must not decrease");
     out.push_back(Range{lo, a, off[lo], off[a]});
     lo = a;
   }
@@ -143,13 +184,6 @@ struct CsrView {
     c.src.p = nullptr;
   }
 };
-
-uint32_t read_flags(const uint32_t* d, hipStream_t s) {
-  uint32_t h = 0;
-  TC_HIP(hipMemcpyAsync(&h, d, sizeof(h), hipMemcpyDeviceToHost, s));
-  TC_HIP(hipStreamSynchronize(s));
-  return h;
-}
 
 }  // namespace
 
@@ -202,6 +236,7 @@ uint64_t count_streamed(const int64_t* off, const int32_t* adj, int32_t n, int64
     if (freed) (void)hipEventDestroy(freed);
     (void)hipStreamDestroy(cs);
   };
+  HostWords hw(s);
   try {
     TC_HIP(hipEventCreateWithFlags(&loaded, hipEventDisableTiming));
     TC_HIP(hipEventCreateWithFlags(&freed, hipEventDisableTiming));
@@ -275,26 +310,34 @@ uint64_t count_streamed(const int64_t* off, const int32_t* adj, int32_t n, int64
         w.c.m = P.e1 - P.e0;
         e_begin = C.e0 - P.e0;
       }
-      if (read_flags(bad.get(), s)) fail(TC_E_INVAL, "rows must hold ascending ranks above their own row, below n");
-      // records (v,u) with u in V_j, sorted by u's local row
-      DevBuf<uint64_t> keys(ec, s), keys2(ec, s), cnt(1, s);
-      compact_if<uint64_t>(ec, IntoPivots{adj_d.get(), e_begin, P.lo, P.hi}, PivotKey{adj_d.get(), e_begin, P.lo},
-                           keys.get(), cnt.get(), s);
-      uint64_t mi = 0;
-      TC_HIP(hipMemcpyAsync(&mi, cnt.get(), sizeof(mi), hipMemcpyDeviceToHost, s));
+      // records (v,u) with u in V_j, sorted by u's local row (the row check is read back
+      // with their count, before anything indexes by an entry's value)
+      DevBuf<uint64_t> keys(ec, s), keys2(ec, s), cnt(2, s);
+      DevBuf<uint32_t> lens(ec, s), lens2(ec, s);
+      const IntoPivots into{adj_d.get(), e_begin, P.lo, P.hi};
+      compact_if<uint64_t>(ec, into, PivotKey{adj_d.get(), e_begin, P.lo}, keys.get(), cnt.get(), s);
+      compact_if<uint32_t>(ec, into, SuffixLen{off_d.get(), src_d.get(), e_begin}, lens.get(), cnt.get() + 1, s);
+      hw.get()[1] = 0;
+      TC_HIP(hipMemcpyAsync(hw.get(), cnt.get(), sizeof(uint64_t), hipMemcpyDeviceToHost, s));
+      TC_HIP(hipMemcpyAsync(hw.get() + 1, bad.get(), sizeof(uint32_t), hipMemcpyDeviceToHost, s));
       TC_HIP(hipStreamSynchronize(s));
+      if (hw[1]) fail(TC_E_INVAL, "rows must hold ascending ranks above their own row, below n");
+      const uint64_t mi = hw[0];
       if (mi == 0) continue;
       const int b = bits_for(np > 1 ? static_cast<uint64_t>(np - 1) : 1);
-      uint64_t* sk = radix_sort<uint64_t>(keys.get(), keys2.get(), mi, 32, 32 + b, s);
+      uint32_t* sl = lens.get();
+      uint64_t* sk = radix_sort_pairs<uint64_t, uint32_t>(keys.get(), keys2.get(), sl, lens2.get(), mi, 32, 32 + b, s);
       PivotPlan plan;
       DevBuf<int64_t> fin;
-      plan_records(w.c, plan, sk, nullptr, mi, fin, s);
+      plan_records(w.c, plan, sk, sl, mi, fin, s);
       keys.release();
       keys2.release();
+      lens.release();
+      lens2.release();
       plan_items(w.c, plan, fin.get(), mi, s, o);
       fin.release();
       launch_pivot(w.c, plan, ca, s, o);
-      TC_HIP(hipStreamSynchronize(s));  // the plan's arrays are freed on leaving this scope
+      plan.release_on(s);  // freed in stream order after the count: no host wait per pair
     }
     info[3] = h2d;
     unsigned long long T = 0;

@@ -723,8 +723,20 @@ def test_streamed_errors(tc):
             tc.count_streamed(good_off, np.array(adj, np.int32), n, 1 << 20)
     with pytest.raises(tc.TCError):  # offsets that do not start at 0
         tc.count_streamed(np.array([1, 2, 3, 3, 3], np.int64), np.array([1, 2, 3], np.int32), n, 1 << 20)
-    with pytest.raises(tc.TCError):  # decreasing offsets
+    with pytest.raises(tc.TCError) as ei:  # decreasing offsets inside a partition (seen on the device)
         tc.count_streamed(np.array([0, 2, 1, 3, 3], np.int64), np.array([1, 2, 3], np.int32), n, 1 << 20)
+    assert ei.value.status == tc.TC_E_INVAL
+    # decreasing offsets where a budget of about one row per range puts a range's end (seen on the
+    # host), and inside one range (seen on the device)
+    el = synth.er(2000, 6.0 / 1999, 21)  # rows of at most 7 entries
+    roff, radj, _ = _rank_csr(el)
+    k = int(np.argmax(np.diff(roff) > 2))
+    bad = roff.copy()
+    bad[k + 1] = bad[k] - 1  # row k ends before it starts
+    for budget in (1 << 20, 8 << 10):
+        with pytest.raises(tc.TCError) as ei:
+            tc.count_streamed(bad, radj, el.n, budget)
+        assert ei.value.status == tc.TC_E_INVAL
     with pytest.raises(tc.TCError):  # budget below the minimum
         tc.count_streamed(good_off, np.array([1, 2, 2], np.int32), n, 1000)
     el = synth.complete(400)  # rows of up to 399 entries: one row needs more than half of 16 KiB
