@@ -13,7 +13,10 @@
 //    block that is at least as large and at most 25 % larger;
 //  * a freed block gets an event recorded on the freeing stream; the stream
 //    that takes the block next waits on that event (stream-ordered reuse, no
-//    host synchronisation);
+//    host synchronisation). An allocation prefers a block freed on its own
+//    stream or one whose event has completed, so that work on one stream (a
+//    graph build) does not queue behind unrelated work on another (a batch of
+//    queries) just because that work freed the last block of the size;
 //  * cached bytes are bounded (kCacheLimit); above the bound the largest
 //    blocks go back to the driver, and an allocation that fails for lack of
 //    memory returns every cached block of its device and tries again.
@@ -39,15 +42,30 @@ constexpr int kClasses = 9;                    // 4 KiB, 8 KiB, ..., 1 MiB
 
 struct Block {
   size_t bytes;
-  hipEvent_t ready;  // recorded when the block was freed (null: never used)
+  hipEvent_t ready;             // recorded when the block was freed (null: never used)
+  hipStream_t freed_on = nullptr;  // the stream it was freed on
 };
+
+// Blocks are looked at this far back from the most recently freed when a
+// reusable one is searched for.
+constexpr int kReuseScan = 16;
+
+// A block the stream s can take without waiting on another stream's work.
+bool free_for(const Block& b, hipStream_t s) {
+  if (!b.ready || b.freed_on == s) return true;
+  const hipError_t e = hipEventQuery(b.ready);
+  if (e == hipSuccess) return true;
+  (void)hipGetLastError();  // hipErrorNotReady
+  return false;
+}
 
 struct DeviceCache {
   std::mutex mu;
   std::multimap<size_t, std::pair<void*, Block>> idle;  // by size
   std::unordered_map<void*, Block> live;
   size_t idle_bytes = 0;
-  std::vector<std::pair<void*, hipEvent_t>> small_free[kClasses];  // freed blocks of each size class
+  std::vector<std::pair<void*, Block>> small_free[kClasses];  // freed blocks of each size class
+  std::vector<void*> small_fresh[kClasses];                   // blocks of each size class never used
 };
 
 int small_class(size_t bytes) {
@@ -91,20 +109,33 @@ hipError_t malloc_or_drop(DeviceCache& c, void** p, size_t bytes) {
   return e;
 }
 
-// Caller holds c.mu. A block of size class k, waited for on s if it was used before.
+// Caller holds c.mu. A block of size class k for stream s: the latest freed block if s freed
+// it; else the first of the oldest freed blocks whose work is done; else a block never used
+// (a new slab is carved when none is left). Freed blocks that are still in use elsewhere are
+// passed over, not waited for; they are taken once their work is done.
 void* small_alloc(DeviceCache& c, int k, hipStream_t s) {
   const size_t cb = kSmallMin << k;
   auto& fl = c.small_free[k];
-  if (fl.empty()) {
+  auto take = [&](size_t i) {
+    const auto blk = fl[i];
+    fl[i] = fl.back();
+    fl.pop_back();
+    c.live.emplace(blk.first, Block{cb, blk.second.ready, nullptr});
+    return blk.first;
+  };
+  if (!fl.empty() && fl.back().second.freed_on == s) return take(fl.size() - 1);
+  for (size_t i = 0; i < fl.size() && i < static_cast<size_t>(kReuseScan); i++)
+    if (free_for(fl[i].second, s)) return take(i);
+  auto& fresh = c.small_fresh[k];
+  if (fresh.empty()) {
     void* slab = nullptr;
     TC_HIP(malloc_or_drop(c, &slab, kGranule));
-    for (size_t off = kGranule; off >= cb; off -= cb) fl.emplace_back(static_cast<char*>(slab) + off - cb, nullptr);
+    for (size_t off = kGranule; off >= cb; off -= cb) fresh.push_back(static_cast<char*>(slab) + off - cb);
   }
-  const auto blk = fl.back();
-  fl.pop_back();
-  if (blk.second) TC_HIP(hipStreamWaitEvent(s, blk.second, 0));
-  c.live.emplace(blk.first, Block{cb, blk.second});
-  return blk.first;
+  void* p = fresh.back();
+  fresh.pop_back();
+  c.live.emplace(p, Block{cb, nullptr, nullptr});
+  return p;
 }
 
 }  // namespace
@@ -117,12 +148,21 @@ void* dev_alloc(size_t bytes, hipStream_t s) {
   const size_t rb = (bytes + kGranule - 1) / kGranule * kGranule;
   auto it = c.idle.lower_bound(rb);
   if (it != c.idle.end() && it->first <= rb + rb / 4) {
-    void* p = it->second.first;
-    const Block b = it->second.second;
-    c.idle.erase(it);
+    // among the blocks that fit, one that s can take without waiting, else the smallest
+    auto pick = it;
+    int seen = 0;
+    for (auto j = it; j != c.idle.end() && j->first <= rb + rb / 4 && seen < kReuseScan; ++j, ++seen) {
+      if (free_for(j->second.second, s)) {
+        pick = j;
+        break;
+      }
+    }
+    void* p = pick->second.first;
+    const Block b = pick->second.second;
+    c.idle.erase(pick);
     c.idle_bytes -= b.bytes;
-    c.live.emplace(p, b);
-    TC_HIP(hipStreamWaitEvent(s, b.ready, 0));
+    c.live.emplace(p, Block{b.bytes, b.ready, nullptr});
+    if (b.freed_on != s) TC_HIP(hipStreamWaitEvent(s, b.ready, 0));
     return p;
   }
   void* p = nullptr;
@@ -134,7 +174,7 @@ void* dev_alloc(size_t bytes, hipStream_t s) {
     (void)hipFree(p);
     TC_HIP(e);
   }
-  c.live.emplace(p, Block{rb, ev});
+  c.live.emplace(p, Block{rb, ev, nullptr});
   return p;
 }
 
@@ -156,7 +196,8 @@ void dev_free(void* p, hipStream_t s) {
       (void)hipGetLastError();
       (void)hipDeviceSynchronize();
     }
-    c.small_free[small_class(b.bytes)].emplace_back(p, b.ready);
+    b.freed_on = s;
+    c.small_free[small_class(b.bytes)].emplace_back(p, b);
     return;
   }
   if (hipEventRecord(b.ready, s) != hipSuccess) {
@@ -167,6 +208,7 @@ void dev_free(void* p, hipStream_t s) {
     (void)hipFree(p);
     return;
   }
+  b.freed_on = s;
   c.idle.emplace(b.bytes, std::make_pair(p, b));
   c.idle_bytes += b.bytes;
   while (c.idle_bytes > kCacheLimit) drop_idle(c, std::prev(c.idle.end()));

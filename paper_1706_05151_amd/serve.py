@@ -126,16 +126,22 @@ class Registry:
         return footprint_bytes(el.n, el.num_edges)
 
     def _evict_for(self, need: int):
-        for key in list(self.graphs.keys()):
-            if self.used + need <= self.budget:
-                return True
+        """Evict unpinned graphs, least recently used first, until need fits; False if it cannot."""
+        victims, freed = [], 0
+        for key in self.graphs:
+            if self.used - freed + need <= self.budget:
+                break
             if self.pinned[key] > 0:
                 continue
-            g = self.graphs.pop(key)
-            g.close()
+            victims.append(key)
+            freed += self.sizes[key]
+        if self.used - freed + need > self.budget:
+            return False
+        for key in victims:
+            self.graphs.pop(key).close()
             self.used -= self.sizes.pop(key)
             self.evictions += 1
-        return self.used + need <= self.budget
+        return True
 
     def peek(self, key) -> Optional[tc.Graph]:
         """The resident graph of key, if any, without counting it as a use."""
@@ -148,11 +154,20 @@ class Registry:
             self.graphs.move_to_end(key)
         return g
 
-    def reserve(self, key) -> bool:
-        """Make room for the estimate of key and charge it; False if the budget is held by pinned graphs."""
+    def reserve(self, key, protect=None) -> bool:
+        """Make room for the estimate of key and charge it; False if the budget is held by pinned
+        graphs. protect (optional) is called only when room must be made, and returns graphs that
+        are then kept as if pinned."""
         need = self.estimate(key)
-        if not self._evict_for(need):
-            return False
+        if self.used + need > self.budget:
+            keep = list(protect()) if protect is not None else []
+            self.pin(keep)
+            try:
+                ok = self._evict_for(need)
+            finally:
+                self.unpin(keep)
+            if not ok:
+                return False
         self.reserved[key] = need
         self.used += need
         return True
@@ -279,6 +294,7 @@ class _Builder:
         self.reg = registry
         self.todo: "queue.Queue" = queue.Queue()
         self.done: "queue.Queue" = queue.Queue()
+        self.spans: List[tuple] = []  # (key, start, end) of every build, perf_counter seconds
         self.device = torch.cuda.current_device()
         self.threads = [threading.Thread(target=self._run, daemon=True) for _ in range(threads)]
         for t in self.threads:
@@ -295,8 +311,10 @@ class _Builder:
                 return
             key, base = item
             try:
+                t0 = time.perf_counter()
                 with torch.cuda.stream(stream):
                     g = self.reg.build(key, stream, base)
+                self.spans.append((key, t0, time.perf_counter()))
                 self.done.put((key, g, ""))
             except Exception as e:  # reported with the requests that wait for it
                 self.done.put((key, None, getattr(e, "status", None) and tc.lib().tc_status_str(e.status).decode()
@@ -342,10 +360,15 @@ class Server:
         self.batches = 0
         self.batch_sizes: List[int] = []
         self.queued: "collections.OrderedDict[object, List[Request]]" = collections.OrderedDict()
+        self.ready: "collections.OrderedDict[object, None]" = collections.OrderedDict()  # queued keys seen resident
         self.building: Dict[object, object] = {}  # key being built -> graph pinned as its base (or None)
         self.nbuilders = builders
         self.max_building = 2 * builders
         self.builder: Optional[_Builder] = None
+        self.timeline: List[tuple] = []  # sampled state, one row per 50 ms of the run
+        self.build_spans: List[tuple] = []  # (key, start s, end s) of every build of the last run
+        self.started = 0                 # builds started
+        self.blocked = 0                 # build starts refused for lack of room
 
     # ------------------------------------------------------------ building
     @staticmethod
@@ -369,21 +392,17 @@ class Server:
             return (key[0],)
         return ()
 
-    def _try_reserve(self, need, protect) -> bool:
-        self.reg.pin(protect)
-        try:
-            return self.reg.reserve(need)
-        finally:
-            self.reg.unpin(protect)
-
     def _start_builds(self, clock) -> bool:
-        """Start builds for the oldest queues; True if the oldest queue's key can never fit."""
+        """Start builds for the oldest queues; True if the oldest queue's key can never fit.
+        Only the queues before the last one started are visited (those resident or building,
+        then the ones whose build starts), and the graphs every queue needs are listed only
+        when a reservation has to evict."""
         if len(self.building) >= self.max_building:
             return False
-        uses_all = [k for key in self.queued for k in self._uses(key)]
+        uses_all = lambda: [k for key in self.queued for k in self._uses(key)]  # noqa: E731
         older: List[object] = []
         head = True  # still at the oldest queue that needs a build
-        for key in list(self.queued):
+        for key in self.queued:
             need = self._need(key)
             if need is None or need in self.building:
                 older.extend(self._uses(key))
@@ -391,13 +410,15 @@ class Server:
             base = need[0] if isinstance(need, tuple) else None
             if base is not None:
                 self.reg.pinned[base] += 1  # the sample is drawn from it
-            ok = self._try_reserve(need, uses_all) or (head and self._try_reserve(need, older))
+            ok = self.reg.reserve(need, uses_all) or (head and self.reg.reserve(need, lambda: older))
             if not ok:
+                self.blocked += 1
                 if base is not None:
                     self.reg.pinned[base] -= 1
                 return head and not self.inflight and not self.building and \
                     not any(self.reg.peek(k) is not None for k in self.queued)
             self.building[need] = base
+            self.started += 1
             self.builder.todo.put((need, self.reg.peek(base) if base is not None else None))
             head = False
             older.extend(self._uses(key))
@@ -420,6 +441,8 @@ class Server:
                 self.reg.pinned[base] -= 1
             if g is not None:
                 self.reg.install(key, g)
+                if key in self.queued:
+                    self.ready[key] = None
                 continue
             self.reg.cancel(key)
             # the requests on key fail, and so do those on samples drawn from it
@@ -428,22 +451,23 @@ class Server:
                     self.answers[r.rid] = Answer(r.rid, r.kind, None, clock(), err)
 
     def _take(self) -> List[Request]:
-        """The oldest queued requests on resident keys, at most max_batch."""
+        """Queued requests on resident keys, at most max_batch, the keys in the order they
+        became resident (only keys seen resident are visited)."""
         take: List[Request] = []
-        done: List[object] = []
-        for key, reqs in self.queued.items():
-            if self.reg.peek(key) is None:
+        for key in list(self.ready):
+            reqs = self.queued.get(key)
+            if reqs is None or self.reg.peek(key) is None:  # launched already, or evicted since
+                del self.ready[key]
                 continue
             room = self.max_batch - len(take)
             take.extend(reqs[:room])
             if room >= len(reqs):
-                done.append(key)
+                del self.queued[key]
+                del self.ready[key]
             else:
                 del reqs[:room]
             if len(take) >= self.max_batch:
                 break
-        for key in done:
-            del self.queued[key]
         return take
 
     # ------------------------------------------------------------ batching
@@ -539,12 +563,26 @@ class Server:
         free_streams = list(self.streams)
         self.builder = _Builder(self.reg, self.nbuilders)
         changed = True
+        next_sample = 0.0
         try:
             while pending or self.queued or self.inflight or self.building:
                 now = clock()
+                if now >= next_sample:
+                    next_sample = now + 0.05
+                    self.timeline.append((round(now, 3), self.started, self.reg.builds, len(self.queued),
+                                          sum(len(v) for v in self.queued.values()), len(self.building),
+                                          len(self.inflight), self.reg.used, sum(self.reg.reserved.values()),
+                                          self.reg.evictions, self.blocked))
                 while pending and pending[0].arrival <= now:
                     r = pending.popleft()
-                    self.queued.setdefault(self._key(r), []).append(r)
+                    key = self._key(r)
+                    q = self.queued.get(key)
+                    if q is None:
+                        self.queued[key] = [r]
+                        if self.reg.peek(key) is not None:
+                            self.ready[key] = None
+                    else:
+                        q.append(r)
                     changed = True
                 if self._collect_builds(clock):
                     changed = True
@@ -578,6 +616,7 @@ class Server:
                         time.sleep(min(wait, 0.002))
         finally:
             self.builder.close()
+            self.build_spans = [(k, a - start, b - start) for k, a, b in self.builder.spans]
             self.builder = None
         return self.answers
 
@@ -662,6 +701,25 @@ def latency_stats(trace: List[Request], answers: Dict[int, Answer], wall: float)
             "req_per_s": len(trace) / wall,
             "p50_ms": float(np.percentile(lat, 50) * 1e3), "p99_ms": float(np.percentile(lat, 99) * 1e3),
             "mean_ms": float(lat.mean() * 1e3)}
+
+
+def tail_breakdown(trace: List[Request], answers: Dict[int, Answer], sizes=None, worst: int = 8):
+    """Where the latency tail sits: p99 per request kind, p99 over arrivals after the
+    first second and the slowest requests (kind, graph, its n, arrival s, latency ms)."""
+    lat = np.array([answers[r.rid].done - r.arrival for r in trace])
+    arr = np.array([r.arrival for r in trace])
+    out = {}
+    for kind in (COUNT, CLUSTER, SPARSE):
+        sel = np.array([r.kind == kind for r in trace])
+        if sel.any():
+            out[f"p99_ms_{kind}"] = float(np.percentile(lat[sel], 99) * 1e3)
+    late = arr >= 1.0
+    if late.any():
+        out["p99_ms_after_first_s"] = float(np.percentile(lat[late], 99) * 1e3)
+    slow = np.argsort(-lat)[:worst]
+    out["slowest"] = [[trace[i].kind, trace[i].graph, int(sizes[trace[i].graph]) if sizes is not None else None,
+                       round(float(arr[i]), 3), round(float(lat[i] * 1e3), 1)] for i in slow]
+    return out
 
 
 def same_answer(a: Answer, b: Answer) -> bool:

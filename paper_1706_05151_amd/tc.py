@@ -83,6 +83,9 @@ def lib():
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is missing: build it with __graft_entry__.build() "
                           "or python paper_1706_05151_amd/build_lib.py")
+    # PyTorch's HIP runtime is loaded first so that the library shares it (loaded the other
+    # way round, a first call such as tc_set_option left no device visible to later calls)
+    import torch  # noqa: F401
     L = ctypes.CDLL(LIB_PATH)
     for name, (args, res) in SIGNATURES.items():
         f = getattr(L, name)

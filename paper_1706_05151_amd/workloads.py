@@ -121,6 +121,7 @@ def run_serve(args):
     specs = synth.pool_specs(1024, 5)
     els = [s.make() for s in specs]
     m_sum = sum(e.num_edges for e in els)
+    sizes = np.array([e.n for e in els])
     _log(f"[serve] pool of {len(els)} graphs, {m_sum} edge records, generated in {time.perf_counter() - t0:.1f} s")
     trace = serve.make_trace(len(els), rate, duration, 5)
     # the pool's edge lists in pinned host memory, shared by every run below (untimed)
@@ -151,7 +152,18 @@ def run_serve(args):
         wall = time.perf_counter() - t0
         st = serve.latency_stats(reqs, ans, wall)
         st.update({"batches": srv.batches, "mean_batch": float(np.mean(srv.batch_sizes)), "builds": reg.builds,
-                   "evictions": reg.evictions, "peak_held_gib": reg.peak / 2**30})
+                   "evictions": reg.evictions, "peak_held_gib": reg.peak / 2**30,
+                   "tail": serve.tail_breakdown(reqs, ans, sizes)})
+        st["timeline_head"] = srv.timeline[:70]  # (s, started, built, queued keys, queued requests, building,
+        # batches in flight, bytes held, bytes reserved, evictions, refused build starts)
+        spans = srv.build_spans
+        if spans:
+            d = np.array([b - a for _, a, b in spans]) * 1e3
+            first = [b - a for _, a, b in spans if a < 1.0]
+            busy = sum(b - a for _, a, b in spans if a < 1.0)
+            st["build_spans"] = {"count": len(spans), "mean_ms": float(d.mean()), "p50_ms": float(np.percentile(d, 50)),
+                                 "p99_ms": float(np.percentile(d, 99)), "max_ms": float(d.max()),
+                                 "first_s_count": len(first), "first_s_builder_busy_s": busy}
         reg.close()
         return ans, st
 
@@ -161,7 +173,7 @@ def run_serve(args):
         t0 = time.perf_counter()
         ans = serve.serve_fifo(reg, reqs, t0)
         st = serve.latency_stats(reqs, ans, time.perf_counter() - t0)
-        st.update({"builds": reg.builds, "evictions": reg.evictions})
+        st.update({"builds": reg.builds, "evictions": reg.evictions, "tail": serve.tail_breakdown(reqs, ans, sizes)})
         reg.close()
         return ans, st
 
