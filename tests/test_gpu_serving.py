@@ -60,6 +60,62 @@ def test_multi_count_matches_single(tcm):
         g.close()
 
 
+def test_concurrent_streams_share_the_block_cache(tcm):
+    """Builds, samples and per-node counts on four threads with streams of their own,
+    the graphs freed as soon as they are counted: blocks freed on one stream and taken
+    on another are reused only once their work is done. Every result equals the one
+    computed alone on one stream."""
+    import threading
+
+    import torch
+
+    els = [s.make() for s in synth.pool_specs(48, 11, n_lo=1e3, n_hi=2e5)]
+    ref = []
+    for e in els:
+        with tcm.Graph.build(torch.from_numpy(e.src).cuda(), torch.from_numpy(e.dst).cuda(), e.n) as g:
+            T, t = g.count_per_node()
+            with g.sparsify_build(0.3, 7) as h:
+                ref.append((T, t.cpu().numpy(), h.count()))
+    say(f"[streams] reference of {len(els)} graphs done")
+    host = [(torch.from_numpy(e.src).pin_memory(), torch.from_numpy(e.dst).pin_memory()) for e in els]
+    got = [None] * len(els)
+    errors = []
+
+    def work(k):
+        try:
+            torch.cuda.set_device(0)
+            st = torch.cuda.Stream()
+            with torch.cuda.stream(st):
+                for rep in range(3):
+                    for i in range(k, len(els), 4):
+                        src = host[i][0].to("cuda", non_blocking=True)
+                        dst = host[i][1].to("cuda", non_blocking=True)
+                        g = tcm.Graph.build(src, dst, els[i].n, st)
+                        T, t = g.count_per_node(stream=st)
+                        h = g.sparsify_build(0.3, 7, st)
+                        Ts = h.count(st)
+                        h.close()
+                        g.close()  # freed at once: another stream may take these blocks next
+                        st.synchronize()
+                        got[i] = (T, t.cpu().numpy(), Ts)
+        except Exception as ex:  # reported below
+            errors.append(ex)
+
+    threads = [threading.Thread(target=work, args=(k,)) for k in range(4)]
+    for th in threads:
+        th.start()
+    for th in threads:
+        th.join()
+    assert not errors, errors
+    for i, (r, x) in enumerate(zip(ref, got)):
+        assert x is not None and x[0] == r[0] and x[2] == r[2], i
+        np.testing.assert_array_equal(x[1], r[1])
+    # the totals against the oracle for a few of them
+    for i in (0, 17, 47):
+        e = els[i]
+        assert ref[i][0] == oracle.solve(e.src, e.dst, e.n, per_node=False).T
+
+
 def test_sparsify_build_matches_sparsify_count(tcm):
     import torch
 
