@@ -38,8 +38,10 @@ __global__ __launch_bounds__(kBlock) void k_count_plain(const int64_t* __restric
   unsigned long long cnt = 0;
   for (uint64_t e = static_cast<uint64_t>(blockIdx.x) * blockDim.x + threadIdx.x; e < m;
        e += static_cast<uint64_t>(gridDim.x) * blockDim.x) {
+    // N_u holds only ranks above u, and u sits at entry e of the ascending row v,
+    // so only the suffix of N_v after e can meet N_u
     const int32_t v = src[e], u = adj[e];
-    int64_t i = off[v], ie = off[v + 1], j = off[u], je = off[u + 1];
+    int64_t i = static_cast<int64_t>(e) + 1, ie = off[v + 1], j = off[u], je = off[u + 1];
     while (i < ie && j < je) {
       const int32_t a = adj[i], b = adj[j];
       cnt += (a == b);
