@@ -136,10 +136,9 @@ uint64_t count_total(tc_graph* g, Csr& c, hipStream_t s, unsigned long long* t_r
     a.total = tot.get();
     a.t_rank = t_rank;
     std::lock_guard<std::mutex> lk(g->mu);
-    count_pivot(c, a, s, o);
-  } else if (o.kernel == 1 || (o.kernel == 0 && c.plan.ready && c.plan.probes < 16ull * static_cast<uint64_t>(c.m))) {
-    // plain merge for graphs with few wedge checks per edge (near-uniform low degrees), where the
-    // persistent pivot kernel's staging overhead exceeds the merge work
+    if (plain_is_best(c, o)) count_plain_mode(c, a, s);
+    else count_pivot(c, a, s, o);
+  } else if (plain_is_best(c, o)) {
     count_plain(c, tot.get(), s);
   } else {
     CountArgs a;
@@ -483,7 +482,9 @@ tc_status tc_list(tc_graph* g, void* stream, int32_t* tri_dev, int64_t cap, int6
     a.cap = static_cast<int64_t>(T);
     {
       std::lock_guard<std::mutex> lk(g->mu);
-      count_pivot(g->csr, a, s, get_options());
+      const Options o = get_options();
+      if (plain_is_best(g->csr, o)) count_plain_mode(g->csr, a, s);
+      else count_pivot(g->csr, a, s, o);
     }
     unsigned long long written = 0;
     TC_HIP(hipMemcpyAsync(&written, cur.get(), sizeof(written), hipMemcpyDeviceToHost, s));

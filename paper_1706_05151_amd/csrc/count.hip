@@ -53,6 +53,56 @@ __global__ __launch_bounds__(kBlock) void k_count_plain(const int64_t* __restric
   if (lane_id() == 0 && cnt) atomicAdd(total, cnt);
 }
 
+// Per-node counts (MODE kCountPerNode) or the triangle list (kCountList) by the
+// same merge: every w in N_v ∩ N_u adds one to t_w and, once per edge, the
+// edge's matches to t_v and t_u (rank space); or the triangle goes to tri as
+// caller ids, ascending, at a slot taken from the cursor (slots past cap are
+// dropped, the cursor still counts them).
+template <int MODE>
+__global__ __launch_bounds__(kBlock) void k_plain_mode(const int64_t* __restrict__ off, const int32_t* __restrict__ adj,
+                                                       const int32_t* __restrict__ src, uint64_t m,
+                                                       unsigned long long* __restrict__ total,
+                                                       unsigned long long* __restrict__ t_rank,
+                                                       const int32_t* __restrict__ order, int32_t* __restrict__ tri,
+                                                       unsigned long long* __restrict__ cursor, int64_t cap) {
+  unsigned long long cnt = 0;
+  for (uint64_t e = static_cast<uint64_t>(blockIdx.x) * blockDim.x + threadIdx.x; e < m;
+       e += static_cast<uint64_t>(gridDim.x) * blockDim.x) {
+    const int32_t v = src[e], u = adj[e];
+    int64_t i = static_cast<int64_t>(e) + 1, ie = off[v + 1], j = off[u], je = off[u + 1];
+    unsigned long long here = 0;
+    while (i < ie && j < je) {
+      const int32_t a = adj[i], b = adj[j];
+      if (a == b) {
+        here++;
+        if (MODE == kCountPerNode) {
+          atomicAdd(&t_rank[a], 1ull);
+        } else {
+          int32_t x = order[v], y = order[u], z = order[a], t;
+          if (x > y) { t = x; x = y; y = t; }
+          if (y > z) { t = y; y = z; z = t; }
+          if (x > y) { t = x; x = y; y = t; }
+          const unsigned long long pos = atomicAdd(cursor, 1ull);
+          if (static_cast<int64_t>(pos) < cap) {
+            tri[3 * pos + 0] = x;
+            tri[3 * pos + 1] = y;
+            tri[3 * pos + 2] = z;
+          }
+        }
+      }
+      i += (a <= b);
+      j += (b <= a);
+    }
+    if (MODE == kCountPerNode && here) {
+      atomicAdd(&t_rank[v], here);
+      atomicAdd(&t_rank[u], here);
+    }
+    cnt += here;
+  }
+  cnt = wave_sum(cnt);
+  if (lane_id() == 0 && cnt && total) atomicAdd(total, cnt);
+}
+
 // W = sum_e (dhat_v + dhat_u) and P = sum_v C(dhat_v, 2)
 __global__ __launch_bounds__(kBlock) void k_work(const int64_t* __restrict__ off, const int32_t* __restrict__ adj,
                                                   const int32_t* __restrict__ src, uint64_t m,
@@ -242,6 +292,26 @@ void count_plain(const Csr& c, unsigned long long* total, hipStream_t s) {
   if (c.m == 0) return;
   const unsigned grid = grid_for(static_cast<uint64_t>(c.m), kBlock, static_cast<unsigned>(device_cus()) * 64u);
   k_count_plain<<<grid, kBlock, 0, s>>>(c.off.p, c.adj.p, c.src.p, static_cast<uint64_t>(c.m), total);
+  TC_LAUNCH_CHECK();
+}
+
+bool plain_is_best(const Csr& c, const Options& o) {
+  // graphs with few wedge checks per edge (near-uniform low degrees), where the persistent
+  // pivot kernel's staging costs more than the merge work
+  return o.kernel == 1 || (o.kernel == 0 && c.plan.ready && c.plan.probes < 16ull * static_cast<uint64_t>(c.m));
+}
+
+void count_plain_mode(const Csr& c, const CountArgs& a, hipStream_t s) {
+  if (c.m == 0) return;
+  const unsigned grid = grid_for(static_cast<uint64_t>(c.m), kBlock, static_cast<unsigned>(device_cus()) * 64u);
+  if (a.mode == kCountPerNode)
+    k_plain_mode<kCountPerNode><<<grid, kBlock, 0, s>>>(c.off.p, c.adj.p, c.src.p, static_cast<uint64_t>(c.m), a.total,
+                                                        a.t_rank, nullptr, nullptr, nullptr, 0);
+  else if (a.mode == kCountList)
+    k_plain_mode<kCountList><<<grid, kBlock, 0, s>>>(c.off.p, c.adj.p, c.src.p, static_cast<uint64_t>(c.m), a.total,
+                                                     nullptr, a.order, a.tri, a.cursor, a.cap);
+  else
+    fail(TC_E_INVAL, "plain merge: mode must be per-node counts or listing");
   TC_LAUNCH_CHECK();
 }
 
