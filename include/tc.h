@@ -388,7 +388,10 @@ tc_status tc_batch_size(const tc_graph* g, int32_t* num_graphs);
 
 /*
  * Per-graph totals T_dev[num_graphs] (device uint64) and, if t_dev != NULL,
- * per-node counts t_dev[sum n] in one launch sequence. Does not synchronise
+ * per-node counts t_dev[sum n] in one launch sequence. The kernel follows
+ * TC_OPT_KERNEL: the plain merge (one thread per oriented edge) for 1, or for
+ * 0 when the batch makes fewer than 16 probes per edge; the pivot kernel
+ * otherwise. Does not synchronise
  * `stream` (results are ready when the stream reaches this point), so the call
  * can be captured in a HIP graph. Scratch memory comes from the graph's own
  * workspace: calls on one batch graph must not overlap. Uses the work plan as

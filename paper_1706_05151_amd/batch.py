@@ -6,8 +6,9 @@ The union keeps each graph's vertices contiguous (graph-major degree ranks), so
 per-graph totals come out of the same launch (each work item's pivot belongs to
 exactly one graph) and per-node counts are per-graph slices of one array.
 The autotuner rebuilds the batch's work plan under each candidate partitioner
-setting (options of the C ABI), times the batched count it deploys and keeps
-the fastest; settings change speed only, never results.
+setting (options of the C ABI, the choice between the pivot kernel and one
+thread per edge among them), times the batched count it deploys and keeps the
+fastest; settings change speed only, never results.
 """
 from __future__ import annotations
 
@@ -22,12 +23,14 @@ from . import tc
 
 AUTOTUNE_FILE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "autotune.json")
 
-# candidate (hub_dhat, item_work, blocks_per_cu, hub_bucket_load)
+# candidate (hub_dhat, item_work, blocks_per_cu, hub_bucket_load, kernel): the pivot kernel's
+# block/wave split, item size, occupancy and hash load, or one thread per edge (kernel 1)
 DEFAULT_CANDIDATES = [
-    (256, 0, 4, 2), (128, 0, 4, 2), (256, 16384, 4, 2), (256, 65536, 4, 2),
-    (128, 16384, 4, 2), (64, 4096, 4, 2), (32, 4096, 4, 2), (256, 0, 3, 1),
+    (256, 0, 4, 2, 2), (128, 0, 4, 2, 2), (256, 16384, 4, 2, 2), (256, 65536, 4, 2, 2),
+    (128, 16384, 4, 2, 2), (64, 4096, 4, 2, 2), (32, 4096, 4, 2, 2), (256, 0, 3, 1, 2),
+    (256, 0, 4, 2, 1),
 ]
-_KEYS = (tc.OPT_HUB_DHAT, tc.OPT_ITEM_WORK, tc.OPT_BLOCKS_PER_CU, tc.OPT_HUB_BUCKET_LOAD)
+_KEYS = (tc.OPT_HUB_DHAT, tc.OPT_ITEM_WORK, tc.OPT_BLOCKS_PER_CU, tc.OPT_HUB_BUCKET_LOAD, tc.OPT_KERNEL)
 
 
 def pack(edge_lists: Sequence) -> Dict[str, np.ndarray]:
@@ -158,7 +161,7 @@ def autotune(bc: BatchCounter, candidates=None, reps: int = 3, key: Optional[str
             except (OSError, ValueError):
                 data = {}
         data[key] = {"options": best["options"], "ms": best["ms"],
-                     "keys": ["hub_dhat", "item_work", "blocks_per_cu", "hub_bucket_load"]}
+                     "keys": ["hub_dhat", "item_work", "blocks_per_cu", "hub_bucket_load", "kernel"]}
         with open(AUTOTUNE_FILE, "w") as f:
             json.dump(data, f, indent=1, sort_keys=True)
     return best, table

@@ -787,7 +787,9 @@ tc_status tc_batch_count(tc_graph* g, void* stream, uint64_t* T_dev, uint64_t* t
       a.t_rank = ws + 3;
       fill_u64(a.t_rank, static_cast<size_t>(g->n), 0ull, s);
     }
-    count_pivot(g->csr, a, s, get_options(), /*allow_rebuild=*/false);
+    const Options o = get_options();
+    if (plain_is_best(g->csr, o)) count_plain_mode(g->csr, a, s);  // one thread per edge, no work plan
+    else count_pivot(g->csr, a, s, o, /*allow_rebuild=*/false);
     if (t_dev && g->n > 0) {
       k_scatter_by_order<<<grid_for(g->n, kBlock, 65536), kBlock, 0, s>>>(a.t_rank, g->order.p, g->n,
                                                                           reinterpret_cast<unsigned long long*>(t_dev));

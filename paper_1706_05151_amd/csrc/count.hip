@@ -53,50 +53,79 @@ __global__ __launch_bounds__(kBlock) void k_count_plain(const int64_t* __restric
   if (lane_id() == 0 && cnt) atomicAdd(total, cnt);
 }
 
-// Per-node counts (MODE kCountPerNode) or the triangle list (kCountList) by the
-// same merge: every w in N_v ∩ N_u adds one to t_w and, once per edge, the
-// edge's matches to t_v and t_u (rank space); or the triangle goes to tri as
-// caller ids, ascending, at a slot taken from the cursor (slots past cap are
-// dropped, the cursor still counts them).
+// dst[key] += val summed over each run of equal keys among the lanes of a wave
+// (keys ascend with the lane; lanes with valid false take no part): one atomic
+// per run, by its last lane, instead of one per lane on the same address.
+__device__ __forceinline__ void run_add(unsigned long long* dst, int32_t key, unsigned long long val, bool valid) {
+  const int lane = lane_id();
+  const int32_t k = valid ? key : -1;
+  unsigned long long x = valid ? val : 0ull;
+#pragma unroll
+  for (int d = 1; d < kWave; d <<= 1) {
+    const unsigned long long y = __shfl_up(x, d, kWave);
+    const int32_t ky = __shfl_up(k, d, kWave);
+    if (lane >= d && ky == k) x += y;  // keys ascend: an equal key d lanes back means one run
+  }
+  const int32_t next = __shfl_down(k, 1, kWave);
+  const bool last = lane == kWave - 1 || next != k;
+  if (valid && last && x) atomicAdd(&dst[k], x);
+}
+
+// The same merge for totals per graph of a batch (MODE kCountTotal), per-node
+// counts (kCountPerNode) or the triangle list (kCountList): every w in
+// N_v ∩ N_u adds one to t_w and, once per edge, the edge's matches to t_v and
+// t_u (rank space); or the triangle goes to tri as caller ids, ascending, at a
+// slot taken from the cursor (slots past cap are dropped, the cursor still
+// counts them). With per_graph, each edge's matches also go to the total of
+// the graph its source belongs to (graph_of_rank, or graph 0). The lanes of a
+// wave take consecutive edges, so their sources (and graphs) ascend and the
+// additions to t_v and to the graph totals are summed over runs first.
 template <int MODE>
 __global__ __launch_bounds__(kBlock) void k_plain_mode(const int64_t* __restrict__ off, const int32_t* __restrict__ adj,
                                                        const int32_t* __restrict__ src, uint64_t m,
                                                        unsigned long long* __restrict__ total,
                                                        unsigned long long* __restrict__ t_rank,
                                                        const int32_t* __restrict__ order, int32_t* __restrict__ tri,
-                                                       unsigned long long* __restrict__ cursor, int64_t cap) {
+                                                       unsigned long long* __restrict__ cursor, int64_t cap,
+                                                       unsigned long long* __restrict__ per_graph,
+                                                       const int32_t* __restrict__ graph_of_rank) {
   unsigned long long cnt = 0;
-  for (uint64_t e = static_cast<uint64_t>(blockIdx.x) * blockDim.x + threadIdx.x; e < m;
-       e += static_cast<uint64_t>(gridDim.x) * blockDim.x) {
-    const int32_t v = src[e], u = adj[e];
-    int64_t i = static_cast<int64_t>(e) + 1, ie = off[v + 1], j = off[u], je = off[u + 1];
+  for (uint64_t base = static_cast<uint64_t>(blockIdx.x) * blockDim.x; base < m;
+       base += static_cast<uint64_t>(gridDim.x) * blockDim.x) {
+    const uint64_t e = base + threadIdx.x;
+    const bool valid = e < m;  // every lane of the wave runs the same iterations
+    int32_t v = 0;
     unsigned long long here = 0;
-    while (i < ie && j < je) {
-      const int32_t a = adj[i], b = adj[j];
-      if (a == b) {
-        here++;
-        if (MODE == kCountPerNode) {
-          atomicAdd(&t_rank[a], 1ull);
-        } else {
-          int32_t x = order[v], y = order[u], z = order[a], t;
-          if (x > y) { t = x; x = y; y = t; }
-          if (y > z) { t = y; y = z; z = t; }
-          if (x > y) { t = x; x = y; y = t; }
-          const unsigned long long pos = atomicAdd(cursor, 1ull);
-          if (static_cast<int64_t>(pos) < cap) {
-            tri[3 * pos + 0] = x;
-            tri[3 * pos + 1] = y;
-            tri[3 * pos + 2] = z;
+    if (valid) {
+      v = src[e];
+      const int32_t u = adj[e];
+      int64_t i = static_cast<int64_t>(e) + 1, ie = off[v + 1], j = off[u], je = off[u + 1];
+      while (i < ie && j < je) {
+        const int32_t a = adj[i], b = adj[j];
+        if (a == b) {
+          here++;
+          if (MODE == kCountPerNode) {
+            atomicAdd(&t_rank[a], 1ull);
+          } else if (MODE == kCountList) {
+            int32_t x = order[v], y = order[u], z = order[a], t;
+            if (x > y) { t = x; x = y; y = t; }
+            if (y > z) { t = y; y = z; z = t; }
+            if (x > y) { t = x; x = y; y = t; }
+            const unsigned long long pos = atomicAdd(cursor, 1ull);
+            if (static_cast<int64_t>(pos) < cap) {
+              tri[3 * pos + 0] = x;
+              tri[3 * pos + 1] = y;
+              tri[3 * pos + 2] = z;
+            }
           }
         }
+        i += (a <= b);
+        j += (b <= a);
       }
-      i += (a <= b);
-      j += (b <= a);
+      if (MODE == kCountPerNode && here) atomicAdd(&t_rank[u], here);
     }
-    if (MODE == kCountPerNode && here) {
-      atomicAdd(&t_rank[v], here);
-      atomicAdd(&t_rank[u], here);
-    }
+    if (MODE == kCountPerNode) run_add(t_rank, v, here, valid);
+    if (per_graph) run_add(per_graph, valid && graph_of_rank ? graph_of_rank[v] : 0, here, valid);
     cnt += here;
   }
   cnt = wave_sum(cnt);
@@ -304,14 +333,16 @@ bool plain_is_best(const Csr& c, const Options& o) {
 void count_plain_mode(const Csr& c, const CountArgs& a, hipStream_t s) {
   if (c.m == 0) return;
   const unsigned grid = grid_for(static_cast<uint64_t>(c.m), kBlock, static_cast<unsigned>(device_cus()) * 64u);
+  const uint64_t m = static_cast<uint64_t>(c.m);
   if (a.mode == kCountPerNode)
-    k_plain_mode<kCountPerNode><<<grid, kBlock, 0, s>>>(c.off.p, c.adj.p, c.src.p, static_cast<uint64_t>(c.m), a.total,
-                                                        a.t_rank, nullptr, nullptr, nullptr, 0);
+    k_plain_mode<kCountPerNode><<<grid, kBlock, 0, s>>>(c.off.p, c.adj.p, c.src.p, m, a.total, a.t_rank, nullptr,
+                                                        nullptr, nullptr, 0, a.per_graph, a.graph_of_rank);
   else if (a.mode == kCountList)
-    k_plain_mode<kCountList><<<grid, kBlock, 0, s>>>(c.off.p, c.adj.p, c.src.p, static_cast<uint64_t>(c.m), a.total,
-                                                     nullptr, a.order, a.tri, a.cursor, a.cap);
+    k_plain_mode<kCountList><<<grid, kBlock, 0, s>>>(c.off.p, c.adj.p, c.src.p, m, a.total, nullptr, a.order, a.tri,
+                                                     a.cursor, a.cap, a.per_graph, a.graph_of_rank);
   else
-    fail(TC_E_INVAL, "plain merge: mode must be per-node counts or listing");
+    k_plain_mode<kCountTotal><<<grid, kBlock, 0, s>>>(c.off.p, c.adj.p, c.src.p, m, a.total, nullptr, nullptr, nullptr,
+                                                      nullptr, 0, a.per_graph, a.graph_of_rank);
   TC_LAUNCH_CHECK();
 }
 

@@ -282,8 +282,9 @@ void count_multi(const std::vector<Csr*>& gs, const std::vector<unsigned long lo
 void count_plain(const Csr& c, unsigned long long* total, hipStream_t s);
 // Whether the plain merge serves this graph (TC_OPT_KERNEL 1, or 0 with fewer than 16 probes per edge)
 bool plain_is_best(const Csr& c, const Options& o);
-// Per-node counts (a.mode kCountPerNode: a.t_rank, a.total) or the triangle list (kCountList: a.order,
-// a.tri, a.cursor, a.cap, a.total) by the plain merge
+// Totals (a.mode kCountTotal), per-node counts (kCountPerNode: a.t_rank) or the triangle list
+// (kCountList: a.order, a.tri, a.cursor, a.cap) by the plain merge, with a.total and, when set,
+// a.per_graph (by a.graph_of_rank)
 void count_plain_mode(const Csr& c, const CountArgs& a, hipStream_t s);
 void graph_work(const Csr& c, unsigned long long* W, unsigned long long* P, hipStream_t s);
 // sum_v d_v * dhat_v (the objective of Theorem 3); deg by caller id, order rank -> id

@@ -198,11 +198,13 @@ def test_autotune_keeps_results(tcm, per_node):
     t0 = [x.copy() for x in bc.per_graph_t()] if per_node else None
     old = batch.current_options()
     try:
-        cands = [(128, 16384, 4, 2), (16, 256, 2, 1), (0, 100000, 3, 2)]
+        # the pivot kernel under three partitioner settings and one thread per edge (kernel 1)
+        cands = [(128, 16384, 4, 2, 2), (16, 256, 2, 1, 2), (0, 100000, 3, 2, 2), (256, 0, 4, 2, 1)]
         best, table = batch.autotune(bc, candidates=cands, reps=1, persist=False)
-        assert len(table) == 3
+        assert len(table) == 4
         info = bc.graph.plan_info()
         assert (info["hub_dhat"], info["item_work"]) == tuple(best["options"][:2])
+        assert tcm.get_option(tcm.OPT_KERNEL) == best["options"][4]
         assert not info["frozen"]
         bc.count()
         torch.cuda.synchronize()
