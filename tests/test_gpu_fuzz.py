@@ -64,7 +64,7 @@ def test_fuzz(case):
     opts = {tc.OPT_HUB_DHAT: int(rng.choice([0, 16, 64, 256])),
             tc.OPT_ITEM_WORK: int(rng.choice([0, 64, 1024, 65536])),
             tc.OPT_HUB_BUCKET_LOAD: int(rng.choice([1, 2])),
-            tc.OPT_KERNEL: int(rng.choice([0, 2]))}
+            tc.OPT_KERNEL: int(rng.choice([0, 1, 2]))}
     saved = {k: tc.get_option(k) for k in opts}
     for k, v in opts.items():
         tc.set_option(k, v)
