@@ -306,6 +306,11 @@ def main():
     ap.add_argument("--serve-seconds", type=float, default=60.0, help="trace length for --workload serve")
     ap.add_argument("--serve-budget-frac", type=float, default=0.85,
                     help="device budget for --workload serve, as a fraction of the pool's resident footprint")
+    ap.add_argument("--budgets", type=int, nargs="+", default=None,
+                    help="device budgets in GiB for --workload streamed (default 4 16 64)")
+    ap.add_argument("--e2e-budgets", type=int, nargs="+", default=None,
+                    help="budgets in GiB of the out-of-core build + count for --workload streamed "
+                         "(default 8 16; 0 skips it)")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--calibrate-copy-gib", type=float, default=0.0,

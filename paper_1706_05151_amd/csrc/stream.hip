@@ -19,7 +19,10 @@
 // Resident sources use rows [0, np) alone.
 // Entries keep their global ranks, and the pivot kernel only compares them.
 // Records (v,u) are keyed by u's local row. The next chunk is copied into a
-// staging buffer on a second stream while the current pair is counted.
+// staging buffer on a second stream while the current pair is counted. A
+// partition is loaded on a third stream, one resident range at a time, last
+// range first: the pair of a resident range reads only its own range and the
+// ones after it, so it is counted while the ranges before it are still coming.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -43,16 +46,16 @@ constexpr uint64_t kChunkEntryBytes = 64;
 constexpr uint64_t kChunkRowBytes = 56;
 constexpr int64_t kMaxRegionEntries = int64_t(1) << 31;  // record keys hold 32-bit entry indices
 
-// dst[r] = base + off[r] - off[0] for r in [0, rows]; flags offsets that decrease.
-// The host has checked only the region's end offsets (off[0] <= off[rows]);
-// an offset between them that breaks the order is clamped into the region, so
-// nothing reads outside it before the flag is seen.
-__global__ void k_rebase(const int64_t* __restrict__ off, int32_t rows, int64_t base, int64_t* __restrict__ dst,
-                         uint32_t* __restrict__ bad) {
-  const int64_t o0 = off[0], span = off[rows] - o0;
+// dst[r] = base + clamp(off[r] - o0, c0, c1) for r in [0, rows]; flags offsets
+// that decrease. The host has checked only the range's end offsets, and knows
+// the entries [c0, c1) that the range spans; an offset between them that breaks
+// the order is clamped into that span, so nothing reads outside the range's own
+// entries before the flag is seen.
+__global__ void k_rebase(const int64_t* __restrict__ off, int32_t rows, int64_t o0, int64_t c0, int64_t c1,
+                         int64_t base, int64_t* __restrict__ dst, uint32_t* __restrict__ bad) {
   for (int32_t r = blockIdx.x * blockDim.x + threadIdx.x; r <= rows; r += gridDim.x * blockDim.x) {
     const int64_t x = off[r] - o0;
-    dst[r] = base + (x < 0 ? 0 : x > span ? span : x);
+    dst[r] = base + (x < c0 ? c0 : x > c1 ? c1 : x);
     if (r < rows && off[r + 1] < off[r]) atomicOr(bad, 1u);
   }
 }
@@ -192,12 +195,18 @@ uint64_t count_streamed(const int64_t* off, const int32_t* adj, int32_t n, int64
   info[0] = info[1] = info[2] = info[3] = 0;
   if (n <= 0 || m == 0) return 0;
   const std::vector<Range> parts = split_rows(off, 0, n, budget / 2, kPivotEntryBytes, kPivotRowBytes);
-  // visiting order: for each partition, its own rows (resident) and then the
-  // rows before it, shipped in chunks
+  // visiting order: for each partition, its own rows (resident) from the last
+  // range to the first, and then the rows before it, shipped in chunks. A
+  // resident range's records point only at rows after its first row, so its
+  // pair needs only the ranges visited so far: the partition is loaded in the
+  // same order, range by range, and each pair starts once its own range is in.
   std::vector<Task> tasks;
+  size_t own_max = 1;
   for (int j = 0; j < static_cast<int>(parts.size()); j++) {
-    for (const Range& r : split_rows(off, parts[j].lo, parts[j].hi, budget / 2, kChunkEntryBytes, kChunkRowBytes))
-      tasks.push_back(Task{j, false, r});
+    const std::vector<Range> own =
+        split_rows(off, parts[j].lo, parts[j].hi, budget / 2, kChunkEntryBytes, kChunkRowBytes);
+    own_max = std::max(own_max, own.size());
+    for (auto r = own.rbegin(); r != own.rend(); ++r) tasks.push_back(Task{j, false, *r});
     for (const Range& r : split_rows(off, 0, parts[j].lo, budget / 2, kChunkEntryBytes, kChunkRowBytes))
       tasks.push_back(Task{j, true, r});
   }
@@ -226,20 +235,30 @@ uint64_t count_streamed(const int64_t* off, const int32_t* adj, int32_t n, int64
   k_fill_words<uint32_t><<<1, 64, 0, s>>>(bad.get(), 1, 0u);
   TC_LAUNCH_CHECK();
 
-  hipStream_t cs = nullptr;
+  // cs ships chunks into the staging buffers, ls loads the partitions
+  hipStream_t cs = nullptr, ls = nullptr;
   TC_HIP(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
-  hipEvent_t loaded = nullptr, freed = nullptr;
+  hipEvent_t loaded = nullptr, freed = nullptr, part_free = nullptr;
+  std::vector<hipEvent_t> range_in(own_max, nullptr);  // range k of the partition being loaded is in
   auto cleanup = [&] {
     (void)hipStreamSynchronize(cs);
+    if (ls) (void)hipStreamSynchronize(ls);
     (void)hipStreamSynchronize(s);
     if (loaded) (void)hipEventDestroy(loaded);
     if (freed) (void)hipEventDestroy(freed);
+    if (part_free) (void)hipEventDestroy(part_free);
+    for (hipEvent_t e : range_in)
+      if (e) (void)hipEventDestroy(e);
     (void)hipStreamDestroy(cs);
+    if (ls) (void)hipStreamDestroy(ls);
   };
   HostWords hw(s);
   try {
+    TC_HIP(hipStreamCreateWithFlags(&ls, hipStreamNonBlocking));
     TC_HIP(hipEventCreateWithFlags(&loaded, hipEventDisableTiming));
     TC_HIP(hipEventCreateWithFlags(&freed, hipEventDisableTiming));
+    TC_HIP(hipEventCreateWithFlags(&part_free, hipEventDisableTiming));
+    for (hipEvent_t& e : range_in) TC_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
     uint64_t h2d = 0;
     auto next_shipped = [&](size_t from) {
       while (from < tasks.size() && !tasks[from].shipped) from++;
@@ -260,7 +279,8 @@ uint64_t count_streamed(const int64_t* off, const int32_t* adj, int32_t n, int64
     TC_HIP(hipEventRecord(freed, s));
     prefetch(next_shipped(0));
     int cur_part = -1;
-    int32_t dhat_p = 0;
+    int32_t dhat_p = 0;  // the longest row among the partition's ranges loaded so far
+    size_t own_k = 0;    // the resident range's place in the partition's loading order
     CountArgs ca;
     ca.mode = kCountTotal;
     ca.total = total.get();
@@ -269,24 +289,25 @@ uint64_t count_streamed(const int64_t* off, const int32_t* adj, int32_t n, int64
       const Range& P = parts[t.part];
       const Range& C = t.src;
       const int32_t np = P.hi - P.lo, nc = C.hi - C.lo;
-      if (t.part != cur_part) {  // load the rows of V_j (on the counting stream)
+      if (t.part != cur_part) {  // load the rows of V_j on ls, range by range in visiting order
         cur_part = t.part;
-        if (P.e1 > P.e0)
-          TC_HIP(hipMemcpyAsync(adj_d.get(), adj + P.e0, static_cast<size_t>(P.e1 - P.e0) * sizeof(int32_t),
-                                hipMemcpyDefault, s));
-        TC_HIP(hipMemcpyAsync(pin_off.get(), off + P.lo, (static_cast<size_t>(np) + 1) * sizeof(int64_t),
-                              hipMemcpyDefault, s));
-        h2d += static_cast<uint64_t>(P.e1 - P.e0) * sizeof(int32_t) + (static_cast<uint64_t>(np) + 1) * 8;
-        k_rebase<<<grid_for(static_cast<uint64_t>(np) + 1, kBlock, 65536), kBlock, 0, s>>>(pin_off.get(), np, 0,
-                                                                                         off_d.get(), bad.get());
-        TC_LAUNCH_CHECK();
-        k_check_rows<<<grid_for(np, kBlock, 65536), kBlock, 0, s>>>(off_d.get(), adj_d.get(), np, 0, P.lo, n,
-                                                                    src_d.get(), bad.get());
-        TC_LAUNCH_CHECK();
-        dhat_p = max_row_length(off_d.get(), np, s);
+        dhat_p = 0;
+        own_k = 0;
+        TC_HIP(hipEventRecord(part_free, s));  // after the last count that reads the previous partition
+        TC_HIP(hipStreamWaitEvent(ls, part_free, 0));
+        for (size_t k = 0; q + k < tasks.size() && tasks[q + k].part == t.part && !tasks[q + k].shipped; k++) {
+          const Range& R = tasks[q + k].src;
+          const int32_t r0 = R.lo - P.lo;
+          const size_t nrow = static_cast<size_t>(R.hi - R.lo) + (R.hi == P.hi ? 1 : 0);  // the end once
+          if (R.e1 > R.e0)
+            TC_HIP(hipMemcpyAsync(adj_d.get() + (R.e0 - P.e0), adj + R.e0,
+                                  static_cast<size_t>(R.e1 - R.e0) * sizeof(int32_t), hipMemcpyDefault, ls));
+          TC_HIP(hipMemcpyAsync(pin_off.get() + r0, off + R.lo, nrow * sizeof(int64_t), hipMemcpyDefault, ls));
+          TC_HIP(hipEventRecord(range_in[k], ls));
+          h2d += static_cast<uint64_t>(R.e1 - R.e0) * sizeof(int32_t) + nrow * 8;
+        }
       }
       CsrView w(off_d.get(), adj_d.get(), src_d.get());
-      w.c.dhat_max = dhat_p;
       int64_t e_begin = 0;  // the source entries in the combined adj
       uint64_t ec = static_cast<uint64_t>(C.e1 - C.e0);
       if (t.shipped) {  // the staged rows after the gap row np
@@ -295,7 +316,7 @@ uint64_t count_streamed(const int64_t* off, const int32_t* adj, int32_t n, int64
           TC_HIP(hipMemcpyAsync(adj_d.get() + cap_p, stage_adj.get(), ec * sizeof(int32_t), hipMemcpyDeviceToDevice,
                                 s));
         k_rebase<<<grid_for(static_cast<uint64_t>(nc) + 1, kBlock, 65536), kBlock, 0, s>>>(
-            stage_off.get(), nc, cap_p, off_d.get() + np + 1, bad.get());
+            stage_off.get(), nc, C.e0, 0, C.e1 - C.e0, cap_p, off_d.get() + np + 1, bad.get());
         TC_LAUNCH_CHECK();
         TC_HIP(hipEventRecord(freed, s));
         prefetch(next_shipped(q + 1));
@@ -305,10 +326,19 @@ uint64_t count_streamed(const int64_t* off, const int32_t* adj, int32_t n, int64
         w.c.n = np + 1 + nc;
         w.c.m = cap_p + static_cast<int64_t>(ec);
         e_begin = cap_p;
-      } else {  // rows of the partition itself
+      } else {  // rows of the partition itself: its range (the ranges after it are in and checked)
         w.c.n = np;
         w.c.m = P.e1 - P.e0;
         e_begin = C.e0 - P.e0;
+        const int32_t r0 = C.lo - P.lo;
+        TC_HIP(hipStreamWaitEvent(s, range_in[own_k++], 0));
+        k_rebase<<<grid_for(static_cast<uint64_t>(nc) + 1, kBlock, 65536), kBlock, 0, s>>>(
+            pin_off.get() + r0, nc, P.e0, C.e0 - P.e0, C.e1 - P.e0, 0, off_d.get() + r0, bad.get());
+        TC_LAUNCH_CHECK();
+        k_check_rows<<<grid_for(nc, kBlock, 65536), kBlock, 0, s>>>(off_d.get(), adj_d.get(), nc, r0, C.lo, n,
+                                                                    src_d.get(), bad.get());
+        TC_LAUNCH_CHECK();
+        row_max_to_host(off_d.get() + r0, nc, s, hw.get() + 2);
       }
       // records (v,u) with u in V_j, sorted by u's local row (the row check is read back
       // with their count, before anything indexes by an entry's value)
@@ -322,6 +352,8 @@ uint64_t count_streamed(const int64_t* off, const int32_t* adj, int32_t n, int64
       TC_HIP(hipMemcpyAsync(hw.get() + 1, bad.get(), sizeof(uint32_t), hipMemcpyDeviceToHost, s));
       TC_HIP(hipStreamSynchronize(s));
       if (hw[1]) fail(TC_E_INVAL, "rows must hold ascending ranks above their own row, below n");
+      if (!t.shipped) dhat_p = std::max(dhat_p, static_cast<int32_t>(hw[2]));
+      w.c.dhat_max = dhat_p;  // pivots of this pair lie in the ranges loaded so far
       const uint64_t mi = hw[0];
       if (mi == 0) continue;
       const int b = bits_for(np > 1 ? static_cast<uint64_t>(np - 1) : 1);

@@ -526,7 +526,7 @@ def run_streamed(args):
     # (tc_build_csr_host), then counted streamed under the same budget
     e2e = []
     for budget in (int(x) << 30 for x in getattr(args, "e2e_budgets", None) or (8, 16)):
-        if budget >= resident_bytes:
+        if budget <= 0 or budget >= resident_bytes:
             continue
         torch.cuda.synchronize()
         t0 = time.perf_counter()
