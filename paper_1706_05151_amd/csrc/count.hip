@@ -154,19 +154,25 @@ __global__ __launch_bounds__(kBlock) void k_work(const int64_t* __restrict__ off
 
 // -------------------------------------------------------- plan building ---
 
-// In-edge key of every oriented edge e = (v, u), in edge order: (u << 32) | e,
-// and the length of the suffix of N_v after u. Pivots with an empty N_u and
+// The in-edge record of oriented edge e = e0 + i, (v, u) with u = adj[e], as
+// the first pass of its sort reads it: key (u << 32) | e, value the length of
+// the suffix of N_v after u, off[v + 1] - e - 1. Pivots with an empty N_u and
 // records with an empty suffix stay in the list; they are given no work.
-__global__ __launch_bounds__(kBlock) void k_inkeys(const int64_t* __restrict__ off, const int32_t* __restrict__ adj,
-                                                   const int32_t* __restrict__ src, uint64_t e0, uint64_t cnt,
-                                                   uint64_t* __restrict__ keys, uint32_t* __restrict__ lens) {
-  for (uint64_t i = static_cast<uint64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < cnt;
-       i += static_cast<uint64_t>(gridDim.x) * blockDim.x) {
+struct InEdgeSource {
+  static constexpr bool kArrays = false;
+  const int64_t* __restrict__ off;
+  const int32_t* __restrict__ adj;
+  const int32_t* __restrict__ src;
+  uint64_t e0;
+  __device__ __forceinline__ uint64_t key(size_t i) const {
     const uint64_t e = e0 + i;
-    keys[i] = (static_cast<uint64_t>(static_cast<uint32_t>(adj[e])) << 32) | e;
-    lens[i] = static_cast<uint32_t>(off[src[e] + 1] - static_cast<int64_t>(e) - 1);
+    return (static_cast<uint64_t>(static_cast<uint32_t>(adj[e])) << 32) | e;
   }
-}
+  __device__ __forceinline__ uint32_t val(size_t i) const {
+    const uint64_t e = e0 + i;
+    return static_cast<uint32_t>(off[src[e] + 1] - static_cast<int64_t>(e) - 1);
+  }
+};
 
 // Records in pivot order from the sorted keys and their suffix lengths (taken
 // from the CSR when lens is null).
@@ -396,13 +402,12 @@ void build_plan(Csr& c, PivotPlan& P, uint64_t e0, uint64_t e1, hipStream_t s, c
   // in-edge records sorted by pivot u (stable: by e within u)
   DevBuf<uint64_t> ik(mi, s), ik2(mi, s);
   DevBuf<uint32_t> il(mi, s), il2(mi, s);
-  k_inkeys<<<grid_for(mi, kBlock, 65536), kBlock, 0, s>>>(c.off.p, c.adj.p, c.src.p, e0, mi, ik.get(), il.get());
-  TC_LAUNCH_CHECK();
   uint32_t* sl = il.get();
   DevBuf<uint32_t> sort_fail(1, s);
   TC_HIP(hipMemsetAsync(sort_fail.get(), 0, sizeof(uint32_t), s));
-  uint64_t* sk = radix_sort_pairs<uint64_t, uint32_t>(ik.get(), ik2.get(), sl, il2.get(), mi, 32, 32 + b, s,
-                                                      sort_fail.get());
+  // the records are made from the CSR by the sort's first pass
+  uint64_t* sk = radix_sort_from<uint64_t, uint32_t>(InEdgeSource{c.off.p, c.adj.p, c.src.p, e0}, ik.get(), ik2.get(),
+                                                     sl, il2.get(), mi, 32, 32 + b, s, sort_fail.get());
   DevBuf<int64_t> fin;
   plan_records(c, P, sk, sl, mi, fin, s);
   ik.release();

@@ -297,15 +297,25 @@ __host__ __device__ __forceinline__ uint32_t radix_digit_mask(int shift, int bit
   return w >= kRadixBits ? kBins - 1u : (1u << w) - 1u;
 }
 
+// Where a sort's first pass reads key i and value i: its key and value
+// arrays, or (another source type) a functor that makes them on the fly.
+template <typename K, typename V>
+struct ArraySource {
+  static constexpr bool kArrays = true;
+  const K* __restrict__ keys;
+  const V* __restrict__ vals;
+  __device__ __forceinline__ K key(size_t i) const { return keys[i]; }
+  __device__ __forceinline__ V val(size_t i) const { return vals[i]; }
+};
+
 // hist[p * kBins + d] += number of keys whose pass-p digit is d. The block's
 // LDS counts are kept in `copies` copies (lane L adds to copy L % copies),
 // each one word further along the banks than the last, so lanes with equal
 // digits in different copies hit different banks, and so do lanes of one copy
 // with digits that differ below 32.
-template <typename K>
-__global__ __launch_bounds__(kSortBlock) void k_sweep_hist(const K* __restrict__ keys, uint32_t N, int bit_lo,
-                                                            int bit_hi, int passes, int copies,
-                                                            uint32_t* __restrict__ hist) {
+template <typename K, typename Src>
+__global__ __launch_bounds__(kSortBlock) void k_sweep_hist(Src keys, uint32_t N, int bit_lo, int bit_hi, int passes,
+                                                            int copies, uint32_t* __restrict__ hist) {
   constexpr int ITEMS = RadixItems<K>::value;
   constexpr int TILE = kSortBlock * ITEMS;
   extern __shared__ uint32_t h[];  // copies * (passes * kBins + 1)
@@ -321,14 +331,14 @@ __global__ __launch_bounds__(kSortBlock) void k_sweep_hist(const K* __restrict__
 #pragma unroll
   for (int i = 0; i < ITEMS; i++) {
     const size_t idx = base + static_cast<size_t>(i) * kSortBlock + threadIdx.x;
-    if (idx < N) k[i] = keys[idx];
+    if (idx < N) k[i] = keys.key(idx);
   }
   for (; base < N; base += stride) {
     const size_t next = base + stride;
 #pragma unroll
     for (int i = 0; i < ITEMS; i++) {
       const size_t idx = next + static_cast<size_t>(i) * kSortBlock + threadIdx.x;
-      if (idx < N) nk[i] = keys[idx];
+      if (idx < N) nk[i] = keys.key(idx);
     }
     for (int p = 0; p < passes; p++) {
       const int shift = bit_lo + kRadixBits * p;
@@ -376,9 +386,8 @@ struct NoVal {};
 // index order and the pass is stable. ctr[0] hands out tile indices; *fail
 // is set if a look-back gave up. With a value type V, each key's value moves
 // with it (staged through the same LDS tile after the keys are written).
-template <typename K, typename V>
-__global__ __launch_bounds__(kScatterBlock) void k_sweep_scatter(const K* __restrict__ in, K* __restrict__ out,
-                                                                 const V* __restrict__ vin, V* __restrict__ vout,
+template <typename K, typename V, typename Src>
+__global__ __launch_bounds__(kScatterBlock) void k_sweep_scatter(Src in, K* __restrict__ out, V* __restrict__ vout,
                                                                  uint32_t N, int shift, uint32_t dmask, uint64_t tag,
                                                                  const uint32_t* __restrict__ starts,
                                                                  uint64_t* __restrict__ status,
@@ -421,14 +430,13 @@ __global__ __launch_bounds__(kScatterBlock) void k_sweep_scatter(const K* __rest
     rk[i] = old + lr;
     __builtin_amdgcn_wave_barrier();
   };
-  const K* chunk = in + base + static_cast<size_t>(w) * CHUNK;
+  const size_t chunk = base + static_cast<size_t>(w) * CHUNK + lane;
   if (base + TILE <= N) {  // full tile (wave-uniform): no bounds checks, one ballot per digit bit
 #pragma unroll
-    for (int i = 0; i < ITEMS; i++) key[i] = chunk[i * kWave + lane];
+    for (int i = 0; i < ITEMS; i++) key[i] = in.key(chunk + static_cast<size_t>(i) * kWave);
     if constexpr (kHasVal) {
-      const V* vchunk = vin + base + static_cast<size_t>(w) * CHUNK;
 #pragma unroll
-      for (int i = 0; i < ITEMS; i++) val[i] = vchunk[i * kWave + lane];
+      for (int i = 0; i < ITEMS; i++) val[i] = in.val(chunk + static_cast<size_t>(i) * kWave);
     }
 #pragma unroll
     for (int i = 0; i < ITEMS; i++) {
@@ -440,10 +448,10 @@ __global__ __launch_bounds__(kScatterBlock) void k_sweep_scatter(const K* __rest
     for (int i = 0; i < ITEMS; i++) {
       const size_t idx = base + static_cast<size_t>(w) * CHUNK + static_cast<size_t>(i) * kWave + lane;
       key[i] = K{};
-      if (idx < N) key[i] = chunk[i * kWave + lane];
+      if (idx < N) key[i] = in.key(idx);
       if constexpr (kHasVal) {
         val[i] = V{};
-        if (idx < N) val[i] = vin[idx];
+        if (idx < N) val[i] = in.val(idx);
       }
     }
 #pragma unroll
@@ -468,10 +476,14 @@ __global__ __launch_bounds__(kScatterBlock) void k_sweep_scatter(const K* __rest
   if (t == 0) {
     status_store(mine, kKindInc | tag | tot);
   } else {
-    status_store(mine, kKindAgg | tag | tot);
+    // a predecessor already inclusive gives the prefix at once: one publication instead of two
+    const uint64_t pv = status_load(status + static_cast<size_t>(t - 1) * kBins + tid);
+    const bool ready = (pv & kKindMask) == kKindInc && (pv & ~kKindMask & ~kValMask) == tag;
+    if (ready) excl = pv & kValMask;
+    else status_store(mine, kKindAgg | tag | tot);
     uint32_t j = t - 1;
     uint32_t polls = 0;
-    for (;;) {
+    while (!ready) {
       const uint64_t v = status_load(status + static_cast<size_t>(j) * kBins + tid);
       const uint64_t kind = v & kKindMask;
       if (kind == 0 || (v & ~kKindMask & ~kValMask) != tag) {
@@ -544,20 +556,41 @@ struct NoHook {
   void operator()(int, const K*) const {}
 };
 
+// keys[i], vals[i] = the source's key i and value i (a source that is not
+// the arrays themselves, when no pass runs).
+template <typename K, typename V, typename Src>
+__global__ void k_materialize(Src src, uint32_t N, K* __restrict__ keys, V* __restrict__ vals) {
+  for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < N; i += gridDim.x * blockDim.x) {
+    keys[i] = src.key(i);
+    if constexpr (!std::is_same<V, NoVal>::value) vals[i] = src.val(i);
+  }
+}
+
 // Sorts N keys ascending by bits [bit_lo, bit_hi) (9-bit digits, stable),
-// each value in `vals` moving with its key. Uses `keys`/`tmp` and
-// `vals`/`vtmp` as ping-pong buffers; returns the key buffer holding the
-// result and points `vals` at the value buffer holding the result. A pass
-// whose look-back gave up sets *fail_dev (device word, never cleared here);
-// the caller checks it at its next synchronisation. Without fail_dev the
-// sort synchronises the stream and checks its own flag before returning.
+// each value moving with its key. The first pass (and the digit count) reads
+// key i and value i from `first`; the passes then ping-pong between
+// `tmp`/`vtmp` and `keys`/`vals`. Returns the key buffer holding the result
+// and points `vals` at the value buffer holding the result. A pass whose
+// look-back gave up sets *fail_dev (device word, never cleared here); the
+// caller checks it at its next synchronisation. Without fail_dev the sort
+// synchronises the stream and checks its own flag before returning.
 // hook(p, buf) runs on the host after pass p is queued (work it queues on s
 // sees the keys sorted by bits [bit_lo, bit_lo + 9 (p + 1))); no pass runs,
-// and the hook is not called, when N <= 1.
-template <typename K, typename V, typename Hook = NoHook>
-K* radix_sort_pairs(K* keys, K* tmp, V*& vals, V* vtmp, size_t N, int bit_lo, int bit_hi, hipStream_t s,
-                    uint32_t* fail_dev = nullptr, Hook hook = Hook()) {
-  if (N <= 1 || bit_hi <= bit_lo) return keys;
+// and the hook is not called, when N <= 1 (the source is then copied to
+// keys/vals unless it is those arrays).
+template <typename K, typename V, typename Src, typename Hook = NoHook>
+K* radix_sort_from(Src first, K* keys, K* tmp, V*& vals, V* vtmp, size_t N, int bit_lo, int bit_hi, hipStream_t s,
+                   uint32_t* fail_dev = nullptr, Hook hook = Hook()) {
+  if (N <= 1 || bit_hi <= bit_lo) {
+    if constexpr (!Src::kArrays) {
+      if (N >= (1ull << 32)) fail(TC_E_INVAL, "radix_sort: more than 2^32 - 1 keys");
+      if (N > 0) {
+        k_materialize<K, V, Src><<<grid_for(N, 256, 65536), 256, 0, s>>>(first, static_cast<uint32_t>(N), keys, vals);
+        TC_LAUNCH_CHECK();
+      }
+    }
+    return keys;
+  }
   if (N >= (1ull << 32)) fail(TC_E_INVAL, "radix_sort: more than 2^32 - 1 keys");
   constexpr int TILE = kScatterBlock * ScatterItems<K>::value;
   const int passes = (bit_hi - bit_lo + kRadixBits - 1) / kRadixBits;
@@ -577,9 +610,9 @@ K* radix_sort_pairs(K* keys, K* tmp, V*& vals, V* vtmp, size_t N, int bit_lo, in
   uint32_t* fail_flag = fail_dev ? fail_dev : ctrs + passes;
   int copies = 4;  // LDS: copies * (passes * kBins + 1) words <= 64 KiB
   while (copies > 1 && static_cast<size_t>(copies) * (static_cast<size_t>(passes) * kBins + 1) * 4 > 65536) copies >>= 1;
-  k_sweep_hist<K><<<tiles < 2048u ? tiles : 2048u, kSortBlock,
-                    static_cast<size_t>(copies) * (static_cast<size_t>(passes) * kBins + 1) * 4, s>>>(
-      keys, static_cast<uint32_t>(N), bit_lo, bit_hi, passes, copies, hist);
+  k_sweep_hist<K, Src><<<tiles < 2048u ? tiles : 2048u, kSortBlock,
+                         static_cast<size_t>(copies) * (static_cast<size_t>(passes) * kBins + 1) * 4, s>>>(
+      first, static_cast<uint32_t>(N), bit_lo, bit_hi, passes, copies, hist);
   TC_LAUNCH_CHECK();
   k_sweep_starts<<<passes, kBins, 0, s>>>(hist);
   TC_LAUNCH_CHECK();
@@ -589,11 +622,15 @@ K* radix_sort_pairs(K* keys, K* tmp, V*& vals, V* vtmp, size_t N, int bit_lo, in
   V* vb = vtmp;
   for (int p = 0; p < passes; p++) {
     const int shift = bit_lo + kRadixBits * p;
-    k_sweep_scatter<K, V><<<tiles, kScatterBlock, 0, s>>>(a, b, va, vb, static_cast<uint32_t>(N), shift,
-                                                          radix_digit_mask(shift, bit_hi),
-                                                          static_cast<uint64_t>(p + 1) << kTagShift,
-                                                          hist + static_cast<size_t>(p) * kBins, status.get(),
-                                                          ctrs + p, fail_flag);
+    const uint32_t dm = radix_digit_mask(shift, bit_hi);
+    const uint64_t tag = static_cast<uint64_t>(p + 1) << kTagShift;
+    if (p == 0)
+      k_sweep_scatter<K, V, Src><<<tiles, kScatterBlock, 0, s>>>(first, b, vb, static_cast<uint32_t>(N), shift, dm,
+                                                                 tag, hist, status.get(), ctrs, fail_flag);
+    else
+      k_sweep_scatter<K, V, ArraySource<K, V>><<<tiles, kScatterBlock, 0, s>>>(
+          ArraySource<K, V>{a, va}, b, vb, static_cast<uint32_t>(N), shift, dm, tag,
+          hist + static_cast<size_t>(p) * kBins, status.get(), ctrs + p, fail_flag);
     TC_LAUNCH_CHECK();
     std::swap(a, b);
     std::swap(va, vb);
@@ -607,6 +644,14 @@ K* radix_sort_pairs(K* keys, K* tmp, V*& vals, V* vtmp, size_t N, int bit_lo, in
     if (h_fail) fail(TC_E_DEVICE, "radix_sort: a tile's look-back did not complete");
   }
   return a;
+}
+
+// radix_sort_from with the first pass reading `keys` and `vals` themselves.
+template <typename K, typename V, typename Hook = NoHook>
+K* radix_sort_pairs(K* keys, K* tmp, V*& vals, V* vtmp, size_t N, int bit_lo, int bit_hi, hipStream_t s,
+                    uint32_t* fail_dev = nullptr, Hook hook = Hook()) {
+  return radix_sort_from<K, V, ArraySource<K, V>, Hook>(ArraySource<K, V>{keys, vals}, keys, tmp, vals, vtmp, N,
+                                                        bit_lo, bit_hi, s, fail_dev, hook);
 }
 
 // Keys-only form of radix_sort_pairs.
