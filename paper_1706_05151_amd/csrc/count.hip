@@ -174,6 +174,15 @@ struct InEdgeSource {
   }
 };
 
+// The last pass of the record sort writes each record in its final form:
+// suffix start e + 1 (e from the key's low word) and suffix length.
+struct RecordSink {
+  InRec* __restrict__ rec;
+  __device__ __forceinline__ void put(size_t g, uint64_t key, uint32_t len) const {
+    rec[g] = InRec{static_cast<uint32_t>(key) + 1u, len};
+  }
+};
+
 // Records in pivot order from the sorted keys and their suffix lengths (taken
 // from the CSR when lens is null).
 __global__ __launch_bounds__(kBlock) void k_inrec_fill(const uint64_t* __restrict__ ikeys,
@@ -405,11 +414,17 @@ void build_plan(Csr& c, PivotPlan& P, uint64_t e0, uint64_t e1, hipStream_t s, c
   uint32_t* sl = il.get();
   DevBuf<uint32_t> sort_fail(1, s);
   TC_HIP(hipMemsetAsync(sort_fail.get(), 0, sizeof(uint32_t), s));
-  // the records are made from the CSR by the sort's first pass
-  uint64_t* sk = radix_sort_from<uint64_t, uint32_t>(InEdgeSource{c.off.p, c.adj.p, c.src.p, e0}, ik.get(), ik2.get(),
-                                                     sl, il2.get(), mi, 32, 32 + b, s, sort_fail.get());
+  // the records are read from the CSR by the sort's first pass and written in
+  // their final form by its last (with one record no pass runs: the record is
+  // then made from the key and value)
+  const bool filled = mi > 1;
+  if (filled) P.inrec.alloc(mi, s);
+  const RecordSink recs{P.inrec.p};
+  uint64_t* sk = radix_sort_from<uint64_t, uint32_t, InEdgeSource, NoHook, RecordSink>(
+      InEdgeSource{c.off.p, c.adj.p, c.src.p, e0}, ik.get(), ik2.get(), sl, il2.get(), mi, 32, 32 + b, s,
+      sort_fail.get(), NoHook(), filled ? &recs : nullptr);
   DevBuf<int64_t> fin;
-  plan_records(c, P, sk, sl, mi, fin, s);
+  plan_records(c, P, sk, filled ? nullptr : sl, mi, fin, s, filled);
   ik.release();
   ik2.release();
   il.release();
@@ -420,13 +435,15 @@ void build_plan(Csr& c, PivotPlan& P, uint64_t e0, uint64_t e1, hipStream_t s, c
 }  // namespace
 
 void plan_records(Csr& c, PivotPlan& P, const uint64_t* sk, const uint32_t* sl, uint64_t mi, DevBuf<int64_t>& fin,
-                  hipStream_t s) {
+                  hipStream_t s, bool filled) {
   const int32_t n = c.n;
   if (!P.in_off.p) P.in_off.alloc(static_cast<size_t>(n) + 1, s);
-  P.inrec.alloc(mi, s);
   fin.alloc(mi + 1, s);
-  k_inrec_fill<<<grid_for(mi, kBlock, 65536), kBlock, 0, s>>>(sk, sl, c.off.p, c.src.p, mi, P.inrec.p);
-  TC_LAUNCH_CHECK();
+  if (!filled) {
+    P.inrec.alloc(mi, s);
+    k_inrec_fill<<<grid_for(mi, kBlock, 65536), kBlock, 0, s>>>(sk, sl, c.off.p, c.src.p, mi, P.inrec.p);
+    TC_LAUNCH_CHECK();
+  }
   offsets_from_key_rows(sk, mi, n, P.in_off.p, s);
   // the cost prefix F over the records (the boundary rule of Section 5 cuts items from it)
   if (sl) exclusive_scan_of<int64_t>(LenCost{sl}, fin.get(), mi, s, fin.get() + mi);

@@ -308,6 +308,15 @@ struct ArraySource {
   __device__ __forceinline__ V val(size_t i) const { return vals[i]; }
 };
 
+// Where a pass writes the value that lands at output position g (with its
+// key at hand): the value array, or (another sink type) a functor that
+// writes something made of both.
+template <typename K, typename V>
+struct ArraySink {
+  V* __restrict__ vals;
+  __device__ __forceinline__ void put(size_t g, const K&, V v) const { vals[g] = v; }
+};
+
 // hist[p * kBins + d] += number of keys whose pass-p digit is d. The block's
 // LDS counts are kept in `copies` copies (lane L adds to copy L % copies),
 // each one word further along the banks than the last, so lanes with equal
@@ -386,8 +395,8 @@ struct NoVal {};
 // index order and the pass is stable. ctr[0] hands out tile indices; *fail
 // is set if a look-back gave up. With a value type V, each key's value moves
 // with it (staged through the same LDS tile after the keys are written).
-template <typename K, typename V, typename Src>
-__global__ __launch_bounds__(kScatterBlock) void k_sweep_scatter(Src in, K* __restrict__ out, V* __restrict__ vout,
+template <typename K, typename V, typename Src, typename Sink>
+__global__ __launch_bounds__(kScatterBlock) void k_sweep_scatter(Src in, K* __restrict__ out, Sink vout,
                                                                  uint32_t N, int shift, uint32_t dmask, uint64_t tag,
                                                                  const uint32_t* __restrict__ starts,
                                                                  uint64_t* __restrict__ status,
@@ -514,7 +523,11 @@ __global__ __launch_bounds__(kScatterBlock) void k_sweep_scatter(Src in, K* __re
   }
   __syncthreads();
   const uint32_t count = static_cast<uint32_t>(N - base < static_cast<size_t>(TILE) ? N - base : TILE);
-  uint32_t gpos[kHasVal ? ITEMS : 1];  // output position of staged position i * kScatterBlock + tid
+  // the array sink needs only the output position of staged position i * kScatterBlock + tid;
+  // another sink gets the key too
+  constexpr bool kKeepKey = kHasVal && !std::is_same<Sink, ArraySink<K, V>>::value;
+  uint32_t gpos[kHasVal ? ITEMS : 1];
+  K gkey[kKeepKey ? ITEMS : 1];
 #pragma unroll
   for (int i = 0; i < ITEMS; i++) {
     const uint32_t j = static_cast<uint32_t>(i * kScatterBlock + tid);
@@ -524,6 +537,7 @@ __global__ __launch_bounds__(kScatterBlock) void k_sweep_scatter(Src in, K* __re
       const uint32_t g = gbase[d] + (j - dstart[d]);
       out[g] = k;
       if constexpr (kHasVal) gpos[i] = g;
+      if constexpr (kKeepKey) gkey[i] = k;
     }
   }
   if constexpr (kHasVal) {
@@ -537,7 +551,10 @@ __global__ __launch_bounds__(kScatterBlock) void k_sweep_scatter(Src in, K* __re
 #pragma unroll
     for (int i = 0; i < ITEMS; i++) {
       const uint32_t j = static_cast<uint32_t>(i * kScatterBlock + tid);
-      if (j < count) vout[gpos[i]] = vt[j];
+      if (j < count) {
+        if constexpr (kKeepKey) vout.put(gpos[i], gkey[i], vt[j]);
+        else vout.put(gpos[i], K{}, vt[j]);
+      }
     }
   }
 }
@@ -577,10 +594,12 @@ __global__ void k_materialize(Src src, uint32_t N, K* __restrict__ keys, V* __re
 // hook(p, buf) runs on the host after pass p is queued (work it queues on s
 // sees the keys sorted by bits [bit_lo, bit_lo + 9 (p + 1))); no pass runs,
 // and the hook is not called, when N <= 1 (the source is then copied to
-// keys/vals unless it is those arrays).
-template <typename K, typename V, typename Src, typename Hook = NoHook>
+// keys/vals unless it is those arrays). With `last`, the last pass hands each
+// value and its key to that sink instead of writing a value buffer (the
+// returned `vals` then holds nothing; `last` is not used when no pass runs).
+template <typename K, typename V, typename Src, typename Hook = NoHook, typename Sink = ArraySink<K, V>>
 K* radix_sort_from(Src first, K* keys, K* tmp, V*& vals, V* vtmp, size_t N, int bit_lo, int bit_hi, hipStream_t s,
-                   uint32_t* fail_dev = nullptr, Hook hook = Hook()) {
+                   uint32_t* fail_dev = nullptr, Hook hook = Hook(), const Sink* last = nullptr) {
   if (N <= 1 || bit_hi <= bit_lo) {
     if constexpr (!Src::kArrays) {
       if (N >= (1ull << 32)) fail(TC_E_INVAL, "radix_sort: more than 2^32 - 1 keys");
@@ -624,13 +643,25 @@ K* radix_sort_from(Src first, K* keys, K* tmp, V*& vals, V* vtmp, size_t N, int 
     const int shift = bit_lo + kRadixBits * p;
     const uint32_t dm = radix_digit_mask(shift, bit_hi);
     const uint64_t tag = static_cast<uint64_t>(p + 1) << kTagShift;
-    if (p == 0)
-      k_sweep_scatter<K, V, Src><<<tiles, kScatterBlock, 0, s>>>(first, b, vb, static_cast<uint32_t>(N), shift, dm,
-                                                                 tag, hist, status.get(), ctrs, fail_flag);
-    else
-      k_sweep_scatter<K, V, ArraySource<K, V>><<<tiles, kScatterBlock, 0, s>>>(
-          ArraySource<K, V>{a, va}, b, vb, static_cast<uint32_t>(N), shift, dm, tag,
-          hist + static_cast<size_t>(p) * kBins, status.get(), ctrs + p, fail_flag);
+    uint32_t* hp = hist + static_cast<size_t>(p) * kBins;
+    const ArraySink<K, V> to{vb};
+    if (p + 1 == passes && last) {
+      if (p == 0)
+        k_sweep_scatter<K, V, Src, Sink><<<tiles, kScatterBlock, 0, s>>>(first, b, *last, static_cast<uint32_t>(N),
+                                                                         shift, dm, tag, hp, status.get(), ctrs + p,
+                                                                         fail_flag);
+      else
+        k_sweep_scatter<K, V, ArraySource<K, V>, Sink><<<tiles, kScatterBlock, 0, s>>>(
+            ArraySource<K, V>{a, va}, b, *last, static_cast<uint32_t>(N), shift, dm, tag, hp, status.get(), ctrs + p,
+            fail_flag);
+    } else if (p == 0) {
+      k_sweep_scatter<K, V, Src, ArraySink<K, V>><<<tiles, kScatterBlock, 0, s>>>(
+          first, b, to, static_cast<uint32_t>(N), shift, dm, tag, hp, status.get(), ctrs + p, fail_flag);
+    } else {
+      k_sweep_scatter<K, V, ArraySource<K, V>, ArraySink<K, V>><<<tiles, kScatterBlock, 0, s>>>(
+          ArraySource<K, V>{a, va}, b, to, static_cast<uint32_t>(N), shift, dm, tag, hp, status.get(), ctrs + p,
+          fail_flag);
+    }
     TC_LAUNCH_CHECK();
     std::swap(a, b);
     std::swap(va, vb);
