@@ -766,31 +766,58 @@ void build_graph(const int32_t* src, const int32_t* dst, int64_t E, int32_t n, c
 //   B.  Ranks in the order of Eq. (1) from the complete degrees.
 //   C1. The unique keys stream through once more to count each row (the
 //       orientation's earlier endpoint); the prefix sum is the CSR offsets.
-//   C2. The rows are cut into ranges whose entries fit the budget.
-//   C3. For each range, the unique keys stream through, the oriented entries
-//       of its rows are kept, sorted by (row, column) and their columns copied
-//       to their place in the host adjacency array.
+//   C2. The rows are cut into ranges whose entries fit the budget. With three
+//       ranges or more, the unique keys stream through once more, are
+//       oriented into rank space and split by range (the same multisplit as
+//       A1, the part found by a search of the range starts), grouped per
+//       chunk in host memory.
+//   C3. For each range, its part is gathered from the chunks (with one or two
+//       ranges: the unique keys stream through and its rows are kept), sorted
+//       by (row, column) and its columns copied to their place in the host
+//       adjacency array.
 
 namespace {
 
 constexpr int kPartLog2Max = 9;  // at most 512 parts
 constexpr int kSplitTile = kBlock * 16;
 
-__device__ __forceinline__ uint32_t part_of(uint64_t key, int b, int plog2) {
+// The part of a key: a multiplicative hash of its high field, or (with
+// range starts rs[0..nr], in LDS) the range r with rs[r] <= field < rs[r+1].
+__device__ __forceinline__ uint32_t part_of(uint64_t key, int b, int plog2, const int32_t* rs, int nr) {
+  const int32_t f = static_cast<int32_t>(key >> b);
+  if (rs) {
+    int lo = 0, hi = nr - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (rs[mid] <= f) lo = mid;
+      else hi = mid - 1;
+    }
+    return static_cast<uint32_t>(lo);
+  }
   return plog2 == 0 ? 0u : static_cast<uint32_t>(((key >> b) * 0x9E3779B97F4A7C15ull) >> (64 - plog2));
+}
+
+// Range starts for part_of in LDS (nr + 1 words, nr <= 512); null without ranges.
+__device__ __forceinline__ const int32_t* stage_ranges(const int32_t* __restrict__ ranges, int nr, int32_t* lds) {
+  if (!ranges) return nullptr;
+  for (int i = threadIdx.x; i <= nr; i += blockDim.x) lds[i] = ranges[i];
+  return lds;
 }
 
 // counts[p] += number of valid keys of part p in this block's tile
 __global__ __launch_bounds__(kBlock) void k_part_count(const uint64_t* __restrict__ keys, uint64_t N, int b, int plog2,
+                                                       const int32_t* __restrict__ ranges,
                                                        uint32_t* __restrict__ counts) {
   __shared__ uint32_t h[1 << kPartLog2Max];
+  __shared__ int32_t rl[(1 << kPartLog2Max) + 1];
   const int P = 1 << plog2;
+  const int32_t* rs = stage_ranges(ranges, P, rl);
   for (int i = threadIdx.x; i < P; i += kBlock) h[i] = 0;
   __syncthreads();
   const uint64_t base = static_cast<uint64_t>(blockIdx.x) * kSplitTile;
   for (int i = threadIdx.x; i < kSplitTile; i += kBlock) {
     const uint64_t idx = base + i;
-    if (idx < N && keys[idx] != ~0ull) atomicAdd(&h[part_of(keys[idx], b, plog2)], 1u);
+    if (idx < N && keys[idx] != ~0ull) atomicAdd(&h[part_of(keys[idx], b, plog2, rs, P)], 1u);
   }
   __syncthreads();
   for (int i = threadIdx.x; i < P; i += kBlock)
@@ -800,17 +827,20 @@ __global__ __launch_bounds__(kBlock) void k_part_count(const uint64_t* __restric
 // Each valid key to out[start[p] + its slot]: the block reserves its part
 // counts with one atomic per part, then hands out slots in LDS.
 __global__ __launch_bounds__(kBlock) void k_part_scatter(const uint64_t* __restrict__ keys, uint64_t N, int b,
-                                                         int plog2, const uint32_t* __restrict__ start,
+                                                         int plog2, const int32_t* __restrict__ ranges,
+                                                         const uint32_t* __restrict__ start,
                                                          uint32_t* __restrict__ cursor, uint64_t* __restrict__ out) {
   __shared__ uint32_t h[1 << kPartLog2Max];
   __shared__ uint32_t base_of[1 << kPartLog2Max];
+  __shared__ int32_t rl[(1 << kPartLog2Max) + 1];
   const int P = 1 << plog2;
+  const int32_t* rs = stage_ranges(ranges, P, rl);
   for (int i = threadIdx.x; i < P; i += kBlock) h[i] = 0;
   __syncthreads();
   const uint64_t base = static_cast<uint64_t>(blockIdx.x) * kSplitTile;
   for (int i = threadIdx.x; i < kSplitTile; i += kBlock) {
     const uint64_t idx = base + i;
-    if (idx < N && keys[idx] != ~0ull) atomicAdd(&h[part_of(keys[idx], b, plog2)], 1u);
+    if (idx < N && keys[idx] != ~0ull) atomicAdd(&h[part_of(keys[idx], b, plog2, rs, P)], 1u);
   }
   __syncthreads();
   for (int i = threadIdx.x; i < P; i += kBlock) {
@@ -823,7 +853,7 @@ __global__ __launch_bounds__(kBlock) void k_part_scatter(const uint64_t* __restr
     if (idx < N) {
       const uint64_t k = keys[idx];
       if (k != ~0ull) {
-        const uint32_t p = part_of(k, b, plog2);
+        const uint32_t p = part_of(k, b, plog2, rs, P);
         out[base_of[p] + atomicAdd(&h[p], 1u)] = k;
       }
     }
@@ -834,6 +864,15 @@ struct KeyAt {
   const uint64_t* k;
   __device__ uint64_t operator()(size_t i) const { return k[i]; }
 };
+
+// out[i] = the oriented key (min rank << b | max rank) of unique key i
+__global__ void k_orient_keys(const uint64_t* __restrict__ keys, uint64_t N, int b, const int32_t* __restrict__ rank,
+                              uint64_t* __restrict__ out) {
+  const RelabelKey rk{keys, b, rank};
+  for (uint64_t i = static_cast<uint64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < N;
+       i += static_cast<uint64_t>(gridDim.x) * blockDim.x)
+    out[i] = rk(i);
+}
 
 // rows[min rank] += 1 per unique key (runs of equal rows with one atomic)
 __global__ __launch_bounds__(kBlock) void k_oriented_row_counts(const uint64_t* __restrict__ keys, uint64_t N, int b,
@@ -953,7 +992,7 @@ void build_host_csr(const int32_t* src, const int32_t* dst, int64_t E, int32_t n
       TC_LAUNCH_CHECK();
       TC_HIP(hipMemsetAsync(cnt.get(), 0, P * sizeof(uint32_t), s));
       const unsigned tiles = static_cast<unsigned>((N + kSplitTile - 1) / kSplitTile);
-      k_part_count<<<tiles, kBlock, 0, s>>>(dk.get(), N, b, plog2, cnt.get());
+      k_part_count<<<tiles, kBlock, 0, s>>>(dk.get(), N, b, plog2, nullptr, cnt.get());
       TC_LAUNCH_CHECK();
       uint32_t* hc = &pcount[c * P];
       TC_HIP(hipMemcpyAsync(hc, cnt.get(), P * sizeof(uint32_t), hipMemcpyDeviceToHost, s));
@@ -965,7 +1004,7 @@ void build_host_csr(const int32_t* src, const int32_t* dst, int64_t E, int32_t n
       }
       TC_HIP(hipMemcpyAsync(cnt.get(), &pstart[c * P], P * sizeof(uint32_t), hipMemcpyHostToDevice, s));
       TC_HIP(hipMemsetAsync(cur.get(), 0, P * sizeof(uint32_t), s));
-      k_part_scatter<<<tiles, kBlock, 0, s>>>(dk.get(), N, b, plog2, cnt.get(), cur.get(), dg.get());
+      k_part_scatter<<<tiles, kBlock, 0, s>>>(dk.get(), N, b, plog2, nullptr, cnt.get(), cur.get(), dg.get());
       TC_LAUNCH_CHECK();
       chunk_at[c + 1] = chunk_at[c] + acc;
       if (acc) TC_HIP(hipMemcpyAsync(grouped.p + chunk_at[c], dg.get(), acc * sizeof(uint64_t), hipMemcpyDeviceToHost, s));
@@ -1068,27 +1107,87 @@ void build_host_csr(const int32_t* src, const int32_t* dst, int64_t E, int32_t n
   if (h_fail) fail(TC_E_DEVICE, "radix_sort: a tile's look-back did not complete");
   if (static_cast<uint64_t>(off_h[n]) != m) fail(TC_E_DEVICE, "oriented row counts do not add up to m");
 
-  // ---- C2-C3: row ranges that fit the budget, each sorted and copied out
-  uint64_t ranges = 0;
+  // ---- C2: row ranges [rs[r], rs[r+1]) whose entries fit the budget (each at least one row)
+  std::vector<int32_t> rs(1, 0);
+  while (rs.back() < n) {
+    const int32_t r0 = rs.back();
+    int32_t lo = r0 + 1, hi = n;  // largest r1 with off[r1] - off[r0] <= Cr
+    while (lo < hi) {
+      const int32_t mid = lo + (hi - lo + 1) / 2;
+      if (static_cast<uint64_t>(off_h[mid] - off_h[r0]) <= Cr) lo = mid;
+      else hi = mid - 1;
+    }
+    if (static_cast<uint64_t>(off_h[lo] - off_h[r0]) > Cr) fail(TC_E_NOMEM, "one oriented row does not fit the device budget");
+    rs.push_back(lo);
+  }
+  const uint64_t ranges = rs.size() - 1;
+  // Splitting costs a pass in and a pass out over the keys and saves one pass in per range
+  // after the first: worth it from three ranges on (up to the multisplit's 512 parts).
+  const bool split = ranges >= 3 && ranges <= (1u << kPartLog2Max) && m > 0;
+  int p2log = 0;
+  while ((1ull << p2log) < ranges) p2log++;
+  const int P2 = 1 << p2log;
+  const uint64_t nch2 = split ? (m + C2 - 1) / C2 : 0;
+  std::vector<uint32_t> pc2(static_cast<size_t>(nch2) * P2, 0), ps2(static_cast<size_t>(nch2) * P2, 0);
+  std::vector<uint64_t> chunk2_at(nch2 + 1, 0);
+  if (split) {  // the oriented keys grouped by range, per chunk, in the host buffer of the grouped records
+    std::vector<int32_t> starts(static_cast<size_t>(P2) + 1, n);  // ranges past the last are empty
+    for (uint64_t r = 0; r < ranges; r++) starts[r] = rs[r];
+    DevBuf<int32_t> drs(static_cast<size_t>(P2) + 1, s);
+    TC_HIP(hipMemcpyAsync(drs.get(), starts.data(), starts.size() * sizeof(int32_t), hipMemcpyHostToDevice, s));
+    DevBuf<uint64_t> dor(c2, s), dgr(c2, s);
+    DevBuf<uint32_t> cnt(P2, s), cur(P2, s);
+    for (uint64_t c = 0; c < nch2; c++) {
+      const uint64_t i0 = c * C2, N = m - i0 < C2 ? m - i0 : C2;
+      TC_HIP(hipMemcpyAsync(dch.get(), uniq.p + i0, N * sizeof(uint64_t), hipMemcpyHostToDevice, s));
+      bytes_in += 8 * N;
+      k_orient_keys<<<grid_for(N, kBlock, 65536), kBlock, 0, s>>>(dch.get(), N, b, rank.get(), dor.get());
+      TC_LAUNCH_CHECK();
+      TC_HIP(hipMemsetAsync(cnt.get(), 0, P2 * sizeof(uint32_t), s));
+      const unsigned tiles = static_cast<unsigned>((N + kSplitTile - 1) / kSplitTile);
+      k_part_count<<<tiles, kBlock, 0, s>>>(dor.get(), N, b, p2log, drs.get(), cnt.get());
+      TC_LAUNCH_CHECK();
+      uint32_t* hc = &pc2[c * P2];
+      TC_HIP(hipMemcpyAsync(hc, cnt.get(), P2 * sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+      TC_HIP(hipStreamSynchronize(s));
+      uint64_t acc = 0;
+      for (int p = 0; p < P2; p++) {
+        ps2[c * P2 + p] = static_cast<uint32_t>(acc);
+        acc += hc[p];
+      }
+      if (acc != N) fail(TC_E_DEVICE, "row range counts do not add up");
+      TC_HIP(hipMemcpyAsync(cnt.get(), &ps2[c * P2], P2 * sizeof(uint32_t), hipMemcpyHostToDevice, s));
+      TC_HIP(hipMemsetAsync(cur.get(), 0, P2 * sizeof(uint32_t), s));
+      k_part_scatter<<<tiles, kBlock, 0, s>>>(dor.get(), N, b, p2log, drs.get(), cnt.get(), cur.get(), dgr.get());
+      TC_LAUNCH_CHECK();
+      chunk2_at[c + 1] = chunk2_at[c] + N;
+      TC_HIP(hipMemcpyAsync(grouped.p + chunk2_at[c], dgr.get(), N * sizeof(uint64_t), hipMemcpyDeviceToHost, s));
+      bytes_out += 8 * N;
+      TC_HIP(hipStreamSynchronize(s));  // the chunk buffers are reused
+    }
+  }
+
+  // ---- C3: each range sorted and its columns copied out
   {
     DevBuf<uint64_t> rk1(Cr, s), rk2(Cr, s);
     DevBuf<int32_t> cols(Cr, s);
     DevBuf<uint64_t> dcnt(1, s);
-    int32_t r0 = 0;
-    while (r0 < n) {
-      // largest r1 with off[r1] - off[r0] <= Cr (at least one row)
-      int32_t lo = r0 + 1, hi = n;
-      while (lo < hi) {
-        const int32_t mid = lo + (hi - lo + 1) / 2;
-        if (static_cast<uint64_t>(off_h[mid] - off_h[r0]) <= Cr) lo = mid;
-        else hi = mid - 1;
-      }
-      const int32_t r1 = lo;
+    for (uint64_t r = 0; r < ranges; r++) {
+      const int32_t r0 = rs[r], r1 = rs[r + 1];
       const uint64_t M = static_cast<uint64_t>(off_h[r1] - off_h[r0]);
-      if (M > Cr) fail(TC_E_NOMEM, "one oriented row does not fit the device budget");
-      ranges++;
-      if (M > 0) {
-        uint64_t got = 0;
+      if (M == 0) continue;
+      uint64_t got = 0;
+      if (split) {  // the range's part of every chunk (already oriented)
+        for (uint64_t c = 0; c < nch2; c++) {
+          const uint32_t k = pc2[c * P2 + r];
+          if (!k) continue;
+          if (got + k > M) fail(TC_E_DEVICE, "row range overflow");
+          TC_HIP(hipMemcpyAsync(rk1.get() + got, grouped.p + chunk2_at[c] + ps2[c * P2 + r], k * sizeof(uint64_t),
+                                hipMemcpyHostToDevice, s));
+          bytes_in += 8ull * k;
+          got += k;
+        }
+      } else {  // every unique key streams through; the range's rows are kept, oriented
         for (uint64_t i0 = 0; i0 < m; i0 += C2) {
           const uint64_t N = m - i0 < C2 ? m - i0 : C2;
           TC_HIP(hipMemcpyAsync(dch.get(), uniq.p + i0, N * sizeof(uint64_t), hipMemcpyHostToDevice, s));
@@ -1101,15 +1200,14 @@ void build_host_csr(const int32_t* src, const int32_t* dst, int64_t E, int32_t n
           got += k;
           if (got > M) fail(TC_E_DEVICE, "row range overflow");
         }
-        if (got != M) fail(TC_E_DEVICE, "row range count mismatch");
-        uint64_t* ok = radix_sort<uint64_t>(rk1.get(), rk2.get(), M, 0, 2 * b, s, sort_fail.get());
-        k_cols_of<<<grid_for(M, kBlock, 65536), kBlock, 0, s>>>(ok, M, b, cols.get());
-        TC_LAUNCH_CHECK();
-        TC_HIP(hipMemcpyAsync(adj_h + off_h[r0], cols.get(), M * sizeof(int32_t), hipMemcpyDeviceToHost, s));
-        bytes_out += 4 * M;
-        TC_HIP(hipStreamSynchronize(s));
       }
-      r0 = r1;
+      if (got != M) fail(TC_E_DEVICE, "row range count mismatch");
+      uint64_t* ok = radix_sort<uint64_t>(rk1.get(), rk2.get(), M, 0, 2 * b, s, sort_fail.get());
+      k_cols_of<<<grid_for(M, kBlock, 65536), kBlock, 0, s>>>(ok, M, b, cols.get());
+      TC_LAUNCH_CHECK();
+      TC_HIP(hipMemcpyAsync(adj_h + off_h[r0], cols.get(), M * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+      bytes_out += 4 * M;
+      TC_HIP(hipStreamSynchronize(s));
     }
   }
   TC_HIP(hipMemcpyAsync(&h_fail, sort_fail.get(), sizeof(uint32_t), hipMemcpyDeviceToHost, s));
