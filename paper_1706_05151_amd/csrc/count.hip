@@ -159,7 +159,9 @@ __global__ __launch_bounds__(kBlock) void k_work(const int64_t* __restrict__ off
 // the suffix of N_v after u, off[v + 1] - e - 1. Pivots with an empty N_u and
 // records with an empty suffix stay in the list; they are given no work.
 struct InEdgeSource {
+  using Key = uint64_t;
   static constexpr bool kArrays = false;
+  static constexpr int kHistShift = 32;  // the digits are those of u = adj[e]: counted from adj itself
   const int64_t* __restrict__ off;
   const int32_t* __restrict__ adj;
   const int32_t* __restrict__ src;
@@ -172,14 +174,20 @@ struct InEdgeSource {
     const uint64_t e = e0 + i;
     return static_cast<uint32_t>(off[src[e] + 1] - static_cast<int64_t>(e) - 1);
   }
+  ArraySource<uint32_t, NoVal> hist() const {
+    return ArraySource<uint32_t, NoVal>{reinterpret_cast<const uint32_t*>(adj + e0), nullptr};
+  }
 };
 
 // The last pass of the record sort writes each record in its final form:
-// suffix start e + 1 (e from the key's low word) and suffix length.
+// suffix start e + 1 (e from the key's low word) and suffix length, and the
+// length alone to lens (for the cost prefix).
 struct RecordSink {
   InRec* __restrict__ rec;
+  uint32_t* __restrict__ lens;
   __device__ __forceinline__ void put(size_t g, uint64_t key, uint32_t len) const {
     rec[g] = InRec{static_cast<uint32_t>(key) + 1u, len};
+    lens[g] = len;
   }
 };
 
@@ -419,12 +427,14 @@ void build_plan(Csr& c, PivotPlan& P, uint64_t e0, uint64_t e1, hipStream_t s, c
   // then made from the key and value)
   const bool filled = mi > 1;
   if (filled) P.inrec.alloc(mi, s);
-  const RecordSink recs{P.inrec.p};
+  // the value buffer the last pass would write (passes alternate from vtmp), free for the lengths
+  uint32_t* lens_out = (((b + kRadixBits - 1) / kRadixBits) & 1) ? il2.get() : il.get();
+  const RecordSink recs{P.inrec.p, lens_out};
   uint64_t* sk = radix_sort_from<uint64_t, uint32_t, InEdgeSource, NoHook, RecordSink>(
       InEdgeSource{c.off.p, c.adj.p, c.src.p, e0}, ik.get(), ik2.get(), sl, il2.get(), mi, 32, 32 + b, s,
       sort_fail.get(), NoHook(), filled ? &recs : nullptr);
   DevBuf<int64_t> fin;
-  plan_records(c, P, sk, filled ? nullptr : sl, mi, fin, s, filled);
+  plan_records(c, P, sk, filled ? lens_out : sl, mi, fin, s, filled);
   ik.release();
   ik2.release();
   il.release();

@@ -259,8 +259,8 @@ void note_plan_use(PivotPlan& P, hipStream_t s);
 // Plan steps from in-edge keys (pivot << 32 | e) sorted by pivot (stable in e):
 // the records and their cost prefix fin (lens: suffix lengths in key order, or
 // null to take them from c.off / c.src; filled: P.inrec already holds the
-// records, and the cost prefix is taken from them), then the classification
-// and items.
+// records, and the cost prefix is taken from lens, or from the records when
+// lens is null), then the classification and items.
 void plan_records(Csr& c, PivotPlan& P, const uint64_t* sk, const uint32_t* sl, uint64_t mi, DevBuf<int64_t>& fin,
                   hipStream_t s, bool filled = false);
 // sort_fail (device, optional): a sort failure flag checked at plan_items' first synchronisation

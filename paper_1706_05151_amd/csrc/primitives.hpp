@@ -299,13 +299,19 @@ __host__ __device__ __forceinline__ uint32_t radix_digit_mask(int shift, int bit
 
 // Where a sort's first pass reads key i and value i: its key and value
 // arrays, or (another source type) a functor that makes them on the fly.
+// The digit count reads hist() instead: keys whose bits [kHistShift, ...)
+// are the sort keys' bits [kHistShift, ...) seen from bit 0 (a narrower key
+// type where the sort bits allow it).
 template <typename K, typename V>
 struct ArraySource {
+  using Key = K;
   static constexpr bool kArrays = true;
+  static constexpr int kHistShift = 0;
   const K* __restrict__ keys;
   const V* __restrict__ vals;
   __device__ __forceinline__ K key(size_t i) const { return keys[i]; }
   __device__ __forceinline__ V val(size_t i) const { return vals[i]; }
+  ArraySource hist() const { return *this; }
 };
 
 // Where a pass writes the value that lands at output position g (with its
@@ -629,9 +635,12 @@ K* radix_sort_from(Src first, K* keys, K* tmp, V*& vals, V* vtmp, size_t N, int 
   uint32_t* fail_flag = fail_dev ? fail_dev : ctrs + passes;
   int copies = 4;  // LDS: copies * (passes * kBins + 1) words <= 64 KiB
   while (copies > 1 && static_cast<size_t>(copies) * (static_cast<size_t>(passes) * kBins + 1) * 4 > 65536) copies >>= 1;
-  k_sweep_hist<K, Src><<<tiles < 2048u ? tiles : 2048u, kSortBlock,
-                         static_cast<size_t>(copies) * (static_cast<size_t>(passes) * kBins + 1) * 4, s>>>(
-      first, static_cast<uint32_t>(N), bit_lo, bit_hi, passes, copies, hist);
+  const auto hsrc = first.hist();
+  using HSrc = decltype(hsrc);
+  k_sweep_hist<typename HSrc::Key, HSrc><<<tiles < 2048u ? tiles : 2048u, kSortBlock,
+                                            static_cast<size_t>(copies) * (static_cast<size_t>(passes) * kBins + 1) * 4,
+                                            s>>>(hsrc, static_cast<uint32_t>(N), bit_lo - Src::kHistShift,
+                                                 bit_hi - Src::kHistShift, passes, copies, hist);
   TC_LAUNCH_CHECK();
   k_sweep_starts<<<passes, kBins, 0, s>>>(hist);
   TC_LAUNCH_CHECK();
