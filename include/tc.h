@@ -251,8 +251,11 @@ tc_status tc_graph_export_csr(tc_graph* g, void* stream, int64_t* off, int32_t* 
  * of Section 6, here larger than one device). The records are split by a hash
  * of their smaller endpoint into parts sorted and deduplicated one at a time
  * (degrees accumulate on the device); after the ranks, the unique edges
- * stream through again to count the rows, and once per range of rows that
- * fits the budget to sort that range and copy its entries out.
+ * stream through again to count the rows. The rows are cut into ranges that
+ * fit the budget; with three ranges or more the unique edges stream through
+ * once more and are split by range (each range then loads only its own
+ * part), with fewer they stream through once per range. Each range is sorted
+ * and its entries copied out.
  *   src, dst : host int32[num_edges] ids in [0,n) (pinned memory copies fastest).
  *   off      : host int64[n+1], written: row r holds adj[off[r] .. off[r+1]).
  *   adj      : host int32 with room for the unique edges (num_edges suffices).
@@ -279,7 +282,9 @@ tc_status tc_build_csr_host(const int32_t* src, const int32_t* dst, int64_t num_
  * chunk, not once per edge). For each source range, the in-edge records
  * (v,u), u in V_j, count |N_v after u ∩ N_u| with the pivot kernel. Each
  * triangle is counted once, at the partition of its middle vertex. The next
- * chunk is copied in while the current one is counted.
+ * chunk is copied in while the current one is counted, and a partition is
+ * loaded range by range (its last rows first) so that its first pairs are
+ * counted while the rest is still being copied.
  *
  * Input: off host int64[n+1] with off[0] = 0 and off[n] = m; adj int32[m]
  * (host, pinned for full copy speed, or device memory). Row r must hold
