@@ -124,3 +124,31 @@ def test_rmat20_end_to_end_under_a_budget(tc):
     say(f"[ooc] count: {sinfo}")
     assert T == gold["T"]
     _check_against_oracle(el, off.numpy(), adj.numpy())
+
+
+@pytest.mark.parametrize("scale", [16, 17])
+def test_row_ranges_streamed_or_split(tc, scale):
+    """At the smallest budget (64 n + 32 MiB: 524,288 entries per row range), R-MAT 16 needs two row
+    ranges (each streams every unique key through) and R-MAT 17 four (the oriented keys are split by
+    range in one pass and each range loads its own part): both give the resident build's CSR, and the
+    streamed count of it gives the oracle's T."""
+    import torch
+
+    el = synth.rmat(scale, 16, 5)
+    ref = oracle.solve(el.src, el.dst, el.n, per_node=False)
+    budget = 64 * el.n + (32 << 20)
+    src = torch.from_numpy(el.src).pin_memory()
+    dst = torch.from_numpy(el.dst).pin_memory()
+    say(f"[ooc] R-MAT {scale} at {budget >> 20} MiB")
+    off, adj, info = tc.build_csr_host(src, dst, el.n, budget)
+    say(f"[ooc] build: {info}")
+    if scale == 16:
+        assert info["row_ranges"] == 2
+    else:
+        assert info["row_ranges"] >= 3
+    with tc.Graph.build(src.cuda(), dst.cuda(), el.n) as g:
+        o2, a2 = g.export_csr()
+    np.testing.assert_array_equal(off.numpy(), o2.numpy())
+    np.testing.assert_array_equal(adj.numpy(), a2.numpy())
+    T, _ = tc.count_streamed(off, adj, el.n, budget)
+    assert T == ref.T
