@@ -119,6 +119,27 @@ def test_families(tc, spec):
         tc.set_option(tc.OPT_KERNEL, old)
 
 
+TINY = [synth.complete(2), synth.path(3), synth.complete(3), synth.star(5), synth.wheel(4)]
+
+
+@pytest.mark.parametrize("el", TINY, ids=[g.name for g in TINY])
+def test_tiny_graphs_on_the_pivot_kernel(tc, el):
+    """The pivot kernel forced on graphs of one to eight edges (a work plan of one record sorts
+    nothing: the record is made from the key as read): total, per-node counts and the list."""
+    ref = oracle.solve(el.src, el.dst, el.n, per_node=True, listing=True)
+    old = tc.get_option(tc.OPT_KERNEL)
+    try:
+        tc.set_option(tc.OPT_KERNEL, 2)
+        with tc.Graph.build(*to_dev(el), el.n) as g:
+            assert g.count() == ref.T
+            T, t = g.count_per_node()
+            assert T == ref.T
+            np.testing.assert_array_equal(u64(t), ref.t)
+            np.testing.assert_array_equal(g.list().cpu().numpy(), ref.tri)
+    finally:
+        tc.set_option(tc.OPT_KERNEL, old)
+
+
 @pytest.mark.parametrize("hub,iw,load", [(0, 64, 1), (0, 4096, 2), (16, 64, 2), (256, 100000, 1), (64, 512, 2),
                                          (128, 16384, 1)])
 def test_partitioner_settings_identical(tc, hub, iw, load):
